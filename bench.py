@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Throughput of restarted PDHG on one MI355X.
+
+One step = one block of the solve loop: `check_period` (30) PDHG iterations
+(A'y and A x+ SpMVs with fused projections and running sums) followed by
+the restart check (check-time SpMVs, KKT at z and z-bar, the normalized
+duality gap by the trust-region bisection, restart decision and restart).
+The timed region replays K blocks through pdhg_solve with tol = 0, so no
+block is skipped.  `value` is PDHG iterations per second with the LP
+already resident in HBM.
+
+Default workload: the large sparse LP, 1,000,000 x 2,000,000 with power-law
+column counts (exponent 2, 1..1000 per column, ~9.1M entries), random-sign
+log-uniform values in [1e-3, 1e3], planted optimum, seed 3.
+
+The roofline figure is for the dominant kernel (the larger of the two
+half-step SpMV kernels), timed with HIP events on the handle's stream right
+after the timed region; algorithmic bytes per launch are
+    primal: 12 nnz + 60 n + 8 m     dual: 12 nnz + 61 m + 8 n
+(values + int32 indices of A' or A, row pointers, the vector reads and
+writes of the epilogue, and one compulsory read of the gathered vector).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "PDHG iter/s + HBM GB/s; time to 1e-8 rel KKT, batched vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    from paper_2105_12715_amd import lpgen
+    if name == "large":
+        return lpgen.large_powerlaw(3), "large power-law LP 1,000,000 x 2,000,000 (seed 3)"
+    if name == "medium":
+        return lpgen.medium(2), "medium LP 20,000 x 50,000, 10 per column (seed 2)"
+    if name == "small":
+        return lpgen.small_dense(1), "small LP 50 x 100, Bernoulli(0.1) (seed 1)"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("pdhg_kernels.hip", "pdhg_device.h", "pdhg_internal.h"):
+        with open(os.path.join(ROOT, "paper_2105_12715_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken with the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(lp, eta, budget_s=12.0):
+    import oracle
+    o = oracle.Oracle(lp, eta=eta, mode=oracle.MODE_ADAPTIVE)
+    # calibrate on 2 iterations, then run whole 30-iteration blocks with
+    # their checks for about budget_s seconds (at least one block)
+    t0 = time.perf_counter()
+    o.step(2)
+    per_iter = (time.perf_counter() - t0) / 2
+    blocks = max(1, int(budget_s / (per_iter * 30 * 1.5)))
+    o2 = oracle.Oracle(lp, eta=eta, mode=oracle.MODE_ADAPTIVE)
+    t0 = time.perf_counter()
+    o2.solve(30 * blocks, 0.0)
+    dt = time.perf_counter() - t0
+    o.close()
+    o2.close()
+    return {"value": 30 * blocks / dt, "unit": "iter/s", "cores": 1, "kind": "oracle",
+            "sample": f"{blocks} block(s) of 30 iterations + restart check on the same LP, "
+                      f"single-threaded FP64 C oracle, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=167, help="timed blocks of 30 iterations")
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="large", choices=["large", "medium", "small"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-iters", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no "
+              "multi-GPU path in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2105_12715_amd import _lib
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    _lib.load(build_if_missing=True)
+    t0 = time.perf_counter()
+    lp, wdesc = make_workload(args.workload)
+    log(f"workload {wdesc}: m={lp.m} n={lp.n} nnz={lp.nnz} generated in "
+        f"{time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    s = _lib.Solver(lp, restart_mode=_lib.RESTART_ADAPTIVE)
+    torch.cuda.synchronize()
+    info = s.info()
+    log(f"setup (validate, transpose, power iteration {info['power_iters_used']} steps) "
+        f"{time.perf_counter() - t0:.2f}s, eta={info['eta']:.6g}")
+    P = 30
+    s.solve(args.warmup * P, 0.0)
+    torch.cuda.synchronize()
+    log("warmup done")
+    t0 = time.perf_counter()
+    s.solve(args.steps * P, 0.0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = args.steps * P
+    value = iters / dt
+    info = s.info()
+    log(f"timed {iters} iterations in {dt:.3f}s: {value:.1f} iter/s, restarts so far "
+        f"{info['restarts']}")
+
+    ms_p, ms_d = s.time_iterations(args.kernel_iters)
+    m, n, nnz = lp.m, lp.n, lp.nnz
+    bytes_p = 12 * nnz + 60 * n + 8 * m
+    bytes_d = 12 * nnz + 61 * m + 8 * n
+    if ms_p >= ms_d:
+        kname, kb, kms = "primal", bytes_p, ms_p
+    else:
+        kname, kb, kms = "dual", bytes_d, ms_d
+    achieved = kb / (kms * 1e-3) / 1e9
+    log(f"kernel ms: primal {ms_p:.4f} ({bytes_p / ms_p / 1e6:.0f} GB/s), dual {ms_d:.4f} "
+        f"({bytes_d / ms_d / 1e6:.0f} GB/s)")
+    traffic = measured_traffic(args.workload, kname)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": f"{kname} half-step SpMV", "algorithmic_bytes_per_launch": kb,
+            "ms_per_launch": round(kms, 5),
+            "other_kernel_ms": round(ms_d if kname == "primal" else ms_p, 5)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(lp, info["eta"])
+        log(f"cpu baseline {cpu['value']:.2f} iter/s")
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "iter/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wdesc, "m": m, "n": n, "nnz": nnz, "check_period": P,
+                   "iterations_per_step": P, "restart": "adaptive", "parallelism": "single GPU"},
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,264 @@
+/*
+ * pdhg.h - C ABI of the MI355X (gfx950) restarted-PDHG LP library.
+ *
+ * Problem (the paper's LP, Section 1 and eq. LP-primal, widened to boxes
+ * and >= rows):
+ *
+ *     minimize   c'x
+ *     subject to (A x)_i  = b_i   for rows of kind 0,
+ *                (A x)_i >= b_i   for rows of kind 1,
+ *                l <= x <= u      (entries of l may be -inf, of u +inf).
+ *
+ * Method: restarted PDHG on the saddle problem
+ * L(x,y) = c'x - y'Ax + b'y over X = {l <= x <= u},
+ * Y = {y : y_i >= 0 on rows of kind 1} (eq. LP-Lagrangian).  One iteration
+ * is the PDHG update (eq. PDHG-update) with primal step tau = eta/omega and
+ * dual step sigma = eta*omega:
+ *     x+ = proj_X(x - tau (c - A'y)),
+ *     y+ = proj_Y(y + sigma (b - A(2x+ - x))),
+ * followed by the running average of Algorithm 1.  Every `check_period`
+ * iterations (Section 7 uses 30) the library evaluates the KKT error at the
+ * current point and at the average, and the restart test of
+ * eq. adaptive-restart-scheme, which needs the normalized duality gap
+ * rho_r(z) of eq. rhorz; rho comes from the linear trust region of
+ * Section 6.3.1 solved by bisection on the multiplier.
+ *
+ * Conventions for every entry point:
+ *  - Device pointers point to memory on the current HIP device.  Host
+ *    pointers are marked "host".  The caller owns every buffer, including
+ *    the workspace, and keeps them alive until pdhg_destroy returns.  The
+ *    library allocates no device memory; its only allocations are the host
+ *    handle and the HIP graph objects it records.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the legacy
+ *    default stream.  All work is enqueued on that stream; calls that
+ *    return host values synchronize it.
+ *  - Return codes: 0 success; >0 a non-error outcome; <0 an error (see
+ *    PDHG_E_*).  No C++ exception crosses the ABI.  After an error in a
+ *    call other than pdhg_create the handle stays usable.
+ *  - One host thread at a time per handle.
+ *  - All floating point is IEEE FP64; indices are int32 (m, n, nnz must be
+ *    below 2^31).
+ */
+#ifndef PDHG_H
+#define PDHG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define PDHG_OK 0
+#define PDHG_NOT_CONVERGED 1  /* iteration budget used up without reaching tol */
+#define PDHG_E_INVALID (-1)   /* bad argument, malformed CSR, l > u, NaN data  */
+#define PDHG_E_WORKSPACE (-2) /* workspace missing, misaligned or too small    */
+#define PDHG_E_HIP (-3)       /* a HIP runtime call failed                     */
+#define PDHG_E_NUMERICAL (-4) /* NaN or Inf appeared in the iterates           */
+
+/* restart schemes (Section 5 and Remark rem:flexible) */
+#define PDHG_RESTART_NONE 0
+#define PDHG_RESTART_ADAPTIVE 1 /* eq. adaptive-restart-scheme                    */
+#define PDHG_RESTART_FLEXIBLE 2 /* adaptive, candidate may be the last iterate    */
+#define PDHG_RESTART_FIXED 3    /* eq. define:t-star with t* = fixed_len          */
+
+/* which KKT error the stopping test uses */
+#define PDHG_KKT_RELATIVE 0  /* max of the three relative residuals            */
+#define PDHG_KKT_PAPER_ABS 1 /* ||(h - Kz)^+||_2, eq. define:K-and-h-for-lp    */
+#define PDHG_KKT_MAX_ABS 2   /* max abs primal residual, dual residual, gap    */
+
+/* points held by a handle */
+#define PDHG_POINT_CURRENT 0  /* z^{n,t}                                       */
+#define PDHG_POINT_AVERAGE 1  /* z-bar^{n,t}, mean of the window's iterates    */
+#define PDHG_POINT_ANCHOR 2   /* z^{n,0}, the last restart point               */
+#define PDHG_POINT_SOLUTION 3 /* the point that met tol in the last solve      */
+
+typedef struct pdhg_lp {
+    int64_t m;               /* rows of A (>= 0)                                */
+    int64_t n;               /* columns of A (>= 1)                             */
+    int64_t nnz;             /* stored entries; row_ptr[m] must equal nnz       */
+    const int32_t *row_ptr;  /* device, m+1, CSR row starts, non-decreasing     */
+    const int32_t *col_idx;  /* device, nnz, in [0, n); order within a row free */
+    const double *vals;      /* device, nnz                                     */
+    const double *c;         /* device, n                                       */
+    const double *b;         /* device, m (may be NULL when m == 0)             */
+    const double *l;         /* device, n, lower bounds (-inf allowed)          */
+    const double *u;         /* device, n, upper bounds (+inf allowed), l <= u  */
+    const int8_t *row_kind;  /* device, m, 0 (=) or 1 (>=); NULL: all equality  */
+} pdhg_lp;
+
+typedef struct pdhg_params {
+    double eta;           /* step size; <= 0: 0.9 / sigma_max(A) by power iteration */
+    double omega;         /* primal weight: primal step eta/omega, dual eta*omega   */
+    double beta;          /* restart factor (exp(-1), Remark on the choice of beta) */
+    int32_t check_period; /* iterations between checks (30)                         */
+    int32_t tau0;         /* first-window length of the adaptive scheme (1)         */
+    int32_t restart_mode; /* PDHG_RESTART_*                                         */
+    int32_t fixed_len;    /* restart length for PDHG_RESTART_FIXED                  */
+    int32_t kkt_kind;     /* PDHG_KKT_*                                             */
+    int32_t power_iters;  /* power-iteration cap (1000)                             */
+    double power_tol;     /* power-iteration relative stop (1e-10)                  */
+} pdhg_params;
+
+typedef struct pdhg_kkt {
+    double kkt;           /* the value of the selected kkt_kind                 */
+    double kkt_rel;       /* max(|p|/(1+|b|), |d|/(1+|c|), |gap|/(1+|pobj|+|dobj|)) */
+    double primal_res;    /* |p|_2: b - Ax on = rows, (b - Ax)^+ on >= rows     */
+    double dual_res;      /* |d|_2: reduced cost minus its projection on the sign set of its bounds */
+    double pobj;          /* c'x                                                */
+    double dobj;          /* b'y + sum_j (l_j lam_j^+ - u_j lam_j^-)            */
+    double kkt_paper_abs; /* ||(h - Kz)^+||_2 with bound violations             */
+    double kkt_max_abs;   /* max(|p|_2, |d|_2, |pobj - dobj|)                   */
+} pdhg_kkt;
+
+typedef struct pdhg_result {
+    int32_t status;       /* PDHG_OK (converged) or PDHG_NOT_CONVERGED         */
+    int32_t which_point;  /* PDHG_POINT_CURRENT / _AVERAGE that met tol, or -1 */
+    int64_t iterations;   /* total iterations of the handle                    */
+    int64_t restarts;     /* total restarts of the handle                      */
+    double kkt;           /* selected KKT error of the returned point          */
+    double pobj, dobj;
+} pdhg_result;
+
+typedef struct pdhg_info {
+    double eta, tau, sigma;   /* step sizes in use                            */
+    double sigma_max;         /* power-iteration estimate (0 if eta was given) */
+    int64_t k;                /* total iterations                              */
+    int64_t t;                /* iterations since the last restart             */
+    int64_t restarts;         /* restarts so far                               */
+    double rho_prev;          /* rho of the last restart point                 */
+    int64_t checks;           /* checks so far                                 */
+    int64_t power_iters_used; /* products used by the power iteration          */
+} pdhg_info;
+
+/* One check, in the order the library performs it (14 doubles):
+ *  k, t, restarts before, KKT at z, KKT at z-bar, r-bar = |z-bar - z^{n,0}|,
+ *  rho at z-bar, r = |z - z^{n,0}|, rho at z (flexible, else -1),
+ *  restarted (0/1), candidate (0 z-bar, 1 z), converged point (-1, 0, 1),
+ *  rho_prev used by the test, lambda of the z-bar trust region. */
+typedef struct pdhg_check_record {
+    double v[14];
+} pdhg_check_record;
+
+typedef struct pdhg_handle pdhg_t;
+
+/* Fill *p with the defaults above (eta auto, omega 1, beta exp(-1),
+ * check_period 30, tau0 1, adaptive restarts, relative KKT,
+ * 1000 power iterations, power_tol 1e-10). */
+void pdhg_default_params(pdhg_params *p);
+
+/* Device workspace (bytes, 256-byte aligned start required) that
+ * pdhg_create needs for an LP of this size.  Returns 0 for sizes it
+ * rejects (negative, n < 1, above int32 range). */
+size_t pdhg_workspace_bytes(int64_t m, int64_t n, int64_t nnz);
+
+/*
+ * Build a solver for `lp` (setup step of the paper's experiments,
+ * Section 7): validates the CSR (row_ptr[0] = 0, non-decreasing,
+ * row_ptr[m] = nnz, 0 <= col_idx < n, no NaN in vals/c/b, l <= u, no
+ * l = +inf or u = -inf) on the device, forms A' explicitly (entries of each
+ * transposed row in increasing row of A), picks eta (power iteration when
+ * prm->eta <= 0), and sets x = proj_X(0), y = 0.  `lp` and `prm` are host
+ * structs read during the call; the device arrays they point to are read
+ * again by later calls and must not change.  prm may be NULL (defaults).
+ * Errors: PDHG_E_INVALID, PDHG_E_WORKSPACE, PDHG_E_HIP.  On error *out is
+ * NULL.  Synchronizes the stream.
+ */
+int pdhg_create(const pdhg_lp *lp, const pdhg_params *prm, void *workspace,
+                size_t workspace_bytes, void *stream, pdhg_t **out);
+
+/* Run `iters` PDHG iterations (eq. PDHG-update + the average of
+ * Algorithm 1) with no check.  With PDHG_RESTART_FIXED the outer loop
+ * restarts whenever t reaches fixed_len.  Does not synchronize. */
+int pdhg_step(pdhg_t *h, int64_t iters);
+
+/* One check now: KKT at z and z-bar (stopping test against tol when
+ * tol > 0), then the restart test of the configured scheme and the restart
+ * itself (eq. adaptive-restart-scheme; Algorithm 1's restart line).
+ * Outputs (host, each may be NULL): *converged, *restarted, *rho (rho at
+ * z-bar), *rec.  Synchronizes. */
+int pdhg_restart_check(pdhg_t *h, double tol, int32_t *converged,
+                       int32_t *restarted, double *rho, pdhg_check_record *rec);
+
+/* KKT error of a held point (PDHG_POINT_*), into *out (host).  Syncs. */
+int pdhg_kkt_error(pdhg_t *h, int32_t which, pdhg_kkt *out);
+
+/* Normalized duality gap rho_r at a held point (eq. rhorz), with r its
+ * distance to the anchor z^{n,0} when r < 0, else the given r.  Outputs
+ * host *rho, *r_used, *lambda (each may be NULL).  Syncs. */
+int pdhg_gap(pdhg_t *h, int32_t which, double r, double *rho, double *r_used,
+             double *lambda);
+
+/* Restarted PDHG for up to `max_iters` more iterations, checking whenever
+ * the total iteration count is a multiple of check_period; stops at the
+ * first check where the KKT error of z or z-bar is <= tol (tol <= 0: never).
+ * Returns PDHG_OK when converged, PDHG_NOT_CONVERGED when the budget ran
+ * out, or an error.  *out (host, may be NULL) is filled either way.  The
+ * check blocks run as a replayed HIP graph; the host reads one status word
+ * per batch of blocks. */
+int pdhg_solve(pdhg_t *h, int64_t max_iters, double tol, pdhg_result *out);
+
+/* Copy a held point (PDHG_POINT_*) into caller device buffers x (n) and
+ * y (m), enqueued on the handle's stream.  Does not synchronize. */
+int pdhg_get_iterate(pdhg_t *h, int32_t which, double *x, double *y);
+
+/* Replace the current point and the anchor by device x (n), y (m), clear
+ * the averaging window (t = 0).  Restart count and rho_prev are kept. */
+int pdhg_set_iterate(pdhg_t *h, const double *x, const double *y);
+
+/* Scalars of the handle into *out (host).  Syncs. */
+int pdhg_get_info(pdhg_t *h, pdhg_info *out);
+
+/* Copy up to `max` most recent check records (oldest first) into host
+ * `out`; *count receives how many were written.  The library keeps the
+ * last 4096.  Syncs. */
+int pdhg_get_check_log(pdhg_t *h, pdhg_check_record *out, int64_t max,
+                       int64_t *count);
+
+/* out = A in (transpose = 0; in n, out m) or A' in (transpose = 1; in m,
+ * out n), with the library's SpMV kernels.  Device buffers; no sync. */
+int pdhg_matvec(pdhg_t *h, int32_t transpose, const double *in, double *out);
+
+/* Copy the device-built A' (CSR, entries in increasing row of A) into
+ * caller device buffers: t_row_ptr (n+1), t_col_idx (nnz), t_vals (nnz),
+ * perm (nnz; index in A of each entry of A'; may be NULL).  No sync. */
+int pdhg_get_transpose(pdhg_t *h, int32_t *t_row_ptr, int32_t *t_col_idx,
+                       double *t_vals, int32_t *perm);
+
+/* Run `iters` PDHG iterations exactly as pdhg_step does (no fixed-length
+ * restarts) with a HIP event recorded around every kernel on the handle's
+ * stream, and return the mean duration in milliseconds of the primal
+ * half-step kernel (x+ from A'y, eq. PDHG-update) and of the dual half-step
+ * kernel (y+ from A x+).  For throughput measurement.  Syncs. */
+int pdhg_time_iterations(pdhg_t *h, int64_t iters, double *ms_primal, double *ms_dual);
+
+/* Release the host handle and its graphs (does not touch caller memory).
+ * Synchronizes the stream first.  NULL is ignored. */
+void pdhg_destroy(pdhg_t *h);
+
+/*
+ * Stand-alone linear trust region of Section 6.3.1 (Algorithm 2 solves the
+ * same problem): for N coordinates with a_i = |g_i| >= 0 and distances
+ * d_i in [0, +inf] to the bound each one moves toward, find
+ *     lambda* = max { lambda >= 0 : sum_i min(lambda a_i, d_i)^2 <= r^2 }
+ * and value = sum_i a_i min(lambda* a_i, d_i), the decrease of the linear
+ * objective (lambda* = +inf when every d_i with a_i > 0 is finite and
+ * sum d_i^2 <= r^2; value = 0 when r <= 0).  a, d: device, N.  Workspace:
+ * device, pdhg_trust_region_workspace_bytes(N) bytes, 256-byte aligned.
+ * Outputs host *value, *lambda.  Syncs.  Errors: PDHG_E_INVALID (N < 0,
+ * negative or NaN a or d), PDHG_E_WORKSPACE, PDHG_E_HIP.
+ */
+size_t pdhg_trust_region_workspace_bytes(int64_t N);
+int pdhg_linear_trust_region(int64_t N, const double *a, const double *d,
+                             double r, void *workspace, size_t workspace_bytes,
+                             void *stream, double *value, double *lambda);
+
+/* Static text for a return code. */
+const char *pdhg_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDHG_H */

@@ -1,0 +1,334 @@
+"""ctypes binding of ``libpdhg.so`` (argument marshalling only).
+
+Every computation runs in the HIP kernels of the library; this module moves
+arrays into torch device tensors, passes raw pointers and sizes, and turns
+return codes into exceptions.  There is no CPU fallback: without the built
+library or a GPU the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdhg.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "pdhg.h")
+
+OK, NOT_CONVERGED = 0, 1
+E_INVALID, E_WORKSPACE, E_HIP, E_NUMERICAL = -1, -2, -3, -4
+RESTART_NONE, RESTART_ADAPTIVE, RESTART_FLEXIBLE, RESTART_FIXED = 0, 1, 2, 3
+KKT_RELATIVE, KKT_PAPER_ABS, KKT_MAX_ABS = 0, 1, 2
+POINT_CURRENT, POINT_AVERAGE, POINT_ANCHOR, POINT_SOLUTION = 0, 1, 2, 3
+
+
+class PdhgError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} (code {code})")
+
+
+class LP(C.Structure):
+    _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("nnz", C.c_int64),
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p),
+                ("vals", C.c_void_p), ("c", C.c_void_p), ("b", C.c_void_p),
+                ("l", C.c_void_p), ("u", C.c_void_p), ("row_kind", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("eta", C.c_double), ("omega", C.c_double), ("beta", C.c_double),
+                ("check_period", C.c_int32), ("tau0", C.c_int32),
+                ("restart_mode", C.c_int32), ("fixed_len", C.c_int32),
+                ("kkt_kind", C.c_int32), ("power_iters", C.c_int32),
+                ("power_tol", C.c_double)]
+
+
+class KKT(C.Structure):
+    _fields_ = [("kkt", C.c_double), ("kkt_rel", C.c_double),
+                ("primal_res", C.c_double), ("dual_res", C.c_double),
+                ("pobj", C.c_double), ("dobj", C.c_double),
+                ("kkt_paper_abs", C.c_double), ("kkt_max_abs", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("which_point", C.c_int32),
+                ("iterations", C.c_int64), ("restarts", C.c_int64),
+                ("kkt", C.c_double), ("pobj", C.c_double), ("dobj", C.c_double)]
+
+
+class Info(C.Structure):
+    _fields_ = [("eta", C.c_double), ("tau", C.c_double), ("sigma", C.c_double),
+                ("sigma_max", C.c_double), ("k", C.c_int64), ("t", C.c_int64),
+                ("restarts", C.c_int64), ("rho_prev", C.c_double),
+                ("checks", C.c_int64), ("power_iters_used", C.c_int64)]
+
+
+class CheckRecord(C.Structure):
+    _fields_ = [("v", C.c_double * 14)]
+
+
+_lib = None
+
+
+def declared_functions():
+    """Names of the functions include/pdhg.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pdhg_[a-z_]+)\s*\(", text)))
+
+
+def load(build_if_missing: bool = True):
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        if not build_if_missing:
+            raise RuntimeError(f"{LIB_PATH} is not built")
+        from . import build as _build
+        _build.build()
+    L = C.CDLL(LIB_PATH)
+    P, i32, i64, d, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
+    L.pdhg_default_params.argtypes = [C.POINTER(Params)]
+    L.pdhg_default_params.restype = None
+    L.pdhg_workspace_bytes.argtypes = [i64, i64, i64]
+    L.pdhg_workspace_bytes.restype = sz
+    L.pdhg_create.argtypes = [C.POINTER(LP), C.POINTER(Params), P, sz, P, C.POINTER(P)]
+    L.pdhg_create.restype = C.c_int
+    L.pdhg_step.argtypes = [P, i64]
+    L.pdhg_step.restype = C.c_int
+    L.pdhg_restart_check.argtypes = [P, d, C.POINTER(i32), C.POINTER(i32),
+                                     C.POINTER(d), C.POINTER(CheckRecord)]
+    L.pdhg_restart_check.restype = C.c_int
+    L.pdhg_kkt_error.argtypes = [P, i32, C.POINTER(KKT)]
+    L.pdhg_kkt_error.restype = C.c_int
+    L.pdhg_gap.argtypes = [P, i32, d, C.POINTER(d), C.POINTER(d), C.POINTER(d)]
+    L.pdhg_gap.restype = C.c_int
+    L.pdhg_solve.argtypes = [P, i64, d, C.POINTER(Result)]
+    L.pdhg_solve.restype = C.c_int
+    L.pdhg_get_iterate.argtypes = [P, i32, P, P]
+    L.pdhg_get_iterate.restype = C.c_int
+    L.pdhg_set_iterate.argtypes = [P, P, P]
+    L.pdhg_set_iterate.restype = C.c_int
+    L.pdhg_get_info.argtypes = [P, C.POINTER(Info)]
+    L.pdhg_get_info.restype = C.c_int
+    L.pdhg_get_check_log.argtypes = [P, P, i64, C.POINTER(i64)]
+    L.pdhg_get_check_log.restype = C.c_int
+    L.pdhg_matvec.argtypes = [P, i32, P, P]
+    L.pdhg_matvec.restype = C.c_int
+    L.pdhg_get_transpose.argtypes = [P, P, P, P, P]
+    L.pdhg_get_transpose.restype = C.c_int
+    L.pdhg_time_iterations.argtypes = [P, i64, C.POINTER(d), C.POINTER(d)]
+    L.pdhg_time_iterations.restype = C.c_int
+    L.pdhg_destroy.argtypes = [P]
+    L.pdhg_destroy.restype = None
+    L.pdhg_trust_region_workspace_bytes.argtypes = [i64]
+    L.pdhg_trust_region_workspace_bytes.restype = sz
+    L.pdhg_linear_trust_region.argtypes = [i64, P, P, d, P, sz, P, C.POINTER(d), C.POINTER(d)]
+    L.pdhg_linear_trust_region.restype = C.c_int
+    L.pdhg_strerror.argtypes = [C.c_int]
+    L.pdhg_strerror.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    return load().pdhg_strerror(int(code)).decode()
+
+
+def default_params() -> Params:
+    p = Params()
+    load().pdhg_default_params(C.byref(p))
+    return p
+
+
+def workspace_bytes(m: int, n: int, nnz: int) -> int:
+    return int(load().pdhg_workspace_bytes(m, n, nnz))
+
+
+def _check(rc, where, allow=(OK,)):
+    if rc not in allow:
+        raise PdhgError(rc, where)
+    return rc
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(None)
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(int(stream.cuda_stream))
+
+
+def _dev_workspace(nbytes, device):
+    import torch
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, buf[off:off + int(nbytes)]
+
+
+class Solver:
+    """One LP on one GPU: a handle of the C library plus the torch tensors
+    that own its device memory (problem data and workspace)."""
+
+    def __init__(self, lp, eta=0.0, omega=1.0, beta=float(np.exp(-1.0)),
+                 check_period=30, tau0=1, restart_mode=RESTART_ADAPTIVE,
+                 fixed_len=0, kkt_kind=KKT_RELATIVE, power_iters=1000,
+                 power_tol=1e-10, device="cuda:0", stream=None):
+        import torch
+        L = load()
+        self._L = L
+        self.device = torch.device(device)
+        self.stream = stream
+        self.m, self.n = int(lp.m), int(lp.n)
+        dev = self.device
+        f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+        i32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.int32)).to(dev)
+        self.row_ptr = i32(lp.row_ptr)
+        self.nnz = int(np.asarray(lp.row_ptr)[-1]) if self.m >= 0 else 0
+        self.col_idx = i32(lp.col_idx) if self.nnz else torch.zeros(1, dtype=torch.int32, device=dev)
+        self.vals = f64(lp.vals) if self.nnz else torch.zeros(1, dtype=torch.float64, device=dev)
+        self.c, self.l, self.u = f64(lp.c), f64(lp.l), f64(lp.u)
+        self.b = f64(lp.b) if self.m else torch.zeros(1, dtype=torch.float64, device=dev)
+        rk = getattr(lp, "row_kind", None)
+        self.row_kind = (torch.as_tensor(np.ascontiguousarray(rk, dtype=np.int8)).to(dev)
+                         if rk is not None and self.m else None)
+        self._lp = LP(self.m, self.n, self.nnz, self.row_ptr.data_ptr(),
+                      self.col_idx.data_ptr(), self.vals.data_ptr(), self.c.data_ptr(),
+                      self.b.data_ptr(), self.l.data_ptr(), self.u.data_ptr(),
+                      self.row_kind.data_ptr() if self.row_kind is not None else None)
+        self.params = Params(float(eta), float(omega), float(beta), int(check_period),
+                             int(tau0), int(restart_mode), int(fixed_len), int(kkt_kind),
+                             int(power_iters), float(power_tol))
+        nbytes = L.pdhg_workspace_bytes(self.m, self.n, self.nnz)
+        if nbytes == 0:
+            raise PdhgError(E_INVALID, "pdhg_workspace_bytes")
+        self._ws_owner, self.workspace = _dev_workspace(nbytes, dev)
+        h = C.c_void_p()
+        rc = L.pdhg_create(C.byref(self._lp), C.byref(self.params),
+                           _ptr(self.workspace), nbytes, _stream_handle(stream), C.byref(h))
+        _check(rc, "pdhg_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.pdhg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- iteration -------------------------------------------------------
+    def step(self, iters):
+        _check(self._L.pdhg_step(self.h, int(iters)), "pdhg_step")
+
+    def check(self, tol=0.0):
+        conv, rst = C.c_int32(), C.c_int32()
+        rho = C.c_double()
+        rec = CheckRecord()
+        _check(self._L.pdhg_restart_check(self.h, float(tol), C.byref(conv), C.byref(rst),
+                                          C.byref(rho), C.byref(rec)), "pdhg_restart_check")
+        return bool(conv.value), np.array(rec.v[:])
+
+    def solve(self, max_iters, tol):
+        res = Result()
+        rc = self._L.pdhg_solve(self.h, int(max_iters), float(tol), C.byref(res))
+        _check(rc, "pdhg_solve", allow=(OK, NOT_CONVERGED))
+        return dict(status=int(res.status), k=int(res.iterations), restarts=int(res.restarts),
+                    kkt=float(res.kkt), which=int(res.which_point), pobj=float(res.pobj),
+                    dobj=float(res.dobj))
+
+    # -- evaluation --------------------------------------------------------
+    def kkt(self, which=POINT_CURRENT):
+        out = KKT()
+        _check(self._L.pdhg_kkt_error(self.h, int(which), C.byref(out)), "pdhg_kkt_error")
+        return {k: getattr(out, k) for k, _ in KKT._fields_}
+
+    def gap(self, which=POINT_AVERAGE, r=-1.0):
+        rho, rr, lam = C.c_double(), C.c_double(), C.c_double()
+        _check(self._L.pdhg_gap(self.h, int(which), float(r), C.byref(rho), C.byref(rr),
+                                C.byref(lam)), "pdhg_gap")
+        return rho.value, rr.value, lam.value
+
+    def get_iterate(self, which=POINT_CURRENT):
+        import torch
+        x = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        y = torch.empty(max(self.m, 1), dtype=torch.float64, device=self.device)
+        _check(self._L.pdhg_get_iterate(self.h, int(which), _ptr(x), _ptr(y)),
+               "pdhg_get_iterate")
+        return x, y[: self.m]
+
+    def set_iterate(self, x, y):
+        import torch
+        x = torch.as_tensor(x, dtype=torch.float64).to(self.device).contiguous()
+        y = torch.as_tensor(y, dtype=torch.float64).to(self.device).contiguous()
+        if self.m == 0:
+            y = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self._keep_point = (x, y)
+        _check(self._L.pdhg_set_iterate(self.h, _ptr(x), _ptr(y)), "pdhg_set_iterate")
+
+    def info(self):
+        out = Info()
+        _check(self._L.pdhg_get_info(self.h, C.byref(out)), "pdhg_get_info")
+        return {k: getattr(out, k) for k, _ in Info._fields_}
+
+    def check_log(self, max_records=4096):
+        arr = (CheckRecord * max_records)()
+        cnt = C.c_int64()
+        _check(self._L.pdhg_get_check_log(self.h, C.cast(arr, C.c_void_p), max_records,
+                                          C.byref(cnt)), "pdhg_get_check_log")
+        return np.array([arr[i].v[:] for i in range(cnt.value)]).reshape(-1, 14)
+
+    def matvec(self, v, transpose=False):
+        import torch
+        v = torch.as_tensor(v, dtype=torch.float64).to(self.device).contiguous()
+        out = torch.empty(self.n if transpose else max(self.m, 1), dtype=torch.float64,
+                          device=self.device)
+        _check(self._L.pdhg_matvec(self.h, 1 if transpose else 0, _ptr(v), _ptr(out)),
+               "pdhg_matvec")
+        return out if transpose else out[: self.m]
+
+    def time_iterations(self, iters):
+        """Mean kernel milliseconds (primal, dual) over `iters` iterations."""
+        a, b = C.c_double(), C.c_double()
+        _check(self._L.pdhg_time_iterations(self.h, int(iters), C.byref(a), C.byref(b)),
+               "pdhg_time_iterations")
+        return a.value, b.value
+
+    def transpose_csr(self):
+        import torch
+        dev = self.device
+        trp = torch.empty(self.n + 1, dtype=torch.int32, device=dev)
+        tci = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)
+        tv = torch.empty(max(self.nnz, 1), dtype=torch.float64, device=dev)
+        perm = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)
+        _check(self._L.pdhg_get_transpose(self.h, _ptr(trp), _ptr(tci), _ptr(tv), _ptr(perm)),
+               "pdhg_get_transpose")
+        k = self.nnz
+        return trp, tci[:k], tv[:k], perm[:k]
+
+
+def linear_trust_region(a, d, r, device="cuda:0", stream=None):
+    """Stand-alone trust region on device tensors (or arrays): returns
+    (value, lambda)."""
+    import torch
+    L = load()
+    a = torch.as_tensor(a, dtype=torch.float64).to(device).contiguous()
+    d = torch.as_tensor(d, dtype=torch.float64).to(device).contiguous()
+    N = int(a.numel())
+    nbytes = L.pdhg_trust_region_workspace_bytes(N)
+    owner, ws = _dev_workspace(nbytes, device)
+    val, lam = C.c_double(), C.c_double()
+    rc = L.pdhg_linear_trust_region(N, _ptr(a) if N else None, _ptr(d) if N else None,
+                                    float(r), _ptr(ws), nbytes, _stream_handle(stream),
+                                    C.byref(val), C.byref(lam))
+    _check(rc, "pdhg_linear_trust_region")
+    del owner
+    return val.value, lam.value

@@ -1,0 +1,676 @@
+// C ABI of the restarted-PDHG library (declared in include/pdhg.h).
+//
+// The host side only orders launches: every arithmetic step runs in the
+// kernels.  State that decides control flow (iteration counters, restart
+// count, the converged flag) lives on the device so that a block of
+// `check_period` iterations plus its check can be recorded once as a HIP
+// graph and replayed; the host reads one status word per batch of replays.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "pdhg.h"
+#include "pdhg_internal.h"
+
+using namespace pdhg;
+
+struct pdhg_handle {
+    Dev d;
+    hipStream_t stream;
+    hipStream_t cap;        // private stream used only to record graphs
+    pdhg_params prm;
+    double eta, tau, sigma, sigma_max;
+    int64_t pw_used;
+    hipGraphExec_t gexec;   // one block of iterations plus its check
+    double g_tol;
+    bool g_valid;
+};
+
+#define CK(expr)                                   \
+    do {                                           \
+        hipError_t e_ = (expr);                    \
+        if (e_ != hipSuccess) return PDHG_E_HIP;   \
+    } while (0)
+
+namespace pdhg {
+
+static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t tr_work_bytes(int64_t N) {
+    size_t b = 0;
+    b += al(sizeof(unsigned int) * 2 * kBuckets);
+    b += al(sizeof(double) * 2 * kBuckets) * 2;
+    b += al(sizeof(double) * kRedBlocks * 4);
+    size_t n1 = (size_t)(N > 0 ? N : 1);
+    b += al(sizeof(unsigned long long) * n1);
+    b += al(sizeof(double) * n1) * 2;
+    return b;
+}
+
+void carve_tr(char *base, int64_t N, TRWork *w) {
+    size_t o = 0;
+    size_t n1 = (size_t)(N > 0 ? N : 1);
+    w->hcnt = (unsigned int *)(base + o);
+    o += al(sizeof(unsigned int) * 2 * kBuckets);
+    w->hD = (double *)(base + o);
+    o += al(sizeof(double) * 2 * kBuckets);
+    w->hA = (double *)(base + o);
+    o += al(sizeof(double) * 2 * kBuckets);
+    w->part = (double *)(base + o);
+    o += al(sizeof(double) * kRedBlocks * 4);
+    w->ckey = (unsigned long long *)(base + o);
+    o += al(sizeof(unsigned long long) * n1);
+    w->ca = (double *)(base + o);
+    o += al(sizeof(double) * n1);
+    w->cd = (double *)(base + o);
+}
+
+bool make_layout(int64_t m, int64_t n, int64_t nnz, Layout *L) {
+    if (m < 0 || n < 1 || nnz < 0) return false;
+    const int64_t lim = 0x7fffffffLL - 4096;
+    if (m > lim || n > lim || nnz > lim || m + nnz > 0x7fffffffLL * 2) return false;
+    const size_t n1 = (size_t)n, m1 = (size_t)(m > 0 ? m : 1), z1 = (size_t)(nnz > 0 ? nnz : 1);
+    size_t o = 0;
+    L->o_state = o;
+    o += al(sizeof(DevState));
+    L->o_err = o;
+    o += al(sizeof(int) * 16);
+    L->o_trp = o;
+    o += al(sizeof(int) * (n1 + 1));
+    L->o_tci = o;
+    o += al(sizeof(int) * z1);
+    L->o_perm = o;
+    o += al(sizeof(int) * z1);
+    L->o_tv = o;
+    o += al(sizeof(double) * z1);
+    L->o_cursor = o;
+    o += al(sizeof(int) * n1);
+    L->o_long = o;
+    o += al(sizeof(int) * n1);
+    const int nbA = nblocks_for((int)m, (int)nnz), nbT = nblocks_for((int)n, (int)nnz);
+    L->o_brA = o;
+    o += al(sizeof(int) * ((size_t)nbA + 1));
+    L->o_brT = o;
+    o += al(sizeof(int) * ((size_t)nbT + 1));
+    for (int k = 0; k < 8; ++k) {
+        L->o_vec_n[k] = o;
+        o += al(sizeof(double) * n1);
+    }
+    for (int k = 0; k < 8; ++k) {
+        L->o_vec_m[k] = o;
+        o += al(sizeof(double) * m1);
+    }
+    L->o_part = o;
+    o += al(sizeof(double) * kRedBlocks * kKktSums);
+    L->o_log = o;
+    o += al(sizeof(double) * kLogCap * kRec);
+    for (int sidx = 0; sidx < kTrSlots; ++sidx) {
+        L->o_tr[sidx] = o;
+        o += tr_work_bytes((int64_t)n1 + (int64_t)(m > 0 ? m : 0));
+    }
+    L->total = o;
+    return true;
+}
+
+}  // namespace pdhg
+
+static int gap_slots_for(int mode) {
+    if (mode == PDHG_RESTART_ADAPTIVE) return 1;
+    if (mode == PDHG_RESTART_FLEXIBLE) return 3;
+    return 0;
+}
+
+// the check of Section 7, enqueued on s (also used while recording graphs)
+static void enqueue_check(pdhg_t *h, double tol, hipStream_t s) {
+    const Dev &d = h->d;
+    const int *gate = &d.st->done;
+    launch_average(d, s);
+    launch_spmv_A(d, d.xbar, d.axb, s, gate);
+    launch_spmv_T(d, d.ybar, d.atyb, s, gate);
+    launch_spmv_T(d, d.y, d.aty, s, gate);
+    launch_kkt_partials(d, s);
+    const int slots = gap_slots_for(h->prm.restart_mode);
+    launch_kkt_final(d, tol, h->prm.kkt_kind, slots, s);
+    if (slots & 1) launch_gap(d, 0, s);
+    if (slots & 2) launch_gap(d, 1, s);
+    launch_decide(d, h->prm.restart_mode, h->prm.beta, h->prm.tau0, s);
+    launch_apply(d, s);
+}
+
+static void enqueue_iters(pdhg_t *h, int64_t iters, hipStream_t s) {
+    for (int64_t i = 0; i < iters; ++i) {
+        launch_primal(h->d, h->tau, s);
+        launch_dual(h->d, h->sigma, s);
+    }
+}
+
+static int read_state(pdhg_t *h, DevState *out) {
+    CK(hipMemcpyAsync(out, h->d.st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    CK(hipStreamSynchronize(h->stream));
+    return PDHG_OK;
+}
+
+static int last_error() {
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? PDHG_OK : PDHG_E_HIP;
+}
+
+extern "C" {
+
+void pdhg_default_params(pdhg_params *p) {
+    if (!p) return;
+    p->eta = 0.0;
+    p->omega = 1.0;
+    p->beta = exp(-1.0);
+    p->check_period = 30;
+    p->tau0 = 1;
+    p->restart_mode = PDHG_RESTART_ADAPTIVE;
+    p->fixed_len = 0;
+    p->kkt_kind = PDHG_KKT_RELATIVE;
+    p->power_iters = 1000;
+    p->power_tol = 1e-10;
+}
+
+size_t pdhg_workspace_bytes(int64_t m, int64_t n, int64_t nnz) {
+    Layout L;
+    if (!make_layout(m, n, nnz, &L)) return 0;
+    return L.total;
+}
+
+const char *pdhg_strerror(int code) {
+    switch (code) {
+    case PDHG_OK: return "ok";
+    case PDHG_NOT_CONVERGED: return "iteration budget used without reaching the tolerance";
+    case PDHG_E_INVALID: return "invalid argument or malformed LP data";
+    case PDHG_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case PDHG_E_HIP: return "HIP runtime error";
+    case PDHG_E_NUMERICAL: return "NaN or Inf in the iterates";
+    default: return "unknown code";
+    }
+}
+
+int pdhg_create(const pdhg_lp *lp, const pdhg_params *prm_in, void *workspace,
+                size_t workspace_bytes, void *stream, pdhg_t **out) {
+    if (!out) return PDHG_E_INVALID;
+    *out = nullptr;
+    if (!lp) return PDHG_E_INVALID;
+    pdhg_params prm;
+    if (prm_in) prm = *prm_in;
+    else pdhg_default_params(&prm);
+    if (!(prm.omega > 0.0) || !isfinite(prm.omega) || !(prm.beta > 0.0) || !(prm.beta < 1.0) ||
+        prm.check_period < 1 || prm.tau0 < 1 || prm.restart_mode < 0 || prm.restart_mode > 3 ||
+        (prm.restart_mode == PDHG_RESTART_FIXED && prm.fixed_len < 1) || prm.kkt_kind < 0 ||
+        prm.kkt_kind > 2 || isnan(prm.eta) || isinf(prm.eta))
+        return PDHG_E_INVALID;
+    if (prm.power_iters < 1) prm.power_iters = 1000;
+    if (!(prm.power_tol > 0.0)) prm.power_tol = 1e-10;
+    Layout L;
+    if (!make_layout(lp->m, lp->n, lp->nnz, &L)) return PDHG_E_INVALID;
+    if (!lp->row_ptr || !lp->c || !lp->l || !lp->u) return PDHG_E_INVALID;
+    if (lp->nnz > 0 && (!lp->col_idx || !lp->vals)) return PDHG_E_INVALID;
+    if (lp->m > 0 && !lp->b) return PDHG_E_INVALID;
+    if (!workspace || ((uintptr_t)workspace & 255u) || workspace_bytes < L.total)
+        return PDHG_E_WORKSPACE;
+
+    pdhg_t *h = new (std::nothrow) pdhg_handle();
+    if (!h) return PDHG_E_HIP;
+    h->stream = (hipStream_t)stream;
+    h->prm = prm;
+    h->g_valid = false;
+    h->gexec = nullptr;
+    h->cap = nullptr;
+    char *ws = (char *)workspace;
+    Dev &d = h->d;
+    memset(&d, 0, sizeof(d));
+    d.m = (int)lp->m;
+    d.n = (int)lp->n;
+    d.nnz = (int)lp->nnz;
+    d.rp = lp->row_ptr;
+    d.ci = lp->col_idx;
+    d.v = lp->vals;
+    d.c = lp->c;
+    d.b = lp->b;
+    d.l = lp->l;
+    d.u = lp->u;
+    d.kind = (const signed char *)lp->row_kind;
+    d.st = (DevState *)(ws + L.o_state);
+    d.err = (int *)(ws + L.o_err);
+    d.trp = (int *)(ws + L.o_trp);
+    d.tci = (int *)(ws + L.o_tci);
+    d.perm = (int *)(ws + L.o_perm);
+    d.tv = (double *)(ws + L.o_tv);
+    d.cursor = (int *)(ws + L.o_cursor);
+    d.long_rows = (int *)(ws + L.o_long);
+    d.nblkA = nblocks_for(d.m, d.nnz);
+    d.nblkT = nblocks_for(d.n, d.nnz);
+    d.brA = (int *)(ws + L.o_brA);
+    d.brT = (int *)(ws + L.o_brT);
+    double *vn[8], *vm[8];
+    for (int k = 0; k < 8; ++k) {
+        vn[k] = (double *)(ws + L.o_vec_n[k]);
+        vm[k] = (double *)(ws + L.o_vec_m[k]);
+    }
+    d.x = vn[0]; d.x0 = vn[1]; d.sx = vn[2]; d.xbar = vn[3];
+    d.atyb = vn[4]; d.aty = vn[5]; d.gx = vn[6]; d.gaty = vn[7];
+    d.y = vm[0]; d.y0 = vm[1]; d.sy = vm[2]; d.q = vm[3];
+    d.ybar = vm[4]; d.axb = vm[5]; d.gy = vm[6]; d.gax = vm[7];
+    d.part = (double *)(ws + L.o_part);
+    d.log = (double *)(ws + L.o_log);
+    for (int sidx = 0; sidx < kTrSlots; ++sidx)
+        carve_tr(ws + L.o_tr[sidx], (int64_t)d.n + d.m, &d.tr[sidx]);
+    d.omega = prm.omega;
+
+    int rc = PDHG_OK;
+    do {
+        hipStream_t s = h->stream;
+        if (hipMemsetAsync(d.st, 0, sizeof(DevState), s) != hipSuccess ||
+            hipMemsetAsync(d.err, 0, sizeof(int) * 16, s) != hipSuccess) {
+            rc = PDHG_E_HIP;
+            break;
+        }
+        launch_validate(d, s);
+        int err[2] = {0, 0};
+        if (hipMemcpyAsync(err, d.err, sizeof(err), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            rc = PDHG_E_HIP;
+            break;
+        }
+        if (err[0]) {
+            rc = PDHG_E_INVALID;
+            break;
+        }
+        launch_rowsplit(d.rp, d.m, d.nnz, d.nblkA, d.brA, s);
+        launch_transpose(d, s);
+        launch_rowsplit(d.trp, d.n, d.nnz, d.nblkT, d.brT, s);
+        launch_norms(d, s);
+        launch_init_point(d, s);
+        if ((rc = last_error()) != PDHG_OK) break;
+        h->sigma_max = 0.0;
+        h->pw_used = 0;
+        if (prm.eta > 0.0) {
+            h->eta = prm.eta;
+        } else {
+            launch_power_init(d, s);
+            DevState hs;
+            int done = 0;
+            while (!done) {
+                for (int q = 0; q < 25; ++q) launch_power_step(d, prm.power_tol, prm.power_iters, s);
+                if ((rc = last_error()) != PDHG_OK) break;
+                if ((rc = read_state(h, &hs)) != PDHG_OK) break;
+                done = hs.pw_done;
+            }
+            if (rc != PDHG_OK) break;
+            h->sigma_max = hs.pw_est;
+            h->pw_used = hs.pw_it;
+            h->eta = h->sigma_max > 0.0 ? 0.9 / h->sigma_max : 1.0;
+        }
+        h->tau = h->eta / prm.omega;
+        h->sigma = h->eta * prm.omega;
+        if (hipStreamSynchronize(s) != hipSuccess) {
+            rc = PDHG_E_HIP;
+            break;
+        }
+        if (hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) {
+            rc = PDHG_E_HIP;
+            break;
+        }
+    } while (0);
+    if (rc != PDHG_OK) {
+        if (h->cap) (void)hipStreamDestroy(h->cap);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return PDHG_OK;
+}
+
+void pdhg_destroy(pdhg_t *h) {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
+    delete h;
+}
+
+// plain iterations; fixed-length restarts happen when t reaches fixed_len
+static int run_iters(pdhg_t *h, int64_t iters, int64_t *t_host) {
+    if (h->prm.restart_mode != PDHG_RESTART_FIXED) {
+        enqueue_iters(h, iters, h->stream);
+        return last_error();
+    }
+    const int64_t T = h->prm.fixed_len;
+    while (iters > 0) {
+        int64_t sstep = T - *t_host;
+        if (sstep > iters) sstep = iters;
+        enqueue_iters(h, sstep, h->stream);
+        iters -= sstep;
+        *t_host += sstep;
+        if (*t_host >= T) {
+            launch_fixed_restart(h->d, h->stream);
+            *t_host = 0;
+        }
+    }
+    return last_error();
+}
+
+int pdhg_step(pdhg_t *h, int64_t iters) {
+    if (!h || iters < 0) return PDHG_E_INVALID;
+    launch_reset_done(h->d, h->stream);
+    int64_t t_host = 0;
+    if (h->prm.restart_mode == PDHG_RESTART_FIXED) {
+        DevState hs;
+        int rc = read_state(h, &hs);
+        if (rc) return rc;
+        t_host = hs.t;
+    }
+    return run_iters(h, iters, &t_host);
+}
+
+static void fill_record(const double *rec, pdhg_check_record *out) {
+    if (out) memcpy(out->v, rec, sizeof(double) * kRec);
+}
+
+static int read_last_record(pdhg_t *h, const DevState &hs, double *rec) {
+    if (hs.checks <= 0) return PDHG_E_INVALID;
+    const double *src = h->d.log + (size_t)((hs.checks - 1) % kLogCap) * kRec;
+    CK(hipMemcpyAsync(rec, src, sizeof(double) * kRec, hipMemcpyDeviceToHost, h->stream));
+    CK(hipStreamSynchronize(h->stream));
+    return PDHG_OK;
+}
+
+int pdhg_restart_check(pdhg_t *h, double tol, int32_t *converged, int32_t *restarted,
+                       double *rho, pdhg_check_record *rec) {
+    if (!h || isnan(tol)) return PDHG_E_INVALID;
+    launch_reset_done(h->d, h->stream);
+    enqueue_check(h, tol, h->stream);
+    int rc = last_error();
+    if (rc) return rc;
+    DevState hs;
+    if ((rc = read_state(h, &hs))) return rc;
+    double r[kRec];
+    if ((rc = read_last_record(h, hs, r))) return rc;
+    if (converged) *converged = hs.conv_which >= 0 ? 1 : 0;
+    if (restarted) *restarted = (int32_t)r[9];
+    if (rho) *rho = r[6];
+    fill_record(r, rec);
+    if (hs.numerr) return PDHG_E_NUMERICAL;
+    return PDHG_OK;
+}
+
+int pdhg_kkt_error(pdhg_t *h, int32_t which, pdhg_kkt *out) {
+    if (!h || which < 0 || which > 3 || !out) return PDHG_E_INVALID;
+    launch_kkt_eval(h->d, which, h->stream);
+    int rc = last_error();
+    if (rc) return rc;
+    DevState hs;
+    if ((rc = read_state(h, &hs))) return rc;
+    const double *k8 = hs.kkt_eval;
+    out->kkt_rel = k8[1];
+    out->primal_res = k8[2];
+    out->dual_res = k8[3];
+    out->pobj = k8[4];
+    out->dobj = k8[5];
+    out->kkt_paper_abs = k8[6];
+    out->kkt_max_abs = k8[7];
+    out->kkt = h->prm.kkt_kind == 1 ? k8[6] : (h->prm.kkt_kind == 2 ? k8[7] : k8[1]);
+    return PDHG_OK;
+}
+
+int pdhg_gap(pdhg_t *h, int32_t which, double r, double *rho, double *r_used, double *lambda) {
+    if (!h || which < 0 || which > 3 || isnan(r)) return PDHG_E_INVALID;
+    launch_gap_point(h->d, which, r, h->stream);
+    int rc = last_error();
+    if (rc) return rc;
+    DevState hs;
+    if ((rc = read_state(h, &hs))) return rc;
+    if (rho) *rho = hs.tr[0].rho;
+    if (r_used) *r_used = hs.tr[0].r;
+    if (lambda) *lambda = hs.tr[0].lam;
+    if (hs.tr[0].nan_seen) return PDHG_E_NUMERICAL;
+    return PDHG_OK;
+}
+
+// record one block: check_period iterations followed by the check
+static int build_graph(pdhg_t *h, double tol) {
+    if (h->g_valid && h->g_tol == tol) return PDHG_OK;
+    if (h->gexec) {
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+    }
+    h->g_valid = false;
+    hipGraph_t g = nullptr;
+    CK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    enqueue_iters(h, h->prm.check_period, h->cap);
+    enqueue_check(h, tol, h->cap);
+    hipError_t e = hipStreamEndCapture(h->cap, &g);
+    if (e != hipSuccess) return PDHG_E_HIP;
+    e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->gexec = nullptr;
+        return PDHG_E_HIP;
+    }
+    h->g_tol = tol;
+    h->g_valid = true;
+    return PDHG_OK;
+}
+
+static int finish_result(pdhg_t *h, const DevState &hs, pdhg_result *out) {
+    if (!out) return PDHG_OK;
+    out->iterations = hs.k;
+    out->restarts = hs.restarts;
+    if (hs.conv_which >= 0) {
+        const double *k8 = hs.conv_which == 1 ? hs.kkt_avg : hs.kkt_cur;
+        out->status = PDHG_OK;
+        out->which_point = hs.conv_which;
+        out->kkt = k8[0];
+        out->pobj = k8[4];
+        out->dobj = k8[5];
+        return PDHG_OK;
+    }
+    pdhg_kkt kk;
+    int rc = pdhg_kkt_error(h, PDHG_POINT_CURRENT, &kk);
+    if (rc) return rc;
+    out->status = PDHG_NOT_CONVERGED;
+    out->which_point = -1;
+    out->kkt = kk.kkt;
+    out->pobj = kk.pobj;
+    out->dobj = kk.dobj;
+    return PDHG_OK;
+}
+
+int pdhg_solve(pdhg_t *h, int64_t max_iters, double tol, pdhg_result *out) {
+    if (!h || max_iters < 0 || isnan(tol)) return PDHG_E_INVALID;
+    int rc;
+    launch_reset_done(h->d, h->stream);
+    DevState hs;
+    if ((rc = read_state(h, &hs))) return rc;
+    const int64_t P = h->prm.check_period;
+    int64_t k = hs.k, t_host = hs.t;
+    const int64_t k_end = k + max_iters;
+    bool conv = false;
+    const bool use_graph = h->prm.restart_mode != PDHG_RESTART_FIXED;
+    while (k < k_end && !conv) {
+        int64_t to_check = P - (k % P);
+        if (use_graph && k % P == 0 && k_end - k >= P) {
+            // replay whole blocks; the device skips everything after convergence
+            if ((rc = build_graph(h, tol))) return rc;
+            int64_t blocks = (k_end - k) / P;
+            int64_t batch = 1;
+            while (blocks > 0 && !conv) {
+                int64_t nb = batch < blocks ? batch : blocks;
+                for (int64_t q = 0; q < nb; ++q) CK(hipGraphLaunch(h->gexec, h->stream));
+                if ((rc = read_state(h, &hs))) return rc;
+                if (hs.numerr) return PDHG_E_NUMERICAL;
+                blocks -= nb;
+                k += nb * P;
+                conv = hs.conv_which >= 0 && hs.done;
+                if (batch < 64) batch *= 2;
+            }
+            continue;
+        }
+        int64_t sstep = to_check < k_end - k ? to_check : k_end - k;
+        if ((rc = run_iters(h, sstep, &t_host))) return rc;
+        k += sstep;
+        if (k % P == 0) {
+            enqueue_check(h, tol, h->stream);
+            if ((rc = last_error())) return rc;
+            if ((rc = read_state(h, &hs))) return rc;
+            if (hs.numerr) return PDHG_E_NUMERICAL;
+            conv = hs.conv_which >= 0 && hs.done;
+            t_host = hs.t;
+        }
+    }
+    if ((rc = read_state(h, &hs))) return rc;
+    if ((rc = finish_result(h, hs, out))) return rc;
+    return conv ? PDHG_OK : PDHG_NOT_CONVERGED;
+}
+
+int pdhg_get_iterate(pdhg_t *h, int32_t which, double *x, double *y) {
+    if (!h || which < 0 || which > 3 || !x || (h->d.m > 0 && !y)) return PDHG_E_INVALID;
+    launch_copy_point(h->d, which, x, y, h->stream);
+    return last_error();
+}
+
+int pdhg_set_iterate(pdhg_t *h, const double *x, const double *y) {
+    if (!h || !x || (h->d.m > 0 && !y)) return PDHG_E_INVALID;
+    launch_set_point(h->d, x, y, h->stream);
+    return last_error();
+}
+
+int pdhg_get_info(pdhg_t *h, pdhg_info *out) {
+    if (!h || !out) return PDHG_E_INVALID;
+    DevState hs;
+    int rc = read_state(h, &hs);
+    if (rc) return rc;
+    out->eta = h->eta;
+    out->tau = h->tau;
+    out->sigma = h->sigma;
+    out->sigma_max = h->sigma_max;
+    out->k = hs.k;
+    out->t = hs.t;
+    out->restarts = hs.restarts;
+    out->rho_prev = hs.rho_prev;
+    out->checks = hs.checks;
+    out->power_iters_used = h->pw_used;
+    return PDHG_OK;
+}
+
+int pdhg_get_check_log(pdhg_t *h, pdhg_check_record *out, int64_t max, int64_t *count) {
+    if (!h || max < 0 || (max > 0 && !out)) return PDHG_E_INVALID;
+    DevState hs;
+    int rc = read_state(h, &hs);
+    if (rc) return rc;
+    int64_t have = hs.checks < kLogCap ? hs.checks : kLogCap;
+    int64_t nret = have < max ? have : max;
+    for (int64_t q = 0; q < nret; ++q) {
+        int64_t idx = hs.checks - nret + q;
+        const double *src = h->d.log + (size_t)(idx % kLogCap) * kRec;
+        CK(hipMemcpyAsync(out[q].v, src, sizeof(double) * kRec, hipMemcpyDeviceToHost, h->stream));
+    }
+    CK(hipStreamSynchronize(h->stream));
+    if (count) *count = nret;
+    return PDHG_OK;
+}
+
+int pdhg_matvec(pdhg_t *h, int32_t transpose, const double *in, double *out) {
+    if (!h || !in || !out || (transpose != 0 && transpose != 1)) return PDHG_E_INVALID;
+    if (transpose) launch_spmv_T(h->d, in, out, h->stream);
+    else launch_spmv_A(h->d, in, out, h->stream);
+    return last_error();
+}
+
+int pdhg_get_transpose(pdhg_t *h, int32_t *t_row_ptr, int32_t *t_col_idx, double *t_vals,
+                       int32_t *perm) {
+    if (!h || !t_row_ptr) return PDHG_E_INVALID;
+    const Dev &d = h->d;
+    CK(hipMemcpyAsync(t_row_ptr, d.trp, sizeof(int) * ((size_t)d.n + 1), hipMemcpyDeviceToDevice,
+                      h->stream));
+    if (d.nnz > 0) {
+        if (t_col_idx)
+            CK(hipMemcpyAsync(t_col_idx, d.tci, sizeof(int) * (size_t)d.nnz,
+                              hipMemcpyDeviceToDevice, h->stream));
+        if (t_vals)
+            CK(hipMemcpyAsync(t_vals, d.tv, sizeof(double) * (size_t)d.nnz,
+                              hipMemcpyDeviceToDevice, h->stream));
+        if (perm)
+            CK(hipMemcpyAsync(perm, d.perm, sizeof(int) * (size_t)d.nnz, hipMemcpyDeviceToDevice,
+                              h->stream));
+    }
+    return PDHG_OK;
+}
+
+int pdhg_time_iterations(pdhg_t *h, int64_t iters, double *ms_primal, double *ms_dual) {
+    if (!h || iters < 1 || iters > 100000) return PDHG_E_INVALID;
+    launch_reset_done(h->d, h->stream);
+    const int64_t ne = 2 * iters + 1;
+    hipEvent_t *ev = new (std::nothrow) hipEvent_t[ne];
+    if (!ev) return PDHG_E_HIP;
+    int64_t made = 0;
+    int rc = PDHG_OK;
+    for (; made < ne; ++made)
+        if (hipEventCreate(&ev[made]) != hipSuccess) {
+            rc = PDHG_E_HIP;
+            break;
+        }
+    if (rc == PDHG_OK) {
+        hipStream_t s = h->stream;
+        if (hipEventRecord(ev[0], s) != hipSuccess) rc = PDHG_E_HIP;
+        for (int64_t i = 0; i < iters && rc == PDHG_OK; ++i) {
+            launch_primal(h->d, h->tau, s);
+            if (hipEventRecord(ev[2 * i + 1], s) != hipSuccess) rc = PDHG_E_HIP;
+            launch_dual(h->d, h->sigma, s);
+            if (hipEventRecord(ev[2 * i + 2], s) != hipSuccess) rc = PDHG_E_HIP;
+        }
+        if (rc == PDHG_OK) rc = last_error();
+        if (rc == PDHG_OK && hipStreamSynchronize(s) != hipSuccess) rc = PDHG_E_HIP;
+        double tp = 0.0, td = 0.0;
+        for (int64_t i = 0; i < iters && rc == PDHG_OK; ++i) {
+            float a = 0.f, b = 0.f;
+            if (hipEventElapsedTime(&a, ev[2 * i], ev[2 * i + 1]) != hipSuccess ||
+                hipEventElapsedTime(&b, ev[2 * i + 1], ev[2 * i + 2]) != hipSuccess)
+                rc = PDHG_E_HIP;
+            tp += a;
+            td += b;
+        }
+        if (rc == PDHG_OK) {
+            if (ms_primal) *ms_primal = tp / (double)iters;
+            if (ms_dual) *ms_dual = td / (double)iters;
+        }
+    }
+    for (int64_t q = 0; q < made; ++q) (void)hipEventDestroy(ev[q]);
+    delete[] ev;
+    return rc;
+}
+
+size_t pdhg_trust_region_workspace_bytes(int64_t N) {
+    if (N < 0 || N > 0x7fffffffLL) return 0;
+    return al(sizeof(TRState)) + tr_work_bytes(N);
+}
+
+int pdhg_linear_trust_region(int64_t N, const double *a, const double *d, double r,
+                             void *workspace, size_t workspace_bytes, void *stream, double *value,
+                             double *lambda) {
+    if (N < 0 || N > 0x7fffffffLL || isnan(r) || (N > 0 && (!a || !d))) return PDHG_E_INVALID;
+    const size_t need = pdhg_trust_region_workspace_bytes(N);
+    if (!workspace || ((uintptr_t)workspace & 255u) || workspace_bytes < need)
+        return PDHG_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    TRState *ts = (TRState *)ws;
+    TRWork w;
+    carve_tr(ws + al(sizeof(TRState)), N, &w);
+    launch_tr_raw(N, a, d, r, w, ts, s);
+    int rc = last_error();
+    if (rc) return rc;
+    TRState hts;
+    CK(hipMemcpyAsync(&hts, ts, sizeof(TRState), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    if (hts.nan_seen) return PDHG_E_INVALID;
+    if (value) *value = hts.value;
+    if (lambda) *lambda = hts.lam;
+    return PDHG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,169 @@
+// Internal declarations shared by the kernels and the C ABI of the
+// restarted-PDHG library.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pdhg {
+
+constexpr int kWG = 256;             // threads per workgroup (4 wave64)
+constexpr int kUnits = 2048;         // SpMV block size in rows + nnz
+constexpr int kLdsProducts = 4096;   // products staged in LDS per SpMV block
+constexpr int kRedBlocks = 1024;     // max blocks of a partial-sum reduction
+constexpr int kKktSums = 14;         // partial sums of the KKT / radius pass
+constexpr int kBuckets = 2048;       // radix buckets of the multiplier search
+constexpr int kTrSlots = 2;          // trust-region evaluations per check
+constexpr int kLogCap = 4096;        // check records kept on the device
+constexpr int kRec = 14;             // doubles per check record
+
+// KKT partial-sum slots
+enum {
+    S_PRES2_C = 0, S_PRES2_A, S_DRES2_C, S_DRES2_A, S_POBJ_C, S_POBJ_A,
+    S_DOBJ_C, S_DOBJ_A, S_BV2_C, S_BV2_A, S_RX2_A, S_RY2_A, S_RX2_C, S_RY2_C
+};
+
+// trust-region evaluation modes
+enum { TR_IDLE = 0, TR_SEARCH = 1, TR_RESOLVED = 2, TR_FULLBOX = 3, TR_ZERO = 4 };
+
+struct TRState {
+    double r, r2;          // radius and its square
+    double F_acc, A_acc;   // sums of d^2 below / a^2 above the bracket
+    double rho, lam;       // results
+    double value;          // r * rho
+    unsigned long long prefix;  // key bits fixed so far
+    unsigned long long klo;     // key of the bracket's lower end
+    int mode;              // TR_*
+    int level;             // radix level reached
+    unsigned int count;    // elements inside the bracket
+    unsigned int ncomp;    // compacted elements
+    int nan_seen;
+    int pad;
+};
+
+struct DevState {
+    long long k, t, restarts, checks;
+    double rho_prev;
+    int done;              // a solve converged: later graph kernels do nothing
+    int conv_which;        // -1 none, 0 current, 1 average
+    long long conv_k;
+    double kkt_cur[8];     // picked, rel, pres, dres, pobj, dobj, paper_abs, max_abs
+    double kkt_avg[8];
+    double kkt_eval[8];    // stand-alone KKT evaluation
+    double r_avg, r_cur;
+    int restarted, cand;   // outcome of the last check
+    int gap_slots;         // bitmask of trust-region slots to evaluate
+    int numerr;            // NaN/Inf seen in a check
+    int in_check;          // a check is in progress (set by the KKT pass)
+    int pad1;
+    double nb2, nc2;       // |b|^2 and |c|^2
+    // power iteration
+    double pw_est, pw_prev, pw_s;
+    int pw_done, pw_it;
+    TRState tr[kTrSlots];
+};
+
+// Trust-region scratch carved from a workspace.
+struct TRWork {
+    unsigned int *hcnt;    // [2][kBuckets]
+    double *hD, *hA;       // [2][kBuckets]
+    double *part;          // [kRedBlocks][4]
+    unsigned long long *ckey;  // [N] compacted keys
+    double *ca, *cd;       // [N]
+};
+
+// Device-side view of one LP and its solver state.
+struct Dev {
+    int m, n, nnz;
+    const int *rp, *ci;
+    const double *v;
+    const double *c, *b, *l, *u;
+    const signed char *kind;   // may be null
+    // transpose
+    int *trp, *tci, *perm;
+    double *tv;
+    int *cursor;               // n, setup scratch
+    int *long_rows;            // n, setup scratch
+    // merge-path block row starts
+    int *brA, *brT;
+    int nblkA, nblkT;
+    // vectors
+    double *x, *y, *x0, *y0, *sx, *sy, *q;
+    double *xbar, *ybar, *axb, *atyb, *aty;
+    double *gx, *gy, *gax, *gaty;   // scratch point of the stand-alone gap
+    double *part;              // [kRedBlocks][kKktSums]
+    double *log;               // [kLogCap][kRec]
+    DevState *st;
+    TRWork tr[kTrSlots];
+    int *err;                  // validation flags; err[1] counts long A' rows
+    double omega;              // primal weight (norm of the gap and radii)
+};
+
+// Workspace layout: offsets (bytes) of every region for given sizes.
+struct Layout {
+    size_t total;
+    size_t o_state, o_err, o_trp, o_tci, o_perm, o_tv, o_cursor, o_long;
+    size_t o_brA, o_brT, o_vec_n[8], o_vec_m[8], o_part, o_log;
+    size_t o_tr[kTrSlots];
+};
+bool make_layout(int64_t m, int64_t n, int64_t nnz, Layout *L);
+size_t tr_work_bytes(int64_t N);
+void carve_tr(char *base, int64_t N, TRWork *w);
+
+// ---------------------------------------------------------------------
+// Launchers (all enqueue on `s`, never synchronize).
+// ---------------------------------------------------------------------
+int nblocks_for(int rows, int nnz);
+
+// setup
+void launch_validate(const Dev &d, hipStream_t s);
+void launch_transpose(const Dev &d, hipStream_t s);
+void launch_rowsplit(const int *rp, int rows, int nnz, int nblk, int *br, hipStream_t s);
+void launch_init_point(const Dev &d, hipStream_t s);
+void launch_norms(const Dev &d, hipStream_t s);   // |b|^2, |c|^2 into part[0..1]
+
+// iteration
+void launch_primal(const Dev &d, double tau, hipStream_t s);
+void launch_dual(const Dev &d, double sigma, hipStream_t s);
+// out = A in / A' in; skip (device flag, may be null) turns the launch into a no-op
+void launch_spmv_A(const Dev &d, const double *in, double *out, hipStream_t s,
+                   const int *skip = nullptr);
+void launch_spmv_T(const Dev &d, const double *in, double *out, hipStream_t s,
+                   const int *skip = nullptr);
+
+// two points for the KKT / radius pass: [0] current, [1] average
+struct KktPoints {
+    const double *x[2], *y[2], *ax[2], *aty[2];
+};
+
+// check
+void launch_average(const Dev &d, hipStream_t s);
+void launch_reset_done(const Dev &d, hipStream_t s);
+void launch_kkt_partials(const Dev &d, hipStream_t s);
+// KKT parts of a held point (0 current, 1 average, 2 anchor, 3 solution) into st->kkt_eval
+void launch_kkt_eval(const Dev &d, int which, hipStream_t s);
+void launch_kkt_final(const Dev &d, double tol, int kkt_kind, int gap_slots, hipStream_t s);
+// trust region of slot 0 (point z-bar) or 1 (point z), if armed
+void launch_gap(const Dev &d, int slot, hipStream_t s);
+void launch_decide(const Dev &d, int mode, double beta, int tau0, hipStream_t s);
+void launch_apply(const Dev &d, hipStream_t s);
+void launch_fixed_restart(const Dev &d, hipStream_t s);
+// which: 0 current, 1 average (from the sums), 2 anchor, 3 solution
+void launch_copy_point(const Dev &d, int which, double *x, double *y, hipStream_t s);
+void launch_set_point(const Dev &d, const double *x, const double *y, hipStream_t s);
+// gap at a held point (0 current, 1 average, 2 anchor) with radius r
+// (r < 0: distance to the anchor); result in st->tr[0]
+void launch_gap_point(const Dev &d, int which, double r, hipStream_t s);
+
+// power iteration
+void launch_power_init(const Dev &d, hipStream_t s);
+void launch_power_step(const Dev &d, double tol, int max_iters, hipStream_t s);
+// shared reductions
+int red_grid(long long N);
+
+// stand-alone trust region on raw (a, d)
+void launch_tr_raw(int64_t N, const double *a, const double *dd, double r,
+                   const TRWork &w, TRState *st, hipStream_t s);
+
+}  // namespace pdhg

@@ -1,0 +1,875 @@
+// HIP kernels of the restarted-PDHG library for gfx950 (MI355X).
+//
+// Hot path (two launches per iteration, eq. PDHG-update):
+//   k_spmv<EpiPrimal> over the explicit A' :  x+ = clamp(x - tau (c - A'y)),
+//                                             sx += x+
+//   k_spmv<EpiDual>   over A               :  q = A x+,
+//                                             y+ = proj(y + sigma (b - (2q - q_prev))),
+//                                             sy += y+, q_prev = q
+// A(2x+ - x) is formed as 2 A x+ - A x from the cached A x of the previous
+// half-step, so each iteration streams A and A' once and gathers x+ and y
+// once per stored entry.
+//
+// SpMV schedule: rows are cut into merge-path blocks of kUnits rows+entries
+// (a row belongs to the block its start falls in), so each workgroup owns
+// whole rows and the per-row epilogue is fused.  A block stages its
+// products value * vector[col] in LDS with coalesced loads, then groups of
+// L lanes (L a power of two near the block's mean row length) reduce one
+// row each with a fixed butterfly.  Every sum has a fixed order, so results
+// are reproducible run to run.  Blocks whose entries exceed the LDS stage
+// fall back to one wave per row straight from HBM.
+//
+// The normalized duality gap (eq. rhorz) needs the multiplier lambda* of the
+// linear trust region of Section 6.3.1.  The GPU finds it by bisection on
+// the multiplier over the IEEE bit patterns of the breakpoints d_i / a_i
+// (monotone for non-negative doubles): 2048-way radix levels narrow the
+// bracket containing lambda*, then lambda* = sqrt((r^2 - F)/A) on the
+// breakpoint-free bracket, the closing formula of Algorithm 2.
+#include "pdhg_device.h"
+
+#include <math.h>
+
+namespace pdhg {
+
+// ---------------------------------------------------------------------
+// SpMV core
+// ---------------------------------------------------------------------
+template <class Epi>
+__device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const int *__restrict__ ci,
+                                          const double *__restrict__ v,
+                                          const double *__restrict__ xin, int r0, int r1,
+                                          const Epi &epi, double *lds) {
+    const int tid = threadIdx.x;
+    const int p0 = rp[r0], p1 = rp[r1];
+    const int nb = p1 - p0;
+    const int R = r1 - r0;
+    if (nb <= kLdsProducts) {
+        for (int e = tid; e < nb; e += kWG) lds[e] = v[p0 + e] * xin[ci[p0 + e]];
+        __syncthreads();
+        const int avg = nb / R;
+        int L = 1;
+        while (L < 64 && 2 * L <= avg) L <<= 1;
+        const int G = kWG / L;
+        const int lane = tid & (L - 1), grp = tid / L;
+        for (int rr = grp; rr < R; rr += G) {
+            const int row = r0 + rr;
+            const int s0 = rp[row] - p0, s1 = rp[row + 1] - p0;
+            double s = 0.0;
+            for (int e = s0 + lane; e < s1; e += L) s += lds[e];
+            for (int off = L >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
+            if (lane == 0) epi(row, s);
+        }
+    } else {
+        const int wave = tid >> 6, lane = tid & 63;
+        for (int row = r0 + wave; row < r1; row += kWG / 64) {
+            double s = 0.0;
+            for (int p = rp[row] + lane; p < rp[row + 1]; p += 64) s += v[p] * xin[ci[p]];
+            s = wave_sum(s);
+            if (lane == 0) epi(row, s);
+        }
+    }
+}
+
+template <class Epi>
+__global__ __launch_bounds__(kWG) void k_spmv(const int *__restrict__ rp,
+                                              const int *__restrict__ ci,
+                                              const double *__restrict__ v,
+                                              const double *__restrict__ xin,
+                                              const int *__restrict__ br, Epi epi,
+                                              const int *skip) {
+    if (skip && *skip) return;
+    __shared__ double lds[kLdsProducts];
+    const int r0 = br[blockIdx.x], r1 = br[blockIdx.x + 1];
+    if (r0 >= r1) return;
+    spmv_rows(rp, ci, v, xin, r0, r1, epi, lds);
+}
+
+struct EpiStore {
+    double *out;
+    __device__ __forceinline__ void operator()(int r, double s) const { out[r] = s; }
+};
+
+// x+ = proj_[l,u](x - tau (c - A'y)); sx += x+   (eq. PDHG-update, primal)
+struct EpiPrimal {
+    const double *__restrict__ c, *__restrict__ l, *__restrict__ u;
+    double *__restrict__ x, *__restrict__ sx;
+    double tau;
+    DevState *st;
+    __device__ __forceinline__ void operator()(int j, double aty) const {
+        double g = c[j] - aty;
+        double xn = x[j] - tau * g;
+        const double lo = l[j], hi = u[j];
+        if (xn < lo) xn = lo;
+        if (xn > hi) xn = hi;
+        x[j] = xn;
+        sx[j] += xn;
+        if (j == 0) {  // iteration counters of Algorithm 1
+            st->k += 1;
+            st->t += 1;
+        }
+    }
+};
+
+// y+ = proj_Y(y + sigma (b - (2 A x+ - A x))); sy += y+; q = A x+
+struct EpiDual {
+    const double *__restrict__ b;
+    const signed char *__restrict__ kind;
+    double *__restrict__ y, *__restrict__ sy, *__restrict__ q;
+    double sigma;
+    __device__ __forceinline__ void operator()(int i, double ax) const {
+        double yv = y[i] + sigma * (b[i] - (2.0 * ax - q[i]));
+        if (kind && kind[i] && yv < 0.0) yv = 0.0;
+        y[i] = yv;
+        sy[i] += yv;
+        q[i] = ax;
+    }
+};
+
+int nblocks_for(int rows, int nnz) {
+    long long u = (long long)rows + nnz;
+    int nb = div_up(u, kUnits);
+    return nb < 1 ? 1 : nb;
+}
+
+// br[c] = first row i in [0, rows] with i + rp[i] >= c * kUnits; br[nblk] = rows.
+__global__ void k_rowsplit(const int *__restrict__ rp, int rows, int nblk, int *br) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > nblk) return;
+    if (c == nblk) {
+        br[c] = rows;
+        return;
+    }
+    long long target = (long long)c * kUnits;
+    int lo = 0, hi = rows;
+    while (lo < hi) {
+        int mid = lo + ((hi - lo) >> 1);
+        if ((long long)mid + rp[mid] >= target) hi = mid;
+        else lo = mid + 1;
+    }
+    br[c] = lo;
+}
+
+void launch_rowsplit(const int *rp, int rows, int nnz, int nblk, int *br, hipStream_t s) {
+    (void)nnz;
+    hipLaunchKernelGGL(k_rowsplit, dim3(div_up(nblk + 1, kWG)), dim3(kWG), 0, s, rp, rows, nblk, br);
+}
+
+void launch_primal(const Dev &d, double tau, hipStream_t s) {
+    EpiPrimal e{d.c, d.l, d.u, d.x, d.sx, tau, d.st};
+    hipLaunchKernelGGL(k_spmv<EpiPrimal>, dim3(d.nblkT), dim3(kWG), 0, s, d.trp, d.tci, d.tv,
+                       d.y, d.brT, e, &d.st->done);
+}
+
+void launch_dual(const Dev &d, double sigma, hipStream_t s) {
+    if (d.m == 0) return;
+    EpiDual e{d.b, d.kind, d.y, d.sy, d.q, sigma};
+    hipLaunchKernelGGL(k_spmv<EpiDual>, dim3(d.nblkA), dim3(kWG), 0, s, d.rp, d.ci, d.v, d.x,
+                       d.brA, e, &d.st->done);
+}
+
+static void spmv_A_gated(const Dev &d, const double *in, double *out, const int *skip,
+                         hipStream_t s) {
+    if (d.m == 0) return;
+    EpiStore e{out};
+    hipLaunchKernelGGL(k_spmv<EpiStore>, dim3(d.nblkA), dim3(kWG), 0, s, d.rp, d.ci, d.v, in,
+                       d.brA, e, skip);
+}
+
+static void spmv_T_gated(const Dev &d, const double *in, double *out, const int *skip,
+                         hipStream_t s) {
+    EpiStore e{out};
+    hipLaunchKernelGGL(k_spmv<EpiStore>, dim3(d.nblkT), dim3(kWG), 0, s, d.trp, d.tci, d.tv, in,
+                       d.brT, e, skip);
+}
+
+void launch_spmv_A(const Dev &d, const double *in, double *out, hipStream_t s,
+                   const int *skip) {
+    spmv_A_gated(d, in, out, skip, s);
+}
+
+void launch_spmv_T(const Dev &d, const double *in, double *out, hipStream_t s,
+                   const int *skip) {
+    spmv_T_gated(d, in, out, skip, s);
+}
+
+// ---------------------------------------------------------------------
+// setup: validation, transpose, initial point, norms
+// ---------------------------------------------------------------------
+enum { ERR_RP = 1, ERR_COL = 2, ERR_VAL = 4, ERR_BOUND = 8, ERR_C = 16, ERR_B = 32, ERR_KIND = 64 };
+
+__global__ void k_validate(Dev d) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long g0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int err = 0;
+    for (long long i = g0; i <= d.m; i += stride) {
+        int a = d.rp[i];
+        if (i == 0 && a != 0) err |= ERR_RP;
+        if (a < 0 || a > d.nnz) err |= ERR_RP;
+        if (i < d.m && d.rp[i + 1] < a) err |= ERR_RP;
+        if (i == d.m && a != d.nnz) err |= ERR_RP;
+    }
+    for (long long p = g0; p < d.nnz; p += stride) {
+        int cc = d.ci[p];
+        if (cc < 0 || cc >= d.n) err |= ERR_COL;
+        if (!isfinite(d.v[p])) err |= ERR_VAL;
+    }
+    for (long long j = g0; j < d.n; j += stride) {
+        double lo = d.l[j], hi = d.u[j];
+        if (isnan(lo) || isnan(hi) || !(lo <= hi) || lo == INFINITY || hi == -INFINITY)
+            err |= ERR_BOUND;
+        if (!isfinite(d.c[j])) err |= ERR_C;
+    }
+    for (long long i = g0; i < d.m; i += stride) {
+        if (!isfinite(d.b[i])) err |= ERR_B;
+        if (d.kind && (d.kind[i] != 0 && d.kind[i] != 1)) err |= ERR_KIND;
+    }
+    if (err) atomicOr(d.err, err);
+}
+
+void launch_validate(const Dev &d, hipStream_t s) {
+    long long mx = d.nnz;
+    if (d.m + 1 > mx) mx = d.m + 1;
+    if (d.n > mx) mx = d.n;
+    int g = div_up(mx, kWG);
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_validate, dim3(g), dim3(kWG), 0, s, d);
+}
+
+__global__ void k_fill_int(int *a, long long len, int val) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) a[i] = val;
+}
+
+__global__ void k_count_cols(const int *__restrict__ ci, int nnz, int *cnt /* n+1 */) {
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nnz) atomicAdd(&cnt[ci[p] + 1], 1);
+}
+
+// In-place inclusive scan of chunks of 2048 ints; chunk totals to bsum.
+constexpr int kScanChunk = 2048;
+__global__ __launch_bounds__(kWG) void k_scan_chunks(int *a, long long len, int *bsum) {
+    __shared__ int sh[kScanChunk];
+    const long long base = (long long)blockIdx.x * kScanChunk;
+    for (int e = threadIdx.x; e < kScanChunk; e += kWG)
+        sh[e] = (base + e < len) ? a[base + e] : 0;
+    __syncthreads();
+    // each thread scans 8 consecutive entries, then a scan of thread totals
+    __shared__ int tot[kWG];
+    int loc[8];
+    int s = 0;
+    for (int k = 0; k < 8; ++k) {
+        s += sh[threadIdx.x * 8 + k];
+        loc[k] = s;
+    }
+    tot[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < kWG; off <<= 1) {
+        int t = threadIdx.x >= off ? tot[threadIdx.x - off] : 0;
+        __syncthreads();
+        tot[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int pre = threadIdx.x ? tot[threadIdx.x - 1] : 0;
+    for (int k = 0; k < 8; ++k) {
+        long long i = base + threadIdx.x * 8 + k;
+        if (i < len) a[i] = loc[k] + pre;
+    }
+    if (threadIdx.x == kWG - 1) bsum[blockIdx.x] = tot[kWG - 1];
+}
+
+// exclusive scan of nb chunk totals by one workgroup (sequential in chunks)
+__global__ __launch_bounds__(kWG) void k_scan_sums(int *bsum, int nb) {
+    __shared__ int tot[kWG];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nb; base += kWG) {
+        int i = base + threadIdx.x;
+        int v = i < nb ? bsum[i] : 0;
+        tot[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < kWG; off <<= 1) {
+            int t = threadIdx.x >= off ? tot[threadIdx.x - off] : 0;
+            __syncthreads();
+            tot[threadIdx.x] += t;
+            __syncthreads();
+        }
+        int excl = tot[threadIdx.x] - v + carry;
+        if (i < nb) bsum[i] = excl;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += tot[kWG - 1];
+        __syncthreads();
+    }
+}
+
+__global__ void k_scan_add(int *a, long long len, const int *boff) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) a[i] += boff[i / kScanChunk];
+}
+
+// each entry p of A (row i, column j) takes the next free slot of column j
+__global__ void k_scatter(const int *__restrict__ rp, const int *__restrict__ ci, int m, int nnz,
+                          int *cursor, int *tci, int *perm) {
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nnz) return;
+    // row of entry p: last i with rp[i] <= p
+    int lo = 0, hi = m - 1;
+    while (lo < hi) {
+        int mid = lo + ((hi - lo + 1) >> 1);
+        if (rp[mid] <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    int q = atomicAdd(&cursor[ci[p]], 1);
+    tci[q] = lo;
+    perm[q] = (int)p;
+}
+
+// Order each row of A' by increasing entry index of A (= increasing row of
+// A).  Short rows: insertion sort by one thread.  Long rows are listed.
+constexpr int kShortRow = 32;
+constexpr int kBitonic = 4096;
+__global__ void k_sort_short(const int *__restrict__ trp, int n, int *tci, int *perm,
+                             int *long_rows, int *nlong) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int a = trp[j], b = trp[j + 1];
+    int len = b - a;
+    if (len <= 1) return;
+    if (len > kShortRow) {
+        int slot = atomicAdd(nlong, 1);
+        long_rows[slot] = j;
+        return;
+    }
+    for (int i = a + 1; i < b; ++i) {
+        int kp = perm[i], kt = tci[i];
+        int q = i - 1;
+        while (q >= a && perm[q] > kp) {
+            perm[q + 1] = perm[q];
+            tci[q + 1] = tci[q];
+            --q;
+        }
+        perm[q + 1] = kp;
+        tci[q + 1] = kt;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_sort_long(const int *__restrict__ trp,
+                                                   const int *__restrict__ long_rows,
+                                                   const int *__restrict__ nlong, int *tci,
+                                                   int *perm) {
+    __shared__ int key[kBitonic];
+    __shared__ int val[kBitonic];
+    const int cnt = *nlong;
+    for (int w = blockIdx.x; w < cnt; w += gridDim.x) {
+        const int j = long_rows[w];
+        const int a = trp[j], len = trp[j + 1] - a;
+        if (len <= kBitonic) {
+            int P = 1;
+            while (P < len) P <<= 1;
+            for (int e = threadIdx.x; e < P; e += kWG) {
+                key[e] = e < len ? perm[a + e] : 0x7fffffff;
+                val[e] = e < len ? tci[a + e] : 0;
+            }
+            __syncthreads();
+            for (int k = 2; k <= P; k <<= 1) {
+                for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                    for (int i = threadIdx.x; i < P; i += kWG) {
+                        int ixj = i ^ jj;
+                        if (ixj > i) {
+                            bool up = (i & k) == 0;
+                            int ki = key[i], kj = key[ixj];
+                            if ((ki > kj) == up) {
+                                key[i] = kj;
+                                key[ixj] = ki;
+                                int t = val[i];
+                                val[i] = val[ixj];
+                                val[ixj] = t;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (int e = threadIdx.x; e < len; e += kWG) {
+                perm[a + e] = key[e];
+                tci[a + e] = val[e];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Rows longer than the LDS stage: each entry's rank is the number of smaller
+// keys in its row (keys are distinct), so entries are placed through a
+// scratch array (the value array of A', filled afterwards).  The cost is
+// quadratic in the row length; only columns of A with more than 4096
+// entries take this path.
+__global__ __launch_bounds__(kWG) void k_sort_huge_rank(const int *__restrict__ trp,
+                                                        const int *__restrict__ long_rows,
+                                                        const int *__restrict__ nlong,
+                                                        const int *__restrict__ perm,
+                                                        const int *__restrict__ tci,
+                                                        int2 *scratch) {
+    const int cnt = *nlong;
+    for (int w = blockIdx.x; w < cnt; w += gridDim.x) {
+        const int j = long_rows[w];
+        const int a = trp[j], len = trp[j + 1] - a;
+        if (len <= kBitonic) continue;
+        for (int e = threadIdx.x; e < len; e += kWG) {
+            const int ke = perm[a + e];
+            int rank = 0;
+            for (int f = 0; f < len; ++f) rank += perm[a + f] < ke;
+            scratch[a + rank] = make_int2(ke, tci[a + e]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_sort_huge_place(const int *__restrict__ trp,
+                                                         const int *__restrict__ long_rows,
+                                                         const int *__restrict__ nlong,
+                                                         const int2 *__restrict__ scratch,
+                                                         int *perm, int *tci) {
+    const int cnt = *nlong;
+    for (int w = blockIdx.x; w < cnt; w += gridDim.x) {
+        const int j = long_rows[w];
+        const int a = trp[j], len = trp[j + 1] - a;
+        if (len <= kBitonic) continue;
+        for (int e = threadIdx.x; e < len; e += kWG) {
+            int2 kv = scratch[a + e];
+            perm[a + e] = kv.x;
+            tci[a + e] = kv.y;
+        }
+    }
+}
+
+__global__ void k_gather_vals(const int *__restrict__ perm, const double *__restrict__ v, int nnz,
+                              double *tv) {
+    long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nnz) tv[q] = v[perm[q]];
+}
+
+__global__ void k_fill_zero(double *a, long long len) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) a[i] = 0.0;
+}
+
+__global__ void k_copy_int(const int *__restrict__ a, int *b, long long len) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) b[i] = a[i];
+}
+
+void launch_transpose(const Dev &d, hipStream_t s) {
+    const int n = d.n, nnz = d.nnz, m = d.m;
+    hipLaunchKernelGGL(k_fill_int, dim3(div_up(n + 1, kWG)), dim3(kWG), 0, s, d.trp,
+                       (long long)n + 1, 0);
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_count_cols, dim3(div_up(nnz, kWG)), dim3(kWG), 0, s, d.ci, nnz,
+                           d.trp);
+    // inclusive scan of trp[0..n] (trp[0] = 0) gives the row starts of A'
+    const long long len = (long long)n + 1;
+    const int nchunk = div_up(len, kScanChunk);
+    int *bsum = d.long_rows;  // n >= nchunk; reused before the sort needs it
+    hipLaunchKernelGGL(k_scan_chunks, dim3(nchunk), dim3(kWG), 0, s, d.trp, len, bsum);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kWG), 0, s, bsum, nchunk);
+    hipLaunchKernelGGL(k_scan_add, dim3(div_up(len, kWG)), dim3(kWG), 0, s, d.trp, len, bsum);
+    if (nnz == 0) return;
+    hipLaunchKernelGGL(k_copy_int, dim3(div_up(n, kWG)), dim3(kWG), 0, s, d.trp, d.cursor,
+                       (long long)n);
+    hipLaunchKernelGGL(k_scatter, dim3(div_up(nnz, kWG)), dim3(kWG), 0, s, d.rp, d.ci, m, nnz,
+                       d.cursor, d.tci, d.perm);
+    int *nlong = d.err + 1;
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(1), 0, s, nlong, 1LL, 0);
+    hipLaunchKernelGGL(k_sort_short, dim3(div_up(n, kWG)), dim3(kWG), 0, s, d.trp, n, d.tci,
+                       d.perm, d.long_rows, nlong);
+    hipLaunchKernelGGL(k_sort_long, dim3(1024), dim3(kWG), 0, s, d.trp, d.long_rows, nlong,
+                       d.tci, d.perm);
+    int2 *scratch = reinterpret_cast<int2 *>(d.tv);  // tv is filled afterwards
+    hipLaunchKernelGGL(k_sort_huge_rank, dim3(1024), dim3(kWG), 0, s, d.trp, d.long_rows, nlong,
+                       d.perm, d.tci, scratch);
+    hipLaunchKernelGGL(k_sort_huge_place, dim3(1024), dim3(kWG), 0, s, d.trp, d.long_rows,
+                       nlong, scratch, d.perm, d.tci);
+    hipLaunchKernelGGL(k_gather_vals, dim3(div_up(nnz, kWG)), dim3(kWG), 0, s, d.perm, d.v, nnz,
+                       d.tv);
+}
+
+// x = proj_X(0), x0 = x, y = y0 = 0, sums 0, counters 0
+__global__ void k_init_point(Dev d) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d.n) {
+        double v = 0.0;
+        if (v < d.l[i]) v = d.l[i];
+        if (v > d.u[i]) v = d.u[i];
+        d.x[i] = v;
+        d.x0[i] = v;
+        d.sx[i] = 0.0;
+    }
+    if (i < d.m) {
+        d.y[i] = 0.0;
+        d.y0[i] = 0.0;
+        d.sy[i] = 0.0;
+    }
+    if (i == 0) {
+        DevState *st = d.st;
+        st->k = 0;
+        st->t = 0;
+        st->restarts = 0;
+        st->checks = 0;
+        st->rho_prev = 0.0;
+        st->done = 0;
+        st->conv_which = -1;
+        st->conv_k = -1;
+        st->restarted = 0;
+        st->cand = 0;
+        st->gap_slots = 0;
+        st->numerr = 0;
+        st->in_check = 0;
+        for (int sidx = 0; sidx < kTrSlots; ++sidx) st->tr[sidx].mode = TR_IDLE;
+    }
+}
+
+void launch_init_point(const Dev &d, hipStream_t s) {
+    long long mx = d.n > d.m ? d.n : d.m;
+    hipLaunchKernelGGL(k_init_point, dim3(div_up(mx, kWG)), dim3(kWG), 0, s, d);
+    if (d.m > 0) launch_spmv_A(d, d.x, d.q, s);
+}
+
+// |b|^2 and |c|^2 (deterministic), stored in the state
+__global__ __launch_bounds__(kWG) void k_norm_partials(Dev d) {
+    __shared__ double sh[4 * 2];
+    double v[2] = {0.0, 0.0};
+    const long long stride = (long long)gridDim.x * kWG;
+    for (long long i = (long long)blockIdx.x * kWG + threadIdx.x; i < (long long)d.n + d.m;
+         i += stride) {
+        if (i < d.n) v[1] += d.c[i] * d.c[i];
+        else {
+            double bb = d.b[i - d.n];
+            v[0] += bb * bb;
+        }
+    }
+    block_sums<2>(v, sh);
+    if (threadIdx.x == 0) {
+        d.part[blockIdx.x * kKktSums + 0] = v[0];
+        d.part[blockIdx.x * kKktSums + 1] = v[1];
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_norm_final(Dev d, int nb) {
+    __shared__ double sh[4 * 2];
+    double out[2];
+    reduce_partials<2>(d.part, nb, kKktSums, out, sh);
+    if (threadIdx.x == 0) {
+        d.st->nb2 = out[0];
+        d.st->nc2 = out[1];
+    }
+}
+
+int red_grid(long long N) {
+    int g = div_up(N, kWG);
+    if (g > kRedBlocks) g = kRedBlocks;
+    if (g < 1) g = 1;
+    return g;
+}
+
+void launch_norms(const Dev &d, hipStream_t s) {
+    int g = red_grid((long long)d.n + d.m);
+    hipLaunchKernelGGL(k_norm_partials, dim3(g), dim3(kWG), 0, s, d);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kWG), 0, s, d, g);
+}
+
+// ---------------------------------------------------------------------
+// check: averages, KKT, radii
+// ---------------------------------------------------------------------
+__global__ void k_reset_done(DevState *st) {
+    st->done = 0;
+    st->in_check = 0;
+}
+
+__global__ void k_average(Dev d) {
+    if (d.st->done) return;
+    const long long t = d.st->t;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const double tt = (double)t;
+    if (i < d.n) d.xbar[i] = t ? d.sx[i] / tt : d.x[i];
+    else if (i < (long long)d.n + d.m) {
+        long long r = i - d.n;
+        d.ybar[r] = t ? d.sy[r] / tt : d.y[r];
+    }
+}
+
+void launch_average(const Dev &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_average, dim3(div_up((long long)d.n + d.m, kWG)), dim3(kWG), 0, s, d);
+}
+
+__device__ void kkt_point(const Dev &d, const double *S, int P, double *out) {
+    const double pres2 = S[S_PRES2_C + P], dres2 = S[S_DRES2_C + P];
+    const double pobj = S[S_POBJ_C + P], dobj = S[S_DOBJ_C + P], bv2 = S[S_BV2_C + P];
+    const double pres = sqrt(pres2), dres = sqrt(dres2);
+    const double gap = pobj - dobj;
+    const double rel_p = pres / (1.0 + sqrt(d.st->nb2));
+    const double rel_d = dres / (1.0 + sqrt(d.st->nc2));
+    const double rel_g = fabs(gap) / (1.0 + fabs(pobj) + fabs(dobj));
+    double rel = rel_p;
+    if (rel_d > rel) rel = rel_d;
+    if (rel_g > rel) rel = rel_g;
+    const double gpos = gap > 0.0 ? gap : 0.0;
+    double mx = pres;
+    if (dres > mx) mx = dres;
+    if (fabs(gap) > mx) mx = fabs(gap);
+    out[1] = rel;
+    out[2] = pres;
+    out[3] = dres;
+    out[4] = pobj;
+    out[5] = dobj;
+    out[6] = sqrt(bv2 + pres2 + dres2 + gpos * gpos);
+    out[7] = mx;
+}
+
+__global__ __launch_bounds__(kWG) void k_kkt_partials(Dev d, KktPoints P2, int gated) {
+    if (gated && d.st->done) return;
+    __shared__ double sh[4 * kKktSums];
+    double v[kKktSums];
+#pragma unroll
+    for (int k = 0; k < kKktSums; ++k) v[k] = 0.0;
+    const long long N = (long long)d.n + d.m;
+    const long long stride = (long long)gridDim.x * kWG;
+    for (long long i = (long long)blockIdx.x * kWG + threadIdx.x; i < N; i += stride) {
+        if (i < d.n) {
+            const int j = (int)i;
+            const double cj = d.c[j], lj = d.l[j], uj = d.u[j], x0 = d.x0[j];
+            const bool lf = isfinite(lj), uf = isfinite(uj);
+            const double xs[2] = {P2.x[0][j], P2.x[1][j]};
+            const double ats[2] = {P2.aty[0][j], P2.aty[1][j]};
+#pragma unroll
+            for (int P = 0; P < 2; ++P) {
+                const double xp = xs[P];
+                const double rc = cj - ats[P];
+                double lam;
+                if (lf && uf) lam = rc;
+                else if (lf) lam = rc > 0.0 ? rc : 0.0;
+                else if (uf) lam = rc < 0.0 ? rc : 0.0;
+                else lam = 0.0;
+                const double dr = rc - lam;
+                v[S_DRES2_C + P] += dr * dr;
+                double dob = 0.0;
+                if (lam > 0.0) dob += lj * lam;
+                if (lam < 0.0) dob += uj * lam;
+                v[S_DOBJ_C + P] += dob;
+                v[S_POBJ_C + P] += cj * xp;
+                double bv = 0.0;
+                if (xp < lj) bv = lj - xp;
+                if (xp > uj) bv = xp - uj;
+                v[S_BV2_C + P] += bv * bv;
+            }
+            const double da = xs[1] - x0, dc = xs[0] - x0;
+            v[S_RX2_A] += da * da;
+            v[S_RX2_C] += dc * dc;
+        } else {
+            const int r = (int)(i - d.n);
+            const double br = d.b[r], y0 = d.y0[r];
+            const bool ge = d.kind && d.kind[r];
+            const double ys[2] = {P2.y[0][r], P2.y[1][r]};
+            const double axs[2] = {P2.ax[0][r], P2.ax[1][r]};
+#pragma unroll
+            for (int P = 0; P < 2; ++P) {
+                double p = br - axs[P];
+                if (ge && p < 0.0) p = 0.0;
+                v[S_PRES2_C + P] += p * p;
+                v[S_DOBJ_C + P] += br * ys[P];
+                if (ge && ys[P] < 0.0) v[S_BV2_C + P] += ys[P] * ys[P];
+            }
+            const double da = ys[1] - y0, dc = ys[0] - y0;
+            v[S_RY2_A] += da * da;
+            v[S_RY2_C] += dc * dc;
+        }
+    }
+    block_sums<kKktSums>(v, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kKktSums; ++k) d.part[(size_t)blockIdx.x * kKktSums + k] = v[k];
+    }
+}
+
+void launch_kkt_partials(const Dev &d, hipStream_t s) {
+    int g = red_grid((long long)d.n + d.m);
+    KktPoints P2{{d.x, d.xbar}, {d.y, d.ybar}, {d.q, d.axb}, {d.aty, d.atyb}};
+    hipLaunchKernelGGL(k_kkt_partials, dim3(g), dim3(kWG), 0, s, d, P2, 1);
+}
+
+// KKT of one held point into st->kkt_eval, leaving the solver state alone
+__global__ __launch_bounds__(kWG) void k_kkt_eval(Dev d, int nb) {
+    __shared__ double sh[4 * kKktSums];
+    double S[kKktSums];
+    reduce_partials<kKktSums>(d.part, nb, kKktSums, S, sh);
+    if (threadIdx.x == 0) kkt_point(d, S, 0, d.st->kkt_eval);
+}
+
+void launch_kkt_eval(const Dev &d, int which, hipStream_t s) {
+    launch_copy_point(d, which, d.gx, d.gy, s);
+    launch_spmv_A(d, d.gx, d.gax, s);
+    launch_spmv_T(d, d.gy, d.gaty, s);
+    int g = red_grid((long long)d.n + d.m);
+    KktPoints P2{{d.gx, d.gx}, {d.gy, d.gy}, {d.gax, d.gax}, {d.gaty, d.gaty}};
+    hipLaunchKernelGGL(k_kkt_partials, dim3(g), dim3(kWG), 0, s, d, P2, 0);
+    hipLaunchKernelGGL(k_kkt_eval, dim3(1), dim3(kWG), 0, s, d, g);
+}
+
+__device__ __forceinline__ double kkt_pick(const double *k8, int kind) {
+    if (kind == 1) return k8[6];
+    if (kind == 2) return k8[7];
+    return k8[1];
+}
+
+// Stopping test and the radii; arms the trust-region slots.
+__global__ __launch_bounds__(kWG) void k_kkt_final(Dev d, int nb, double tol, int kkt_kind,
+                                                   double omega, int gap_slots) {
+    DevState *st = d.st;
+    if (st->done) return;
+    __shared__ double sh[4 * kKktSums];
+    __shared__ int armed;
+    double S[kKktSums];
+    reduce_partials<kKktSums>(d.part, nb, kKktSums, S, sh);
+    if (threadIdx.x == 0) {
+        st->in_check = 1;
+        st->restarted = 0;
+        st->cand = 0;
+        kkt_point(d, S, 0, st->kkt_cur);
+        kkt_point(d, S, 1, st->kkt_avg);
+        const double kc = kkt_pick(st->kkt_cur, kkt_kind), ka = kkt_pick(st->kkt_avg, kkt_kind);
+        st->kkt_cur[0] = kc;
+        st->kkt_avg[0] = ka;
+        bool bad = false;
+        for (int k = 0; k < kKktSums; ++k) bad |= !isfinite(S[k]);
+        st->numerr = bad ? 1 : 0;
+        int conv = (tol > 0.0 && (kc <= tol || ka <= tol)) ? 1 : 0;
+        st->conv_which = -1;
+        if (conv) {
+            st->done = 1;
+            st->conv_which = (ka <= kc) ? 1 : 0;
+            st->conv_k = st->k;
+        }
+        st->r_avg = sqrt(omega * S[S_RX2_A] + S[S_RY2_A] / omega);
+        st->r_cur = sqrt(omega * S[S_RX2_C] + S[S_RY2_C] / omega);
+        int slots = 0;
+        if (!conv && !bad && st->t > 0) slots = gap_slots;
+        st->gap_slots = slots;
+        for (int sidx = 0; sidx < kTrSlots; ++sidx) {
+            TRState &ts = st->tr[sidx];
+            ts.mode = TR_IDLE;
+            ts.rho = 0.0;
+            ts.lam = 0.0;
+            if (slots & (1 << sidx)) {
+                ts.mode = TR_SEARCH;
+                ts.r = sidx == 0 ? st->r_avg : st->r_cur;
+                ts.r2 = ts.r * ts.r;
+                ts.F_acc = 0.0;
+                ts.A_acc = 0.0;
+                ts.prefix = 0ull;
+                ts.klo = 0ull;
+                ts.level = 0;
+                ts.count = 0;
+                ts.ncomp = 0;
+                ts.nan_seen = 0;
+            }
+        }
+        armed = slots;
+    }
+    __syncthreads();
+    // clear level-0 histograms of the armed slots
+    for (int sidx = 0; sidx < kTrSlots; ++sidx) {
+        if (!(armed & (1 << sidx))) continue;
+        const TRWork &w = d.tr[sidx];
+        for (int b = threadIdx.x; b < kBuckets; b += kWG) {
+            w.hcnt[b] = 0u;
+            w.hD[b] = 0.0;
+            w.hA[b] = 0.0;
+        }
+    }
+}
+
+void launch_kkt_final(const Dev &d, double tol, int kkt_kind, int gap_slots, hipStream_t s) {
+    int g = red_grid((long long)d.n + d.m);
+    hipLaunchKernelGGL(k_kkt_final, dim3(1), dim3(kWG), 0, s, d, g, tol, kkt_kind, d.omega,
+                       gap_slots);
+}
+
+void launch_reset_done(const Dev &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_done, dim3(1), dim3(1), 0, s, d.st);
+}
+
+// ---------------------------------------------------------------------
+// power iteration on A'A for sigma_max(A) (Section 7 step size):
+// v = 1/sqrt(n); repeat w = A v, u = A'w, s = |u|, v = u/s, est = sqrt(s)
+// until |est - prev| <= tol est or max_iters products.
+// ---------------------------------------------------------------------
+__global__ void k_power_init(Dev d) {
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < d.n) d.atyb[j] = 1.0 / sqrt((double)d.n);
+    if (j == 0) {
+        d.st->pw_done = 0;
+        d.st->pw_it = 0;
+        d.st->pw_est = 0.0;
+        d.st->pw_prev = 0.0;
+        d.st->pw_s = 0.0;
+    }
+}
+
+void launch_power_init(const Dev &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_power_init, dim3(div_up(d.n, kWG)), dim3(kWG), 0, s, d);
+}
+
+__global__ __launch_bounds__(kWG) void k_sq_partials(const double *v, long long N, double *part,
+                                                     const int *gate) {
+    if (gate && *gate) return;
+    __shared__ double sh[4];
+    double a[1] = {0.0};
+    for (long long i = (long long)blockIdx.x * kWG + threadIdx.x; i < N;
+         i += (long long)gridDim.x * kWG)
+        a[0] += v[i] * v[i];
+    block_sums<1>(a, sh);
+    if (threadIdx.x == 0) part[(size_t)blockIdx.x * kKktSums] = a[0];
+}
+
+__global__ __launch_bounds__(kWG) void k_power_final(Dev d, int nb, double tol, int max_iters) {
+    DevState *st = d.st;
+    if (st->pw_done) return;
+    __shared__ double sh[4];
+    double tot[1];
+    reduce_partials<1>(d.part, nb, kKktSums, tot, sh);
+    if (threadIdx.x == 0) {
+        const double sn = sqrt(tot[0]);
+        if (!(sn > 0.0)) {
+            st->pw_est = 0.0;
+            st->pw_s = 0.0;
+            st->pw_done = 1;
+        } else {
+            st->pw_s = sn;
+            const double est = sqrt(sn);
+            st->pw_est = est;
+            if (st->pw_it > 0 && fabs(est - st->pw_prev) <= tol * est) st->pw_done = 1;
+            st->pw_prev = est;
+            st->pw_it += 1;
+            if (st->pw_it >= max_iters) st->pw_done = 1;
+        }
+    }
+}
+
+__global__ void k_power_norm(Dev d) {
+    const double sn = d.st->pw_s;
+    if (!(sn > 0.0)) return;
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < d.n) d.atyb[j] = d.aty[j] / sn;
+}
+
+// one power-iteration product pair; every kernel skips once converged
+void launch_power_step(const Dev &d, double tol, int max_iters, hipStream_t s) {
+    const int *gate = &d.st->pw_done;
+    spmv_A_gated(d, d.atyb, d.axb, gate, s);
+    spmv_T_gated(d, d.axb, d.aty, gate, s);
+    const int g = red_grid(d.n);
+    hipLaunchKernelGGL(k_sq_partials, dim3(g), dim3(kWG), 0, s, d.aty, (long long)d.n, d.part,
+                       gate);
+    hipLaunchKernelGGL(k_power_final, dim3(1), dim3(kWG), 0, s, d, g, tol, max_iters);
+    hipLaunchKernelGGL(k_power_norm, dim3(div_up(d.n, kWG)), dim3(kWG), 0, s, d);
+}
+
+}  // namespace pdhg

@@ -1,0 +1,747 @@
+// Normalized duality gap, restart decision and point bookkeeping.
+//
+// rho_r(w) (eq. rhorz) for the LP saddle function equals
+//     max { F(w)'(w - w~) : w~ in Z, ||w~ - w|| <= r } / r
+// (eq. bilinear-0), a linear trust region over a box (Section 6.3.1).
+// Coordinate i with gradient g_i moves toward the bound that lowers g'w~:
+// a_i = |g_i|, d_i = distance to that bound (inf when there is none), and
+// w~_i = w_i - sign(g_i) min(lambda a_i, d_i).  lambda* is the largest
+// lambda with f(lambda) = sum_i min(lambda a_i, d_i)^2 <= r^2
+// (eq. lp-trust-region:summation).
+//
+// The search is bisection on the multiplier, 2048 candidates at a time:
+// the keys are the IEEE bit patterns of the breakpoints d_i / a_i, which
+// order like the values for non-negative doubles.  Level 0 histograms the
+// 11 exponent bits over all N coordinates, level 1 the next 11 bits over
+// the coordinates still in the bracket (and compacts them), and levels 2-5
+// finish on the compacted list inside one workgroup.  At each level the
+// bracket moves to the last bucket whose lower end keeps f <= r^2.  Once
+// the bracket holds no breakpoint (or one repeated value), every
+// coordinate is either clamped (key <= klo) or free, and a deterministic
+// pass gives F = sum_clamped d^2, A = sum_free a^2, lambda* =
+// sqrt((r^2 - F)/A), the closing formula of Algorithm 2.
+#include "pdhg_device.h"
+
+#include <math.h>
+
+namespace pdhg {
+
+__constant__ int kShift[6] = {52, 41, 30, 19, 8, 0};
+
+// ---------------------------------------------------------------------
+// coordinate providers
+// ---------------------------------------------------------------------
+struct GapElems {
+    int n, m;
+    const double *c, *b, *l, *u;
+    const signed char *kind;
+    const double *x, *y, *ax, *aty;
+    double sw;  // sqrt(omega): the norm is omega |x|^2 + |y|^2 / omega
+    __device__ __forceinline__ long long size() const { return (long long)n + m; }
+    __device__ __forceinline__ void get(long long i, double &a, double &d) const {
+        if (i < n) {
+            const int j = (int)i;
+            const double g = c[j] - aty[j];
+            double dist = 0.0;
+            if (g > 0.0) dist = x[j] - l[j];
+            else if (g < 0.0) dist = u[j] - x[j];
+            if (dist < 0.0) dist = 0.0;
+            a = fabs(g) / sw;
+            d = dist * sw;
+        } else {
+            const int r = (int)(i - n);
+            const double g = ax[r] - b[r];
+            const double lo = (kind && kind[r]) ? 0.0 : -INFINITY;
+            double dist = 0.0;
+            if (g > 0.0) dist = y[r] - lo;
+            else if (g < 0.0) dist = INFINITY;
+            if (dist < 0.0) dist = 0.0;
+            a = fabs(g) * sw;
+            d = dist / sw;
+        }
+    }
+};
+
+struct RawElems {
+    long long N;
+    const double *a, *d;
+    __device__ __forceinline__ long long size() const { return N; }
+    __device__ __forceinline__ void get(long long i, double &aa, double &dd) const {
+        aa = a[i];
+        dd = d[i];
+    }
+};
+
+__device__ __forceinline__ unsigned long long key_of(double a, double d) {
+    return (unsigned long long)__double_as_longlong(d / a);
+}
+
+__device__ __forceinline__ bool bad_pair(double a, double d) {
+    return a != a || d != d || a < 0.0 || d < 0.0 || a == INFINITY;
+}
+
+// deterministic exclusive prefix (from the left) and suffix (from the right)
+// of one double per thread
+__device__ double block_excl_prefix(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kWG; off <<= 1) {
+        double o = t >= off ? sh[t - off] : 0.0;
+        __syncthreads();
+        sh[t] += o;
+        __syncthreads();
+    }
+    double r = t ? sh[t - 1] : 0.0;
+    __syncthreads();
+    return r;
+}
+
+__device__ double block_excl_suffix(double v, double *sh) {
+    const int p = kWG - 1 - threadIdx.x;
+    sh[p] = v;
+    __syncthreads();
+    for (int off = 1; off < kWG; off <<= 1) {
+        double o = p >= off ? sh[p - off] : 0.0;
+        __syncthreads();
+        sh[p] += o;
+        __syncthreads();
+    }
+    double r = p ? sh[p - 1] : 0.0;
+    __syncthreads();
+    return r;
+}
+
+struct ChooseShared {
+    double pre[kWG];
+    int best;
+};
+
+// Move the bracket to the last bucket b (of nbuck at bit position `shift`)
+// whose lower end lambda_b keeps
+//   f(lambda_b) = F_acc + sum_{b'<b} D[b'] + lambda_b^2 (A_acc + sum_{b'>=b} A[b'])
+// at most r^2.  ts lives in LDS; called by the whole workgroup.
+__device__ void choose_bucket(TRState &ts, const unsigned int *cnt, const double *D,
+                              const double *A, int nbuck, int level, ChooseShared &cs) {
+    const int shift = kShift[level];
+    constexpr int per = kBuckets / kWG;
+    const int tid = threadIdx.x;
+    const int b0 = tid * per;
+    double dl[per], al[per];
+    unsigned int cl[per];
+    double Dt = 0.0, At = 0.0;
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        const int b = b0 + k;
+        if (b < nbuck) {
+            dl[k] = D[b];
+            al[k] = A[b];
+            cl[k] = cnt[b];
+        } else {
+            dl[k] = 0.0;
+            al[k] = 0.0;
+            cl[k] = 0u;
+        }
+        Dt += dl[k];
+        At += al[k];
+    }
+    const double Dpre = block_excl_prefix(Dt, cs.pre);
+    const double Asuf = block_excl_suffix(At, cs.pre);
+    double asuf_in[per];
+    double acc = Asuf;
+#pragma unroll
+    for (int k = per - 1; k >= 0; --k) {
+        acc += al[k];
+        asuf_in[k] = acc;
+    }
+    if (tid == 0) cs.best = -1;
+    __syncthreads();
+    const double F0 = ts.F_acc, A0 = ts.A_acc, r2 = ts.r2;
+    const unsigned long long prefix = ts.prefix;
+    double dacc = Dpre;
+    int best = -1;
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        const int b = b0 + k;
+        if (b < nbuck) {
+            const double lam =
+                __longlong_as_double((long long)(prefix | ((unsigned long long)b << shift)));
+            const double f = F0 + dacc + lam * lam * (A0 + asuf_in[k]);
+            if (f <= r2) best = b;
+        }
+        dacc += dl[k];
+    }
+    if (best >= 0) atomicMax(&cs.best, best);
+    __syncthreads();
+    int bb = cs.best;
+    if (bb < 0) bb = 0;  // the bracket's own lower end (f <= r^2 up to rounding)
+    if (bb / per == tid) {
+        const int k = bb - b0;
+        double dpre = Dpre;
+        for (int q = 0; q < k; ++q) dpre += dl[q];
+        const double aex = (k + 1 < per) ? asuf_in[k + 1] : Asuf;
+        ts.F_acc = F0 + dpre;
+        ts.A_acc = A0 + aex;
+        ts.klo = prefix | ((unsigned long long)bb << shift);
+        ts.prefix = ts.klo;
+        ts.count = cl[k];
+        if (ts.count == 0u || level == 5) ts.mode = TR_RESOLVED;
+        else ts.level = level + 1;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------
+// level 0: exponent histogram over all coordinates + full-box sums
+// ---------------------------------------------------------------------
+template <class E>
+__global__ __launch_bounds__(kWG) void k_tr_hist0(E e, TRState *ts, TRWork w, const int *gate) {
+    if (gate && !*gate) return;
+    if (ts->mode != TR_SEARCH || ts->level != 0) return;
+    __shared__ unsigned int scnt[kBuckets];
+    __shared__ double sD[kBuckets], sA[kBuckets];
+    __shared__ double sh[4 * 4];
+    for (int b = threadIdx.x; b < kBuckets; b += kWG) {
+        scnt[b] = 0u;
+        sD[b] = 0.0;
+        sA[b] = 0.0;
+    }
+    __syncthreads();
+    double v[4] = {0.0, 0.0, 0.0, 0.0};  // sum d^2 (finite d), #inf d, sum a d, #bad
+    const long long N = e.size();
+    for (long long base = (long long)blockIdx.x * kWG; base < N; base += (long long)gridDim.x * kWG) {
+        const long long i = base + threadIdx.x;
+        if (i < N) {
+            double a, d;
+            e.get(i, a, d);
+            if (bad_pair(a, d)) {
+                v[3] += 1.0;
+            } else if (a > 0.0) {
+                const unsigned long long key = key_of(a, d);
+                const int b = (int)(key >> 52);
+                atomicAdd(&scnt[b], 1u);
+                atomicAdd(&sA[b], a * a);
+                if (d < INFINITY) {
+                    atomicAdd(&sD[b], d * d);
+                    v[0] += d * d;
+                    v[2] += a * d;
+                } else {
+                    v[1] += 1.0;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kBuckets; b += kWG) {
+        if (scnt[b]) {
+            atomicAdd(&w.hcnt[b], scnt[b]);
+            atomicAdd(&w.hD[b], sD[b]);
+            atomicAdd(&w.hA[b], sA[b]);
+        }
+    }
+    block_sums<4>(v, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w.part[blockIdx.x * 4 + k] = v[k];
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_tr_decide0(TRState *ts, TRWork w, int nb, const int *gate) {
+    if (gate && !*gate) return;
+    if (ts->mode != TR_SEARCH || ts->level != 0) return;
+    __shared__ TRState sts;
+    __shared__ ChooseShared cs;
+    __shared__ double sh[4 * 4];
+    __shared__ int go;
+    if (threadIdx.x == 0) sts = *ts;
+    double tot[4];
+    reduce_partials<4>(w.part, nb, 4, tot, sh);
+    if (threadIdx.x == 0) {
+        go = 0;
+        if (tot[3] > 0.0) {
+            sts.nan_seen = 1;
+            sts.mode = TR_ZERO;
+            sts.rho = NAN;
+            sts.lam = NAN;
+            sts.value = NAN;
+        } else if (!(sts.r > 0.0)) {
+            sts.mode = TR_ZERO;
+            sts.rho = 0.0;
+            sts.lam = 0.0;
+            sts.value = 0.0;
+        } else if (tot[1] == 0.0 && tot[0] <= sts.r2) {
+            // first line of Algorithm 2: the whole box fits in the ball
+            sts.mode = TR_FULLBOX;
+            sts.value = tot[2];
+            sts.rho = tot[2] / sts.r;
+            sts.lam = INFINITY;
+        } else {
+            go = 1;
+        }
+    }
+    __syncthreads();
+    if (go) choose_bucket(sts, w.hcnt, w.hD, w.hA, kBuckets, 0, cs);
+    // clear the level-1 histogram and the compaction counter
+    for (int b = threadIdx.x; b < kBuckets; b += kWG) {
+        w.hcnt[kBuckets + b] = 0u;
+        w.hD[kBuckets + b] = 0.0;
+        w.hA[kBuckets + b] = 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sts.ncomp = 0u;
+        *ts = sts;
+    }
+}
+
+// level 1: next 11 bits over the bracket's coordinates, which are compacted
+template <class E>
+__global__ __launch_bounds__(kWG) void k_tr_hist1(E e, TRState *ts, TRWork w, const int *gate) {
+    if (gate && !*gate) return;
+    if (ts->mode != TR_SEARCH || ts->level != 1) return;
+    __shared__ unsigned int scnt[kBuckets];
+    __shared__ double sD[kBuckets], sA[kBuckets];
+    for (int b = threadIdx.x; b < kBuckets; b += kWG) {
+        scnt[b] = 0u;
+        sD[b] = 0.0;
+        sA[b] = 0.0;
+    }
+    __syncthreads();
+    const unsigned long long top = ts->prefix >> 52;
+    const int lane = threadIdx.x & 63;
+    const long long N = e.size();
+    for (long long base = (long long)blockIdx.x * kWG; base < N; base += (long long)gridDim.x * kWG) {
+        const long long i = base + threadIdx.x;
+        bool take = false;
+        double a = 0.0, d = 0.0;
+        unsigned long long key = 0ull;
+        if (i < N) {
+            e.get(i, a, d);
+            if (!bad_pair(a, d) && a > 0.0) {
+                key = key_of(a, d);
+                take = (key >> 52) == top;
+            }
+        }
+        if (take) {
+            const int b = (int)((key >> 41) & (kBuckets - 1));
+            atomicAdd(&scnt[b], 1u);
+            atomicAdd(&sD[b], d * d);
+            atomicAdd(&sA[b], a * a);
+        }
+        const unsigned long long mask = __ballot(take);
+        const int cnt = __popcll(mask);
+        unsigned int slot = 0u;
+        if (lane == 0 && cnt) slot = atomicAdd(&ts->ncomp, (unsigned int)cnt);
+        slot = __shfl(slot, 0, 64);
+        if (take) {
+            const unsigned int off = (unsigned int)__popcll(mask & ((1ull << lane) - 1ull));
+            w.ckey[slot + off] = key;
+            w.ca[slot + off] = a;
+            w.cd[slot + off] = d;
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kBuckets; b += kWG) {
+        if (scnt[b]) {
+            atomicAdd(&w.hcnt[kBuckets + b], scnt[b]);
+            atomicAdd(&w.hD[kBuckets + b], sD[b]);
+            atomicAdd(&w.hA[kBuckets + b], sA[b]);
+        }
+    }
+}
+
+// levels 1 (decision) to 5 on the compacted list, one workgroup
+__global__ __launch_bounds__(kWG) void k_tr_finish(TRState *ts, TRWork w, const int *gate) {
+    if (gate && !*gate) return;
+    if (ts->mode != TR_SEARCH || ts->level != 1) return;
+    __shared__ TRState sts;
+    __shared__ ChooseShared cs;
+    __shared__ unsigned int scnt[kBuckets];
+    __shared__ double sD[kBuckets], sA[kBuckets];
+    if (threadIdx.x == 0) sts = *ts;
+    __syncthreads();
+    choose_bucket(sts, w.hcnt + kBuckets, w.hD + kBuckets, w.hA + kBuckets, kBuckets, 1, cs);
+    const unsigned int nc = sts.ncomp;
+    while (sts.mode == TR_SEARCH) {
+        const int level = sts.level;
+        const int shift = kShift[level];
+        const int nbuck = level == 5 ? 256 : kBuckets;
+        const int above = kShift[level - 1];
+        const unsigned long long want = sts.prefix >> above;
+        for (int b = threadIdx.x; b < kBuckets; b += kWG) {
+            scnt[b] = 0u;
+            sD[b] = 0.0;
+            sA[b] = 0.0;
+        }
+        __syncthreads();
+        for (unsigned int e = threadIdx.x; e < nc; e += kWG) {
+            const unsigned long long key = w.ckey[e];
+            if ((key >> above) == want) {
+                const int b = (int)((key >> shift) & (unsigned long long)(nbuck - 1));
+                const double a = w.ca[e], d = w.cd[e];
+                atomicAdd(&scnt[b], 1u);
+                atomicAdd(&sD[b], d * d);
+                atomicAdd(&sA[b], a * a);
+            }
+        }
+        __syncthreads();
+        choose_bucket(sts, scnt, sD, sA, nbuck, level, cs);
+    }
+    if (threadIdx.x == 0) *ts = sts;
+}
+
+// deterministic sums on either side of klo
+template <class E>
+__global__ __launch_bounds__(kWG) void k_tr_final_partials(E e, TRState *ts, TRWork w,
+                                                           const int *gate) {
+    if (gate && !*gate) return;
+    if (ts->mode != TR_RESOLVED) return;
+    __shared__ double sh[4 * 3];
+    const unsigned long long klo = ts->klo;
+    double v[3] = {0.0, 0.0, 0.0};  // F = sum d^2 (clamped), A = sum a^2 (free), AD = sum a d
+    const long long N = e.size();
+    for (long long i = (long long)blockIdx.x * kWG + threadIdx.x; i < N;
+         i += (long long)gridDim.x * kWG) {
+        double a, d;
+        e.get(i, a, d);
+        if (bad_pair(a, d) || !(a > 0.0)) continue;
+        const unsigned long long key = key_of(a, d);
+        if (key <= klo) {
+            v[0] += d * d;
+            v[2] += a * d;
+        } else {
+            v[1] += a * a;
+        }
+    }
+    block_sums<3>(v, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) w.part[blockIdx.x * 4 + k] = v[k];
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_tr_final(TRState *ts, TRWork w, int nb, const int *gate) {
+    if (gate && !*gate) return;
+    if (ts->mode != TR_RESOLVED) return;
+    __shared__ double sh[4 * 3];
+    double tot[3];
+    reduce_partials<3>(w.part, nb, 4, tot, sh);
+    if (threadIdx.x == 0) {
+        const double F = tot[0], A = tot[1], AD = tot[2];
+        double lam, val;
+        if (A > 0.0) {
+            double num = ts->r2 - F;
+            if (num < 0.0) num = 0.0;
+            lam = sqrt(num / A);
+            val = AD + lam * A;
+        } else {
+            lam = INFINITY;
+            val = AD;
+        }
+        ts->lam = lam;
+        ts->value = val;
+        ts->rho = val / ts->r;
+    }
+}
+
+template <class E>
+static void run_tr(const E &e, long long N, TRState *ts, const TRWork &w, const int *gate,
+                   hipStream_t s) {
+    const int g = red_grid(N);
+    hipLaunchKernelGGL(k_tr_hist0<E>, dim3(g), dim3(kWG), 0, s, e, ts, w, gate);
+    hipLaunchKernelGGL(k_tr_decide0, dim3(1), dim3(kWG), 0, s, ts, w, g, gate);
+    hipLaunchKernelGGL(k_tr_hist1<E>, dim3(g), dim3(kWG), 0, s, e, ts, w, gate);
+    hipLaunchKernelGGL(k_tr_finish, dim3(1), dim3(kWG), 0, s, ts, w, gate);
+    hipLaunchKernelGGL(k_tr_final_partials<E>, dim3(g), dim3(kWG), 0, s, e, ts, w, gate);
+    hipLaunchKernelGGL(k_tr_final, dim3(1), dim3(kWG), 0, s, ts, w, g, gate);
+}
+
+static GapElems gap_elems(const Dev &d, const double *x, const double *y, const double *ax,
+                          const double *aty) {
+    GapElems e;
+    e.n = d.n;
+    e.m = d.m;
+    e.c = d.c;
+    e.b = d.b;
+    e.l = d.l;
+    e.u = d.u;
+    e.kind = d.kind;
+    e.x = x;
+    e.y = y;
+    e.ax = ax;
+    e.aty = aty;
+    e.sw = sqrt(d.omega);
+    return e;
+}
+
+void launch_gap(const Dev &d, int slot, hipStream_t s) {
+    GapElems e = slot == 0 ? gap_elems(d, d.xbar, d.ybar, d.axb, d.atyb)
+                           : gap_elems(d, d.x, d.y, d.q, d.aty);
+    run_tr(e, (long long)d.n + d.m, &d.st->tr[slot], d.tr[slot], &d.st->in_check, s);
+}
+
+// arm a trust-region evaluation with radius r and clear the level-0 histogram
+__global__ void k_tr_arm(TRState *ts, TRWork w, double r) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ts->mode = TR_SEARCH;
+        ts->r = r;
+        ts->r2 = r * r;
+        ts->F_acc = 0.0;
+        ts->A_acc = 0.0;
+        ts->prefix = 0ull;
+        ts->klo = 0ull;
+        ts->level = 0;
+        ts->count = 0u;
+        ts->ncomp = 0u;
+        ts->nan_seen = 0;
+        ts->rho = 0.0;
+        ts->lam = 0.0;
+        ts->value = 0.0;
+    }
+    for (int b = threadIdx.x; b < kBuckets; b += blockDim.x) {
+        w.hcnt[b] = 0u;
+        w.hD[b] = 0.0;
+        w.hA[b] = 0.0;
+    }
+}
+
+void launch_tr_raw(int64_t N, const double *a, const double *dd, double r, const TRWork &w,
+                   TRState *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_tr_arm, dim3(1), dim3(kWG), 0, s, st, w, r);
+    RawElems e{N, a, dd};
+    run_tr(e, (long long)N, st, w, nullptr, s);
+}
+
+// ---------------------------------------------------------------------
+// restart decision (eq. adaptive-restart-scheme, Remark rem:flexible) and
+// the restart itself (Algorithm 1: z^{n+1,0} = candidate, window cleared)
+// ---------------------------------------------------------------------
+__global__ void k_decide(Dev d, int mode, double beta, int tau0) {
+    DevState *st = d.st;
+    if (!st->in_check) return;
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double rec[kRec];
+    rec[0] = (double)st->k;
+    rec[1] = (double)st->t;
+    rec[2] = (double)st->restarts;
+    rec[3] = st->kkt_cur[0];
+    rec[4] = st->kkt_avg[0];
+    rec[5] = 0.0;
+    rec[6] = 0.0;
+    rec[7] = 0.0;
+    rec[8] = -1.0;
+    rec[9] = 0.0;
+    rec[10] = 0.0;
+    rec[11] = (double)st->conv_which;
+    rec[12] = st->rho_prev;
+    rec[13] = 0.0;
+    const int slots = st->gap_slots;
+    if (slots & 1) {
+        rec[5] = st->r_avg;
+        rec[6] = st->tr[0].rho;
+        rec[13] = st->tr[0].lam;
+        if (st->tr[0].nan_seen) st->numerr = 1;
+    }
+    if (slots & 2) {
+        rec[7] = st->r_cur;
+        rec[8] = st->tr[1].rho;
+        if (st->tr[1].nan_seen) st->numerr = 1;
+    }
+    (void)mode;
+    if ((slots & 1) && !st->done && !st->numerr) {
+        const double rho_a = st->tr[0].rho;
+        double rho_c = rho_a;
+        int cand = 0;
+        if ((slots & 2) && st->tr[1].rho < rho_a) {  // strict, as in Remark rem:flexible
+            cand = 1;
+            rho_c = st->tr[1].rho;
+        }
+        bool restart;
+        if (st->restarts == 0) restart = st->t >= (long long)tau0;
+        else restart = rho_c <= beta * st->rho_prev;
+        rec[10] = (double)cand;
+        if (restart) {
+            rec[9] = 1.0;
+            st->restarted = 1;
+            st->cand = cand;
+            st->restarts += 1;
+            st->t = 0;
+            st->rho_prev = rho_c;
+        }
+    }
+    double *dst = d.log + (size_t)(st->checks % kLogCap) * kRec;
+    for (int q = 0; q < kRec; ++q) dst[q] = rec[q];
+    st->checks += 1;
+    st->in_check = 0;
+}
+
+void launch_decide(const Dev &d, int mode, double beta, int tau0, hipStream_t s) {
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, s, d, mode, beta, tau0);
+}
+
+__global__ void k_apply(Dev d, int force) {
+    const DevState *st = d.st;
+    if (!force && !st->restarted) return;
+    const int cand = force ? 0 : st->cand;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d.n) {
+        if (cand == 0) {
+            const double v = d.xbar[i];
+            d.x[i] = v;
+            d.x0[i] = v;
+        } else {
+            d.x0[i] = d.x[i];
+        }
+        d.sx[i] = 0.0;
+    }
+    if (i < d.m) {
+        if (cand == 0) {
+            const double v = d.ybar[i];
+            d.y[i] = v;
+            d.y0[i] = v;
+            d.q[i] = d.axb[i];
+        } else {
+            d.y0[i] = d.y[i];
+        }
+        d.sy[i] = 0.0;
+    }
+}
+
+void launch_apply(const Dev &d, hipStream_t s) {
+    const long long mx = d.n > d.m ? d.n : d.m;
+    hipLaunchKernelGGL(k_apply, dim3(div_up(mx, kWG)), dim3(kWG), 0, s, d, 0);
+}
+
+__global__ void k_fixed_bump(DevState *st) {
+    st->restarts += 1;
+    st->t = 0;
+    st->rho_prev = 0.0;
+}
+
+// fixed-length restart (eq. define:t-star): restart to the average now
+void launch_fixed_restart(const Dev &d, hipStream_t s) {
+    launch_average(d, s);
+    launch_spmv_A(d, d.xbar, d.axb, s);
+    const long long mx = d.n > d.m ? d.n : d.m;
+    hipLaunchKernelGGL(k_apply, dim3(div_up(mx, kWG)), dim3(kWG), 0, s, d, 1);
+    hipLaunchKernelGGL(k_fixed_bump, dim3(1), dim3(1), 0, s, d.st);
+}
+
+// ---------------------------------------------------------------------
+// points
+// ---------------------------------------------------------------------
+__global__ void k_copy_point(Dev d, int which, double *ox, double *oy) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const DevState *st = d.st;
+    const long long t = st->t;
+    const bool sol_avg = st->conv_which == 1;
+    if (i < d.n) {
+        double v;
+        if (which == 0) v = d.x[i];
+        else if (which == 1) v = t ? d.sx[i] / (double)t : d.x[i];
+        else if (which == 2) v = d.x0[i];
+        else v = sol_avg ? d.xbar[i] : d.x[i];
+        ox[i] = v;
+    }
+    if (i < d.m) {
+        double v;
+        if (which == 0) v = d.y[i];
+        else if (which == 1) v = t ? d.sy[i] / (double)t : d.y[i];
+        else if (which == 2) v = d.y0[i];
+        else v = sol_avg ? d.ybar[i] : d.y[i];
+        oy[i] = v;
+    }
+}
+
+void launch_copy_point(const Dev &d, int which, double *x, double *y, hipStream_t s) {
+    const long long mx = d.n > d.m ? d.n : d.m;
+    hipLaunchKernelGGL(k_copy_point, dim3(div_up(mx, kWG)), dim3(kWG), 0, s, d, which, x, y);
+}
+
+__global__ void k_set_point(Dev d, const double *ix, const double *iy) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d.n) {
+        d.x[i] = ix[i];
+        d.x0[i] = ix[i];
+        d.sx[i] = 0.0;
+    }
+    if (i < d.m) {
+        d.y[i] = iy[i];
+        d.y0[i] = iy[i];
+        d.sy[i] = 0.0;
+    }
+    if (i == 0) d.st->t = 0;
+}
+
+void launch_set_point(const Dev &d, const double *x, const double *y, hipStream_t s) {
+    const long long mx = d.n > d.m ? d.n : d.m;
+    hipLaunchKernelGGL(k_set_point, dim3(div_up(mx, kWG)), dim3(kWG), 0, s, d, x, y);
+    launch_spmv_A(d, d.x, d.q, s);
+}
+
+// distance of (gx, gy) to the anchor in the primal-weight norm
+__global__ __launch_bounds__(kWG) void k_dist_partials(Dev d) {
+    __shared__ double sh[4 * 2];
+    double v[2] = {0.0, 0.0};
+    const long long N = (long long)d.n + d.m;
+    for (long long i = (long long)blockIdx.x * kWG + threadIdx.x; i < N;
+         i += (long long)gridDim.x * kWG) {
+        if (i < d.n) {
+            const double dx = d.gx[i] - d.x0[i];
+            v[0] += dx * dx;
+        } else {
+            const double dy = d.gy[i - d.n] - d.y0[i - d.n];
+            v[1] += dy * dy;
+        }
+    }
+    block_sums<2>(v, sh);
+    if (threadIdx.x == 0) {
+        d.part[blockIdx.x * kKktSums + 0] = v[0];
+        d.part[blockIdx.x * kKktSums + 1] = v[1];
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_dist_arm(Dev d, int nb, double r_given) {
+    __shared__ double sh[4 * 2];
+    double tot[2];
+    reduce_partials<2>(d.part, nb, kKktSums, tot, sh);
+    __shared__ double rr;
+    if (threadIdx.x == 0) rr = r_given >= 0.0 ? r_given : sqrt(d.omega * tot[0] + tot[1] / d.omega);
+    __syncthreads();
+    TRState *ts = &d.st->tr[0];
+    const TRWork &w = d.tr[0];
+    if (threadIdx.x == 0) {
+        ts->mode = TR_SEARCH;
+        ts->r = rr;
+        ts->r2 = rr * rr;
+        ts->F_acc = 0.0;
+        ts->A_acc = 0.0;
+        ts->prefix = 0ull;
+        ts->klo = 0ull;
+        ts->level = 0;
+        ts->count = 0u;
+        ts->ncomp = 0u;
+        ts->nan_seen = 0;
+        ts->rho = 0.0;
+        ts->lam = 0.0;
+        ts->value = 0.0;
+    }
+    for (int b = threadIdx.x; b < kBuckets; b += kWG) {
+        w.hcnt[b] = 0u;
+        w.hD[b] = 0.0;
+        w.hA[b] = 0.0;
+    }
+}
+
+void launch_gap_point(const Dev &d, int which, double r, hipStream_t s) {
+    launch_copy_point(d, which, d.gx, d.gy, s);
+    launch_spmv_A(d, d.gx, d.gax, s);
+    launch_spmv_T(d, d.gy, d.gaty, s);
+    const int g = red_grid((long long)d.n + d.m);
+    hipLaunchKernelGGL(k_dist_partials, dim3(g), dim3(kWG), 0, s, d);
+    hipLaunchKernelGGL(k_dist_arm, dim3(1), dim3(kWG), 0, s, d, g, r);
+    GapElems e = gap_elems(d, d.gx, d.gy, d.gax, d.gaty);
+    run_tr(e, (long long)d.n + d.m, &d.st->tr[0], d.tr[0], nullptr, s);
+}
+
+}  // namespace pdhg

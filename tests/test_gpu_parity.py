@@ -1,0 +1,385 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on
+the same seeded inputs.
+
+Tolerances: iterates match to a relative 1e-10 (norm of the difference
+over the norm of the oracle's iterate) over the first 1000 iterations, the
+bar the spec workload sets; scalars that are sums of many rounded
+terms (KKT parts, rho) match to 1e-9 relative; integer work (transpose,
+restart decisions, iteration counts) matches exactly.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_12715_amd import lpgen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2105_12715_amd import _lib
+    _lib.load(build_if_missing=False)
+    return _lib
+
+
+def rel(a, b):
+    a = np.asarray(a, float)
+    b = np.asarray(b, float)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def cases():
+    return {
+        "small50x100": lambda: lpgen.small_dense(1),
+        "ge_rows": lambda: lpgen.bernoulli_lp(11, 30, 60, 0.15, lpgen.BOX01, ge_frac=0.4),
+        "mixed_inf": lambda: lpgen.column_count_lp(13, 600, 1300, per_col=5,
+                                                   bounds="mixed_inf", ge_frac=0.5),
+        "powerlaw": lambda: lpgen.column_count_lp(3, 3000, 7000, counts="powerlaw2",
+                                                  values="loguniform", bounds="mix"),
+        "medium20kx50k": lambda: lpgen.medium(2),
+    }
+
+
+_CACHE = {}
+
+
+def get_case(name):
+    if name not in _CACHE:
+        _CACHE[name] = cases()[name]()
+    return _CACHE[name]
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+# ------------------------------------------------------------ building ---
+
+@pytest.mark.parametrize("name", ["small50x100", "mixed_inf", "powerlaw", "medium20kx50k"])
+def test_transpose_is_exact(lib, name):
+    lp = get_case(name)
+    _say("transpose", name)
+    s = lib.Solver(lp, eta=0.1)
+    trp, tci, tv, perm = (to_np(t) for t in s.transpose_csr())
+    e_rp, e_ci, e_v, e_perm = oracle.transpose(lp.m, lp.n, lp.row_ptr, lp.col_idx, lp.vals)
+    np.testing.assert_array_equal(trp, e_rp)
+    np.testing.assert_array_equal(tci, e_ci)
+    np.testing.assert_array_equal(tv, e_v)
+    np.testing.assert_array_equal(perm, e_perm)
+
+
+def test_transpose_long_columns(lib):
+    """Columns longer than the LDS sort stage (4096 entries) take the
+    counting-rank path; a 9000-row LP with a few dense columns covers it."""
+    rng = np.random.default_rng(21)
+    m, n = 9000, 40
+    cnt = np.full(n, 3)
+    cnt[:3] = [8000, 4500, 5000]
+    rows, cols = lpgen._distinct_rows_per_column(rng, m, cnt)
+    vals = rng.standard_normal(rows.size)
+    lp = lpgen.planted_lp(rng, m, n, rows, cols, vals, np.zeros(n), np.ones(n))
+    _say("transpose long columns")
+    s = lib.Solver(lp, eta=0.01)
+    trp, tci, tv, perm = (to_np(t) for t in s.transpose_csr())
+    e_rp, e_ci, e_v, e_perm = oracle.transpose(lp.m, lp.n, lp.row_ptr, lp.col_idx, lp.vals)
+    np.testing.assert_array_equal(trp, e_rp)
+    np.testing.assert_array_equal(perm, e_perm)
+    np.testing.assert_array_equal(tci, e_ci)
+    np.testing.assert_array_equal(tv, e_v)
+
+
+@pytest.mark.parametrize("name", ["small50x100", "powerlaw", "medium20kx50k"])
+def test_matvec_parity(lib, name):
+    lp = get_case(name)
+    _say("matvec", name)
+    s = lib.Solver(lp, eta=0.1)
+    o = oracle.Oracle(lp, eta=0.1)
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(lp.n)
+    y = rng.standard_normal(lp.m)
+    assert rel(to_np(s.matvec(x)), o.matvec(x)) <= 1e-14
+    assert rel(to_np(s.matvec(y, transpose=True)), o.matvec_t(y)) <= 1e-14
+
+
+@pytest.mark.parametrize("name", ["small50x100", "mixed_inf", "powerlaw"])
+def test_power_iteration_step_size(lib, name):
+    lp = get_case(name)
+    _say("power", name)
+    s = lib.Solver(lp)
+    o = oracle.Oracle(lp)
+    gi, oi = s.info(), o.info()
+    assert gi["sigma_max"] == pytest.approx(oi["sigma_max"], rel=1e-9)
+    assert gi["eta"] == pytest.approx(0.9 / gi["sigma_max"], rel=1e-15)
+
+
+# ------------------------------------------------------- trust region ---
+
+def _tr_case(seed, N, inf_frac, zero_frac=0.1, atb=0.1, dup=False):
+    rng = np.random.default_rng(seed)
+    a = np.abs(rng.standard_normal(N)) * 10 ** rng.uniform(-3, 3, N)
+    d = np.abs(rng.standard_normal(N)) * 10 ** rng.uniform(-3, 3, N)
+    a[rng.random(N) < zero_frac] = 0.0
+    d[rng.random(N) < inf_frac] = np.inf
+    d[rng.random(N) < atb] = 0.0
+    if dup:
+        d = np.round(d, 1)
+        a = np.where(a > 0, 1.0, 0.0)
+    return a, d
+
+
+@pytest.mark.parametrize("seed,N,inf_frac,dup", [
+    (0, 1, 0.0, False), (1, 7, 0.3, False), (2, 1000, 0.0, False), (3, 1000, 0.5, False),
+    (4, 5000, 0.1, True), (5, 100_000, 0.2, False), (6, 1_000_000, 0.05, False),
+    (7, 300_000, 0.0, True), (8, 3, 1.0, False),
+])
+def test_trust_region_parity(lib, seed, N, inf_frac, dup):
+    a, d = _tr_case(seed, N, inf_frac, dup=dup)
+    fin = d[np.isfinite(d) & (a > 0)]
+    full = np.sqrt(np.sum(fin ** 2)) if fin.size else 1.0
+    _say("trust region", seed, N)
+    for r in [0.0, 1e-6 * full, 0.01 * full, 0.3 * full, 0.9 * full, 1.5 * full + 1.0]:
+        v_gpu, l_gpu = lib.linear_trust_region(a, d, r)
+        v_cpu, l_cpu = oracle.trust_region(a, d, r)
+        assert v_gpu == pytest.approx(v_cpu, rel=1e-11, abs=1e-300)
+        if np.isfinite(l_cpu):
+            assert l_gpu == pytest.approx(l_cpu, rel=1e-9)
+        else:
+            assert np.isinf(l_gpu)
+
+
+def test_trust_region_edge_cases(lib):
+    assert lib.linear_trust_region(np.zeros(0), np.zeros(0), 1.0)[0] == 0.0
+    assert lib.linear_trust_region([0.0, 0.0], [1.0, np.inf], 2.0)[0] == 0.0
+    v, lam = lib.linear_trust_region([3.0, 4.0], [np.inf, np.inf], 2.0)
+    assert v == pytest.approx(10.0) and lam == pytest.approx(0.4)
+    v, lam = lib.linear_trust_region([1.0, 1.0], [0.5, 0.5], 5.0)
+    assert v == pytest.approx(1.0) and np.isinf(lam)
+    with pytest.raises(lib.PdhgError):
+        lib.linear_trust_region([1.0, -1.0], [1.0, 1.0], 1.0)
+    with pytest.raises(lib.PdhgError):
+        lib.linear_trust_region([1.0, np.nan], [1.0, 1.0], 1.0)
+
+
+# ---------------------------------------------------------- iterates ---
+
+def _pair(lp, mode, eta=None, **kw):
+    if eta is None:
+        eta = oracle.Oracle(lp).info()["eta"]
+    o = oracle.Oracle(lp, eta=eta, mode=mode, **kw)
+    from paper_2105_12715_amd import _lib
+    s = _lib.Solver(lp, eta=eta, restart_mode=mode, **kw)
+    return o, s
+
+
+def _compare_points(o, s, tol=1e-10):
+    for which in (0, 1, 2):
+        xo, yo = o.get(which)
+        xg, yg = (to_np(t) for t in s.get_iterate(which))
+        zo = np.concatenate([xo, yo])
+        zg = np.concatenate([xg, yg])
+        assert rel(zg, zo) <= tol, (which, rel(zg, zo))
+
+
+@pytest.mark.parametrize("name", ["small50x100", "ge_rows", "mixed_inf", "powerlaw",
+                                  "medium20kx50k"])
+def test_iterates_no_restart_first_1000(lib, name):
+    lp = get_case(name)
+    _say("iterates none", name)
+    o, s = _pair(lp, oracle.MODE_NONE)
+    done = 0
+    for k in [1, 2, 3, 10, 29, 30, 31, 100, 500, 1000]:
+        o.step(k - done)
+        s.step(k - done)
+        done = k
+        _compare_points(o, s)
+    assert s.info()["k"] == 1000 and s.info()["t"] == 1000
+
+
+@pytest.mark.parametrize("name,mode", [
+    ("small50x100", oracle.MODE_ADAPTIVE), ("ge_rows", oracle.MODE_ADAPTIVE),
+    ("mixed_inf", oracle.MODE_ADAPTIVE), ("powerlaw", oracle.MODE_ADAPTIVE),
+    ("medium20kx50k", oracle.MODE_ADAPTIVE), ("small50x100", oracle.MODE_FLEXIBLE),
+    ("mixed_inf", oracle.MODE_FLEXIBLE),
+])
+def test_iterates_with_restarts_first_1000(lib, name, mode):
+    """Same iterates and the same check records over 1000 iterations of the
+    solve loop (checks every 30), compared after every stretch."""
+    lp = get_case(name)
+    _say("iterates restarts", name, mode)
+    o, s = _pair(lp, mode)
+    done = 0
+    for k in [29, 30, 60, 61, 150, 300, 600, 1000]:
+        o.solve(k - done, 0.0)
+        s.solve(k - done, 0.0)
+        done = k
+        _compare_points(o, s)
+    lo, lg = o.log(), s.check_log()
+    assert lo.shape == lg.shape == (33, 14)
+    np.testing.assert_array_equal(lg[:, [0, 1, 2, 9, 10, 11]], lo[:, [0, 1, 2, 9, 10, 11]])
+    for col in (3, 4, 5, 6, 7, 8, 12):
+        np.testing.assert_allclose(lg[:, col], lo[:, col], rtol=1e-9, atol=1e-300)
+    assert lo[:, 9].sum() >= 2
+
+
+def test_fixed_length_restarts(lib):
+    lp = get_case("ge_rows")
+    _say("fixed restarts")
+    o, s = _pair(lp, oracle.MODE_FIXED, fixed_len=64)
+    done = 0
+    for k in [63, 64, 65, 200, 640, 1000]:
+        o.solve(k - done, 0.0)
+        s.solve(k - done, 0.0)
+        done = k
+        _compare_points(o, s)
+    assert s.info()["restarts"] == o.info()["restarts"] == 1000 // 64
+
+
+# -------------------------------------------------------- KKT and gap ---
+
+@pytest.mark.parametrize("name", ["small50x100", "ge_rows", "mixed_inf", "powerlaw"])
+def test_kkt_and_gap_parity(lib, name):
+    lp = get_case(name)
+    _say("kkt gap", name)
+    o, s = _pair(lp, oracle.MODE_NONE)
+    o.step(77)
+    s.step(77)
+    for which in (0, 1, 2):
+        ko = o.kkt(which)
+        kg = s.kkt(which)
+        assert kg["kkt_rel"] == pytest.approx(ko[0], rel=1e-9)
+        assert kg["primal_res"] == pytest.approx(ko[1], rel=1e-9, abs=1e-13)
+        assert kg["dual_res"] == pytest.approx(ko[2], rel=1e-9, abs=1e-13)
+        assert kg["pobj"] == pytest.approx(ko[3], rel=1e-11, abs=1e-11)
+        assert kg["dobj"] == pytest.approx(ko[4], rel=1e-11, abs=1e-11)
+        assert kg["kkt_paper_abs"] == pytest.approx(ko[5], rel=1e-9)
+        assert kg["kkt_max_abs"] == pytest.approx(ko[6], rel=1e-9)
+    for which in (0, 1):
+        for r in (-1.0, 1e-3, 1.0, 1e3):
+            go, ro, lo_ = o.gap(which, r)
+            gg, rg, lg_ = s.gap(which, r)
+            assert rg == pytest.approx(ro, rel=1e-12)
+            assert gg == pytest.approx(go, rel=1e-9, abs=1e-300)
+
+
+# ------------------------------------------------------------- solves ---
+
+@pytest.mark.parametrize("name,budget", [("small50x100", 200_000), ("ge_rows", 200_000),
+                                         ("mixed_inf", 400_000)])
+def test_solve_to_1e8_matches_oracle(lib, name, budget):
+    lp = get_case(name)
+    _say("solve", name)
+    o, s = _pair(lp, oracle.MODE_ADAPTIVE)
+    ro = o.solve(budget, 1e-8)
+    rg = s.solve(budget, 1e-8)
+    assert ro["status"] == 0 and rg["status"] == 0
+    assert rg["k"] == ro["k"] and rg["restarts"] == ro["restarts"] and rg["which"] == ro["which"]
+    assert rg["kkt"] <= 1e-8
+    x, y = (to_np(t) for t in s.get_iterate(3))
+    # the oracle's own KKT at the GPU's answer
+    assert oracle.Oracle(lp, eta=0.1).kkt_at(x, y)[0] <= 1.0001e-8
+    assert rg["pobj"] == pytest.approx(lp.objective_star(), rel=1e-6, abs=1e-6)
+
+
+def test_medium_solve_to_1e8(lib):
+    """The 20,000 x 50,000 workload: iterate until relative KKT <= 1e-8 on
+    both sides; same iteration count and restarts."""
+    lp = get_case("medium20kx50k")
+    _say("solve medium")
+    o, s = _pair(lp, oracle.MODE_ADAPTIVE)
+    rg = s.solve(300_000, 1e-8)
+    _say("gpu", rg)
+    assert rg["status"] == 0 and rg["kkt"] <= 1e-8
+    x, y = (to_np(t) for t in s.get_iterate(3))
+    assert oracle.Oracle(lp, eta=0.1).kkt_at(x, y)[0] <= 1.0001e-8
+    assert rg["pobj"] == pytest.approx(lp.objective_star(), rel=1e-6)
+
+
+def test_graph_replay_matches_eager(lib):
+    """pdhg_solve replays a recorded graph; the same iterations driven by
+    pdhg_step + pdhg_restart_check give bit-identical iterates, across
+    several replays with eager work in between."""
+    lp = get_case("mixed_inf")
+    _say("graph vs eager")
+    eta = oracle.Oracle(lp).info()["eta"]
+    from paper_2105_12715_amd import _lib
+    a = _lib.Solver(lp, eta=eta)
+    b = _lib.Solver(lp, eta=eta)
+    for rep in range(4):
+        a.solve(300, 0.0)
+        for _ in range(10):
+            b.step(30)
+            b.check(0.0)
+        xa, ya = a.get_iterate(0)
+        xb, yb = b.get_iterate(0)
+        torch.cuda.synchronize()
+        assert torch.equal(xa, xb) and torch.equal(ya, yb)
+        _ = a.kkt(1)  # eager work between replays
+    assert a.info()["restarts"] == b.info()["restarts"]
+
+
+def test_runs_are_deterministic(lib):
+    lp = get_case("powerlaw")
+    _say("determinism")
+    eta = oracle.Oracle(lp).info()["eta"]
+    from paper_2105_12715_amd import _lib
+    outs = []
+    for _ in range(2):
+        s = _lib.Solver(lp, eta=eta)
+        s.solve(600, 0.0)
+        outs.append([t.clone() for t in s.get_iterate(0)])
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+# ------------------------------------------------------ edge cases ---
+
+def test_lp_without_rows_and_empty_columns(lib):
+    """m = 0 (only bounds) and columns with no entries."""
+    from tests.lp_cases import lp_from_dense
+    _say("edge m=0")
+    lp = lp_from_dense(np.zeros((0, 4)), [], [1.0, -1.0, 0.5, 0.0], [0, 0, -1, -2],
+                       [1, 1, 1, 2])
+    o, s = _pair(lp, oracle.MODE_ADAPTIVE, eta=0.5)
+    ro, rg = o.solve(600, 1e-9), s.solve(600, 1e-9)
+    assert rg["status"] == ro["status"] and rg["k"] == ro["k"]
+    _compare_points(o, s, tol=1e-14)
+    A = np.array([[1.0, 0, 2.0, 0], [0, 0, -1.0, 0], [3.0, 0, 0, 0]])
+    lp = lp_from_dense(A, [1.0, -0.5, 2.0], [1.0, 1.0, 1.0, -1.0], [0, 0, 0, -1], [5, 5, 5, 3],
+                       kind=[0, 1, 0])
+    o, s = _pair(lp, oracle.MODE_FLEXIBLE)
+    o.solve(900, 0.0)
+    s.solve(900, 0.0)
+    _compare_points(o, s)
+
+
+def test_invalid_lp_is_rejected(lib):
+    _say("invalid")
+    lp = lpgen.small_dense(3)
+    bad = lpgen.LP(**{**lp.__dict__, "col_idx": lp.col_idx.copy()})
+    bad.col_idx[5] = lp.n + 3
+    with pytest.raises(lib.PdhgError) as e:
+        lib.Solver(bad, eta=0.1)
+    assert e.value.code == lib.E_INVALID
+    bad = lpgen.LP(**{**lp.__dict__, "row_ptr": lp.row_ptr.copy()})
+    bad.row_ptr[3], bad.row_ptr[4] = bad.row_ptr[4], bad.row_ptr[3] + 1
+    with pytest.raises(lib.PdhgError):
+        lib.Solver(bad, eta=0.1)
+    bad = lpgen.LP(**{**lp.__dict__, "l": lp.l.copy()})
+    bad.l[0] = 2.0
+    with pytest.raises(lib.PdhgError):
+        lib.Solver(bad, eta=0.1)
+    bad = lpgen.LP(**{**lp.__dict__, "vals": lp.vals.copy()})
+    bad.vals[0] = np.nan
+    with pytest.raises(lib.PdhgError):
+        lib.Solver(bad, eta=0.1)
