@@ -42,7 +42,8 @@ size_t tr_work_bytes(int64_t N) {
     b += al(sizeof(unsigned int) * 2 * kBuckets);
     b += al(sizeof(double) * 2 * kBuckets) * 2;
     b += al(sizeof(double) * kRedBlocks * 4);
-    size_t n1 = (size_t)(N > 0 ? N : 1);
+    b += al(sizeof(unsigned int) * kRedBlocks) + al(sizeof(unsigned int) * (kRedBlocks + 1));
+    size_t n1 = (size_t)(N > 0 ? N : 1) + (size_t)kRedBlocks * kWG;
     b += al(sizeof(unsigned long long) * n1);
     b += al(sizeof(double) * n1) * 2;
     return b;
@@ -50,7 +51,7 @@ size_t tr_work_bytes(int64_t N) {
 
 void carve_tr(char *base, int64_t N, TRWork *w) {
     size_t o = 0;
-    size_t n1 = (size_t)(N > 0 ? N : 1);
+    size_t n1 = (size_t)(N > 0 ? N : 1) + (size_t)kRedBlocks * kWG;
     w->hcnt = (unsigned int *)(base + o);
     o += al(sizeof(unsigned int) * 2 * kBuckets);
     w->hD = (double *)(base + o);
@@ -59,6 +60,10 @@ void carve_tr(char *base, int64_t N, TRWork *w) {
     o += al(sizeof(double) * 2 * kBuckets);
     w->part = (double *)(base + o);
     o += al(sizeof(double) * kRedBlocks * 4);
+    w->ccount = (unsigned int *)(base + o);
+    o += al(sizeof(unsigned int) * kRedBlocks);
+    w->coff = (unsigned int *)(base + o);
+    o += al(sizeof(unsigned int) * (kRedBlocks + 1));
     w->ckey = (unsigned long long *)(base + o);
     o += al(sizeof(unsigned long long) * n1);
     w->ca = (double *)(base + o);

@@ -9,8 +9,8 @@
 namespace pdhg {
 
 constexpr int kWG = 256;             // threads per workgroup (4 wave64)
-constexpr int kUnits = 2048;         // SpMV block size in rows + nnz
-constexpr int kLdsProducts = 4096;   // products staged in LDS per SpMV block
+constexpr int kUnits = 1024;         // SpMV block size in rows + nnz
+constexpr int kLdsProducts = 2048;   // products staged in LDS per SpMV block
 constexpr int kRedBlocks = 1024;     // max blocks of a partial-sum reduction
 constexpr int kKktSums = 14;         // partial sums of the KKT / radius pass
 constexpr int kBuckets = 2048;       // radix buckets of the multiplier search
@@ -37,9 +37,9 @@ struct TRState {
     int mode;              // TR_*
     int level;             // radix level reached
     unsigned int count;    // elements inside the bracket
-    unsigned int ncomp;    // compacted elements
+    unsigned int ncomp;    // compacted elements (after the level-1 pass)
     int nan_seen;
-    int pad;
+    int cap;               // compaction region length per block
 };
 
 struct DevState {
@@ -69,8 +69,10 @@ struct TRWork {
     unsigned int *hcnt;    // [2][kBuckets]
     double *hD, *hA;       // [2][kBuckets]
     double *part;          // [kRedBlocks][4]
-    unsigned long long *ckey;  // [N] compacted keys
-    double *ca, *cd;       // [N]
+    unsigned int *ccount;  // [kRedBlocks] compacted elements per block
+    unsigned int *coff;    // [kRedBlocks + 1] their exclusive prefix
+    unsigned long long *ckey;  // [N + kRedBlocks * kWG] compacted keys, one region per block
+    double *ca, *cd;       // same length
 };
 
 // Device-side view of one LP and its solver state.

@@ -10,10 +10,11 @@
 // half-step, so each iteration streams A and A' once and gathers x+ and y
 // once per stored entry.
 //
-// SpMV schedule: rows are cut into merge-path blocks of kUnits rows+entries
-// (a row belongs to the block its start falls in), so each workgroup owns
-// whole rows and the per-row epilogue is fused.  A block stages its
-// products value * vector[col] in LDS with coalesced loads, then groups of
+// SpMV schedule: rows are cut into merge-path blocks of kUnits (1024)
+// rows+entries (a row belongs to the block its start falls in), so each
+// workgroup owns whole rows and the per-row epilogue is fused.  A block
+// stages its products value * vector[col] in 16 KB of LDS with coalesced
+// non-temporal loads of the matrix, then groups of
 // L lanes (L a power of two near the block's mean row length) reduce one
 // row each with a fixed butterfly.  Every sum has a fixed order, so results
 // are reproducible run to run.  Blocks whose entries exceed the LDS stage
@@ -44,7 +45,11 @@ __device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const int 
     const int nb = p1 - p0;
     const int R = r1 - r0;
     if (nb <= kLdsProducts) {
-        for (int e = tid; e < nb; e += kWG) lds[e] = v[p0 + e] * xin[ci[p0 + e]];
+        // matrix streams are read once per launch: non-temporal loads keep
+        // them from evicting the gathered vector from L2 and the MALL
+        for (int e = tid; e < nb; e += kWG)
+            lds[e] = __builtin_nontemporal_load(v + p0 + e) *
+                     xin[__builtin_nontemporal_load(ci + p0 + e)];
         __syncthreads();
         const int avg = nb / R;
         int L = 1;
@@ -63,7 +68,8 @@ __device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const int 
         const int wave = tid >> 6, lane = tid & 63;
         for (int row = r0 + wave; row < r1; row += kWG / 64) {
             double s = 0.0;
-            for (int p = rp[row] + lane; p < rp[row + 1]; p += 64) s += v[p] * xin[ci[p]];
+            for (int p = rp[row] + lane; p < rp[row + 1]; p += 64)
+                s += __builtin_nontemporal_load(v + p) * xin[__builtin_nontemporal_load(ci + p)];
             s = wave_sum(s);
             if (lane == 0) epi(row, s);
         }

@@ -12,9 +12,11 @@
 // The search is bisection on the multiplier, 2048 candidates at a time:
 // the keys are the IEEE bit patterns of the breakpoints d_i / a_i, which
 // order like the values for non-negative doubles.  Level 0 histograms the
-// 11 exponent bits over all N coordinates, level 1 the next 11 bits over
-// the coordinates still in the bracket (and compacts them), and levels 2-5
-// finish on the compacted list inside one workgroup.  At each level the
+// 11 exponent bits over all N coordinates; level 1 histograms the next 11
+// bits over the coordinates still in the bracket and each block copies
+// them into its own region of a compaction buffer; levels 2 and 3 run over
+// the compacted regions on all blocks while the bracket holds more than
+// 65536 coordinates, and one workgroup finishes the remaining levels.  At each level the
 // bracket moves to the last bucket whose lower end keeps f <= r^2.  Once
 // the bracket holds no breakpoint (or one repeated value), every
 // coordinate is either clamped (key <= klo) or free, and a deterministic
@@ -246,6 +248,14 @@ __global__ __launch_bounds__(kWG) void k_tr_hist0(E e, TRState *ts, TRWork w, co
     }
 }
 
+__device__ void zero_hist(const TRWork &w, int slot) {
+    for (int b = threadIdx.x; b < kBuckets; b += kWG) {
+        w.hcnt[slot * kBuckets + b] = 0u;
+        w.hD[slot * kBuckets + b] = 0.0;
+        w.hA[slot * kBuckets + b] = 0.0;
+    }
+}
+
 __global__ __launch_bounds__(kWG) void k_tr_decide0(TRState *ts, TRWork w, int nb, const int *gate) {
     if (gate && !*gate) return;
     if (ts->mode != TR_SEARCH || ts->level != 0) return;
@@ -281,12 +291,7 @@ __global__ __launch_bounds__(kWG) void k_tr_decide0(TRState *ts, TRWork w, int n
     }
     __syncthreads();
     if (go) choose_bucket(sts, w.hcnt, w.hD, w.hA, kBuckets, 0, cs);
-    // clear the level-1 histogram and the compaction counter
-    for (int b = threadIdx.x; b < kBuckets; b += kWG) {
-        w.hcnt[kBuckets + b] = 0u;
-        w.hD[kBuckets + b] = 0.0;
-        w.hA[kBuckets + b] = 0.0;
-    }
+    zero_hist(w, 1);
     __syncthreads();
     if (threadIdx.x == 0) {
         sts.ncomp = 0u;
@@ -294,51 +299,42 @@ __global__ __launch_bounds__(kWG) void k_tr_decide0(TRState *ts, TRWork w, int n
     }
 }
 
-// level 1: next 11 bits over the bracket's coordinates, which are compacted
+// Level 1 over all coordinates: histogram of bits 51..41 of the bracket's
+// keys, and each block copies its bracket members into its own region of
+// the compaction buffer (no global counter).
 template <class E>
-__global__ __launch_bounds__(kWG) void k_tr_hist1(E e, TRState *ts, TRWork w, const int *gate) {
+__global__ __launch_bounds__(kWG) void k_tr_pass1(E e, TRState *ts, TRWork w, const int *gate,
+                                                  int cap) {
     if (gate && !*gate) return;
     if (ts->mode != TR_SEARCH || ts->level != 1) return;
     __shared__ unsigned int scnt[kBuckets];
     __shared__ double sD[kBuckets], sA[kBuckets];
+    __shared__ unsigned int nloc;
     for (int b = threadIdx.x; b < kBuckets; b += kWG) {
         scnt[b] = 0u;
         sD[b] = 0.0;
         sA[b] = 0.0;
     }
+    if (threadIdx.x == 0) nloc = 0u;
     __syncthreads();
     const unsigned long long top = ts->prefix >> 52;
-    const int lane = threadIdx.x & 63;
+    const size_t region = (size_t)blockIdx.x * (size_t)cap;
     const long long N = e.size();
-    for (long long base = (long long)blockIdx.x * kWG; base < N; base += (long long)gridDim.x * kWG) {
-        const long long i = base + threadIdx.x;
-        bool take = false;
-        double a = 0.0, d = 0.0;
-        unsigned long long key = 0ull;
-        if (i < N) {
-            e.get(i, a, d);
-            if (!bad_pair(a, d) && a > 0.0) {
-                key = key_of(a, d);
-                take = (key >> 52) == top;
-            }
-        }
-        if (take) {
-            const int b = (int)((key >> 41) & (kBuckets - 1));
-            atomicAdd(&scnt[b], 1u);
-            atomicAdd(&sD[b], d * d);
-            atomicAdd(&sA[b], a * a);
-        }
-        const unsigned long long mask = __ballot(take);
-        const int cnt = __popcll(mask);
-        unsigned int slot = 0u;
-        if (lane == 0 && cnt) slot = atomicAdd(&ts->ncomp, (unsigned int)cnt);
-        slot = __shfl(slot, 0, 64);
-        if (take) {
-            const unsigned int off = (unsigned int)__popcll(mask & ((1ull << lane) - 1ull));
-            w.ckey[slot + off] = key;
-            w.ca[slot + off] = a;
-            w.cd[slot + off] = d;
-        }
+    for (long long i = (long long)blockIdx.x * kWG + threadIdx.x; i < N;
+         i += (long long)gridDim.x * kWG) {
+        double a, d;
+        e.get(i, a, d);
+        if (bad_pair(a, d) || !(a > 0.0)) continue;
+        const unsigned long long key = key_of(a, d);
+        if ((key >> 52) != top) continue;
+        const int b = (int)((key >> 41) & (kBuckets - 1));
+        atomicAdd(&scnt[b], 1u);
+        atomicAdd(&sD[b], d * d);
+        atomicAdd(&sA[b], a * a);
+        const unsigned int slot = atomicAdd(&nloc, 1u);
+        w.ckey[region + slot] = key;
+        w.ca[region + slot] = a;
+        w.cd[region + slot] = d;
     }
     __syncthreads();
     for (int b = threadIdx.x; b < kBuckets; b += kWG) {
@@ -348,20 +344,127 @@ __global__ __launch_bounds__(kWG) void k_tr_hist1(E e, TRState *ts, TRWork w, co
             atomicAdd(&w.hA[kBuckets + b], sA[b]);
         }
     }
+    if (threadIdx.x == 0) w.ccount[blockIdx.x] = nloc;
 }
 
-// levels 1 (decision) to 5 on the compacted list, one workgroup
-__global__ __launch_bounds__(kWG) void k_tr_finish(TRState *ts, TRWork w, const int *gate) {
+// exclusive prefix of the per-block counts (nb <= kRedBlocks = 4 * kWG)
+__device__ void scan_counts(const TRWork &w, int nb, unsigned int *sh) {
+    const int t = threadIdx.x;
+    unsigned int loc[4];
+    unsigned int sum = 0u;
+    for (int k = 0; k < 4; ++k) {
+        const int b = 4 * t + k;
+        loc[k] = b < nb ? w.ccount[b] : 0u;
+        sum += loc[k];
+    }
+    sh[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < kWG; off <<= 1) {
+        unsigned int o = t >= off ? sh[t - off] : 0u;
+        __syncthreads();
+        sh[t] += o;
+        __syncthreads();
+    }
+    unsigned int run = t ? sh[t - 1] : 0u;
+    for (int k = 0; k < 4; ++k) {
+        const int b = 4 * t + k;
+        if (b < nb) w.coff[b] = run;
+        run += loc[k];
+    }
+    if (t == kWG - 1) w.coff[nb] = sh[kWG - 1];  // the total (nb may equal 4 * kWG)
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kWG) void k_tr_decide1(TRState *ts, TRWork w, int nb, const int *gate) {
     if (gate && !*gate) return;
     if (ts->mode != TR_SEARCH || ts->level != 1) return;
     __shared__ TRState sts;
     __shared__ ChooseShared cs;
-    __shared__ unsigned int scnt[kBuckets];
-    __shared__ double sD[kBuckets], sA[kBuckets];
+    __shared__ unsigned int shs[kWG];
     if (threadIdx.x == 0) sts = *ts;
+    scan_counts(w, nb, shs);
+    if (threadIdx.x == 0) sts.ncomp = shs[kWG - 1];  // total, still in LDS
     __syncthreads();
     choose_bucket(sts, w.hcnt + kBuckets, w.hD + kBuckets, w.hA + kBuckets, kBuckets, 1, cs);
-    const unsigned int nc = sts.ncomp;
+    zero_hist(w, 0);
+    __syncthreads();
+    if (threadIdx.x == 0) *ts = sts;
+}
+
+// Levels 2 and 3 across all blocks while the bracket is still large: block b
+// histograms the members of its own compaction region.
+constexpr unsigned int kFinishMax = 65536;
+
+__global__ __launch_bounds__(kWG) void k_tr_cpass(TRState *ts, TRWork w, const int *gate, int cap,
+                                                  int level) {
+    if (gate && !*gate) return;
+    if (ts->mode != TR_SEARCH || ts->level != level || ts->count <= kFinishMax) return;
+    __shared__ unsigned int scnt[kBuckets];
+    __shared__ double sD[kBuckets], sA[kBuckets];
+    for (int b = threadIdx.x; b < kBuckets; b += kWG) {
+        scnt[b] = 0u;
+        sD[b] = 0.0;
+        sA[b] = 0.0;
+    }
+    __syncthreads();
+    const int shift = kShift[level], above = kShift[level - 1];
+    const unsigned long long want = ts->prefix >> above;
+    const size_t region = (size_t)blockIdx.x * (size_t)cap;
+    unsigned int cnt = w.ccount[blockIdx.x];
+    if (cnt > (unsigned int)cap) cnt = (unsigned int)cap;
+    for (unsigned int q = threadIdx.x; q < cnt; q += kWG) {
+        const unsigned long long key = w.ckey[region + q];
+        if ((key >> above) != want) continue;
+        const int b = (int)((key >> shift) & (kBuckets - 1));
+        const double a = w.ca[region + q], d = w.cd[region + q];
+        atomicAdd(&scnt[b], 1u);
+        atomicAdd(&sD[b], d * d);
+        atomicAdd(&sA[b], a * a);
+    }
+    __syncthreads();
+    const int hs = level & 1;
+    for (int b = threadIdx.x; b < kBuckets; b += kWG) {
+        if (scnt[b]) {
+            atomicAdd(&w.hcnt[hs * kBuckets + b], scnt[b]);
+            atomicAdd(&w.hD[hs * kBuckets + b], sD[b]);
+            atomicAdd(&w.hA[hs * kBuckets + b], sA[b]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_tr_cdecide(TRState *ts, TRWork w, const int *gate,
+                                                    int level) {
+    if (gate && !*gate) return;
+    if (ts->mode != TR_SEARCH || ts->level != level || ts->count <= kFinishMax) return;
+    __shared__ TRState sts;
+    __shared__ ChooseShared cs;
+    if (threadIdx.x == 0) sts = *ts;
+    __syncthreads();
+    const int hs = level & 1;
+    choose_bucket(sts, w.hcnt + hs * kBuckets, w.hD + hs * kBuckets, w.hA + hs * kBuckets,
+                  kBuckets, level, cs);
+    zero_hist(w, 1 - hs);
+    __syncthreads();
+    if (threadIdx.x == 0) *ts = sts;
+}
+
+// remaining levels on the compacted list, one workgroup
+__global__ __launch_bounds__(kWG) void k_tr_finish(TRState *ts, TRWork w, const int *gate, int cap,
+                                                   int nb) {
+    if (gate && !*gate) return;
+    if (ts->mode != TR_SEARCH) return;
+    __shared__ TRState sts;
+    __shared__ ChooseShared cs;
+    __shared__ unsigned int scnt[kBuckets];
+    __shared__ double sD[kBuckets], sA[kBuckets];
+    __shared__ unsigned int off[kRedBlocks + 1];
+    if (threadIdx.x == 0) sts = *ts;
+    for (int b = threadIdx.x; b <= nb; b += kWG) off[b] = w.coff[b];
+    __syncthreads();
+    // never walk past the compaction buffer, whatever the counts say
+    unsigned int total = off[nb];
+    const unsigned long long room = (unsigned long long)nb * (unsigned long long)cap;
+    if ((unsigned long long)total > room) total = (unsigned int)room;
     while (sts.mode == TR_SEARCH) {
         const int level = sts.level;
         const int shift = kShift[level];
@@ -374,15 +477,24 @@ __global__ __launch_bounds__(kWG) void k_tr_finish(TRState *ts, TRWork w, const 
             sA[b] = 0.0;
         }
         __syncthreads();
-        for (unsigned int e = threadIdx.x; e < nc; e += kWG) {
-            const unsigned long long key = w.ckey[e];
-            if ((key >> above) == want) {
-                const int b = (int)((key >> shift) & (unsigned long long)(nbuck - 1));
-                const double a = w.ca[e], d = w.cd[e];
-                atomicAdd(&scnt[b], 1u);
-                atomicAdd(&sD[b], d * d);
-                atomicAdd(&sA[b], a * a);
+        for (unsigned int idx = threadIdx.x; idx < total; idx += kWG) {
+            // region holding the idx-th compacted element: last b with off[b] <= idx
+            int lo = 0, hi = nb - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (off[mid] <= idx) lo = mid;
+                else hi = mid - 1;
             }
+            const unsigned int within = idx - off[lo];
+            if (within >= (unsigned int)cap) continue;
+            const size_t at = (size_t)lo * (size_t)cap + within;
+            const unsigned long long key = w.ckey[at];
+            if ((key >> above) != want) continue;
+            const int b = (int)((key >> shift) & (unsigned long long)(nbuck - 1));
+            const double a = w.ca[at], d = w.cd[at];
+            atomicAdd(&scnt[b], 1u);
+            atomicAdd(&sD[b], d * d);
+            atomicAdd(&sA[b], a * a);
         }
         __syncthreads();
         choose_bucket(sts, scnt, sD, sA, nbuck, level, cs);
@@ -448,10 +560,18 @@ template <class E>
 static void run_tr(const E &e, long long N, TRState *ts, const TRWork &w, const int *gate,
                    hipStream_t s) {
     const int g = red_grid(N);
+    // longest run of coordinates one block visits in a grid-stride pass
+    const long long per = (N + (long long)g * kWG - 1) / ((long long)g * kWG);
+    const int cap = (int)(per * kWG);
     hipLaunchKernelGGL(k_tr_hist0<E>, dim3(g), dim3(kWG), 0, s, e, ts, w, gate);
     hipLaunchKernelGGL(k_tr_decide0, dim3(1), dim3(kWG), 0, s, ts, w, g, gate);
-    hipLaunchKernelGGL(k_tr_hist1<E>, dim3(g), dim3(kWG), 0, s, e, ts, w, gate);
-    hipLaunchKernelGGL(k_tr_finish, dim3(1), dim3(kWG), 0, s, ts, w, gate);
+    hipLaunchKernelGGL(k_tr_pass1<E>, dim3(g), dim3(kWG), 0, s, e, ts, w, gate, cap);
+    hipLaunchKernelGGL(k_tr_decide1, dim3(1), dim3(kWG), 0, s, ts, w, g, gate);
+    for (int level = 2; level <= 3; ++level) {
+        hipLaunchKernelGGL(k_tr_cpass, dim3(g), dim3(kWG), 0, s, ts, w, gate, cap, level);
+        hipLaunchKernelGGL(k_tr_cdecide, dim3(1), dim3(kWG), 0, s, ts, w, gate, level);
+    }
+    hipLaunchKernelGGL(k_tr_finish, dim3(1), dim3(kWG), 0, s, ts, w, gate, cap, g);
     hipLaunchKernelGGL(k_tr_final_partials<E>, dim3(g), dim3(kWG), 0, s, e, ts, w, gate);
     hipLaunchKernelGGL(k_tr_final, dim3(1), dim3(kWG), 0, s, ts, w, g, gate);
 }
