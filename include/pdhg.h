@@ -254,6 +254,38 @@ int pdhg_linear_trust_region(int64_t N, const double *a, const double *d,
                              double r, void *workspace, size_t workspace_bytes,
                              void *stream, double *value, double *lambda);
 
+/*
+ * Batched solver: `count` independent LPs advanced by the same launches
+ * (the LPs are concatenated into one block-diagonal system on the device).
+ * Each LP keeps its own step sizes (power iteration per LP when its
+ * eta <= 0), iteration and restart counters, restart state and stopping
+ * test; an LP that reaches tol stops changing while the others continue.
+ * `lps` and `prm` are host arrays of `count` structs (prm may be NULL for
+ * defaults); restart_mode (none, adaptive or flexible), check_period and
+ * kkt_kind must be equal across the batch.  Workspace and stream rules are
+ * those of pdhg_create.  Sizes: host arrays m, n, nnz of `count` entries.
+ */
+typedef struct pdhg_batch_handle pdhg_batch_t;
+size_t pdhg_batch_workspace_bytes(int32_t count, const int64_t *m, const int64_t *n,
+                                  const int64_t *nnz);
+int pdhg_batch_create(int32_t count, const pdhg_lp *lps, const pdhg_params *prm,
+                      void *workspace, size_t workspace_bytes, void *stream,
+                      pdhg_batch_t **out);
+/* `iters` PDHG iterations of every LP that has not converged (no checks). */
+int pdhg_batch_step(pdhg_batch_t *h, int64_t iters);
+/* Restarted PDHG on all LPs for up to max_iters more iterations with the
+ * checks of pdhg_solve; returns PDHG_OK when every LP met tol.  results:
+ * host array of `count` (may be NULL).  Graph-replayed like pdhg_solve. */
+int pdhg_batch_solve(pdhg_batch_t *h, int64_t max_iters, double tol, pdhg_result *results);
+/* Held point (PDHG_POINT_*) of LP `index` into device x (n_index), y (m_index). */
+int pdhg_batch_get_iterate(pdhg_batch_t *h, int32_t index, int32_t which, double *x,
+                           double *y);
+int pdhg_batch_get_info(pdhg_batch_t *h, int32_t index, pdhg_info *out);
+/* Last check records of LP `index` (the last 512 are kept). */
+int pdhg_batch_get_check_log(pdhg_batch_t *h, int32_t index, pdhg_check_record *out,
+                             int64_t max, int64_t *count);
+void pdhg_batch_destroy(pdhg_batch_t *h);
+
 /* Static text for a return code. */
 const char *pdhg_strerror(int code);
 

@@ -127,6 +127,22 @@ def load(build_if_missing: bool = True):
     L.pdhg_trust_region_workspace_bytes.restype = sz
     L.pdhg_linear_trust_region.argtypes = [i64, P, P, d, P, sz, P, C.POINTER(d), C.POINTER(d)]
     L.pdhg_linear_trust_region.restype = C.c_int
+    L.pdhg_batch_workspace_bytes.argtypes = [i32, P, P, P]
+    L.pdhg_batch_workspace_bytes.restype = sz
+    L.pdhg_batch_create.argtypes = [i32, P, P, P, sz, P, C.POINTER(P)]
+    L.pdhg_batch_create.restype = C.c_int
+    L.pdhg_batch_step.argtypes = [P, i64]
+    L.pdhg_batch_step.restype = C.c_int
+    L.pdhg_batch_solve.argtypes = [P, i64, d, P]
+    L.pdhg_batch_solve.restype = C.c_int
+    L.pdhg_batch_get_iterate.argtypes = [P, i32, i32, P, P]
+    L.pdhg_batch_get_iterate.restype = C.c_int
+    L.pdhg_batch_get_info.argtypes = [P, i32, C.POINTER(Info)]
+    L.pdhg_batch_get_info.restype = C.c_int
+    L.pdhg_batch_get_check_log.argtypes = [P, i32, P, i64, C.POINTER(i64)]
+    L.pdhg_batch_get_check_log.restype = C.c_int
+    L.pdhg_batch_destroy.argtypes = [P]
+    L.pdhg_batch_destroy.restype = None
     L.pdhg_strerror.argtypes = [C.c_int]
     L.pdhg_strerror.restype = C.c_char_p
     _lib = L
@@ -313,6 +329,115 @@ class Solver:
                "pdhg_get_transpose")
         k = self.nnz
         return trp, tci[:k], tv[:k], perm[:k]
+
+
+class _DeviceLP:
+    """Device tensors of one LP and its C struct."""
+
+    def __init__(self, lp, dev):
+        import torch
+        f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+        i32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.int32)).to(dev)
+        self.m, self.n = int(lp.m), int(lp.n)
+        self.nnz = int(np.asarray(lp.row_ptr)[-1])
+        self.row_ptr = i32(lp.row_ptr)
+        self.col_idx = i32(lp.col_idx) if self.nnz else torch.zeros(1, dtype=torch.int32, device=dev)
+        self.vals = f64(lp.vals) if self.nnz else torch.zeros(1, dtype=torch.float64, device=dev)
+        self.c, self.l, self.u = f64(lp.c), f64(lp.l), f64(lp.u)
+        self.b = f64(lp.b) if self.m else torch.zeros(1, dtype=torch.float64, device=dev)
+        rk = getattr(lp, "row_kind", None)
+        self.row_kind = (torch.as_tensor(np.ascontiguousarray(rk, dtype=np.int8)).to(dev)
+                         if rk is not None and self.m else None)
+        self.struct = LP(self.m, self.n, self.nnz, self.row_ptr.data_ptr(),
+                         self.col_idx.data_ptr(), self.vals.data_ptr(), self.c.data_ptr(),
+                         self.b.data_ptr(), self.l.data_ptr(), self.u.data_ptr(),
+                         self.row_kind.data_ptr() if self.row_kind is not None else None)
+
+
+class BatchSolver:
+    """Many independent LPs solved by the same launches (pdhg_batch_*)."""
+
+    def __init__(self, lps, params=None, device="cuda:0", stream=None, **common):
+        import torch
+        L = load()
+        self._L = L
+        self.device = torch.device(device)
+        self.lps = [_DeviceLP(lp, self.device) for lp in lps]
+        self.count = len(self.lps)
+        arr = (LP * self.count)(*[d.struct for d in self.lps])
+        if params is None:
+            params = [{}] * self.count
+        elif isinstance(params, dict):
+            params = [params] * self.count
+        prm = (Params * self.count)()
+        for i, p in enumerate(params):
+            q = dict(eta=0.0, omega=1.0, beta=float(np.exp(-1.0)), check_period=30, tau0=1,
+                     restart_mode=RESTART_ADAPTIVE, fixed_len=0, kkt_kind=KKT_RELATIVE,
+                     power_iters=1000, power_tol=1e-10)
+            q.update(common)
+            q.update(p)
+            prm[i] = Params(float(q["eta"]), float(q["omega"]), float(q["beta"]),
+                            int(q["check_period"]), int(q["tau0"]), int(q["restart_mode"]),
+                            int(q["fixed_len"]), int(q["kkt_kind"]), int(q["power_iters"]),
+                            float(q["power_tol"]))
+        ms = np.array([d.m for d in self.lps], np.int64)
+        ns = np.array([d.n for d in self.lps], np.int64)
+        zs = np.array([d.nnz for d in self.lps], np.int64)
+        nbytes = L.pdhg_batch_workspace_bytes(self.count, ms.ctypes.data, ns.ctypes.data,
+                                              zs.ctypes.data)
+        if nbytes == 0:
+            raise PdhgError(E_INVALID, "pdhg_batch_workspace_bytes")
+        self._ws_owner, self.workspace = _dev_workspace(nbytes, self.device)
+        h = C.c_void_p()
+        rc = L.pdhg_batch_create(self.count, C.cast(arr, C.c_void_p), C.cast(prm, C.c_void_p),
+                                 _ptr(self.workspace), nbytes, _stream_handle(stream), C.byref(h))
+        _check(rc, "pdhg_batch_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.pdhg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, iters):
+        _check(self._L.pdhg_batch_step(self.h, int(iters)), "pdhg_batch_step")
+
+    def solve(self, max_iters, tol):
+        res = (Result * self.count)()
+        rc = self._L.pdhg_batch_solve(self.h, int(max_iters), float(tol), C.cast(res, C.c_void_p))
+        _check(rc, "pdhg_batch_solve", allow=(OK, NOT_CONVERGED))
+        return [dict(status=int(r.status), k=int(r.iterations), restarts=int(r.restarts),
+                     kkt=float(r.kkt), which=int(r.which_point), pobj=float(r.pobj),
+                     dobj=float(r.dobj)) for r in res]
+
+    def get_iterate(self, index, which=POINT_CURRENT):
+        import torch
+        d = self.lps[index]
+        x = torch.empty(d.n, dtype=torch.float64, device=self.device)
+        y = torch.empty(max(d.m, 1), dtype=torch.float64, device=self.device)
+        _check(self._L.pdhg_batch_get_iterate(self.h, int(index), int(which), _ptr(x), _ptr(y)),
+               "pdhg_batch_get_iterate")
+        return x, y[: d.m]
+
+    def info(self, index):
+        out = Info()
+        _check(self._L.pdhg_batch_get_info(self.h, int(index), C.byref(out)),
+               "pdhg_batch_get_info")
+        return {k: getattr(out, k) for k, _ in Info._fields_}
+
+    def check_log(self, index, max_records=512):
+        arr = (CheckRecord * max_records)()
+        cnt = C.c_int64()
+        _check(self._L.pdhg_batch_get_check_log(self.h, int(index), C.cast(arr, C.c_void_p),
+                                                max_records, C.byref(cnt)),
+               "pdhg_batch_get_check_log")
+        return np.array([arr[i].v[:] for i in range(cnt.value)]).reshape(-1, 14)
 
 
 def linear_trust_region(a, d, r, device="cuda:0", stream=None):

@@ -1,0 +1,1590 @@
+// Batched restarted PDHG: many independent LPs solved by the same launches.
+//
+// The LPs are concatenated into one block-diagonal CSR (rows of LP i follow
+// those of LP i-1, column indices shifted by its column offset), so each
+// half-step of eq. PDHG-update is one SpMV launch over every LP at once
+// with the update fused into the row epilogue.  Each LP keeps its own step
+// sizes, iteration and restart counters, trust-region bracket and done
+// flag (struct BLP); epilogues look the LP of a row or column up in
+// lp_row / lp_col and leave converged LPs untouched, and SpMV blocks whose
+// rows all belong to converged LPs exit at once.
+//
+// Per-LP reductions (KKT, radii, the normalized duality gap of eq. rhorz,
+// power iteration) run over a block table: the element space of LP i
+// (its n_i primal coordinates, then its m_i dual ones) is cut into chunks
+// of kChunk elements, each owned by one block, and a workgroup per LP
+// reduces its blocks' partial sums in a fixed order.  The trust region is
+// the same radix bisection on the multiplier as the single-LP solver, with
+// a histogram and a bracket per LP.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "pdhg.h"
+#include "pdhg_device.h"
+
+namespace pdhg {
+
+constexpr int kChunk = 2048;  // elements per block of the per-LP passes
+constexpr int kBLog = 512;    // check records kept per LP
+
+struct BLP {
+    // sizes and offsets in the concatenated arrays
+    int m, n, row_off, col_off;
+    int blk_begin, blk_end;  // element blocks of this LP
+    double eta, tau, sigma, omega, beta, sw;
+    int tau0, pad0;
+    // Algorithm 1 state
+    long long k, t, restarts, checks;
+    double rho_prev;
+    int done, conv_which;
+    long long conv_k;
+    double kkt_cur[8], kkt_avg[8];
+    double r_avg, r_cur;
+    int restarted, cand, gap_slots, numerr, in_check, pad1;
+    double nb2, nc2;
+    // power iteration
+    double pw_est, pw_prev, pw_s;
+    int pw_done, pw_it;
+    TRState tr[kTrSlots];
+};
+
+struct BDev {
+    int count, M, N, NNZ, nblk;
+    int *rp, *ci;
+    double *v, *c, *b, *l, *u;
+    signed char *kind;
+    int *trp, *tci, *perm;
+    double *tv;
+    int *cursor, *long_rows;
+    int *brA, *brT;
+    int nblkA, nblkT;
+    int *lp_row, *lp_col;
+    int *blk_lp, *blk_first;
+    double *x, *y, *x0, *y0, *sx, *sy, *q, *xbar, *ybar, *axb, *atyb, *aty;
+    double *part;    // [nblk][kKktSums]
+    double *log;     // [count][kBLog][kRec]
+    BLP *lp;
+    unsigned int *hcnt;  // [count][kTrSlots][2][kBuckets]
+    double *hD, *hA;
+    double *tpart;       // [kTrSlots][nblk][4]
+    unsigned int *ccount;  // [kTrSlots][nblk]
+    unsigned int *coff;    // [kTrSlots][nblk + count]
+    unsigned long long *ckey;  // [kTrSlots][nblk * kChunk]
+    double *ca, *cd;
+    int *err;
+};
+
+__device__ __forceinline__ size_t hist_at(int lp, int slot, int half) {
+    return ((size_t)(lp * kTrSlots + slot) * 2 + half) * kBuckets;
+}
+
+// element e of LP L: its index in the concatenated x (e < n) or y array
+__device__ __forceinline__ bool elem_is_x(const BLP &L, int e) { return e < L.n; }
+
+// ---------------------------------------------------------------------
+// SpMV over the block-diagonal matrix; blocks of converged LPs exit
+// ---------------------------------------------------------------------
+template <class Epi>
+__global__ __launch_bounds__(kWG) void k_bspmv(const int *__restrict__ rp, const int *__restrict__ ci,
+                                               const double *__restrict__ v,
+                                               const double *__restrict__ xin,
+                                               const int *__restrict__ br, Epi epi,
+                                               const int *__restrict__ lp_of, const BLP *lps,
+                                               int gate_kind) {
+    __shared__ double lds[kLdsProducts];
+    const int r0 = br[blockIdx.x], r1 = br[blockIdx.x + 1];
+    if (r0 >= r1) return;
+    const int a = lp_of[r0], z = lp_of[r1 - 1];
+    if (a == z) {
+        const BLP &L = lps[a];
+        if (gate_kind == 0 ? L.done : L.pw_done) return;
+    }
+    spmv_rows(rp, ci, v, xin, r0, r1, epi, lds);
+}
+
+struct EpiPrimalB {
+    const double *__restrict__ c, *__restrict__ l, *__restrict__ u;
+    double *__restrict__ x, *__restrict__ sx;
+    const int *__restrict__ lpc;
+    BLP *lp;
+    __device__ __forceinline__ void operator()(int j, double aty) const {
+        BLP &L = lp[lpc[j]];
+        if (L.done) return;
+        double g = c[j] - aty;
+        double xn = x[j] - L.tau * g;
+        const double lo = l[j], hi = u[j];
+        if (xn < lo) xn = lo;
+        if (xn > hi) xn = hi;
+        x[j] = xn;
+        sx[j] += xn;
+        if (j == L.col_off) {
+            L.k += 1;
+            L.t += 1;
+        }
+    }
+};
+
+struct EpiDualB {
+    const double *__restrict__ b;
+    const signed char *__restrict__ kind;
+    double *__restrict__ y, *__restrict__ sy, *__restrict__ q;
+    const int *__restrict__ lpr;
+    const BLP *lp;
+    __device__ __forceinline__ void operator()(int i, double ax) const {
+        const BLP &L = lp[lpr[i]];
+        if (L.done) return;
+        double yv = y[i] + L.sigma * (b[i] - (2.0 * ax - q[i]));
+        if (kind[i] && yv < 0.0) yv = 0.0;
+        y[i] = yv;
+        sy[i] += yv;
+        q[i] = ax;
+    }
+};
+
+static void bspmv_A(const BDev &d, const double *in, double *out, int gate_kind, hipStream_t s) {
+    EpiStore e{out};
+    hipLaunchKernelGGL(k_bspmv<EpiStore>, dim3(d.nblkA), dim3(kWG), 0, s, d.rp, d.ci, d.v, in,
+                       d.brA, e, d.lp_row, d.lp, gate_kind);
+}
+
+static void bspmv_T(const BDev &d, const double *in, double *out, int gate_kind, hipStream_t s) {
+    EpiStore e{out};
+    hipLaunchKernelGGL(k_bspmv<EpiStore>, dim3(d.nblkT), dim3(kWG), 0, s, d.trp, d.tci, d.tv, in,
+                       d.brT, e, d.lp_col, d.lp, gate_kind);
+}
+
+static void b_iteration(const BDev &d, hipStream_t s) {
+    EpiPrimalB ep{d.c, d.l, d.u, d.x, d.sx, d.lp_col, d.lp};
+    hipLaunchKernelGGL(k_bspmv<EpiPrimalB>, dim3(d.nblkT), dim3(kWG), 0, s, d.trp, d.tci, d.tv, d.y,
+                       d.brT, ep, d.lp_col, d.lp, 0);
+    EpiDualB ed{d.b, d.kind, d.y, d.sy, d.q, d.lp_row, d.lp};
+    hipLaunchKernelGGL(k_bspmv<EpiDualB>, dim3(d.nblkA), dim3(kWG), 0, s, d.rp, d.ci, d.v, d.x,
+                       d.brA, ed, d.lp_row, d.lp, 0);
+}
+
+// ---------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------
+// copy LP `lp` into the concatenated arrays
+__global__ void k_bconcat(BDev d, int lpi, const int *rp, const int *ci, const double *v,
+                          const double *c, const double *b, const double *l, const double *u,
+                          const signed char *kind, int m, int n, int nnz, int row_off,
+                          int col_off, int nnz_off) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nnz) {
+        d.ci[nnz_off + i] = ci[i] + col_off;
+        d.v[nnz_off + i] = v[i];
+    }
+    if (i < m) {
+        d.rp[row_off + i] = rp[i] + nnz_off;
+        d.b[row_off + i] = b[i];
+        d.kind[row_off + i] = kind ? kind[i] : (signed char)0;
+        d.lp_row[row_off + i] = lpi;
+    }
+    if (i < n) {
+        d.c[col_off + i] = c[i];
+        d.l[col_off + i] = l[i];
+        d.u[col_off + i] = u[i];
+        d.lp_col[col_off + i] = lpi;
+    }
+}
+
+__global__ void k_bclose_rp(BDev d) { d.rp[d.M] = d.NNZ; }
+
+// x = proj_X(0), y = 0, anchors, sums
+__global__ void k_binit(BDev d) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d.N) {
+        double v = 0.0;
+        if (v < d.l[i]) v = d.l[i];
+        if (v > d.u[i]) v = d.u[i];
+        d.x[i] = v;
+        d.x0[i] = v;
+        d.sx[i] = 0.0;
+    }
+    if (i < d.M) {
+        d.y[i] = 0.0;
+        d.y0[i] = 0.0;
+        d.sy[i] = 0.0;
+    }
+}
+
+// |b_i|^2 and |c_i|^2 per LP
+__global__ __launch_bounds__(kWG) void k_bnorm_partials(BDev d) {
+    __shared__ double sh[4 * 2];
+    const int bb = blockIdx.x;
+    const BLP &L = d.lp[d.blk_lp[bb]];
+    const int first = d.blk_first[bb];
+    const int E = L.n + L.m;
+    const int end = first + kChunk < E ? first + kChunk : E;
+    double v[2] = {0.0, 0.0};
+    for (int e = first + threadIdx.x; e < end; e += kWG) {
+        if (e < L.n) {
+            const double cc = d.c[L.col_off + e];
+            v[1] += cc * cc;
+        } else {
+            const double b2 = d.b[L.row_off + e - L.n];
+            v[0] += b2 * b2;
+        }
+    }
+    block_sums<2>(v, sh);
+    if (threadIdx.x == 0) {
+        d.part[(size_t)bb * kKktSums + 0] = v[0];
+        d.part[(size_t)bb * kKktSums + 1] = v[1];
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_bnorm_final(BDev d) {
+    BLP &L = d.lp[blockIdx.x];
+    __shared__ double sh[4 * 2];
+    double out[2];
+    reduce_partials<2>(d.part + (size_t)L.blk_begin * kKktSums, L.blk_end - L.blk_begin, kKktSums,
+                       out, sh);
+    if (threadIdx.x == 0) {
+        L.nb2 = out[0];
+        L.nc2 = out[1];
+    }
+}
+
+// power iteration per LP (the single-LP rule, each LP stops on its own)
+__global__ void k_bpw_init(BDev d) {
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < d.N) d.atyb[j] = 1.0 / sqrt((double)d.lp[d.lp_col[j]].n);
+    if (j < d.count) {
+        BLP &L = d.lp[j];
+        L.pw_done = 0;
+        L.pw_it = 0;
+        L.pw_est = 0.0;
+        L.pw_prev = 0.0;
+        L.pw_s = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_bpw_partials(BDev d) {
+    __shared__ double sh[4];
+    const int bb = blockIdx.x;
+    const BLP &L = d.lp[d.blk_lp[bb]];
+    if (L.pw_done) return;
+    const int first = d.blk_first[bb];
+    const int end = first + kChunk < L.n ? first + kChunk : L.n;
+    double a[1] = {0.0};
+    for (int e = first + threadIdx.x; e < end; e += kWG) {
+        const double uu = d.aty[L.col_off + e];
+        a[0] += uu * uu;
+    }
+    block_sums<1>(a, sh);
+    if (threadIdx.x == 0) d.part[(size_t)bb * kKktSums] = a[0];
+}
+
+__global__ __launch_bounds__(kWG) void k_bpw_final(BDev d, double tol, int max_iters) {
+    BLP &L = d.lp[blockIdx.x];
+    if (L.pw_done) return;
+    __shared__ double sh[4];
+    // blocks of the LP whose chunk starts inside its x part
+    int nbx = L.blk_end - L.blk_begin;
+    const int need = (L.n + kChunk - 1) / kChunk;
+    if (need < nbx) nbx = need;
+    double tot[1];
+    reduce_partials<1>(d.part + (size_t)L.blk_begin * kKktSums, nbx, kKktSums, tot, sh);
+    if (threadIdx.x == 0) {
+        const double sn = sqrt(tot[0]);
+        if (!(sn > 0.0)) {
+            L.pw_est = 0.0;
+            L.pw_s = 0.0;
+            L.pw_done = 1;
+        } else {
+            L.pw_s = sn;
+            const double est = sqrt(sn);
+            L.pw_est = est;
+            if (L.pw_it > 0 && fabs(est - L.pw_prev) <= tol * est) L.pw_done = 2;
+            L.pw_prev = est;
+            L.pw_it += 1;
+            if (L.pw_it >= max_iters) L.pw_done = 2;
+        }
+    }
+}
+
+// v = u / s for LPs still iterating (pw_done 2 marks the step that stopped)
+__global__ void k_bpw_norm(BDev d) {
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= d.N) return;
+    const BLP &L = d.lp[d.lp_col[j]];
+    if (L.pw_done == 1) return;
+    const double sn = L.pw_s;
+    if (sn > 0.0) d.atyb[j] = d.aty[j] / sn;
+}
+
+__global__ void k_bpw_settle(BDev d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d.count && d.lp[i].pw_done == 2) d.lp[i].pw_done = 1;
+}
+
+// step sizes: eta given, else 0.9 / sigma_max; tau = eta / omega, sigma = eta * omega
+__global__ void k_bset_steps(BDev d, const double *eta_in) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.count) return;
+    BLP &L = d.lp[i];
+    double eta = eta_in[i];
+    if (!(eta > 0.0)) eta = L.pw_est > 0.0 ? 0.9 / L.pw_est : 1.0;
+    L.eta = eta;
+    L.tau = eta / L.omega;
+    L.sigma = eta * L.omega;
+}
+
+// ---------------------------------------------------------------------
+// check
+// ---------------------------------------------------------------------
+__global__ void k_bavg(BDev d) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d.N) {
+        const BLP &L = d.lp[d.lp_col[i]];
+        if (L.done) return;
+        d.xbar[i] = L.t ? d.sx[i] / (double)L.t : d.x[i];
+    } else if (i < (long long)d.N + d.M) {
+        const long long r = i - d.N;
+        const BLP &L = d.lp[d.lp_row[r]];
+        if (L.done) return;
+        d.ybar[r] = L.t ? d.sy[r] / (double)L.t : d.y[r];
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_bkkt_partials(BDev d) {
+    const int bb = blockIdx.x;
+    const BLP &L = d.lp[d.blk_lp[bb]];
+    if (L.done) return;
+    __shared__ double sh[4 * kKktSums];
+    double v[kKktSums];
+#pragma unroll
+    for (int k = 0; k < kKktSums; ++k) v[k] = 0.0;
+    const int first = d.blk_first[bb];
+    const int E = L.n + L.m;
+    const int end = first + kChunk < E ? first + kChunk : E;
+    for (int e = first + threadIdx.x; e < end; e += kWG) {
+        if (e < L.n) {
+            const int j = L.col_off + e;
+            const double cj = d.c[j], lj = d.l[j], uj = d.u[j], x0 = d.x0[j];
+            const bool lf = isfinite(lj), uf = isfinite(uj);
+            const double xs[2] = {d.x[j], d.xbar[j]};
+            const double ats[2] = {d.aty[j], d.atyb[j]};
+#pragma unroll
+            for (int P = 0; P < 2; ++P) {
+                const double xp = xs[P];
+                const double rc = cj - ats[P];
+                double lam;
+                if (lf && uf) lam = rc;
+                else if (lf) lam = rc > 0.0 ? rc : 0.0;
+                else if (uf) lam = rc < 0.0 ? rc : 0.0;
+                else lam = 0.0;
+                const double dr = rc - lam;
+                v[S_DRES2_C + P] += dr * dr;
+                double dob = 0.0;
+                if (lam > 0.0) dob += lj * lam;
+                if (lam < 0.0) dob += uj * lam;
+                v[S_DOBJ_C + P] += dob;
+                v[S_POBJ_C + P] += cj * xp;
+                double bv = 0.0;
+                if (xp < lj) bv = lj - xp;
+                if (xp > uj) bv = xp - uj;
+                v[S_BV2_C + P] += bv * bv;
+            }
+            const double da = xs[1] - x0, dc = xs[0] - x0;
+            v[S_RX2_A] += da * da;
+            v[S_RX2_C] += dc * dc;
+        } else {
+            const int r = L.row_off + e - L.n;
+            const double br = d.b[r], y0 = d.y0[r];
+            const bool ge = d.kind[r] != 0;
+            const double ys[2] = {d.y[r], d.ybar[r]};
+            const double axs[2] = {d.q[r], d.axb[r]};
+#pragma unroll
+            for (int P = 0; P < 2; ++P) {
+                double p = br - axs[P];
+                if (ge && p < 0.0) p = 0.0;
+                v[S_PRES2_C + P] += p * p;
+                v[S_DOBJ_C + P] += br * ys[P];
+                if (ge && ys[P] < 0.0) v[S_BV2_C + P] += ys[P] * ys[P];
+            }
+            const double da = ys[1] - y0, dc = ys[0] - y0;
+            v[S_RY2_A] += da * da;
+            v[S_RY2_C] += dc * dc;
+        }
+    }
+    block_sums<kKktSums>(v, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kKktSums; ++k) d.part[(size_t)bb * kKktSums + k] = v[k];
+    }
+}
+
+__device__ void bkkt_point(const BLP &L, const double *S, int P, double *out) {
+    const double pres2 = S[S_PRES2_C + P], dres2 = S[S_DRES2_C + P];
+    const double pobj = S[S_POBJ_C + P], dobj = S[S_DOBJ_C + P], bv2 = S[S_BV2_C + P];
+    const double pres = sqrt(pres2), dres = sqrt(dres2);
+    const double gap = pobj - dobj;
+    const double rel_p = pres / (1.0 + sqrt(L.nb2));
+    const double rel_d = dres / (1.0 + sqrt(L.nc2));
+    const double rel_g = fabs(gap) / (1.0 + fabs(pobj) + fabs(dobj));
+    double rel = rel_p;
+    if (rel_d > rel) rel = rel_d;
+    if (rel_g > rel) rel = rel_g;
+    const double gpos = gap > 0.0 ? gap : 0.0;
+    double mx = pres;
+    if (dres > mx) mx = dres;
+    if (fabs(gap) > mx) mx = fabs(gap);
+    out[1] = rel;
+    out[2] = pres;
+    out[3] = dres;
+    out[4] = pobj;
+    out[5] = dobj;
+    out[6] = sqrt(bv2 + pres2 + dres2 + gpos * gpos);
+    out[7] = mx;
+}
+
+__device__ __forceinline__ double bkkt_pick(const double *k8, int kind) {
+    if (kind == 1) return k8[6];
+    if (kind == 2) return k8[7];
+    return k8[1];
+}
+
+__global__ __launch_bounds__(kWG) void k_bkkt_final(BDev d, double tol, int kkt_kind, int gap_slots) {
+    const int lpi = blockIdx.x;
+    BLP &L = d.lp[lpi];
+    if (L.done) return;
+    __shared__ double sh[4 * kKktSums];
+    __shared__ int armed;
+    double S[kKktSums];
+    reduce_partials<kKktSums>(d.part + (size_t)L.blk_begin * kKktSums, L.blk_end - L.blk_begin,
+                              kKktSums, S, sh);
+    if (threadIdx.x == 0) {
+        L.in_check = 1;
+        L.restarted = 0;
+        L.cand = 0;
+        bkkt_point(L, S, 0, L.kkt_cur);
+        bkkt_point(L, S, 1, L.kkt_avg);
+        const double kc = bkkt_pick(L.kkt_cur, kkt_kind), ka = bkkt_pick(L.kkt_avg, kkt_kind);
+        L.kkt_cur[0] = kc;
+        L.kkt_avg[0] = ka;
+        bool bad = false;
+        for (int k = 0; k < kKktSums; ++k) bad |= !isfinite(S[k]);
+        L.numerr = bad ? 1 : 0;
+        const int conv = (tol > 0.0 && (kc <= tol || ka <= tol)) ? 1 : 0;
+        L.conv_which = -1;
+        if (conv) {
+            L.done = 1;
+            L.conv_which = (ka <= kc) ? 1 : 0;
+            L.conv_k = L.k;
+        }
+        L.r_avg = sqrt(L.omega * S[S_RX2_A] + S[S_RY2_A] / L.omega);
+        L.r_cur = sqrt(L.omega * S[S_RX2_C] + S[S_RY2_C] / L.omega);
+        int slots = 0;
+        if (!conv && !bad && L.t > 0) slots = gap_slots;
+        L.gap_slots = slots;
+        for (int sidx = 0; sidx < kTrSlots; ++sidx) {
+            TRState &ts = L.tr[sidx];
+            ts.mode = TR_IDLE;
+            ts.rho = 0.0;
+            ts.lam = 0.0;
+            if (slots & (1 << sidx)) {
+                ts.mode = TR_SEARCH;
+                ts.r = sidx == 0 ? L.r_avg : L.r_cur;
+                ts.r2 = ts.r * ts.r;
+                ts.F_acc = 0.0;
+                ts.A_acc = 0.0;
+                ts.prefix = 0ull;
+                ts.klo = 0ull;
+                ts.level = 0;
+                ts.count = 0u;
+                ts.ncomp = 0u;
+                ts.nan_seen = 0;
+                ts.cap = kChunk;
+            }
+        }
+        armed = slots;
+    }
+    __syncthreads();
+    for (int sidx = 0; sidx < kTrSlots; ++sidx) {
+        if (!(armed & (1 << sidx))) continue;
+        const size_t h0 = hist_at(lpi, sidx, 0);
+        for (int b = threadIdx.x; b < kBuckets; b += kWG) {
+            d.hcnt[h0 + b] = 0u;
+            d.hD[h0 + b] = 0.0;
+            d.hA[h0 + b] = 0.0;
+        }
+    }
+}
+
+// coordinate (a, d) pair of element e of LP L for the gap at slot 0 (z-bar)
+// or slot 1 (z): the same formulas as the single-LP solver
+__device__ __forceinline__ void bgap_elem(const BDev &d, const BLP &L, int slot, int e, double &a,
+                                          double &dd) {
+    if (e < L.n) {
+        const int j = L.col_off + e;
+        const double xv = slot == 0 ? d.xbar[j] : d.x[j];
+        const double at = slot == 0 ? d.atyb[j] : d.aty[j];
+        const double g = d.c[j] - at;
+        double dist = 0.0;
+        if (g > 0.0) dist = xv - d.l[j];
+        else if (g < 0.0) dist = d.u[j] - xv;
+        if (dist < 0.0) dist = 0.0;
+        a = fabs(g) / L.sw;
+        dd = dist * L.sw;
+    } else {
+        const int r = L.row_off + e - L.n;
+        const double yv = slot == 0 ? d.ybar[r] : d.y[r];
+        const double ax = slot == 0 ? d.axb[r] : d.q[r];
+        const double g = ax - d.b[r];
+        const double lo = d.kind[r] ? 0.0 : -INFINITY;
+        double dist = 0.0;
+        if (g > 0.0) dist = yv - lo;
+        else if (g < 0.0) dist = INFINITY;
+        if (dist < 0.0) dist = 0.0;
+        a = fabs(g) * L.sw;
+        dd = dist / L.sw;
+    }
+}
+
+__device__ __forceinline__ int blk_end_elem(const BDev &d, const BLP &L, int bb) {
+    const int first = d.blk_first[bb];
+    const int E = L.n + L.m;
+    return first + kChunk < E ? first + kChunk : E;
+}
+
+__global__ __launch_bounds__(kWG) void k_btr_hist0(BDev d, int slot) {
+    const int bb = blockIdx.x;
+    const BLP &L = d.lp[d.blk_lp[bb]];
+    const TRState &ts = L.tr[slot];
+    if (!L.in_check || ts.mode != TR_SEARCH || ts.level != 0) return;
+    __shared__ unsigned int scnt[kBuckets];
+    __shared__ double sD[kBuckets], sA[kBuckets];
+    __shared__ double sh[4 * 4];
+    for (int b = threadIdx.x; b < kBuckets; b += kWG) {
+        scnt[b] = 0u;
+        sD[b] = 0.0;
+        sA[b] = 0.0;
+    }
+    __syncthreads();
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const int end = blk_end_elem(d, L, bb);
+    for (int e = d.blk_first[bb] + threadIdx.x; e < end; e += kWG) {
+        double a, dd;
+        bgap_elem(d, L, slot, e, a, dd);
+        if (bad_pair(a, dd)) {
+            v[3] += 1.0;
+        } else if (a > 0.0) {
+            const unsigned long long key = key_of(a, dd);
+            const int b = (int)(key >> 52);
+            atomicAdd(&scnt[b], 1u);
+            atomicAdd(&sA[b], a * a);
+            if (dd < INFINITY) {
+                atomicAdd(&sD[b], dd * dd);
+                v[0] += dd * dd;
+                v[2] += a * dd;
+            } else {
+                v[1] += 1.0;
+            }
+        }
+    }
+    __syncthreads();
+    const size_t h0 = hist_at(d.blk_lp[bb], slot, 0);
+    for (int b = threadIdx.x; b < kBuckets; b += kWG) {
+        if (scnt[b]) {
+            atomicAdd(&d.hcnt[h0 + b], scnt[b]);
+            atomicAdd(&d.hD[h0 + b], sD[b]);
+            atomicAdd(&d.hA[h0 + b], sA[b]);
+        }
+    }
+    block_sums<4>(v, sh);
+    if (threadIdx.x == 0) {
+        double *tp = d.tpart + ((size_t)slot * d.nblk + bb) * 4;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) tp[k] = v[k];
+    }
+}
+
+__device__ void bzero_hist(const BDev &d, int lpi, int slot, int half) {
+    const size_t h = hist_at(lpi, slot, half);
+    for (int b = threadIdx.x; b < kBuckets; b += kWG) {
+        d.hcnt[h + b] = 0u;
+        d.hD[h + b] = 0.0;
+        d.hA[h + b] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_btr_decide0(BDev d, int slot) {
+    const int lpi = blockIdx.x;
+    BLP &L = d.lp[lpi];
+    if (!L.in_check || L.tr[slot].mode != TR_SEARCH || L.tr[slot].level != 0) return;
+    __shared__ TRState sts;
+    __shared__ ChooseShared cs;
+    __shared__ double sh[4 * 4];
+    __shared__ int go;
+    if (threadIdx.x == 0) sts = L.tr[slot];
+    double tot[4];
+    reduce_partials<4>(d.tpart + ((size_t)slot * d.nblk + L.blk_begin) * 4,
+                       L.blk_end - L.blk_begin, 4, tot, sh);
+    if (threadIdx.x == 0) {
+        go = 0;
+        if (tot[3] > 0.0) {
+            sts.nan_seen = 1;
+            sts.mode = TR_ZERO;
+            sts.rho = NAN;
+            sts.lam = NAN;
+            sts.value = NAN;
+        } else if (!(sts.r > 0.0)) {
+            sts.mode = TR_ZERO;
+            sts.rho = 0.0;
+            sts.lam = 0.0;
+            sts.value = 0.0;
+        } else if (tot[1] == 0.0 && tot[0] <= sts.r2) {
+            sts.mode = TR_FULLBOX;
+            sts.value = tot[2];
+            sts.rho = tot[2] / sts.r;
+            sts.lam = INFINITY;
+        } else {
+            go = 1;
+        }
+    }
+    __syncthreads();
+    const size_t h0 = hist_at(lpi, slot, 0);
+    if (go) choose_bucket(sts, d.hcnt + h0, d.hD + h0, d.hA + h0, kBuckets, 0, cs);
+    bzero_hist(d, lpi, slot, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sts.ncomp = 0u;
+        L.tr[slot] = sts;
+    }
+}
+
+// level 1 + compaction of the bracket's members into the block's region
+__global__ __launch_bounds__(kWG) void k_btr_pass1(BDev d, int slot) {
+    const int bb = blockIdx.x;
+    const int lpi = d.blk_lp[bb];
+    const BLP &L = d.lp[lpi];
+    const TRState &ts = L.tr[slot];
+    if (!L.in_check || ts.mode != TR_SEARCH || ts.level != 1) return;
+    __shared__ unsigned int scnt[kBuckets];
+    __shared__ double sD[kBuckets], sA[kBuckets];
+    __shared__ unsigned int nloc;
+    for (int b = threadIdx.x; b < kBuckets; b += kWG) {
+        scnt[b] = 0u;
+        sD[b] = 0.0;
+        sA[b] = 0.0;
+    }
+    if (threadIdx.x == 0) nloc = 0u;
+    __syncthreads();
+    const unsigned long long top = ts.prefix >> 52;
+    const size_t region = ((size_t)slot * d.nblk + bb) * kChunk;
+    const int end = blk_end_elem(d, L, bb);
+    for (int e = d.blk_first[bb] + threadIdx.x; e < end; e += kWG) {
+        double a, dd;
+        bgap_elem(d, L, slot, e, a, dd);
+        if (bad_pair(a, dd) || !(a > 0.0)) continue;
+        const unsigned long long key = key_of(a, dd);
+        if ((key >> 52) != top) continue;
+        const int b = (int)((key >> 41) & (kBuckets - 1));
+        atomicAdd(&scnt[b], 1u);
+        atomicAdd(&sD[b], dd * dd);
+        atomicAdd(&sA[b], a * a);
+        const unsigned int q = atomicAdd(&nloc, 1u);
+        d.ckey[region + q] = key;
+        d.ca[region + q] = a;
+        d.cd[region + q] = dd;
+    }
+    __syncthreads();
+    const size_t h1 = hist_at(lpi, slot, 1);
+    for (int b = threadIdx.x; b < kBuckets; b += kWG) {
+        if (scnt[b]) {
+            atomicAdd(&d.hcnt[h1 + b], scnt[b]);
+            atomicAdd(&d.hD[h1 + b], sD[b]);
+            atomicAdd(&d.hA[h1 + b], sA[b]);
+        }
+    }
+    if (threadIdx.x == 0) d.ccount[(size_t)slot * d.nblk + bb] = nloc;
+}
+
+// exclusive prefix of the LP's block counts into coff (one entry per block
+// plus the LP's total); the total is returned through LDS
+__device__ unsigned int bscan_counts(const BDev &d, const BLP &L, int lpi, int slot,
+                                     unsigned int *sh) {
+    const int nb = L.blk_end - L.blk_begin;
+    const unsigned int *cnt = d.ccount + (size_t)slot * d.nblk + L.blk_begin;
+    unsigned int *off = d.coff + (size_t)slot * (d.nblk + d.count) + L.blk_begin + lpi;
+    __shared__ unsigned int carry;
+    if (threadIdx.x == 0) carry = 0u;
+    __syncthreads();
+    for (int base = 0; base < nb; base += kWG) {
+        const int i = base + threadIdx.x;
+        const unsigned int v = i < nb ? cnt[i] : 0u;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < kWG; o <<= 1) {
+            unsigned int t = threadIdx.x >= o ? sh[threadIdx.x - o] : 0u;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nb) off[i] = carry + sh[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += sh[kWG - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) off[nb] = carry;
+    __syncthreads();
+    return carry;
+}
+
+__global__ __launch_bounds__(kWG) void k_btr_decide1(BDev d, int slot) {
+    const int lpi = blockIdx.x;
+    BLP &L = d.lp[lpi];
+    if (!L.in_check || L.tr[slot].mode != TR_SEARCH || L.tr[slot].level != 1) return;
+    __shared__ TRState sts;
+    __shared__ ChooseShared cs;
+    __shared__ unsigned int shs[kWG];
+    if (threadIdx.x == 0) sts = L.tr[slot];
+    const unsigned int total = bscan_counts(d, L, lpi, slot, shs);
+    if (threadIdx.x == 0) sts.ncomp = total;
+    __syncthreads();
+    const size_t h1 = hist_at(lpi, slot, 1);
+    choose_bucket(sts, d.hcnt + h1, d.hD + h1, d.hA + h1, kBuckets, 1, cs);
+    bzero_hist(d, lpi, slot, 0);
+    __syncthreads();
+    if (threadIdx.x == 0) L.tr[slot] = sts;
+}
+
+constexpr unsigned int kBFinishMax = 65536;
+
+__global__ __launch_bounds__(kWG) void k_btr_cpass(BDev d, int slot, int level) {
+    const int bb = blockIdx.x;
+    const int lpi = d.blk_lp[bb];
+    const BLP &L = d.lp[lpi];
+    const TRState &ts = L.tr[slot];
+    if (!L.in_check || ts.mode != TR_SEARCH || ts.level != level || ts.count <= kBFinishMax) return;
+    __shared__ unsigned int scnt[kBuckets];
+    __shared__ double sD[kBuckets], sA[kBuckets];
+    for (int b = threadIdx.x; b < kBuckets; b += kWG) {
+        scnt[b] = 0u;
+        sD[b] = 0.0;
+        sA[b] = 0.0;
+    }
+    __syncthreads();
+    const int shift = shift_of(level), above = shift_of(level - 1);
+    const unsigned long long want = ts.prefix >> above;
+    const size_t region = ((size_t)slot * d.nblk + bb) * kChunk;
+    unsigned int cnt = d.ccount[(size_t)slot * d.nblk + bb];
+    if (cnt > (unsigned int)kChunk) cnt = kChunk;
+    for (unsigned int q = threadIdx.x; q < cnt; q += kWG) {
+        const unsigned long long key = d.ckey[region + q];
+        if ((key >> above) != want) continue;
+        const int b = (int)((key >> shift) & (kBuckets - 1));
+        const double a = d.ca[region + q], dd = d.cd[region + q];
+        atomicAdd(&scnt[b], 1u);
+        atomicAdd(&sD[b], dd * dd);
+        atomicAdd(&sA[b], a * a);
+    }
+    __syncthreads();
+    const size_t h = hist_at(lpi, slot, level & 1);
+    for (int b = threadIdx.x; b < kBuckets; b += kWG) {
+        if (scnt[b]) {
+            atomicAdd(&d.hcnt[h + b], scnt[b]);
+            atomicAdd(&d.hD[h + b], sD[b]);
+            atomicAdd(&d.hA[h + b], sA[b]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_btr_cdecide(BDev d, int slot, int level) {
+    const int lpi = blockIdx.x;
+    BLP &L = d.lp[lpi];
+    const TRState &ts0 = L.tr[slot];
+    if (!L.in_check || ts0.mode != TR_SEARCH || ts0.level != level || ts0.count <= kBFinishMax)
+        return;
+    __shared__ TRState sts;
+    __shared__ ChooseShared cs;
+    if (threadIdx.x == 0) sts = L.tr[slot];
+    __syncthreads();
+    const size_t h = hist_at(lpi, slot, level & 1);
+    choose_bucket(sts, d.hcnt + h, d.hD + h, d.hA + h, kBuckets, level, cs);
+    bzero_hist(d, lpi, slot, 1 - (level & 1));
+    __syncthreads();
+    if (threadIdx.x == 0) L.tr[slot] = sts;
+}
+
+__global__ __launch_bounds__(kWG) void k_btr_finish(BDev d, int slot) {
+    const int lpi = blockIdx.x;
+    BLP &L = d.lp[lpi];
+    if (!L.in_check || L.tr[slot].mode != TR_SEARCH) return;
+    __shared__ TRState sts;
+    __shared__ ChooseShared cs;
+    __shared__ unsigned int scnt[kBuckets];
+    __shared__ double sD[kBuckets], sA[kBuckets];
+    if (threadIdx.x == 0) sts = L.tr[slot];
+    __syncthreads();
+    const int nb = L.blk_end - L.blk_begin;
+    const unsigned int *off = d.coff + (size_t)slot * (d.nblk + d.count) + L.blk_begin + lpi;
+    unsigned int total = off[nb];
+    const unsigned long long room = (unsigned long long)nb * kChunk;
+    if ((unsigned long long)total > room) total = (unsigned int)room;
+    while (sts.mode == TR_SEARCH) {
+        const int level = sts.level;
+        const int shift = shift_of(level);
+        const int nbuck = level == 5 ? 256 : kBuckets;
+        const int above = shift_of(level - 1);
+        const unsigned long long want = sts.prefix >> above;
+        for (int b = threadIdx.x; b < kBuckets; b += kWG) {
+            scnt[b] = 0u;
+            sD[b] = 0.0;
+            sA[b] = 0.0;
+        }
+        __syncthreads();
+        for (unsigned int idx = threadIdx.x; idx < total; idx += kWG) {
+            int lo = 0, hi = nb - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (off[mid] <= idx) lo = mid;
+                else hi = mid - 1;
+            }
+            const unsigned int within = idx - off[lo];
+            if (within >= (unsigned int)kChunk) continue;
+            const size_t at = ((size_t)slot * d.nblk + L.blk_begin + lo) * kChunk + within;
+            const unsigned long long key = d.ckey[at];
+            if ((key >> above) != want) continue;
+            const int b = (int)((key >> shift) & (unsigned long long)(nbuck - 1));
+            const double a = d.ca[at], dd = d.cd[at];
+            atomicAdd(&scnt[b], 1u);
+            atomicAdd(&sD[b], dd * dd);
+            atomicAdd(&sA[b], a * a);
+        }
+        __syncthreads();
+        choose_bucket(sts, scnt, sD, sA, nbuck, level, cs);
+    }
+    if (threadIdx.x == 0) L.tr[slot] = sts;
+}
+
+__global__ __launch_bounds__(kWG) void k_btr_final_partials(BDev d, int slot) {
+    const int bb = blockIdx.x;
+    const BLP &L = d.lp[d.blk_lp[bb]];
+    const TRState &ts = L.tr[slot];
+    if (!L.in_check || ts.mode != TR_RESOLVED) return;
+    __shared__ double sh[4 * 3];
+    const unsigned long long klo = ts.klo;
+    double v[3] = {0.0, 0.0, 0.0};
+    const int end = blk_end_elem(d, L, bb);
+    for (int e = d.blk_first[bb] + threadIdx.x; e < end; e += kWG) {
+        double a, dd;
+        bgap_elem(d, L, slot, e, a, dd);
+        if (bad_pair(a, dd) || !(a > 0.0)) continue;
+        if (key_of(a, dd) <= klo) {
+            v[0] += dd * dd;
+            v[2] += a * dd;
+        } else {
+            v[1] += a * a;
+        }
+    }
+    block_sums<3>(v, sh);
+    if (threadIdx.x == 0) {
+        double *tp = d.tpart + ((size_t)slot * d.nblk + bb) * 4;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) tp[k] = v[k];
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_btr_final(BDev d, int slot) {
+    BLP &L = d.lp[blockIdx.x];
+    if (!L.in_check || L.tr[slot].mode != TR_RESOLVED) return;
+    __shared__ double sh[4 * 3];
+    double tot[3];
+    reduce_partials<3>(d.tpart + ((size_t)slot * d.nblk + L.blk_begin) * 4,
+                       L.blk_end - L.blk_begin, 4, tot, sh);
+    if (threadIdx.x == 0) {
+        TRState &ts = L.tr[slot];
+        const double F = tot[0], A = tot[1], AD = tot[2];
+        double lam, val;
+        if (A > 0.0) {
+            double num = ts.r2 - F;
+            if (num < 0.0) num = 0.0;
+            lam = sqrt(num / A);
+            val = AD + lam * A;
+        } else {
+            lam = INFINITY;
+            val = AD;
+        }
+        ts.lam = lam;
+        ts.value = val;
+        ts.rho = val / ts.r;
+    }
+}
+
+static void b_gap(const BDev &d, int slot, hipStream_t s) {
+    hipLaunchKernelGGL(k_btr_hist0, dim3(d.nblk), dim3(kWG), 0, s, d, slot);
+    hipLaunchKernelGGL(k_btr_decide0, dim3(d.count), dim3(kWG), 0, s, d, slot);
+    hipLaunchKernelGGL(k_btr_pass1, dim3(d.nblk), dim3(kWG), 0, s, d, slot);
+    hipLaunchKernelGGL(k_btr_decide1, dim3(d.count), dim3(kWG), 0, s, d, slot);
+    for (int level = 2; level <= 3; ++level) {
+        hipLaunchKernelGGL(k_btr_cpass, dim3(d.nblk), dim3(kWG), 0, s, d, slot, level);
+        hipLaunchKernelGGL(k_btr_cdecide, dim3(d.count), dim3(kWG), 0, s, d, slot, level);
+    }
+    hipLaunchKernelGGL(k_btr_finish, dim3(d.count), dim3(kWG), 0, s, d, slot);
+    hipLaunchKernelGGL(k_btr_final_partials, dim3(d.nblk), dim3(kWG), 0, s, d, slot);
+    hipLaunchKernelGGL(k_btr_final, dim3(d.count), dim3(kWG), 0, s, d, slot);
+}
+
+// restart decision per LP (eq. adaptive-restart-scheme, Remark rem:flexible)
+__global__ void k_bdecide(BDev d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.count) return;
+    BLP &L = d.lp[i];
+    if (!L.in_check) return;
+    double rec[kRec];
+    rec[0] = (double)L.k;
+    rec[1] = (double)L.t;
+    rec[2] = (double)L.restarts;
+    rec[3] = L.kkt_cur[0];
+    rec[4] = L.kkt_avg[0];
+    rec[5] = 0.0;
+    rec[6] = 0.0;
+    rec[7] = 0.0;
+    rec[8] = -1.0;
+    rec[9] = 0.0;
+    rec[10] = 0.0;
+    rec[11] = (double)L.conv_which;
+    rec[12] = L.rho_prev;
+    rec[13] = 0.0;
+    const int slots = L.gap_slots;
+    if (slots & 1) {
+        rec[5] = L.r_avg;
+        rec[6] = L.tr[0].rho;
+        rec[13] = L.tr[0].lam;
+        if (L.tr[0].nan_seen) L.numerr = 1;
+    }
+    if (slots & 2) {
+        rec[7] = L.r_cur;
+        rec[8] = L.tr[1].rho;
+        if (L.tr[1].nan_seen) L.numerr = 1;
+    }
+    if ((slots & 1) && !L.done && !L.numerr) {
+        const double rho_a = L.tr[0].rho;
+        double rho_c = rho_a;
+        int cand = 0;
+        if ((slots & 2) && L.tr[1].rho < rho_a) {
+            cand = 1;
+            rho_c = L.tr[1].rho;
+        }
+        bool restart;
+        if (L.restarts == 0) restart = L.t >= (long long)L.tau0;
+        else restart = rho_c <= L.beta * L.rho_prev;
+        rec[10] = (double)cand;
+        if (restart) {
+            rec[9] = 1.0;
+            L.restarted = 1;
+            L.cand = cand;
+            L.restarts += 1;
+            L.t = 0;
+            L.rho_prev = rho_c;
+        }
+    }
+    double *dst = d.log + ((size_t)i * kBLog + (size_t)(L.checks % kBLog)) * kRec;
+    for (int q = 0; q < kRec; ++q) dst[q] = rec[q];
+    L.checks += 1;
+    L.in_check = 0;
+}
+
+__global__ void k_bapply(BDev d) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d.N) {
+        const BLP &L = d.lp[d.lp_col[i]];
+        if (!L.restarted) return;
+        if (L.cand == 0) {
+            const double v = d.xbar[i];
+            d.x[i] = v;
+            d.x0[i] = v;
+        } else {
+            d.x0[i] = d.x[i];
+        }
+        d.sx[i] = 0.0;
+    } else if (i < (long long)d.N + d.M) {
+        const long long r = i - d.N;
+        const BLP &L = d.lp[d.lp_row[r]];
+        if (!L.restarted) return;
+        if (L.cand == 0) {
+            const double v = d.ybar[r];
+            d.y[r] = v;
+            d.y0[r] = v;
+            d.q[r] = d.axb[r];
+        } else {
+            d.y0[r] = d.y[r];
+        }
+        d.sy[r] = 0.0;
+    }
+}
+
+__global__ void k_breset(BDev d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d.count) d.lp[i].in_check = 0;
+}
+
+static void b_check(const BDev &d, double tol, int kkt_kind, int slots, hipStream_t s) {
+    const long long NM = (long long)d.N + d.M;
+    hipLaunchKernelGGL(k_bavg, dim3(div_up(NM, kWG)), dim3(kWG), 0, s, d);
+    bspmv_A(d, d.xbar, d.axb, 0, s);
+    bspmv_T(d, d.ybar, d.atyb, 0, s);
+    bspmv_T(d, d.y, d.aty, 0, s);
+    hipLaunchKernelGGL(k_bkkt_partials, dim3(d.nblk), dim3(kWG), 0, s, d);
+    hipLaunchKernelGGL(k_bkkt_final, dim3(d.count), dim3(kWG), 0, s, d, tol, kkt_kind, slots);
+    if (slots & 1) b_gap(d, 0, s);
+    if (slots & 2) b_gap(d, 1, s);
+    hipLaunchKernelGGL(k_bdecide, dim3(div_up(d.count, 64)), dim3(64), 0, s, d);
+    hipLaunchKernelGGL(k_bapply, dim3(div_up(NM, kWG)), dim3(kWG), 0, s, d);
+}
+
+__global__ void k_bget(BDev d, int lpi, int which, double *ox, double *oy) {
+    const BLP &L = d.lp[lpi];
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long t = L.t;
+    const bool sol_avg = L.conv_which == 1;
+    if (i < L.n) {
+        const int j = L.col_off + (int)i;
+        double v;
+        if (which == 0) v = d.x[j];
+        else if (which == 1) v = t ? d.sx[j] / (double)t : d.x[j];
+        else if (which == 2) v = d.x0[j];
+        else v = sol_avg ? d.xbar[j] : d.x[j];
+        ox[i] = v;
+    }
+    if (i < L.m) {
+        const int r = L.row_off + (int)i;
+        double v;
+        if (which == 0) v = d.y[r];
+        else if (which == 1) v = t ? d.sy[r] / (double)t : d.y[r];
+        else if (which == 2) v = d.y0[r];
+        else v = sol_avg ? d.ybar[r] : d.y[r];
+        oy[i] = v;
+    }
+}
+
+// ---------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------
+struct BLayout {
+    size_t total;
+    size_t o_lp, o_err, o_rp, o_ci, o_v, o_c, o_b, o_l, o_u, o_kind, o_trp, o_tci, o_perm, o_tv;
+    size_t o_cursor, o_long, o_brA, o_brT, o_lprow, o_lpcol, o_blklp, o_blkfirst, o_vn, o_vm;
+    size_t o_part, o_log, o_hcnt, o_hD, o_hA, o_tpart, o_ccount, o_coff, o_ckey, o_ca, o_cd;
+    int M, N, NNZ, nblk, nblkA, nblkT;
+};
+
+static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static bool b_layout(int count, const int64_t *m, const int64_t *n, const int64_t *nnz,
+                     BLayout *L) {
+    if (count < 1 || count > (1 << 20)) return false;
+    long long M = 0, N = 0, Z = 0, nblk = 0;
+    for (int i = 0; i < count; ++i) {
+        if (m[i] < 0 || n[i] < 1 || nnz[i] < 0) return false;
+        M += m[i];
+        N += n[i];
+        Z += nnz[i];
+        long long E = n[i] + m[i];
+        nblk += (E + kChunk - 1) / kChunk;
+    }
+    const long long lim = 0x7fffffffLL - 4096;
+    if (M > lim || N > lim || Z > lim || nblk > lim / kChunk) return false;
+    L->M = (int)M;
+    L->N = (int)N;
+    L->NNZ = (int)Z;
+    L->nblk = (int)nblk;
+    L->nblkA = nblocks_for((int)M, (int)Z);
+    L->nblkT = nblocks_for((int)N, (int)Z);
+    const size_t M1 = (size_t)(M > 0 ? M : 1), N1 = (size_t)N, Z1 = (size_t)(Z > 0 ? Z : 1);
+    size_t o = 0;
+    auto put = [&](size_t &off, size_t bytes) {
+        off = o;
+        o += al(bytes);
+    };
+    put(L->o_lp, sizeof(BLP) * (size_t)count);
+    put(L->o_err, sizeof(int) * 16);
+    put(L->o_rp, sizeof(int) * (M1 + 1));
+    put(L->o_ci, sizeof(int) * Z1);
+    put(L->o_v, sizeof(double) * Z1);
+    put(L->o_c, sizeof(double) * N1);
+    put(L->o_b, sizeof(double) * M1);
+    put(L->o_l, sizeof(double) * N1);
+    put(L->o_u, sizeof(double) * N1);
+    put(L->o_kind, M1);
+    put(L->o_trp, sizeof(int) * (N1 + 1));
+    put(L->o_tci, sizeof(int) * Z1);
+    put(L->o_perm, sizeof(int) * Z1);
+    put(L->o_tv, sizeof(double) * Z1);
+    put(L->o_cursor, sizeof(int) * N1);
+    put(L->o_long, sizeof(int) * N1);
+    put(L->o_brA, sizeof(int) * ((size_t)L->nblkA + 1));
+    put(L->o_brT, sizeof(int) * ((size_t)L->nblkT + 1));
+    put(L->o_lprow, sizeof(int) * M1);
+    put(L->o_lpcol, sizeof(int) * N1);
+    put(L->o_blklp, sizeof(int) * (size_t)nblk);
+    put(L->o_blkfirst, sizeof(int) * (size_t)nblk);
+    put(L->o_vn, al(sizeof(double) * N1) * 6);
+    put(L->o_vm, al(sizeof(double) * M1) * 6);
+    put(L->o_part, sizeof(double) * (size_t)nblk * kKktSums);
+    put(L->o_log, sizeof(double) * (size_t)count * kBLog * kRec);
+    put(L->o_hcnt, sizeof(unsigned int) * (size_t)count * kTrSlots * 2 * kBuckets);
+    put(L->o_hD, sizeof(double) * (size_t)count * kTrSlots * 2 * kBuckets);
+    put(L->o_hA, sizeof(double) * (size_t)count * kTrSlots * 2 * kBuckets);
+    put(L->o_tpart, sizeof(double) * kTrSlots * (size_t)nblk * 4);
+    put(L->o_ccount, sizeof(unsigned int) * kTrSlots * (size_t)nblk);
+    put(L->o_coff, sizeof(unsigned int) * kTrSlots * ((size_t)nblk + count));
+    put(L->o_ckey, sizeof(unsigned long long) * kTrSlots * (size_t)nblk * kChunk);
+    put(L->o_ca, sizeof(double) * kTrSlots * (size_t)nblk * kChunk);
+    put(L->o_cd, sizeof(double) * kTrSlots * (size_t)nblk * kChunk);
+    L->total = o;
+    return true;
+}
+
+}  // namespace pdhg
+
+using namespace pdhg;
+
+struct pdhg_batch_handle {
+    BDev d;
+    hipStream_t stream, cap;
+    int count;
+    int mode, period, kkt_kind;
+    hipGraphExec_t gexec;
+    double g_tol;
+    bool g_valid;
+    std::vector<int> pw_used;
+};
+
+#define BCK(expr)                                  \
+    do {                                           \
+        if ((expr) != hipSuccess) return PDHG_E_HIP; \
+    } while (0)
+
+static int b_last_error() { return hipGetLastError() == hipSuccess ? PDHG_OK : PDHG_E_HIP; }
+
+static int b_read_lps(pdhg_batch_t *h, std::vector<BLP> &out) {
+    out.resize((size_t)h->count);
+    BCK(hipMemcpyAsync(out.data(), h->d.lp, sizeof(BLP) * (size_t)h->count, hipMemcpyDeviceToHost,
+                       h->stream));
+    BCK(hipStreamSynchronize(h->stream));
+    return PDHG_OK;
+}
+
+static int b_slots(int mode) {
+    if (mode == PDHG_RESTART_ADAPTIVE) return 1;
+    if (mode == PDHG_RESTART_FLEXIBLE) return 3;
+    return 0;
+}
+
+extern "C" {
+
+size_t pdhg_batch_workspace_bytes(int32_t count, const int64_t *m, const int64_t *n,
+                                  const int64_t *nnz) {
+    if (!m || !n || !nnz) return 0;
+    BLayout L;
+    if (!b_layout(count, m, n, nnz, &L)) return 0;
+    return L.total;
+}
+
+int pdhg_batch_create(int32_t count, const pdhg_lp *lps, const pdhg_params *prm,
+                      void *workspace, size_t workspace_bytes, void *stream, pdhg_batch_t **out) {
+    if (!out) return PDHG_E_INVALID;
+    *out = nullptr;
+    if (count < 1 || !lps) return PDHG_E_INVALID;
+    std::vector<int64_t> ms(count), ns(count), zs(count);
+    std::vector<pdhg_params> P(count);
+    for (int i = 0; i < count; ++i) {
+        const pdhg_lp &lp = lps[i];
+        ms[i] = lp.m;
+        ns[i] = lp.n;
+        zs[i] = lp.nnz;
+        if (!lp.row_ptr || !lp.c || !lp.l || !lp.u) return PDHG_E_INVALID;
+        if (lp.nnz > 0 && (!lp.col_idx || !lp.vals)) return PDHG_E_INVALID;
+        if (lp.m > 0 && !lp.b) return PDHG_E_INVALID;
+        if (prm) P[i] = prm[i];
+        else pdhg_default_params(&P[i]);
+        const pdhg_params &p = P[i];
+        if (!(p.omega > 0.0) || !isfinite(p.omega) || !(p.beta > 0.0) || !(p.beta < 1.0) ||
+            p.check_period < 1 || p.tau0 < 1 || p.kkt_kind < 0 || p.kkt_kind > 2 ||
+            isnan(p.eta) || isinf(p.eta) || p.restart_mode < 0 || p.restart_mode > 2)
+            return PDHG_E_INVALID;
+        if (p.restart_mode != P[0].restart_mode || p.check_period != P[0].check_period ||
+            p.kkt_kind != P[0].kkt_kind)
+            return PDHG_E_INVALID;
+    }
+    BLayout L;
+    if (!b_layout(count, ms.data(), ns.data(), zs.data(), &L)) return PDHG_E_INVALID;
+    if (!workspace || ((uintptr_t)workspace & 255u) || workspace_bytes < L.total)
+        return PDHG_E_WORKSPACE;
+    pdhg_batch_t *h = new (std::nothrow) pdhg_batch_handle();
+    if (!h) return PDHG_E_HIP;
+    h->stream = (hipStream_t)stream;
+    h->cap = nullptr;
+    h->gexec = nullptr;
+    h->g_valid = false;
+    h->count = count;
+    h->mode = P[0].restart_mode;
+    h->period = P[0].check_period;
+    h->kkt_kind = P[0].kkt_kind;
+    char *ws = (char *)workspace;
+    BDev &d = h->d;
+    memset(&d, 0, sizeof(d));
+    d.count = count;
+    d.M = L.M;
+    d.N = L.N;
+    d.NNZ = L.NNZ;
+    d.nblk = L.nblk;
+    d.nblkA = L.nblkA;
+    d.nblkT = L.nblkT;
+    d.lp = (BLP *)(ws + L.o_lp);
+    d.err = (int *)(ws + L.o_err);
+    d.rp = (int *)(ws + L.o_rp);
+    d.ci = (int *)(ws + L.o_ci);
+    d.v = (double *)(ws + L.o_v);
+    d.c = (double *)(ws + L.o_c);
+    d.b = (double *)(ws + L.o_b);
+    d.l = (double *)(ws + L.o_l);
+    d.u = (double *)(ws + L.o_u);
+    d.kind = (signed char *)(ws + L.o_kind);
+    d.trp = (int *)(ws + L.o_trp);
+    d.tci = (int *)(ws + L.o_tci);
+    d.perm = (int *)(ws + L.o_perm);
+    d.tv = (double *)(ws + L.o_tv);
+    d.cursor = (int *)(ws + L.o_cursor);
+    d.long_rows = (int *)(ws + L.o_long);
+    d.brA = (int *)(ws + L.o_brA);
+    d.brT = (int *)(ws + L.o_brT);
+    d.lp_row = (int *)(ws + L.o_lprow);
+    d.lp_col = (int *)(ws + L.o_lpcol);
+    d.blk_lp = (int *)(ws + L.o_blklp);
+    d.blk_first = (int *)(ws + L.o_blkfirst);
+    const size_t sn = al(sizeof(double) * (size_t)L.N), sm = al(sizeof(double) * (size_t)(L.M > 0 ? L.M : 1));
+    double **vn[6] = {&d.x, &d.x0, &d.sx, &d.xbar, &d.atyb, &d.aty};
+    double **vm[6] = {&d.y, &d.y0, &d.sy, &d.q, &d.ybar, &d.axb};
+    for (int k = 0; k < 6; ++k) {
+        *vn[k] = (double *)(ws + L.o_vn + k * sn);
+        *vm[k] = (double *)(ws + L.o_vm + k * sm);
+    }
+    d.part = (double *)(ws + L.o_part);
+    d.log = (double *)(ws + L.o_log);
+    d.hcnt = (unsigned int *)(ws + L.o_hcnt);
+    d.hD = (double *)(ws + L.o_hD);
+    d.hA = (double *)(ws + L.o_hA);
+    d.tpart = (double *)(ws + L.o_tpart);
+    d.ccount = (unsigned int *)(ws + L.o_ccount);
+    d.coff = (unsigned int *)(ws + L.o_coff);
+    d.ckey = (unsigned long long *)(ws + L.o_ckey);
+    d.ca = (double *)(ws + L.o_ca);
+    d.cd = (double *)(ws + L.o_cd);
+
+    // host-side tables: per-LP offsets and the element-block table
+    std::vector<BLP> hl((size_t)count);
+    std::vector<int> blk_lp, blk_first;
+    std::vector<double> etas((size_t)count);
+    int roff = 0, coff_ = 0;
+    for (int i = 0; i < count; ++i) {
+        BLP &b = hl[i];
+        memset(&b, 0, sizeof(BLP));
+        b.m = (int)ms[i];
+        b.n = (int)ns[i];
+        b.row_off = roff;
+        b.col_off = coff_;
+        b.blk_begin = (int)blk_lp.size();
+        const int E = b.n + b.m;
+        for (int f = 0; f < E; f += kChunk) {
+            blk_lp.push_back(i);
+            blk_first.push_back(f);
+        }
+        b.blk_end = (int)blk_lp.size();
+        b.omega = P[i].omega;
+        b.beta = P[i].beta;
+        b.sw = sqrt(P[i].omega);
+        b.tau0 = P[i].tau0;
+        b.conv_which = -1;
+        b.conv_k = -1;
+        etas[i] = P[i].eta;
+        roff += b.m;
+        coff_ += b.n;
+    }
+    int rc = PDHG_OK;
+    hipStream_t s = h->stream;
+    double *eta_keep = d.log;  // requested step sizes; the log is written only by checks
+    do {
+        if (hipMemsetAsync(d.err, 0, sizeof(int) * 16, s) != hipSuccess) { rc = PDHG_E_HIP; break; }
+        // validate every LP with the single-LP validation kernel
+        for (int i = 0; i < count; ++i) {
+            Dev vd;
+            memset(&vd, 0, sizeof(vd));
+            vd.m = (int)ms[i];
+            vd.n = (int)ns[i];
+            vd.nnz = (int)zs[i];
+            vd.rp = lps[i].row_ptr;
+            vd.ci = lps[i].col_idx;
+            vd.v = lps[i].vals;
+            vd.c = lps[i].c;
+            vd.b = lps[i].b;
+            vd.l = lps[i].l;
+            vd.u = lps[i].u;
+            vd.kind = (const signed char *)lps[i].row_kind;
+            vd.err = d.err;
+            launch_validate(vd, s);
+        }
+        int err = 0;
+        if (hipMemcpyAsync(&err, d.err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) { rc = PDHG_E_HIP; break; }
+        if (err) { rc = PDHG_E_INVALID; break; }
+        if (hipMemcpyAsync(d.lp, hl.data(), sizeof(BLP) * (size_t)count, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(d.blk_lp, blk_lp.data(), sizeof(int) * blk_lp.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(d.blk_first, blk_first.data(), sizeof(int) * blk_first.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(eta_keep, etas.data(), sizeof(double) * (size_t)count, hipMemcpyHostToDevice, s) != hipSuccess) {
+            rc = PDHG_E_HIP;
+            break;
+        }
+        long long nz_off = 0;
+        for (int i = 0; i < count; ++i) {
+            const BLP &b = hl[i];
+            long long mx = zs[i];
+            if (b.m > mx) mx = b.m;
+            if (b.n > mx) mx = b.n;
+            if (mx > 0)
+                hipLaunchKernelGGL(k_bconcat, dim3(div_up(mx, kWG)), dim3(kWG), 0, s, d, i,
+                                   lps[i].row_ptr, lps[i].col_idx, lps[i].vals, lps[i].c, lps[i].b,
+                                   lps[i].l, lps[i].u, (const signed char *)lps[i].row_kind, b.m,
+                                   b.n, (int)zs[i], b.row_off, b.col_off, (int)nz_off);
+            nz_off += zs[i];
+        }
+        hipLaunchKernelGGL(k_bclose_rp, dim3(1), dim3(1), 0, s, d);
+        // explicit A' of the block-diagonal matrix and the SpMV row splits
+        Dev td;
+        memset(&td, 0, sizeof(td));
+        td.m = d.M;
+        td.n = d.N;
+        td.nnz = d.NNZ;
+        td.rp = d.rp;
+        td.ci = d.ci;
+        td.v = d.v;
+        td.trp = d.trp;
+        td.tci = d.tci;
+        td.perm = d.perm;
+        td.tv = d.tv;
+        td.cursor = d.cursor;
+        td.long_rows = d.long_rows;
+        td.err = d.err;
+        launch_rowsplit(d.rp, d.M, d.NNZ, d.nblkA, d.brA, s);
+        launch_transpose(td, s);
+        launch_rowsplit(d.trp, d.N, d.NNZ, d.nblkT, d.brT, s);
+        hipLaunchKernelGGL(k_bnorm_partials, dim3(d.nblk), dim3(kWG), 0, s, d);
+        hipLaunchKernelGGL(k_bnorm_final, dim3(count), dim3(kWG), 0, s, d);
+        const long long NM = (long long)d.N + d.M;
+        hipLaunchKernelGGL(k_binit, dim3(div_up(NM, kWG)), dim3(kWG), 0, s, d);
+        bspmv_A(d, d.x, d.q, 0, s);
+        if ((rc = b_last_error()) != PDHG_OK) break;
+        // power iteration for the LPs without a given step size
+        bool need_pw = false;
+        for (int i = 0; i < count; ++i) need_pw |= !(etas[i] > 0.0);
+        h->pw_used.assign((size_t)count, 0);
+        if (need_pw) {
+            const int pw_max = P[0].power_iters > 0 ? P[0].power_iters : 1000;
+            const double pw_tol = P[0].power_tol > 0.0 ? P[0].power_tol : 1e-10;
+            hipLaunchKernelGGL(k_bpw_init, dim3(div_up(d.N > count ? d.N : count, kWG)), dim3(kWG), 0, s, d);
+            std::vector<BLP> cur;
+            bool all = false;
+            while (!all && rc == PDHG_OK) {
+                for (int q = 0; q < 25; ++q) {
+                    bspmv_A(d, d.atyb, d.axb, 1, s);
+                    bspmv_T(d, d.axb, d.aty, 1, s);
+                    hipLaunchKernelGGL(k_bpw_partials, dim3(d.nblk), dim3(kWG), 0, s, d);
+                    hipLaunchKernelGGL(k_bpw_final, dim3(count), dim3(kWG), 0, s, d, pw_tol, pw_max);
+                    hipLaunchKernelGGL(k_bpw_norm, dim3(div_up(d.N, kWG)), dim3(kWG), 0, s, d);
+                    hipLaunchKernelGGL(k_bpw_settle, dim3(div_up(count, kWG)), dim3(kWG), 0, s, d);
+                }
+                if ((rc = b_last_error()) != PDHG_OK) break;
+                if ((rc = b_read_lps(h, cur)) != PDHG_OK) break;
+                all = true;
+                for (int i = 0; i < count; ++i) all &= cur[i].pw_done != 0;
+            }
+            if (rc != PDHG_OK) break;
+            for (int i = 0; i < count; ++i) h->pw_used[i] = cur[i].pw_it;
+        }
+        hipLaunchKernelGGL(k_bset_steps, dim3(div_up(count, kWG)), dim3(kWG), 0, s, d, eta_keep);
+        if ((rc = b_last_error()) != PDHG_OK) break;
+        if (hipStreamSynchronize(s) != hipSuccess) { rc = PDHG_E_HIP; break; }
+        if (hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) { rc = PDHG_E_HIP; break; }
+    } while (0);
+    if (rc != PDHG_OK) {
+        if (h->cap) (void)hipStreamDestroy(h->cap);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return PDHG_OK;
+}
+
+void pdhg_batch_destroy(pdhg_batch_t *h) {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
+    delete h;
+}
+
+int pdhg_batch_step(pdhg_batch_t *h, int64_t iters) {
+    if (!h || iters < 0) return PDHG_E_INVALID;
+    for (int64_t i = 0; i < iters; ++i) b_iteration(h->d, h->stream);
+    return b_last_error();
+}
+
+static int b_build_graph(pdhg_batch_t *h, double tol) {
+    if (h->g_valid && h->g_tol == tol) return PDHG_OK;
+    if (h->gexec) {
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+    }
+    h->g_valid = false;
+    hipGraph_t g = nullptr;
+    BCK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < h->period; ++i) b_iteration(h->d, h->cap);
+    b_check(h->d, tol, h->kkt_kind, b_slots(h->mode), h->cap);
+    if (hipStreamEndCapture(h->cap, &g) != hipSuccess) return PDHG_E_HIP;
+    hipError_t e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->gexec = nullptr;
+        return PDHG_E_HIP;
+    }
+    h->g_tol = tol;
+    h->g_valid = true;
+    return PDHG_OK;
+}
+
+int pdhg_batch_solve(pdhg_batch_t *h, int64_t max_iters, double tol, pdhg_result *results) {
+    if (!h || max_iters < 0 || isnan(tol)) return PDHG_E_INVALID;
+    int rc;
+    std::vector<BLP> cur;
+    hipLaunchKernelGGL(k_breset, dim3(div_up(h->count, kWG)), dim3(kWG), 0, h->stream, h->d);
+    if ((rc = b_read_lps(h, cur))) return rc;
+    // every LP of a batch has run the same iterations until it converged;
+    // the schedule follows the LPs that are still running
+    long long k = -1;
+    bool all_done = true;
+    for (int i = 0; i < h->count; ++i)
+        if (!cur[i].done) {
+            all_done = false;
+            if (k < 0) k = cur[i].k;
+        }
+    if (all_done) k = 0;
+    const int64_t P = h->period;
+    const int64_t k_end = k + max_iters;
+    while (!all_done && k < k_end) {
+        if (k % P == 0 && k_end - k >= P) {
+            if ((rc = b_build_graph(h, tol))) return rc;
+            int64_t blocks = (k_end - k) / P, batch = 1;
+            while (blocks > 0 && !all_done) {
+                const int64_t nb = batch < blocks ? batch : blocks;
+                for (int64_t q = 0; q < nb; ++q) BCK(hipGraphLaunch(h->gexec, h->stream));
+                if ((rc = b_read_lps(h, cur))) return rc;
+                blocks -= nb;
+                k += nb * P;
+                all_done = true;
+                for (int i = 0; i < h->count; ++i) {
+                    if (cur[i].numerr) return PDHG_E_NUMERICAL;
+                    all_done &= cur[i].done != 0;
+                }
+                if (batch < 64) batch *= 2;
+            }
+            continue;
+        }
+        const int64_t to_check = P - (k % P);
+        const int64_t sstep = to_check < k_end - k ? to_check : k_end - k;
+        for (int64_t i = 0; i < sstep; ++i) b_iteration(h->d, h->stream);
+        k += sstep;
+        if (k % P == 0) {
+            b_check(h->d, tol, h->kkt_kind, b_slots(h->mode), h->stream);
+            if ((rc = b_last_error())) return rc;
+        }
+        if ((rc = b_read_lps(h, cur))) return rc;
+        all_done = true;
+        for (int i = 0; i < h->count; ++i) {
+            if (cur[i].numerr) return PDHG_E_NUMERICAL;
+            all_done &= cur[i].done != 0;
+        }
+    }
+    if ((rc = b_read_lps(h, cur))) return rc;
+    bool every = true;
+    for (int i = 0; i < h->count; ++i) {
+        const BLP &L = cur[i];
+        every &= L.conv_which >= 0;
+        if (!results) continue;
+        pdhg_result &r = results[i];
+        r.iterations = L.k;
+        r.restarts = L.restarts;
+        r.which_point = L.conv_which;
+        if (L.conv_which >= 0) {
+            const double *k8 = L.conv_which == 1 ? L.kkt_avg : L.kkt_cur;
+            r.status = PDHG_OK;
+            r.kkt = k8[0];
+            r.pobj = k8[4];
+            r.dobj = k8[5];
+        } else {
+            r.status = PDHG_NOT_CONVERGED;
+            r.kkt = L.kkt_cur[0];
+            r.pobj = L.kkt_cur[4];
+            r.dobj = L.kkt_cur[5];
+        }
+    }
+    return every ? PDHG_OK : PDHG_NOT_CONVERGED;
+}
+
+int pdhg_batch_get_iterate(pdhg_batch_t *h, int32_t index, int32_t which, double *x, double *y) {
+    if (!h || index < 0 || index >= h->count || which < 0 || which > 3 || !x) return PDHG_E_INVALID;
+    std::vector<BLP> cur;
+    int rc = b_read_lps(h, cur);
+    if (rc) return rc;
+    const BLP &L = cur[index];
+    if (L.m > 0 && !y) return PDHG_E_INVALID;
+    const int mx = L.n > L.m ? L.n : L.m;
+    hipLaunchKernelGGL(k_bget, dim3(div_up(mx, kWG)), dim3(kWG), 0, h->stream, h->d, index, which, x, y);
+    return b_last_error();
+}
+
+int pdhg_batch_get_info(pdhg_batch_t *h, int32_t index, pdhg_info *out) {
+    if (!h || index < 0 || index >= h->count || !out) return PDHG_E_INVALID;
+    std::vector<BLP> cur;
+    int rc = b_read_lps(h, cur);
+    if (rc) return rc;
+    const BLP &L = cur[index];
+    out->eta = L.eta;
+    out->tau = L.tau;
+    out->sigma = L.sigma;
+    out->sigma_max = L.pw_est;
+    out->k = L.k;
+    out->t = L.t;
+    out->restarts = L.restarts;
+    out->rho_prev = L.rho_prev;
+    out->checks = L.checks;
+    out->power_iters_used = h->pw_used.empty() ? 0 : h->pw_used[index];
+    return PDHG_OK;
+}
+
+int pdhg_batch_get_check_log(pdhg_batch_t *h, int32_t index, pdhg_check_record *out, int64_t max,
+                             int64_t *count) {
+    if (!h || index < 0 || index >= h->count || max < 0 || (max > 0 && !out)) return PDHG_E_INVALID;
+    std::vector<BLP> cur;
+    int rc = b_read_lps(h, cur);
+    if (rc) return rc;
+    const long long checks = cur[index].checks;
+    const int64_t have = checks < kBLog ? checks : kBLog;
+    const int64_t nret = have < max ? have : max;
+    for (int64_t q = 0; q < nret; ++q) {
+        const long long idx = checks - nret + q;
+        const double *src = h->d.log + ((size_t)index * kBLog + (size_t)(idx % kBLog)) * kRec;
+        BCK(hipMemcpyAsync(out[q].v, src, sizeof(double) * kRec, hipMemcpyDeviceToHost, h->stream));
+    }
+    BCK(hipStreamSynchronize(h->stream));
+    if (count) *count = nret;
+    return PDHG_OK;
+}
+
+}  // extern "C"

@@ -51,4 +51,189 @@ __device__ __forceinline__ void reduce_partials(const double *part, int nb, int 
 
 __host__ __device__ inline int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+// ---------------------------------------------------------------------
+// SpMV core
+// ---------------------------------------------------------------------
+template <class Epi>
+__device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const int *__restrict__ ci,
+                                          const double *__restrict__ v,
+                                          const double *__restrict__ xin, int r0, int r1,
+                                          const Epi &epi, double *lds) {
+    const int tid = threadIdx.x;
+    const int p0 = rp[r0], p1 = rp[r1];
+    const int nb = p1 - p0;
+    const int R = r1 - r0;
+    if (nb <= kLdsProducts) {
+        // matrix streams are read once per launch: non-temporal loads keep
+        // them from evicting the gathered vector from L2 and the MALL
+        for (int e = tid; e < nb; e += kWG)
+            lds[e] = __builtin_nontemporal_load(v + p0 + e) *
+                     xin[__builtin_nontemporal_load(ci + p0 + e)];
+        __syncthreads();
+        const int avg = nb / R;
+        int L = 1;
+        while (L < 64 && 2 * L <= avg) L <<= 1;
+        const int G = kWG / L;
+        const int lane = tid & (L - 1), grp = tid / L;
+        for (int rr = grp; rr < R; rr += G) {
+            const int row = r0 + rr;
+            const int s0 = rp[row] - p0, s1 = rp[row + 1] - p0;
+            double s = 0.0;
+            for (int e = s0 + lane; e < s1; e += L) s += lds[e];
+            for (int off = L >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
+            if (lane == 0) epi(row, s);
+        }
+    } else {
+        const int wave = tid >> 6, lane = tid & 63;
+        for (int row = r0 + wave; row < r1; row += kWG / 64) {
+            double s = 0.0;
+            for (int p = rp[row] + lane; p < rp[row + 1]; p += 64)
+                s += __builtin_nontemporal_load(v + p) * xin[__builtin_nontemporal_load(ci + p)];
+            s = wave_sum(s);
+            if (lane == 0) epi(row, s);
+        }
+    }
+}
+
+template <class Epi>
+__global__ __launch_bounds__(kWG) void k_spmv(const int *__restrict__ rp,
+                                              const int *__restrict__ ci,
+                                              const double *__restrict__ v,
+                                              const double *__restrict__ xin,
+                                              const int *__restrict__ br, Epi epi,
+                                              const int *skip) {
+    if (skip && *skip) return;
+    __shared__ double lds[kLdsProducts];
+    const int r0 = br[blockIdx.x], r1 = br[blockIdx.x + 1];
+    if (r0 >= r1) return;
+    spmv_rows(rp, ci, v, xin, r0, r1, epi, lds);
+}
+
+struct EpiStore {
+    double *out;
+    __device__ __forceinline__ void operator()(int r, double s) const { out[r] = s; }
+};
+
+// bit position of the radix digit of level 0..5 (11-bit digits, last 8)
+__host__ __device__ constexpr int shift_of(int level) { return level >= 5 ? 0 : 52 - 11 * level; }
+
+__device__ __forceinline__ unsigned long long key_of(double a, double d) {
+    return (unsigned long long)__double_as_longlong(d / a);
+}
+
+__device__ __forceinline__ bool bad_pair(double a, double d) {
+    return a != a || d != d || a < 0.0 || d < 0.0 || a == INFINITY;
+}
+
+// deterministic exclusive prefix (from the left) and suffix (from the right)
+// of one double per thread
+__device__ double block_excl_prefix(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kWG; off <<= 1) {
+        double o = t >= off ? sh[t - off] : 0.0;
+        __syncthreads();
+        sh[t] += o;
+        __syncthreads();
+    }
+    double r = t ? sh[t - 1] : 0.0;
+    __syncthreads();
+    return r;
+}
+
+__device__ double block_excl_suffix(double v, double *sh) {
+    const int p = kWG - 1 - threadIdx.x;
+    sh[p] = v;
+    __syncthreads();
+    for (int off = 1; off < kWG; off <<= 1) {
+        double o = p >= off ? sh[p - off] : 0.0;
+        __syncthreads();
+        sh[p] += o;
+        __syncthreads();
+    }
+    double r = p ? sh[p - 1] : 0.0;
+    __syncthreads();
+    return r;
+}
+
+struct ChooseShared {
+    double pre[kWG];
+    int best;
+};
+
+// Move the bracket to the last bucket b (of nbuck at bit position `shift`)
+// whose lower end lambda_b keeps
+//   f(lambda_b) = F_acc + sum_{b'<b} D[b'] + lambda_b^2 (A_acc + sum_{b'>=b} A[b'])
+// at most r^2.  ts lives in LDS; called by the whole workgroup.
+__device__ void choose_bucket(TRState &ts, const unsigned int *cnt, const double *D,
+                              const double *A, int nbuck, int level, ChooseShared &cs) {
+    const int shift = shift_of(level);
+    constexpr int per = kBuckets / kWG;
+    const int tid = threadIdx.x;
+    const int b0 = tid * per;
+    double dl[per], al[per];
+    unsigned int cl[per];
+    double Dt = 0.0, At = 0.0;
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        const int b = b0 + k;
+        if (b < nbuck) {
+            dl[k] = D[b];
+            al[k] = A[b];
+            cl[k] = cnt[b];
+        } else {
+            dl[k] = 0.0;
+            al[k] = 0.0;
+            cl[k] = 0u;
+        }
+        Dt += dl[k];
+        At += al[k];
+    }
+    const double Dpre = block_excl_prefix(Dt, cs.pre);
+    const double Asuf = block_excl_suffix(At, cs.pre);
+    double asuf_in[per];
+    double acc = Asuf;
+#pragma unroll
+    for (int k = per - 1; k >= 0; --k) {
+        acc += al[k];
+        asuf_in[k] = acc;
+    }
+    if (tid == 0) cs.best = -1;
+    __syncthreads();
+    const double F0 = ts.F_acc, A0 = ts.A_acc, r2 = ts.r2;
+    const unsigned long long prefix = ts.prefix;
+    double dacc = Dpre;
+    int best = -1;
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        const int b = b0 + k;
+        if (b < nbuck) {
+            const double lam =
+                __longlong_as_double((long long)(prefix | ((unsigned long long)b << shift)));
+            const double f = F0 + dacc + lam * lam * (A0 + asuf_in[k]);
+            if (f <= r2) best = b;
+        }
+        dacc += dl[k];
+    }
+    if (best >= 0) atomicMax(&cs.best, best);
+    __syncthreads();
+    int bb = cs.best;
+    if (bb < 0) bb = 0;  // the bracket's own lower end (f <= r^2 up to rounding)
+    if (bb / per == tid) {
+        const int k = bb - b0;
+        double dpre = Dpre;
+        for (int q = 0; q < k; ++q) dpre += dl[q];
+        const double aex = (k + 1 < per) ? asuf_in[k + 1] : Asuf;
+        ts.F_acc = F0 + dpre;
+        ts.A_acc = A0 + aex;
+        ts.klo = prefix | ((unsigned long long)bb << shift);
+        ts.prefix = ts.klo;
+        ts.count = cl[k];
+        if (ts.count == 0u || level == 5) ts.mode = TR_RESOLVED;
+        else ts.level = level + 1;
+    }
+    __syncthreads();
+}
+
 }  // namespace pdhg

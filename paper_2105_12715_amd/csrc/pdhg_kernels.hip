@@ -32,69 +32,6 @@
 
 namespace pdhg {
 
-// ---------------------------------------------------------------------
-// SpMV core
-// ---------------------------------------------------------------------
-template <class Epi>
-__device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const int *__restrict__ ci,
-                                          const double *__restrict__ v,
-                                          const double *__restrict__ xin, int r0, int r1,
-                                          const Epi &epi, double *lds) {
-    const int tid = threadIdx.x;
-    const int p0 = rp[r0], p1 = rp[r1];
-    const int nb = p1 - p0;
-    const int R = r1 - r0;
-    if (nb <= kLdsProducts) {
-        // matrix streams are read once per launch: non-temporal loads keep
-        // them from evicting the gathered vector from L2 and the MALL
-        for (int e = tid; e < nb; e += kWG)
-            lds[e] = __builtin_nontemporal_load(v + p0 + e) *
-                     xin[__builtin_nontemporal_load(ci + p0 + e)];
-        __syncthreads();
-        const int avg = nb / R;
-        int L = 1;
-        while (L < 64 && 2 * L <= avg) L <<= 1;
-        const int G = kWG / L;
-        const int lane = tid & (L - 1), grp = tid / L;
-        for (int rr = grp; rr < R; rr += G) {
-            const int row = r0 + rr;
-            const int s0 = rp[row] - p0, s1 = rp[row + 1] - p0;
-            double s = 0.0;
-            for (int e = s0 + lane; e < s1; e += L) s += lds[e];
-            for (int off = L >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
-            if (lane == 0) epi(row, s);
-        }
-    } else {
-        const int wave = tid >> 6, lane = tid & 63;
-        for (int row = r0 + wave; row < r1; row += kWG / 64) {
-            double s = 0.0;
-            for (int p = rp[row] + lane; p < rp[row + 1]; p += 64)
-                s += __builtin_nontemporal_load(v + p) * xin[__builtin_nontemporal_load(ci + p)];
-            s = wave_sum(s);
-            if (lane == 0) epi(row, s);
-        }
-    }
-}
-
-template <class Epi>
-__global__ __launch_bounds__(kWG) void k_spmv(const int *__restrict__ rp,
-                                              const int *__restrict__ ci,
-                                              const double *__restrict__ v,
-                                              const double *__restrict__ xin,
-                                              const int *__restrict__ br, Epi epi,
-                                              const int *skip) {
-    if (skip && *skip) return;
-    __shared__ double lds[kLdsProducts];
-    const int r0 = br[blockIdx.x], r1 = br[blockIdx.x + 1];
-    if (r0 >= r1) return;
-    spmv_rows(rp, ci, v, xin, r0, r1, epi, lds);
-}
-
-struct EpiStore {
-    double *out;
-    __device__ __forceinline__ void operator()(int r, double s) const { out[r] = s; }
-};
-
 // x+ = proj_[l,u](x - tau (c - A'y)); sx += x+   (eq. PDHG-update, primal)
 struct EpiPrimal {
     const double *__restrict__ c, *__restrict__ l, *__restrict__ u;

@@ -28,8 +28,6 @@
 
 namespace pdhg {
 
-__constant__ int kShift[6] = {52, 41, 30, 19, 8, 0};
-
 // ---------------------------------------------------------------------
 // coordinate providers
 // ---------------------------------------------------------------------
@@ -73,125 +71,6 @@ struct RawElems {
         dd = d[i];
     }
 };
-
-__device__ __forceinline__ unsigned long long key_of(double a, double d) {
-    return (unsigned long long)__double_as_longlong(d / a);
-}
-
-__device__ __forceinline__ bool bad_pair(double a, double d) {
-    return a != a || d != d || a < 0.0 || d < 0.0 || a == INFINITY;
-}
-
-// deterministic exclusive prefix (from the left) and suffix (from the right)
-// of one double per thread
-__device__ double block_excl_prefix(double v, double *sh) {
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int off = 1; off < kWG; off <<= 1) {
-        double o = t >= off ? sh[t - off] : 0.0;
-        __syncthreads();
-        sh[t] += o;
-        __syncthreads();
-    }
-    double r = t ? sh[t - 1] : 0.0;
-    __syncthreads();
-    return r;
-}
-
-__device__ double block_excl_suffix(double v, double *sh) {
-    const int p = kWG - 1 - threadIdx.x;
-    sh[p] = v;
-    __syncthreads();
-    for (int off = 1; off < kWG; off <<= 1) {
-        double o = p >= off ? sh[p - off] : 0.0;
-        __syncthreads();
-        sh[p] += o;
-        __syncthreads();
-    }
-    double r = p ? sh[p - 1] : 0.0;
-    __syncthreads();
-    return r;
-}
-
-struct ChooseShared {
-    double pre[kWG];
-    int best;
-};
-
-// Move the bracket to the last bucket b (of nbuck at bit position `shift`)
-// whose lower end lambda_b keeps
-//   f(lambda_b) = F_acc + sum_{b'<b} D[b'] + lambda_b^2 (A_acc + sum_{b'>=b} A[b'])
-// at most r^2.  ts lives in LDS; called by the whole workgroup.
-__device__ void choose_bucket(TRState &ts, const unsigned int *cnt, const double *D,
-                              const double *A, int nbuck, int level, ChooseShared &cs) {
-    const int shift = kShift[level];
-    constexpr int per = kBuckets / kWG;
-    const int tid = threadIdx.x;
-    const int b0 = tid * per;
-    double dl[per], al[per];
-    unsigned int cl[per];
-    double Dt = 0.0, At = 0.0;
-#pragma unroll
-    for (int k = 0; k < per; ++k) {
-        const int b = b0 + k;
-        if (b < nbuck) {
-            dl[k] = D[b];
-            al[k] = A[b];
-            cl[k] = cnt[b];
-        } else {
-            dl[k] = 0.0;
-            al[k] = 0.0;
-            cl[k] = 0u;
-        }
-        Dt += dl[k];
-        At += al[k];
-    }
-    const double Dpre = block_excl_prefix(Dt, cs.pre);
-    const double Asuf = block_excl_suffix(At, cs.pre);
-    double asuf_in[per];
-    double acc = Asuf;
-#pragma unroll
-    for (int k = per - 1; k >= 0; --k) {
-        acc += al[k];
-        asuf_in[k] = acc;
-    }
-    if (tid == 0) cs.best = -1;
-    __syncthreads();
-    const double F0 = ts.F_acc, A0 = ts.A_acc, r2 = ts.r2;
-    const unsigned long long prefix = ts.prefix;
-    double dacc = Dpre;
-    int best = -1;
-#pragma unroll
-    for (int k = 0; k < per; ++k) {
-        const int b = b0 + k;
-        if (b < nbuck) {
-            const double lam =
-                __longlong_as_double((long long)(prefix | ((unsigned long long)b << shift)));
-            const double f = F0 + dacc + lam * lam * (A0 + asuf_in[k]);
-            if (f <= r2) best = b;
-        }
-        dacc += dl[k];
-    }
-    if (best >= 0) atomicMax(&cs.best, best);
-    __syncthreads();
-    int bb = cs.best;
-    if (bb < 0) bb = 0;  // the bracket's own lower end (f <= r^2 up to rounding)
-    if (bb / per == tid) {
-        const int k = bb - b0;
-        double dpre = Dpre;
-        for (int q = 0; q < k; ++q) dpre += dl[q];
-        const double aex = (k + 1 < per) ? asuf_in[k + 1] : Asuf;
-        ts.F_acc = F0 + dpre;
-        ts.A_acc = A0 + aex;
-        ts.klo = prefix | ((unsigned long long)bb << shift);
-        ts.prefix = ts.klo;
-        ts.count = cl[k];
-        if (ts.count == 0u || level == 5) ts.mode = TR_RESOLVED;
-        else ts.level = level + 1;
-    }
-    __syncthreads();
-}
 
 // ---------------------------------------------------------------------
 // level 0: exponent histogram over all coordinates + full-box sums
@@ -407,7 +286,7 @@ __global__ __launch_bounds__(kWG) void k_tr_cpass(TRState *ts, TRWork w, const i
         sA[b] = 0.0;
     }
     __syncthreads();
-    const int shift = kShift[level], above = kShift[level - 1];
+    const int shift = shift_of(level), above = shift_of(level - 1);
     const unsigned long long want = ts->prefix >> above;
     const size_t region = (size_t)blockIdx.x * (size_t)cap;
     unsigned int cnt = w.ccount[blockIdx.x];
@@ -467,9 +346,9 @@ __global__ __launch_bounds__(kWG) void k_tr_finish(TRState *ts, TRWork w, const 
     if ((unsigned long long)total > room) total = (unsigned int)room;
     while (sts.mode == TR_SEARCH) {
         const int level = sts.level;
-        const int shift = kShift[level];
+        const int shift = shift_of(level);
         const int nbuck = level == 5 ? 256 : kBuckets;
-        const int above = kShift[level - 1];
+        const int above = shift_of(level - 1);
         const unsigned long long want = sts.prefix >> above;
         for (int b = threadIdx.x; b < kBuckets; b += kWG) {
             scnt[b] = 0u;

@@ -1,0 +1,126 @@
+"""GPU parity of the batched solver: every LP of a batch follows its own
+oracle run (same iterates to 1e-10, same check records, same iteration
+count to 1e-8), whatever the other LPs in the batch do."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_12715_amd import lpgen
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2105_12715_amd import _lib
+    _lib.load(build_if_missing=False)
+    return _lib
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0)
+
+
+def batch_lps():
+    return [
+        lpgen.small_dense(1),
+        lpgen.bernoulli_lp(11, 30, 60, 0.15, lpgen.BOX01, ge_frac=0.4),
+        lpgen.column_count_lp(13, 600, 1300, per_col=5, bounds="mixed_inf", ge_frac=0.5),
+        lpgen.column_count_lp(3, 3000, 7000, counts="powerlaw2", values="loguniform", bounds="mix"),
+        lpgen.small_dense(4),
+        lpgen.column_count_lp(21, 2500, 5000, per_col=5, bounds="box01"),
+    ]
+
+
+def _cmp(o, b, i, tol=1e-10):
+    for which in (0, 1, 2):
+        xo, yo = o.get(which)
+        xg, yg = (t.cpu().numpy() for t in b.get_iterate(i, which))
+        r = rel(np.concatenate([xg, yg]), np.concatenate([xo, yo]))
+        assert r <= tol, (i, which, r)
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_batch_iterates_and_logs_match_oracle(lib, mode):
+    lps = batch_lps()
+    _say("batch iterates mode", mode)
+    etas = [oracle.Oracle(lp).info()["eta"] for lp in lps]
+    orcs = [oracle.Oracle(lp, eta=e, mode=mode) for lp, e in zip(lps, etas)]
+    b = lib.BatchSolver(lps, params=[{"eta": e} for e in etas], restart_mode=mode)
+    done = 0
+    for k in [30, 31, 90, 300, 1000]:
+        b.solve(k - done, 0.0)
+        for o in orcs:
+            o.solve(k - done, 0.0)
+        done = k
+        for i, o in enumerate(orcs):
+            _cmp(o, b, i)
+    for i, o in enumerate(orcs):
+        lo, lg = o.log(), b.check_log(i)
+        assert lo.shape == lg.shape == (33, 14)
+        np.testing.assert_array_equal(lg[:, [0, 1, 2, 9, 10, 11]], lo[:, [0, 1, 2, 9, 10, 11]])
+        for col in (3, 4, 5, 6, 7, 8, 12):
+            np.testing.assert_allclose(lg[:, col], lo[:, col], rtol=1e-9, atol=1e-300)
+
+
+def test_batch_power_iteration_per_lp(lib):
+    lps = batch_lps()
+    _say("batch power iteration")
+    b = lib.BatchSolver(lps)
+    for i, lp in enumerate(lps):
+        oi = oracle.Oracle(lp).info()
+        gi = b.info(i)
+        assert gi["sigma_max"] == pytest.approx(oi["sigma_max"], rel=1e-9)
+        assert gi["eta"] == pytest.approx(0.9 / gi["sigma_max"], rel=1e-15)
+
+
+def test_batch_solve_to_1e8_each_lp_like_its_oracle(lib):
+    lps = batch_lps()[:3] + [lpgen.small_dense(7)]
+    _say("batch solve")
+    etas = [oracle.Oracle(lp).info()["eta"] for lp in lps]
+    b = lib.BatchSolver(lps, params=[{"eta": e} for e in etas])
+    res = b.solve(400_000, 1e-8)
+    for i, (lp, e) in enumerate(zip(lps, etas)):
+        ro = oracle.Oracle(lp, eta=e).solve(400_000, 1e-8)
+        assert ro["status"] == 0 and res[i]["status"] == 0
+        assert res[i]["k"] == ro["k"] and res[i]["restarts"] == ro["restarts"]
+        assert res[i]["kkt"] <= 1e-8
+        x, y = (t.cpu().numpy() for t in b.get_iterate(i, 3))
+        assert oracle.Oracle(lp, eta=0.1).kkt_at(x, y)[0] <= 1.0001e-8
+
+
+def test_batch_of_one_equals_single_solver(lib):
+    lp = batch_lps()[2]
+    _say("batch of one")
+    eta = oracle.Oracle(lp).info()["eta"]
+    b = lib.BatchSolver([lp], params=[{"eta": eta}])
+    s = lib.Solver(lp, eta=eta)
+    b.solve(600, 0.0)
+    s.solve(600, 0.0)
+    xb, yb = (t.cpu().numpy() for t in b.get_iterate(0))
+    xs, ys = (t.cpu().numpy() for t in s.get_iterate(0))
+    assert rel(np.concatenate([xb, yb]), np.concatenate([xs, ys])) <= 1e-12
+    assert b.info(0)["restarts"] == s.info()["restarts"]
+
+
+def test_uneven_batch_members(lib):
+    """Members of the uneven batch workload (sizes drawn per LP)."""
+    lps = [lpgen.batch_member(i) for i in range(4)]
+    _say("uneven batch", [lp.m for lp in lps])
+    etas = [oracle.Oracle(lp).info()["eta"] for lp in lps]
+    orcs = [oracle.Oracle(lp, eta=e) for lp, e in zip(lps, etas)]
+    b = lib.BatchSolver(lps, params=[{"eta": e} for e in etas])
+    b.solve(300, 0.0)
+    for i, o in enumerate(orcs):
+        o.solve(300, 0.0)
+        _cmp(o, b, i)
