@@ -76,6 +76,14 @@ def _load():
     L.orc_power_iteration.restype = d
     L.orc_power_iteration.argtypes = [i64, i64, P, P, P, i32, d]
     L.orc_transpose.argtypes = [i64, i64, P, P, P, P, P, P, P]
+    L.orc_unrolled_grad.restype = d
+    L.orc_unrolled_grad.argtypes = [P, i64, P, P, P, P, P]
+    L.orc_unrolled_tangent.argtypes = [P, i64, P, P, P, P]
+    L.orc_unrolled_value.argtypes = [P, i64, P]
+    L.orc_branch_signature.restype = C.c_uint64
+    L.orc_branch_signature.argtypes = [P, i64]
+    L.orc_restart_iters.restype = i64
+    L.orc_restart_iters.argtypes = [P, i64, P, i64]
     _lib = L
     return L
 
@@ -226,6 +234,35 @@ class Oracle:
         out = np.zeros(self.n)
         self._L.orc_matvec_t(self.h, _p(y), _p(out))
         return out
+
+    def unrolled_grad(self, K, x_target):
+        """Loss |x_K - x_target|^2 after K unrolled iterations from the
+        initial point, and its gradients (c, b, values of A)."""
+        xt = _f64(x_target)
+        gc, gb = np.zeros(self.n), np.zeros(max(self.m, 1))
+        gA = np.zeros(max(int(self._keep[0][-1]), 1))
+        xk = np.zeros(self.n)
+        loss = self._L.orc_unrolled_grad(self.h, int(K), _p(xt), _p(gc), _p(gb), _p(gA), _p(xk))
+        return loss, gc, gb[: self.m], gA[: int(self._keep[0][-1])], xk
+
+    def unrolled_tangent(self, K, dc, db, dA):
+        dc, db, dA = _f64(dc), _f64(db if self.m else np.zeros(1)), _f64(dA if len(dA) else np.zeros(1))
+        out = np.zeros(self.n)
+        self._L.orc_unrolled_tangent(self.h, int(K), _p(dc), _p(db), _p(dA), _p(out))
+        return out
+
+    def unrolled_value(self, K):
+        out = np.zeros(self.n)
+        self._L.orc_unrolled_value(self.h, int(K), _p(out))
+        return out
+
+    def branch_signature(self, K):
+        return int(self._L.orc_branch_signature(self.h, int(K)))
+
+    def restart_iters(self, K):
+        out = np.zeros(4096, np.int64)
+        c = self._L.orc_restart_iters(self.h, int(K), _p(out), 4096)
+        return out[: min(c, 4096)]
 
     def log(self):
         n = self._L.orc_log_len(self.h)

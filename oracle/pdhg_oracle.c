@@ -773,3 +773,274 @@ void orc_pdhg_map(orc_t *o, const double *x, const double *y, double *xo, double
 
 void orc_matvec(orc_t *o, const double *x, double *out) { mat_vec(o, x, out); }
 void orc_matvec_t(orc_t *o, const double *y, double *out) { mat_tvec(o, y, out); }
+
+/* ------------------------------------------------------------------ */
+/* Differentiation of K unrolled restarted-PDHG iterations.             */
+/*                                                                      */
+/* The forward pass is the solve loop above from the initial point with */
+/* no stopping test (checks still decide restarts).  Restart decisions  */
+/* and projection masks are frozen; what remains is the chain rule     */
+/* through eq. PDHG-update, the running average (Algorithm 1) and the   */
+/* restart line of Algorithm 1:                                         */
+/*   u = x - tau (c - A'y),   x+ = proj_X(u)    (derivative: 1 inside)  */
+/*   w = 2 x+ - x,  v = y + sigma (b - A w),  y+ = proj_Y(v)            */
+/*   S_x += x+, S_y += y+; at a restart to the average x = S_x / T      */
+/* The loss is |x_K - x_target|^2 with x_K the primal point after K     */
+/* iterations (including a restart at iteration K).                     */
+/* ------------------------------------------------------------------ */
+static void reinit(orc_t *o)
+{
+    for (int64_t j = 0; j < o->n; ++j) {
+        o->x[j] = clampd(0.0, o->l[j], o->u[j]);
+        o->x0[j] = o->x[j];
+        o->sx[j] = 0.0;
+    }
+    for (int64_t i = 0; i < o->m; ++i) {
+        o->y[i] = 0.0;
+        o->y0[i] = 0.0;
+        o->sy[i] = 0.0;
+    }
+    o->k = 0; o->t = 0; o->nrst = 0; o->rho_prev = 0.0; o->log_len = 0;
+}
+
+typedef struct {
+    int64_t K;
+    double *X, *Y;       /* iterate after step k, k = 0..K (row k) */
+    int8_t *ev;          /* restart after step k: 0 none, 1 to average, 2 to current */
+    int64_t *T;          /* window length of that restart */
+    double **XR, **YR;   /* restart point after step k (when ev[k] == 1) */
+} tape_t;
+
+static void tape_free(tape_t *tp)
+{
+    if (tp->XR) for (int64_t k = 0; k <= tp->K; ++k) { free(tp->XR[k]); free(tp->YR[k]); }
+    free(tp->X); free(tp->Y); free(tp->ev); free(tp->T); free(tp->XR); free(tp->YR);
+}
+
+/* forward pass recording the iterates and the restart events */
+static void unrolled_forward(orc_t *o, int64_t K, tape_t *tp)
+{
+    int64_t n = o->n, m = o->m;
+    tp->K = K;
+    tp->X = dalloc((K + 1) * n);
+    tp->Y = dalloc((K + 1) * (m > 0 ? m : 1));
+    tp->ev = (int8_t *)calloc((size_t)(K + 1), 1);
+    tp->T = (int64_t *)calloc((size_t)(K + 1), sizeof(int64_t));
+    tp->XR = (double **)calloc((size_t)(K + 1), sizeof(double *));
+    tp->YR = (double **)calloc((size_t)(K + 1), sizeof(double *));
+    reinit(o);
+    memcpy(tp->X, o->x, sizeof(double) * (size_t)n);
+    memcpy(tp->Y, o->y, sizeof(double) * (size_t)m);
+    for (int64_t k = 1; k <= K; ++k) {
+        int64_t r0 = o->nrst;
+        pdhg_step1(o);
+        memcpy(tp->X + k * n, o->x, sizeof(double) * (size_t)n);
+        memcpy(tp->Y + k * m, o->y, sizeof(double) * (size_t)m);
+        int64_t tlen = o->t;
+        if (o->mode == ORC_MODE_FIXED && o->fixed_len > 0 && o->t >= o->fixed_len) {
+            average(o, o->xa, o->ya);
+            restart_to(o, o->xa, o->ya, 0.0);
+        } else if (o->k % o->period == 0) {
+            double rec[ORC_REC];
+            orc_check(o, 0.0, rec);
+            if (o->nrst > r0 && rec[10] == 1.0) {
+                tp->ev[k] = 2;
+                tp->T[k] = tlen;
+                continue;
+            }
+        }
+        if (o->nrst > r0) {
+            tp->ev[k] = 1;
+            tp->T[k] = tlen;
+            tp->XR[k] = dalloc(n);
+            tp->YR[k] = dalloc(m);
+            memcpy(tp->XR[k], o->x, sizeof(double) * (size_t)n);
+            memcpy(tp->YR[k], o->y, sizeof(double) * (size_t)m);
+        }
+    }
+}
+
+static const double *tape_x_in(const tape_t *tp, int64_t k, int64_t n)
+{   /* the primal point entering step k */
+    return tp->ev[k - 1] == 1 ? tp->XR[k - 1] : tp->X + (k - 1) * n;
+}
+
+static const double *tape_y_in(const tape_t *tp, int64_t k, int64_t m)
+{
+    return tp->ev[k - 1] == 1 ? tp->YR[k - 1] : tp->Y + (k - 1) * m;
+}
+
+/*
+ * Loss |x_K - x_target|^2 and its gradient with respect to c (n), b (m)
+ * and the stored values of A (nnz, CSR order), by a reverse sweep over
+ * the recorded iterates.  x_K (n) is returned in xK_out when given.
+ */
+double orc_unrolled_grad(orc_t *o, int64_t K, const double *x_target, double *gc,
+                         double *gb, double *gA, double *xK_out)
+{
+    int64_t n = o->n, m = o->m;
+    tape_t tp;
+    memset(&tp, 0, sizeof(tp));
+    unrolled_forward(o, K, &tp);
+    const double *xK = o->x;
+    double loss = 0.0;
+    double *xh = dalloc(n), *yh = dalloc(m), *sxh = dalloc(n), *syh = dalloc(m);
+    double *vh = dalloc(m), *wh = dalloc(n), *uh = dalloc(n), *au = dalloc(m);
+    for (int64_t j = 0; j < n; ++j) {
+        double d = xK[j] - x_target[j];
+        loss += d * d;
+        xh[j] = 2.0 * d;
+    }
+    if (xK_out) memcpy(xK_out, xK, sizeof(double) * (size_t)n);
+    for (int64_t j = 0; j < n; ++j) gc[j] = 0.0;
+    for (int64_t i = 0; i < m; ++i) gb[i] = 0.0;
+    for (int64_t p = 0; p < o->nnz; ++p) gA[p] = 0.0;
+    for (int64_t k = K; k >= 1; --k) {
+        /* restart after step k: x = S_x / T (average) or the current point */
+        if (tp.ev[k] == 1) {
+            double T = (double)tp.T[k];
+            for (int64_t j = 0; j < n; ++j) { sxh[j] = xh[j] / T; xh[j] = 0.0; }
+            for (int64_t i = 0; i < m; ++i) { syh[i] = yh[i] / T; yh[i] = 0.0; }
+        } else if (tp.ev[k] == 2) {
+            for (int64_t j = 0; j < n; ++j) sxh[j] = 0.0;
+            for (int64_t i = 0; i < m; ++i) syh[i] = 0.0;
+        }
+        const double *xin = tape_x_in(&tp, k, n), *yin = tape_y_in(&tp, k, m);
+        const double *xout = tp.X + k * n, *yout = tp.Y + k * m;
+        /* dual half-step */
+        for (int64_t i = 0; i < m; ++i) {
+            int inside = !o->kind[i] || yout[i] > 0.0;
+            vh[i] = inside ? yh[i] + syh[i] : 0.0;
+            gb[i] += o->sigma * vh[i];
+        }
+        mat_tvec(o, vh, wh);
+        for (int64_t j = 0; j < n; ++j) wh[j] = -o->sigma * wh[j];
+        /* primal half-step */
+        for (int64_t j = 0; j < n; ++j) {
+            double tot = xh[j] + sxh[j] + 2.0 * wh[j];
+            int inside = o->l[j] < xout[j] && xout[j] < o->u[j];
+            uh[j] = inside ? tot : 0.0;
+            gc[j] += -o->tau * uh[j];
+        }
+        mat_vec(o, uh, au);
+        for (int64_t i = 0; i < o->m; ++i)
+            for (int32_t p = o->rp[i]; p < o->rp[i + 1]; ++p) {
+                int32_t j = o->ci[p];
+                double w = 2.0 * xout[j] - xin[j];
+                gA[p] += -o->sigma * vh[i] * w + o->tau * yin[i] * uh[j];
+            }
+        for (int64_t j = 0; j < n; ++j) xh[j] = -wh[j] + uh[j];
+        for (int64_t i = 0; i < m; ++i) yh[i] = vh[i] + o->tau * au[i];
+    }
+    free(xh); free(yh); free(sxh); free(syh); free(vh); free(wh); free(uh); free(au);
+    tape_free(&tp);
+    return loss;
+}
+
+/*
+ * Tangent (forward-mode) derivative of x_K in the direction (dc, db, dA)
+ * along the same frozen decisions; dxK (n).
+ */
+void orc_unrolled_tangent(orc_t *o, int64_t K, const double *dc, const double *db,
+                          const double *dA, double *dxK)
+{
+    int64_t n = o->n, m = o->m;
+    tape_t tp;
+    memset(&tp, 0, sizeof(tp));
+    unrolled_forward(o, K, &tp);
+    double *xd = dalloc(n), *yd = dalloc(m), *sxd = dalloc(n), *syd = dalloc(m);
+    double *t1 = dalloc(n), *t2 = dalloc(m), *xo = dalloc(n), *wd = dalloc(n);
+    for (int64_t k = 1; k <= K; ++k) {
+        const double *xin = tape_x_in(&tp, k, n), *yin = tape_y_in(&tp, k, m);
+        const double *xout = tp.X + k * n, *yout = tp.Y + k * m;
+        /* u' = x' - tau (c' - (dA' y + A' y')) */
+        for (int64_t j = 0; j < n; ++j) t1[j] = 0.0;
+        for (int64_t i = 0; i < m; ++i)
+            for (int32_t p = o->rp[i]; p < o->rp[i + 1]; ++p)
+                t1[o->ci[p]] += dA[p] * yin[i] + o->v[p] * yd[i];
+        for (int64_t j = 0; j < n; ++j) {
+            double ud = xd[j] - o->tau * (dc[j] - t1[j]);
+            int inside = o->l[j] < xout[j] && xout[j] < o->u[j];
+            xo[j] = inside ? ud : 0.0;
+            wd[j] = 2.0 * xo[j] - xd[j];
+        }
+        /* v' = y' + sigma (b' - (dA w + A w')) */
+        for (int64_t i = 0; i < m; ++i) {
+            double s = 0.0;
+            for (int32_t p = o->rp[i]; p < o->rp[i + 1]; ++p) {
+                int32_t j = o->ci[p];
+                s += dA[p] * (2.0 * xout[j] - xin[j]) + o->v[p] * wd[j];
+            }
+            double vd = yd[i] + o->sigma * (db[i] - s);
+            int inside = !o->kind[i] || yout[i] > 0.0;
+            t2[i] = inside ? vd : 0.0;
+        }
+        memcpy(xd, xo, sizeof(double) * (size_t)n);
+        memcpy(yd, t2, sizeof(double) * (size_t)m);
+        for (int64_t j = 0; j < n; ++j) sxd[j] += xd[j];
+        for (int64_t i = 0; i < m; ++i) syd[i] += yd[i];
+        if (tp.ev[k] == 1) {
+            double T = (double)tp.T[k];
+            for (int64_t j = 0; j < n; ++j) { xd[j] = sxd[j] / T; sxd[j] = 0.0; }
+            for (int64_t i = 0; i < m; ++i) { yd[i] = syd[i] / T; syd[i] = 0.0; }
+        } else if (tp.ev[k] == 2) {
+            for (int64_t j = 0; j < n; ++j) sxd[j] = 0.0;
+            for (int64_t i = 0; i < m; ++i) syd[i] = 0.0;
+        }
+    }
+    memcpy(dxK, xd, sizeof(double) * (size_t)n);
+    free(xd); free(yd); free(sxd); free(syd); free(t1); free(t2); free(xo); free(wd);
+    tape_free(&tp);
+}
+
+/* x_K of the same forward pass (for finite differences) */
+void orc_unrolled_value(orc_t *o, int64_t K, double *xK)
+{
+    tape_t tp;
+    memset(&tp, 0, sizeof(tp));
+    unrolled_forward(o, K, &tp);
+    memcpy(xK, o->x, sizeof(double) * (size_t)o->n);
+    tape_free(&tp);
+}
+
+/* restart events of the last unrolled forward pass are visible through the
+ * check log; this reports the iterations at which restarts happened */
+int64_t orc_restart_iters(orc_t *o, int64_t K, int64_t *out, int64_t cap)
+{
+    tape_t tp;
+    memset(&tp, 0, sizeof(tp));
+    unrolled_forward(o, K, &tp);
+    int64_t c = 0;
+    for (int64_t k = 1; k <= K; ++k)
+        if (tp.ev[k]) {
+            if (c < cap) out[c] = k;
+            ++c;
+        }
+    tape_free(&tp);
+    return c;
+}
+
+/* Hash of every projection mask and restart event of the unrolled
+ * forward pass: runs with equal hashes took the same piecewise-linear
+ * branch, so finite differences between them see no kink. */
+uint64_t orc_branch_signature(orc_t *o, int64_t K)
+{
+    tape_t tp;
+    memset(&tp, 0, sizeof(tp));
+    unrolled_forward(o, K, &tp);
+    uint64_t h = 1469598103934665603ULL;
+    for (int64_t k = 1; k <= K; ++k) {
+        const double *xo = tp.X + k * o->n, *yo = tp.Y + k * o->m;
+        for (int64_t j = 0; j < o->n; ++j) {
+            uint64_t bit = (o->l[j] < xo[j] && xo[j] < o->u[j]) ? 1u : 0u;
+            h = (h ^ bit) * 1099511628211ULL;
+        }
+        for (int64_t i = 0; i < o->m; ++i) {
+            uint64_t bit = (!o->kind[i] || yo[i] > 0.0) ? 1u : 0u;
+            h = (h ^ bit) * 1099511628211ULL;
+        }
+        h = (h ^ (uint64_t)tp.ev[k]) * 1099511628211ULL;
+    }
+    tape_free(&tp);
+    return h;
+}

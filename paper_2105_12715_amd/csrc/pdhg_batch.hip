@@ -62,6 +62,7 @@ struct BDev {
     int *brA, *brT;
     int nblkA, nblkT;
     int *lp_row, *lp_col;
+    double *tau_col, *sigma_row;  // step of each column / row's LP, 0 once it converged
     int *blk_lp, *blk_first;
     double *x, *y, *x0, *y0, *sx, *sy, *q, *xbar, *ybar, *axb, *atyb, *aty;
     double *part;    // [nblk][kKktSums]
@@ -108,22 +109,15 @@ __global__ __launch_bounds__(kWG) void k_bspmv(const int *__restrict__ rp, const
 struct EpiPrimalB {
     const double *__restrict__ c, *__restrict__ l, *__restrict__ u;
     double *__restrict__ x, *__restrict__ sx;
-    const int *__restrict__ lpc;
-    BLP *lp;
+    const double *__restrict__ tau;
     __device__ __forceinline__ void operator()(int j, double aty) const {
-        BLP &L = lp[lpc[j]];
-        if (L.done) return;
         double g = c[j] - aty;
-        double xn = x[j] - L.tau * g;
+        double xn = x[j] - tau[j] * g;  // tau = 0 leaves a converged LP's x as it is
         const double lo = l[j], hi = u[j];
         if (xn < lo) xn = lo;
         if (xn > hi) xn = hi;
         x[j] = xn;
         sx[j] += xn;
-        if (j == L.col_off) {
-            L.k += 1;
-            L.t += 1;
-        }
     }
 };
 
@@ -131,12 +125,9 @@ struct EpiDualB {
     const double *__restrict__ b;
     const signed char *__restrict__ kind;
     double *__restrict__ y, *__restrict__ sy, *__restrict__ q;
-    const int *__restrict__ lpr;
-    const BLP *lp;
+    const double *__restrict__ sigma;
     __device__ __forceinline__ void operator()(int i, double ax) const {
-        const BLP &L = lp[lpr[i]];
-        if (L.done) return;
-        double yv = y[i] + L.sigma * (b[i] - (2.0 * ax - q[i]));
+        double yv = y[i] + sigma[i] * (b[i] - (2.0 * ax - q[i]));
         if (kind[i] && yv < 0.0) yv = 0.0;
         y[i] = yv;
         sy[i] += yv;
@@ -157,12 +148,42 @@ static void bspmv_T(const BDev &d, const double *in, double *out, int gate_kind,
 }
 
 static void b_iteration(const BDev &d, hipStream_t s) {
-    EpiPrimalB ep{d.c, d.l, d.u, d.x, d.sx, d.lp_col, d.lp};
+    EpiPrimalB ep{d.c, d.l, d.u, d.x, d.sx, d.tau_col};
     hipLaunchKernelGGL(k_bspmv<EpiPrimalB>, dim3(d.nblkT), dim3(kWG), 0, s, d.trp, d.tci, d.tv, d.y,
                        d.brT, ep, d.lp_col, d.lp, 0);
-    EpiDualB ed{d.b, d.kind, d.y, d.sy, d.q, d.lp_row, d.lp};
+    EpiDualB ed{d.b, d.kind, d.y, d.sy, d.q, d.sigma_row};
     hipLaunchKernelGGL(k_bspmv<EpiDualB>, dim3(d.nblkA), dim3(kWG), 0, s, d.rp, d.ci, d.v, d.x,
                        d.brA, ed, d.lp_row, d.lp, 0);
+}
+
+// iteration counters of Algorithm 1 for the LPs still running (every LP
+// of the batch takes the same iterations until it converges)
+__global__ void k_badvance(BDev d, int iters) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.count) return;
+    BLP &L = d.lp[i];
+    if (L.done) return;
+    L.k += iters;
+    L.t += iters;
+}
+
+static void b_iterations(const BDev &d, long long iters, hipStream_t s) {
+    if (iters <= 0) return;
+    for (long long i = 0; i < iters; ++i) b_iteration(d, s);
+    hipLaunchKernelGGL(k_badvance, dim3(div_up(d.count, kWG)), dim3(kWG), 0, s, d, (int)iters);
+}
+
+// per-element step sizes from the LPs (0 for converged LPs)
+__global__ void k_bsteps(BDev d) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d.N) {
+        const BLP &L = d.lp[d.lp_col[i]];
+        d.tau_col[i] = L.done ? 0.0 : L.tau;
+    } else if (i < (long long)d.N + d.M) {
+        const long long r = i - d.N;
+        const BLP &L = d.lp[d.lp_row[r]];
+        d.sigma_row[r] = L.done ? 0.0 : L.sigma;
+    }
 }
 
 // ---------------------------------------------------------------------
@@ -995,6 +1016,7 @@ __global__ void k_bapply(BDev d) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < d.N) {
         const BLP &L = d.lp[d.lp_col[i]];
+        d.tau_col[i] = L.done ? 0.0 : L.tau;
         if (!L.restarted) return;
         if (L.cand == 0) {
             const double v = d.xbar[i];
@@ -1007,6 +1029,7 @@ __global__ void k_bapply(BDev d) {
     } else if (i < (long long)d.N + d.M) {
         const long long r = i - d.N;
         const BLP &L = d.lp[d.lp_row[r]];
+        d.sigma_row[r] = L.done ? 0.0 : L.sigma;
         if (!L.restarted) return;
         if (L.cand == 0) {
             const double v = d.ybar[r];
@@ -1070,7 +1093,7 @@ __global__ void k_bget(BDev d, int lpi, int which, double *ox, double *oy) {
 struct BLayout {
     size_t total;
     size_t o_lp, o_err, o_rp, o_ci, o_v, o_c, o_b, o_l, o_u, o_kind, o_trp, o_tci, o_perm, o_tv;
-    size_t o_cursor, o_long, o_brA, o_brT, o_lprow, o_lpcol, o_blklp, o_blkfirst, o_vn, o_vm;
+    size_t o_cursor, o_long, o_brA, o_brT, o_lprow, o_lpcol, o_tau, o_sig, o_blklp, o_blkfirst, o_vn, o_vm;
     size_t o_part, o_log, o_hcnt, o_hD, o_hA, o_tpart, o_ccount, o_coff, o_ckey, o_ca, o_cd;
     int M, N, NNZ, nblk, nblkA, nblkT;
 };
@@ -1123,6 +1146,8 @@ static bool b_layout(int count, const int64_t *m, const int64_t *n, const int64_
     put(L->o_brT, sizeof(int) * ((size_t)L->nblkT + 1));
     put(L->o_lprow, sizeof(int) * M1);
     put(L->o_lpcol, sizeof(int) * N1);
+    put(L->o_tau, sizeof(double) * N1);
+    put(L->o_sig, sizeof(double) * M1);
     put(L->o_blklp, sizeof(int) * (size_t)nblk);
     put(L->o_blkfirst, sizeof(int) * (size_t)nblk);
     put(L->o_vn, al(sizeof(double) * N1) * 6);
@@ -1258,6 +1283,8 @@ int pdhg_batch_create(int32_t count, const pdhg_lp *lps, const pdhg_params *prm,
     d.brT = (int *)(ws + L.o_brT);
     d.lp_row = (int *)(ws + L.o_lprow);
     d.lp_col = (int *)(ws + L.o_lpcol);
+    d.tau_col = (double *)(ws + L.o_tau);
+    d.sigma_row = (double *)(ws + L.o_sig);
     d.blk_lp = (int *)(ws + L.o_blklp);
     d.blk_first = (int *)(ws + L.o_blkfirst);
     const size_t sn = al(sizeof(double) * (size_t)L.N), sm = al(sizeof(double) * (size_t)(L.M > 0 ? L.M : 1));
@@ -1409,6 +1436,7 @@ int pdhg_batch_create(int32_t count, const pdhg_lp *lps, const pdhg_params *prm,
             for (int i = 0; i < count; ++i) h->pw_used[i] = cur[i].pw_it;
         }
         hipLaunchKernelGGL(k_bset_steps, dim3(div_up(count, kWG)), dim3(kWG), 0, s, d, eta_keep);
+        hipLaunchKernelGGL(k_bsteps, dim3(div_up((long long)d.N + d.M, kWG)), dim3(kWG), 0, s, d);
         if ((rc = b_last_error()) != PDHG_OK) break;
         if (hipStreamSynchronize(s) != hipSuccess) { rc = PDHG_E_HIP; break; }
         if (hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) { rc = PDHG_E_HIP; break; }
@@ -1432,7 +1460,7 @@ void pdhg_batch_destroy(pdhg_batch_t *h) {
 
 int pdhg_batch_step(pdhg_batch_t *h, int64_t iters) {
     if (!h || iters < 0) return PDHG_E_INVALID;
-    for (int64_t i = 0; i < iters; ++i) b_iteration(h->d, h->stream);
+    b_iterations(h->d, iters, h->stream);
     return b_last_error();
 }
 
@@ -1445,7 +1473,7 @@ static int b_build_graph(pdhg_batch_t *h, double tol) {
     h->g_valid = false;
     hipGraph_t g = nullptr;
     BCK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < h->period; ++i) b_iteration(h->d, h->cap);
+    b_iterations(h->d, h->period, h->cap);
     b_check(h->d, tol, h->kkt_kind, b_slots(h->mode), h->cap);
     if (hipStreamEndCapture(h->cap, &g) != hipSuccess) return PDHG_E_HIP;
     hipError_t e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
@@ -1498,7 +1526,7 @@ int pdhg_batch_solve(pdhg_batch_t *h, int64_t max_iters, double tol, pdhg_result
         }
         const int64_t to_check = P - (k % P);
         const int64_t sstep = to_check < k_end - k ? to_check : k_end - k;
-        for (int64_t i = 0; i < sstep; ++i) b_iteration(h->d, h->stream);
+        b_iterations(h->d, sstep, h->stream);
         k += sstep;
         if (k % P == 0) {
             b_check(h->d, tol, h->kkt_kind, b_slots(h->mode), h->stream);
