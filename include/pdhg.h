@@ -286,6 +286,36 @@ int pdhg_batch_get_check_log(pdhg_batch_t *h, int32_t index, pdhg_check_record *
                              int64_t max, int64_t *count);
 void pdhg_batch_destroy(pdhg_batch_t *h);
 
+/* Replace the problem data of the whole batch with device arrays in the
+ * concatenated layout (c: sum n_i, b: sum m_i, vals: sum nnz_i, each LP's
+ * entries in its own CSR order); the sparsity pattern and the step sizes
+ * stay.  Enqueued, no sync. */
+int pdhg_batch_set_data(pdhg_batch_t *h, const double *c, const double *b, const double *vals);
+
+/*
+ * Differentiation of K unrolled restarted-PDHG iterations.  The forward
+ * call puts every LP back at its initial point and runs K iterations with
+ * the configured restart checks (no stopping test), recording into `tape`
+ * (device, pdhg_batch_tape_bytes(h, K) bytes, 256-byte aligned) a
+ * checkpoint of (x, y, A x) at every check boundary (so at every restart)
+ * and each check's restart decision; x_K (concatenated, sum n_i) goes to
+ * device xK when given.  The backward call takes dL/dx_K (device,
+ * concatenated) and writes dL/dc, dL/db and dL/d(values of A) (device,
+ * concatenated; they are overwritten) through the PDHG update
+ * (eq. PDHG-update), the running average and restarts of Algorithm 1 with
+ * the restart decisions and projection masks of the forward pass held
+ * fixed.  Each window between checkpoints is recomputed from its
+ * checkpoint and swept in reverse.  The step sizes are constants.  After
+ * the backward call the batch's iterates are those at the first window's
+ * end; call the forward or a solve before reading them.
+ */
+size_t pdhg_batch_tape_bytes(pdhg_batch_t *h, int64_t K);
+int pdhg_batch_unrolled_forward(pdhg_batch_t *h, int64_t K, void *tape, size_t tape_bytes,
+                                double *xK);
+int pdhg_batch_unrolled_backward(pdhg_batch_t *h, int64_t K, void *tape, size_t tape_bytes,
+                                 const double *dL_dxK, double *grad_c, double *grad_b,
+                                 double *grad_vals);
+
 /* Static text for a return code. */
 const char *pdhg_strerror(int code);
 

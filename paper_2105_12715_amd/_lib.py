@@ -141,6 +141,14 @@ def load(build_if_missing: bool = True):
     L.pdhg_batch_get_info.restype = C.c_int
     L.pdhg_batch_get_check_log.argtypes = [P, i32, P, i64, C.POINTER(i64)]
     L.pdhg_batch_get_check_log.restype = C.c_int
+    L.pdhg_batch_set_data.argtypes = [P, P, P, P]
+    L.pdhg_batch_set_data.restype = C.c_int
+    L.pdhg_batch_tape_bytes.argtypes = [P, i64]
+    L.pdhg_batch_tape_bytes.restype = sz
+    L.pdhg_batch_unrolled_forward.argtypes = [P, i64, P, sz, P]
+    L.pdhg_batch_unrolled_forward.restype = C.c_int
+    L.pdhg_batch_unrolled_backward.argtypes = [P, i64, P, sz, P, P, P, P]
+    L.pdhg_batch_unrolled_backward.restype = C.c_int
     L.pdhg_batch_destroy.argtypes = [P]
     L.pdhg_batch_destroy.restype = None
     L.pdhg_strerror.argtypes = [C.c_int]
@@ -431,6 +439,57 @@ class BatchSolver:
                "pdhg_batch_get_info")
         return {k: getattr(out, k) for k, _ in Info._fields_}
 
+    # -- differentiation -------------------------------------------------
+    @property
+    def sizes(self):
+        return ([d.n for d in self.lps], [d.m for d in self.lps], [d.nnz for d in self.lps])
+
+    def concat_data(self):
+        """(c, b, vals) of the whole batch as concatenated device tensors."""
+        import torch
+        c = torch.cat([d.c for d in self.lps])
+        b = torch.cat([d.b[: d.m] for d in self.lps])
+        v = torch.cat([d.vals[: d.nnz] for d in self.lps])
+        return c, b, v
+
+    def set_data(self, c, b, vals):
+        import torch
+        c = c.detach().to(self.device, torch.float64).contiguous()
+        b = b.detach().to(self.device, torch.float64).contiguous()
+        vals = vals.detach().to(self.device, torch.float64).contiguous()
+        self._data_keep = (c, b, vals)
+        _check(self._L.pdhg_batch_set_data(self.h, _ptr(c), _ptr(b), _ptr(vals)),
+               "pdhg_batch_set_data")
+
+    def unrolled_forward(self, K):
+        """x_K (concatenated) after K unrolled iterations from the initial
+        points, and the tape the backward pass needs."""
+        import torch
+        nbytes = self._L.pdhg_batch_tape_bytes(self.h, int(K))
+        if nbytes == 0:
+            raise PdhgError(E_INVALID, "pdhg_batch_tape_bytes")
+        owner, tape = _dev_workspace(nbytes, self.device)
+        N = sum(d.n for d in self.lps)
+        xk = torch.empty(N, dtype=torch.float64, device=self.device)
+        _check(self._L.pdhg_batch_unrolled_forward(self.h, int(K), _ptr(tape), nbytes, _ptr(xk)),
+               "pdhg_batch_unrolled_forward")
+        return xk, (owner, tape, nbytes, int(K))
+
+    def unrolled_backward(self, tape, dL_dxK):
+        import torch
+        owner, buf, nbytes, K = tape
+        N = sum(d.n for d in self.lps)
+        M = sum(d.m for d in self.lps)
+        Z = sum(d.nnz for d in self.lps)
+        g = dL_dxK.detach().to(self.device, torch.float64).contiguous()
+        gc = torch.empty(N, dtype=torch.float64, device=self.device)
+        gb = torch.empty(max(M, 1), dtype=torch.float64, device=self.device)
+        gA = torch.empty(max(Z, 1), dtype=torch.float64, device=self.device)
+        _check(self._L.pdhg_batch_unrolled_backward(self.h, K, _ptr(buf), nbytes, _ptr(g),
+                                                    _ptr(gc), _ptr(gb), _ptr(gA)),
+               "pdhg_batch_unrolled_backward")
+        return gc, gb[:M], gA[:Z]
+
     def check_log(self, index, max_records=512):
         arr = (CheckRecord * max_records)()
         cnt = C.c_int64()
@@ -438,6 +497,42 @@ class BatchSolver:
                                                 max_records, C.byref(cnt)),
                "pdhg_batch_get_check_log")
         return np.array([arr[i].v[:] for i in range(cnt.value)]).reshape(-1, 14)
+
+
+def _make_unrolled():
+    import torch
+
+    class PDHGUnrolled(torch.autograd.Function):
+        """x_K of K unrolled restarted-PDHG iterations for every LP of a
+        BatchSolver, differentiable in the concatenated (c, b, values of A).
+        Restart decisions and projection masks are those of the forward
+        pass; step sizes are constants."""
+
+        @staticmethod
+        def forward(ctx, c, b, vals, solver, K):
+            solver.set_data(c, b, vals)
+            xk, tape = solver.unrolled_forward(K)
+            ctx.solver = solver
+            ctx.tape = tape
+            return xk
+
+        @staticmethod
+        def backward(ctx, grad_xk):
+            gc, gb, gA = ctx.solver.unrolled_backward(ctx.tape, grad_xk)
+            return gc, gb, gA, None, None
+
+    return PDHGUnrolled
+
+
+_UNROLLED = None
+
+
+def pdhg_unrolled(c, b, vals, solver, K):
+    """Differentiable x_K (see PDHGUnrolled)."""
+    global _UNROLLED
+    if _UNROLLED is None:
+        _UNROLLED = _make_unrolled()
+    return _UNROLLED.apply(c, b, vals, solver, K)
 
 
 def linear_trust_region(a, d, r, device="cuda:0", stream=None):

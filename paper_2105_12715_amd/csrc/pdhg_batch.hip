@@ -44,6 +44,7 @@ struct BLP {
     double kkt_cur[8], kkt_avg[8];
     double r_avg, r_cur;
     int restarted, cand, gap_slots, numerr, in_check, pad1;
+    long long t_check;  // t when the last check started (window length of a restart)
     double nb2, nc2;
     // power iteration
     double pw_est, pw_prev, pw_s;
@@ -483,6 +484,7 @@ __global__ __launch_bounds__(kWG) void k_bkkt_final(BDev d, double tol, int kkt_
         L.in_check = 1;
         L.restarted = 0;
         L.cand = 0;
+        L.t_check = L.t;
         bkkt_point(L, S, 0, L.kkt_cur);
         bkkt_point(L, S, 1, L.kkt_avg);
         const double kc = bkkt_pick(L.kkt_cur, kkt_kind), ka = bkkt_pick(L.kkt_avg, kkt_kind);
@@ -1088,6 +1090,179 @@ __global__ void k_bget(BDev d, int lpi, int which, double *ox, double *oy) {
 }
 
 // ---------------------------------------------------------------------
+// Differentiation of K unrolled iterations (reverse sweep with frozen
+// projection masks and restart decisions).  Forward per iteration:
+//   u = x - tau (c - A'y), x+ = proj_X(u); w = 2x+ - x,
+//   v = y + sigma (b - A w), y+ = proj_Y(v); S_x += x+, S_y += y+,
+// and at a restart to the average x = S_x / T (Algorithm 1).
+// Reverse of one iteration, with xh, yh the adjoints of x+, y+ from later
+// iterations and Sxh, Syh those of the running sums:
+//   vh = mask_y (yh + Syh);                    b^ += sigma vh
+//   wh = -sigma A' vh;  uh = mask_x (xh + Sxh + 2 wh);  c^ += -tau uh
+//   xh <- -wh + uh;     yh <- vh + tau A uh
+//   A^_ij += -sigma vh_i (2x+_j - x_j) + tau y_i uh_j
+// ---------------------------------------------------------------------
+struct Tape {
+    double *cx, *cy, *cq;   // checkpoints (x, y, A x) at every window start
+    int *ev;                // [nwin][count] restart after the window: 0 none, 1 average, 2 current
+    long long *evT;         // window length of that restart
+    double *sx, *sy;        // recomputed iterates of one window: [(P+1)][N], [(P+1)][M]
+    double *xh, *yh, *sxh, *syh, *vh, *uh;
+    int nwin, P;
+    long long K;
+};
+
+__global__ void k_breset_lps(BDev d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.count) return;
+    BLP &L = d.lp[i];
+    L.k = 0;
+    L.t = 0;
+    L.restarts = 0;
+    L.checks = 0;
+    L.rho_prev = 0.0;
+    L.done = 0;
+    L.conv_which = -1;
+    L.conv_k = -1;
+    L.restarted = 0;
+    L.cand = 0;
+    L.in_check = 0;
+    L.numerr = 0;
+    L.t_check = 0;
+    for (int sidx = 0; sidx < kTrSlots; ++sidx) L.tr[sidx].mode = TR_IDLE;
+}
+
+__global__ void k_record_events(BDev d, int *ev, long long *evT) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.count) return;
+    const BLP &L = d.lp[i];
+    ev[i] = L.restarted ? (L.cand ? 2 : 1) : 0;
+    evT[i] = L.t_check;
+}
+
+__global__ void k_adj_event(BDev d, const int *ev, const long long *evT, double *xh, double *yh,
+                            double *sxh, double *syh) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d.N) {
+        const int lp = d.lp_col[i];
+        const int e = ev[lp];
+        if (e == 1) {
+            sxh[i] = xh[i] / (double)evT[lp];
+            xh[i] = 0.0;
+        } else if (e == 2) {
+            sxh[i] = 0.0;
+        }
+    } else if (i < (long long)d.N + d.M) {
+        const long long r = i - d.N;
+        const int lp = d.lp_row[r];
+        const int e = ev[lp];
+        if (e == 1) {
+            syh[r] = yh[r] / (double)evT[lp];
+            yh[r] = 0.0;
+        } else if (e == 2) {
+            syh[r] = 0.0;
+        }
+    }
+}
+
+__global__ void k_adj_dual(BDev d, const double *yt, const double *yh, const double *syh,
+                           double *vh, double *gb) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.M) return;
+    const BLP &L = d.lp[d.lp_row[i]];
+    const bool inside = !d.kind[i] || yt[i] > 0.0;
+    const double v = inside ? yh[i] + syh[i] : 0.0;
+    vh[i] = v;
+    gb[i] += L.sigma * v;
+}
+
+struct EpiAdjPrimal {
+    const double *__restrict__ xt, *__restrict__ l, *__restrict__ u;
+    double *__restrict__ xh, *__restrict__ sxh, *__restrict__ uh, *__restrict__ gc;
+    const int *__restrict__ lpc;
+    const BLP *lp;
+    __device__ __forceinline__ void operator()(int j, double atv) const {
+        const BLP &L = lp[lpc[j]];
+        const double wh = -L.sigma * atv;
+        const double tot = xh[j] + sxh[j] + 2.0 * wh;
+        const bool inside = l[j] < xt[j] && xt[j] < u[j];
+        const double uu = inside ? tot : 0.0;
+        uh[j] = uu;
+        gc[j] += -L.tau * uu;
+        xh[j] = -wh + uu;
+    }
+};
+
+// rows of A: yh_i = vh_i + tau (A uh)_i and the A^ entries of the row
+__global__ __launch_bounds__(kWG) void k_adj_rows(BDev d, const double *__restrict__ uh,
+                                                  const double *__restrict__ xt,
+                                                  const double *__restrict__ xprev,
+                                                  const double *__restrict__ yprev,
+                                                  const double *__restrict__ vh, double *yh,
+                                                  double *gA) {
+    __shared__ double sp[kLdsProducts], sw[kLdsProducts], su[kLdsProducts];
+    const int r0 = d.brA[blockIdx.x], r1 = d.brA[blockIdx.x + 1];
+    if (r0 >= r1) return;
+    const int *rp = d.rp, *ci = d.ci;
+    const double *v = d.v;
+    const int tid = threadIdx.x;
+    const int p0 = rp[r0], p1 = rp[r1], nb = p1 - p0, R = r1 - r0;
+    if (nb <= kLdsProducts) {
+        for (int e = tid; e < nb; e += kWG) {
+            const int j = ci[p0 + e];
+            const double uu = uh[j];
+            sp[e] = v[p0 + e] * uu;
+            sw[e] = 2.0 * xt[j] - xprev[j];
+            su[e] = uu;
+        }
+        __syncthreads();
+        const int avg = nb / R;
+        int L = 1;
+        while (L < 64 && 2 * L <= avg) L <<= 1;
+        const int G = kWG / L, lane = tid & (L - 1), grp = tid / L;
+        for (int rr = grp; rr < R; rr += G) {
+            const int row = r0 + rr;
+            const BLP &LP = d.lp[d.lp_row[row]];
+            const double sig = LP.sigma, tau = LP.tau, vr = vh[row], yr = yprev[row];
+            const int s0 = rp[row] - p0, s1 = rp[row + 1] - p0;
+            double s = 0.0;
+            for (int e = s0 + lane; e < s1; e += L) {
+                s += sp[e];
+                gA[p0 + e] += -sig * vr * sw[e] + tau * yr * su[e];
+            }
+            for (int off = L >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
+            if (lane == 0) yh[row] = vr + tau * s;
+        }
+    } else {
+        const int wave = tid >> 6, lane = tid & 63;
+        for (int row = r0 + wave; row < r1; row += kWG / 64) {
+            const BLP &LP = d.lp[d.lp_row[row]];
+            const double sig = LP.sigma, tau = LP.tau, vr = vh[row], yr = yprev[row];
+            double s = 0.0;
+            for (int p = rp[row] + lane; p < rp[row + 1]; p += 64) {
+                const int j = ci[p];
+                const double uu = uh[j];
+                s += v[p] * uu;
+                gA[p] += -sig * vr * (2.0 * xt[j] - xprev[j]) + tau * yr * uu;
+            }
+            s = wave_sum(s);
+            if (lane == 0) yh[row] = vr + tau * s;
+        }
+    }
+}
+
+__global__ void k_fill_d(double *a, long long len, double v) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) a[i] = v;
+}
+
+// refresh A' values after new A values (entries keep their positions)
+__global__ void k_bgather_tv(BDev d) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < d.NNZ) d.tv[q] = d.v[d.perm[q]];
+}
+
+// ---------------------------------------------------------------------
 // workspace layout
 // ---------------------------------------------------------------------
 struct BLayout {
@@ -1613,6 +1788,175 @@ int pdhg_batch_get_check_log(pdhg_batch_t *h, int32_t index, pdhg_check_record *
     BCK(hipStreamSynchronize(h->stream));
     if (count) *count = nret;
     return PDHG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------
+// unrolled forward / reverse
+// ---------------------------------------------------------------------
+static bool tape_carve(const pdhg_batch_t *h, int64_t K, char *base, Tape *t, size_t *total) {
+    if (K < 0 || K > (int64_t)1 << 40) return false;
+    const BDev &d = h->d;
+    const long long P = h->period;
+    const long long nwin = (K + P - 1) / P;
+    const size_t N = (size_t)d.N, M = (size_t)(d.M > 0 ? d.M : 1), C = (size_t)d.count;
+    size_t o = 0;
+    auto put = [&](size_t bytes) {
+        size_t at = o;
+        o += al(bytes);
+        return at;
+    };
+    const size_t ocx = put(sizeof(double) * N * (size_t)(nwin > 0 ? nwin : 1));
+    const size_t ocy = put(sizeof(double) * M * (size_t)(nwin > 0 ? nwin : 1));
+    const size_t ocq = put(sizeof(double) * M * (size_t)(nwin > 0 ? nwin : 1));
+    const size_t oev = put(sizeof(int) * C * (size_t)(nwin > 0 ? nwin : 1));
+    const size_t oet = put(sizeof(long long) * C * (size_t)(nwin > 0 ? nwin : 1));
+    const size_t osx = put(sizeof(double) * N * (size_t)(P + 1));
+    const size_t osy = put(sizeof(double) * M * (size_t)(P + 1));
+    const size_t oxh = put(sizeof(double) * N), oyh = put(sizeof(double) * M);
+    const size_t osxh = put(sizeof(double) * N), osyh = put(sizeof(double) * M);
+    const size_t ovh = put(sizeof(double) * M), ouh = put(sizeof(double) * N);
+    *total = o;
+    if (base && t) {
+        t->cx = (double *)(base + ocx);
+        t->cy = (double *)(base + ocy);
+        t->cq = (double *)(base + ocq);
+        t->ev = (int *)(base + oev);
+        t->evT = (long long *)(base + oet);
+        t->sx = (double *)(base + osx);
+        t->sy = (double *)(base + osy);
+        t->xh = (double *)(base + oxh);
+        t->yh = (double *)(base + oyh);
+        t->sxh = (double *)(base + osxh);
+        t->syh = (double *)(base + osyh);
+        t->vh = (double *)(base + ovh);
+        t->uh = (double *)(base + ouh);
+        t->nwin = (int)nwin;
+        t->P = (int)P;
+        t->K = K;
+    }
+    return true;
+}
+
+extern "C" {
+
+size_t pdhg_batch_tape_bytes(pdhg_batch_t *h, int64_t K) {
+    if (!h) return 0;
+    size_t total = 0;
+    if (!tape_carve(h, K, nullptr, nullptr, &total)) return 0;
+    return total;
+}
+
+int pdhg_batch_set_data(pdhg_batch_t *h, const double *c, const double *b, const double *vals) {
+    if (!h || !c || (h->d.M > 0 && !b) || (h->d.NNZ > 0 && !vals)) return PDHG_E_INVALID;
+    const BDev &d = h->d;
+    hipStream_t s = h->stream;
+    BCK(hipMemcpyAsync(d.c, c, sizeof(double) * (size_t)d.N, hipMemcpyDeviceToDevice, s));
+    if (d.M > 0) BCK(hipMemcpyAsync(d.b, b, sizeof(double) * (size_t)d.M, hipMemcpyDeviceToDevice, s));
+    if (d.NNZ > 0) {
+        BCK(hipMemcpyAsync(d.v, vals, sizeof(double) * (size_t)d.NNZ, hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(k_bgather_tv, dim3(div_up(d.NNZ, kWG)), dim3(kWG), 0, s, d);
+    }
+    hipLaunchKernelGGL(k_bnorm_partials, dim3(d.nblk), dim3(kWG), 0, s, d);
+    hipLaunchKernelGGL(k_bnorm_final, dim3(d.count), dim3(kWG), 0, s, d);
+    return b_last_error();
+}
+
+int pdhg_batch_unrolled_forward(pdhg_batch_t *h, int64_t K, void *tape, size_t tape_bytes,
+                                double *xK) {
+    if (!h) return PDHG_E_INVALID;
+    Tape t;
+    size_t need = 0;
+    if (!tape_carve(h, K, (char *)tape, &t, &need)) return PDHG_E_INVALID;
+    if (!tape || ((uintptr_t)tape & 255u) || tape_bytes < need) return PDHG_E_WORKSPACE;
+    const BDev &d = h->d;
+    hipStream_t s = h->stream;
+    const long long NM = (long long)d.N + d.M;
+    // every LP back to its initial point with fresh counters
+    hipLaunchKernelGGL(k_breset_lps, dim3(div_up(d.count, kWG)), dim3(kWG), 0, s, d);
+    hipLaunchKernelGGL(k_binit, dim3(div_up(NM, kWG)), dim3(kWG), 0, s, d);
+    bspmv_A(d, d.x, d.q, 0, s);
+    hipLaunchKernelGGL(k_bsteps, dim3(div_up(NM, kWG)), dim3(kWG), 0, s, d);
+    const size_t N = (size_t)d.N, M = (size_t)d.M;
+    for (int w = 0; w < t.nwin; ++w) {
+        BCK(hipMemcpyAsync(t.cx + w * N, d.x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+        if (M) {
+            BCK(hipMemcpyAsync(t.cy + w * M, d.y, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+            BCK(hipMemcpyAsync(t.cq + w * M, d.q, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+        }
+        const long long len = (K - (long long)w * t.P) < t.P ? (K - (long long)w * t.P) : t.P;
+        b_iterations(d, len, s);
+        if (len == t.P) {
+            b_check(d, 0.0, h->kkt_kind, b_slots(h->mode), s);
+            hipLaunchKernelGGL(k_record_events, dim3(div_up(d.count, kWG)), dim3(kWG), 0, s, d,
+                               t.ev + (size_t)w * d.count, t.evT + (size_t)w * d.count);
+        } else {
+            BCK(hipMemsetAsync(t.ev + (size_t)w * d.count, 0, sizeof(int) * (size_t)d.count, s));
+        }
+        int rc = b_last_error();
+        if (rc) return rc;
+    }
+    if (xK) BCK(hipMemcpyAsync(xK, d.x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    return b_last_error();
+}
+
+int pdhg_batch_unrolled_backward(pdhg_batch_t *h, int64_t K, void *tape, size_t tape_bytes,
+                                 const double *dLdx, double *gc, double *gb, double *gA) {
+    if (!h || !dLdx || !gc || (h->d.M > 0 && !gb) || (h->d.NNZ > 0 && !gA)) return PDHG_E_INVALID;
+    Tape t;
+    size_t need = 0;
+    if (!tape_carve(h, K, (char *)tape, &t, &need)) return PDHG_E_INVALID;
+    if (!tape || ((uintptr_t)tape & 255u) || tape_bytes < need) return PDHG_E_WORKSPACE;
+    const BDev &d = h->d;
+    hipStream_t s = h->stream;
+    const size_t N = (size_t)d.N, M = (size_t)d.M;
+    const long long NM = (long long)d.N + d.M;
+    BCK(hipMemcpyAsync(t.xh, dLdx, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_fill_d, dim3(div_up(d.N, kWG)), dim3(kWG), 0, s, t.sxh, (long long)d.N, 0.0);
+    hipLaunchKernelGGL(k_fill_d, dim3(div_up(d.N, kWG)), dim3(kWG), 0, s, gc, (long long)d.N, 0.0);
+    if (M) {
+        hipLaunchKernelGGL(k_fill_d, dim3(div_up(d.M, kWG)), dim3(kWG), 0, s, t.yh, (long long)d.M, 0.0);
+        hipLaunchKernelGGL(k_fill_d, dim3(div_up(d.M, kWG)), dim3(kWG), 0, s, t.syh, (long long)d.M, 0.0);
+        hipLaunchKernelGGL(k_fill_d, dim3(div_up(d.M, kWG)), dim3(kWG), 0, s, gb, (long long)d.M, 0.0);
+    }
+    if (d.NNZ) hipLaunchKernelGGL(k_fill_d, dim3(div_up(d.NNZ, kWG)), dim3(kWG), 0, s, gA, (long long)d.NNZ, 0.0);
+    for (int w = t.nwin - 1; w >= 0; --w) {
+        const long long len = (K - (long long)w * t.P) < t.P ? (K - (long long)w * t.P) : t.P;
+        if (len == t.P)
+            hipLaunchKernelGGL(k_adj_event, dim3(div_up(NM, kWG)), dim3(kWG), 0, s, d,
+                               t.ev + (size_t)w * d.count, t.evT + (size_t)w * d.count, t.xh,
+                               t.yh, t.sxh, t.syh);
+        // recompute the window from its checkpoint, keeping every iterate
+        BCK(hipMemcpyAsync(d.x, t.cx + w * N, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+        BCK(hipMemcpyAsync(t.sx, d.x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+        if (M) {
+            BCK(hipMemcpyAsync(d.y, t.cy + w * M, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+            BCK(hipMemcpyAsync(d.q, t.cq + w * M, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+            BCK(hipMemcpyAsync(t.sy, d.y, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+        }
+        for (long long q = 1; q <= len; ++q) {
+            b_iteration(d, s);
+            BCK(hipMemcpyAsync(t.sx + q * N, d.x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+            if (M) BCK(hipMemcpyAsync(t.sy + q * M, d.y, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+        }
+        for (long long q = len; q >= 1; --q) {
+            const double *xt = t.sx + q * N, *xp = t.sx + (q - 1) * N;
+            const double *yt = t.sy + q * M, *yp = t.sy + (q - 1) * M;
+            if (M)
+                hipLaunchKernelGGL(k_adj_dual, dim3(div_up(d.M, kWG)), dim3(kWG), 0, s, d, yt,
+                                   t.yh, t.syh, t.vh, gb);
+            EpiAdjPrimal ep{xt, d.l, d.u, t.xh, t.sxh, t.uh, gc, d.lp_col, d.lp};
+            hipLaunchKernelGGL(k_spmv<EpiAdjPrimal>, dim3(d.nblkT), dim3(kWG), 0, s, d.trp, d.tci,
+                               d.tv, t.vh, d.brT, ep, (const int *)nullptr);
+            if (M)
+                hipLaunchKernelGGL(k_adj_rows, dim3(d.nblkA), dim3(kWG), 0, s, d, t.uh, xt, xp, yp,
+                                   t.vh, t.yh, gA);
+        }
+        int rc = b_last_error();
+        if (rc) return rc;
+    }
+    return b_last_error();
 }
 
 }  // extern "C"
