@@ -270,3 +270,27 @@ class Oracle:
         if n:
             self._L.orc_log_copy(self.h, _p(out))
         return out
+
+
+def weight_search(lp, omegas, iters, eta):
+    """Primal-weight search of Section 7 (experimental setup): plain PDHG
+    without restarts for `iters` iterations from the initial point at each
+    weight, primal step eta/omega and dual step eta*omega; the criterion is
+    the KKT error ||(h - Kz)^+||_2 (eq. define:K-and-h-for-lp) of the last
+    iterate.  One independent oracle run per weight.  Returns (KKT parts of
+    each run as rows [rel, |p|, |d|, pobj, dobj, paper_abs, max_abs], index
+    of the smallest paper_abs (NaN as +inf, first on ties), x of each run,
+    y of each run)."""
+    parts, xs, ys = [], [], []
+    for om in omegas:
+        o = Oracle(lp, eta=eta, omega=float(om), mode=MODE_NONE)
+        o.step(int(iters))
+        parts.append(o.kkt(0))
+        x, y = o.get(0)
+        xs.append(x)
+        ys.append(y)
+        o.close()
+    parts = np.array(parts)
+    crit = np.where(np.isnan(parts[:, 5]), np.inf, parts[:, 5])
+    best = int(np.argmin(crit)) if np.isfinite(crit).any() else -1
+    return parts, best, np.array(xs), np.array(ys)

@@ -235,3 +235,29 @@ def diff_member(i: int, base_seed: int = 5000, m: int = 5000,
 
 def x_target(i: int, n: int, base_seed: int = 5100) -> np.ndarray:
     return np.random.default_rng(base_seed + i).uniform(0.0, 1.0, size=n)
+
+
+# Sizes (rows, columns, entries) of the four LPs of Table 2.
+TABLE2 = {
+    "qap10": (1820, 4150, 18200),
+    "qap15": (6330, 22275, 94950),
+    "nug08-3rd": (19728, 20448, 139008),
+    "nug20": (15240, 72600, 304800),
+}
+
+
+def paper_shaped(name: str, seed: int = 6000) -> LP:
+    """Planted LP with exactly the size of a Table 2 instance: every column
+    gets floor or ceil of nnz/n distinct uniform rows (the extra entries go
+    to a random set of columns), values +1 or -1 with equal odds, x >= 0,
+    all rows equalities.  A stand-in of the same shape, not the instance."""
+    m, n, nnz = TABLE2[name]
+    rng = np.random.default_rng(seed + sorted(TABLE2).index(name))
+    base, extra = divmod(nnz, n)
+    cnt = np.full(n, base, dtype=np.int64)
+    cnt[rng.permutation(n)[:extra]] += 1
+    rows, cols = _distinct_rows_per_column(rng, m, cnt)
+    vals = np.where(rng.random(rows.size) < 0.5, -1.0, 1.0)
+    l = np.zeros(n)
+    u = np.full(n, INF)
+    return planted_lp(rng, m, n, rows, cols, vals, l, u, name=f"{name}-shaped")
