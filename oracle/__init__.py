@@ -20,6 +20,7 @@ _SRC = os.path.join(_HERE, "pdhg_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 MODE_NONE, MODE_ADAPTIVE, MODE_FLEXIBLE, MODE_FIXED = 0, 1, 2, 3
+METHOD_PDHG, METHOD_EGM = 0, 1
 KKT_RELATIVE, KKT_PAPER_ABS, KKT_MAX_ABS = 0, 1, 2
 REC = 14
 
@@ -51,6 +52,7 @@ def _load():
     L.orc_create.argtypes = [i64, i64, P, P, P, P, P, P, P, P, d, d, d, i32,
                              i32, i32, i32, i32, i32, d]
     L.orc_destroy.argtypes = [P]
+    L.orc_set_method.argtypes = [P, i32]
     L.orc_info.argtypes = [P, P]
     L.orc_step.argtypes = [P, i64]
     L.orc_check.restype = i32
@@ -132,7 +134,8 @@ class Oracle:
 
     def __init__(self, lp, eta=0.0, omega=1.0, beta=float(np.exp(-1.0)),
                  check_period=30, tau0=1, mode=MODE_ADAPTIVE, fixed_len=0,
-                 kkt_kind=KKT_RELATIVE, power_iters=1000, power_tol=1e-10):
+                 kkt_kind=KKT_RELATIVE, power_iters=1000, power_tol=1e-10,
+                 method=METHOD_PDHG):
         L = _load()
         self._L = L
         self.m, self.n = int(lp.m), int(lp.n)
@@ -147,6 +150,8 @@ class Oracle:
                               float(omega), float(beta), int(check_period),
                               int(tau0), int(mode), int(fixed_len),
                               int(kkt_kind), int(power_iters), float(power_tol))
+        self.method = int(method)
+        L.orc_set_method(self.h, self.method)
 
     def close(self):
         if self.h:
@@ -272,10 +277,12 @@ class Oracle:
         return out
 
 
-def weight_search(lp, omegas, iters, eta):
-    """Primal-weight search of Section 7 (experimental setup): plain PDHG
-    without restarts for `iters` iterations from the initial point at each
-    weight, primal step eta/omega and dual step eta*omega; the criterion is
+def weight_search(lp, omegas, iters, eta, method=METHOD_PDHG):
+    """Primal-weight search of Section 7 (experimental setup; the same
+    procedure tunes the extragradient method, appendix on EGM and ADMM):
+    the method without restarts for `iters` iterations from the initial
+    point at each weight, primal step eta/omega and dual step eta*omega; the
+    criterion is
     the KKT error ||(h - Kz)^+||_2 (eq. define:K-and-h-for-lp) of the last
     iterate.  One independent oracle run per weight.  Returns (KKT parts of
     each run as rows [rel, |p|, |d|, pobj, dobj, paper_abs, max_abs], index
@@ -283,7 +290,7 @@ def weight_search(lp, omegas, iters, eta):
     y of each run)."""
     parts, xs, ys = [], [], []
     for om in omegas:
-        o = Oracle(lp, eta=eta, omega=float(om), mode=MODE_NONE)
+        o = Oracle(lp, eta=eta, omega=float(om), mode=MODE_NONE, method=method)
         o.step(int(iters))
         parts.append(o.kkt(0))
         x, y = o.get(0)

@@ -20,8 +20,12 @@
  *     coupling y'(-A)x and g(y) = -b'y + 1_Y, primal step tau = eta/omega and
  *     dual step sigma = eta*omega (footnote to eq. PDHG-update; primal weight
  *     paragraph of Section 7).  The dual step forms A(2x+ - x) literally.
+ *   - Extragradient step (the paper's second method): eq.
+ *     extra-gradient-update with the same F, Z and step sizes; Algorithm 1
+ *     averages its target points z~ (the averaging of Section 2).
  *   - Running average: Algorithm 1, average line, kept as the sum of the
- *     window's iterates divided by its length.
+ *     window's iterates (targets, for the extragradient method) divided by
+ *     its length.
  *   - Restart schemes: Algorithm 1 with eq. adaptive-restart-scheme,
  *     eq. define:t-star (fixed length) and Remark rem:flexible.
  *   - Normalized duality gap: eq. rhorz with L(x,y~)-L(x~,y) = F(z)'(z-z~)
@@ -48,6 +52,9 @@
 #define ORC_MODE_FLEXIBLE 2
 #define ORC_MODE_FIXED 3
 
+#define ORC_METHOD_PDHG 0
+#define ORC_METHOD_EGM 1
+
 #define ORC_KKT_RELATIVE 0
 #define ORC_KKT_PAPER_ABS 1
 #define ORC_KKT_MAX_ABS 2
@@ -62,13 +69,13 @@ typedef struct orc {
     double *c, *b, *l, *u;
     int8_t *kind;
     double eta, omega, tau, sigma, beta, sigma_max;
-    int32_t period, tau0, mode, fixed_len, kkt_kind;
+    int32_t period, tau0, mode, fixed_len, kkt_kind, method;
     /* state */
     double *x, *y, *x0, *y0, *sx, *sy;
     int64_t k, t, nrst;
     double rho_prev;
     /* scratch */
-    double *ax, *aty, *xa, *ya, *axa, *atya, *xn, *yn, *e, *ga, *gd;
+    double *ax, *aty, *xa, *ya, *axa, *atya, *xn, *yn, *e, *ga, *gd, *xt, *yt;
     /* check log */
     double *log;
     int64_t log_len, log_cap;
@@ -448,6 +455,8 @@ orc_t *orc_create(int64_t m, int64_t n, const int32_t *rp, const int32_t *ci,
     o->axa = dalloc(m); o->atya = dalloc(n); o->xn = dalloc(n); o->yn = dalloc(m);
     o->e = dalloc(n > m ? n : m);
     o->ga = dalloc(n + m); o->gd = dalloc(n + m);
+    o->xt = dalloc(n); o->yt = dalloc(m);
+    o->method = ORC_METHOD_PDHG;
     /* initial point (the paper leaves it open): x = proj_X(0), y = 0 */
     for (int64_t j = 0; j < n; ++j) {
         o->x[j] = clampd(0.0, o->l[j], o->u[j]);
@@ -465,7 +474,7 @@ void orc_destroy(orc_t *o)
     free(o->u); free(o->kind); free(o->x); free(o->y); free(o->x0); free(o->y0);
     free(o->sx); free(o->sy); free(o->ax); free(o->aty); free(o->xa); free(o->ya);
     free(o->axa); free(o->atya); free(o->xn); free(o->yn); free(o->e);
-    free(o->ga); free(o->gd); free(o->log);
+    free(o->ga); free(o->gd); free(o->xt); free(o->yt); free(o->log);
     free(o);
 }
 
@@ -526,13 +535,56 @@ static void pdhg_step1(orc_t *o)
     o->k += 1;
 }
 
+/*
+ * One extragradient step (eq. extra-gradient-update) for the LP saddle
+ * problem, F(z) = (c - A'y, Ax - b), with the step scaled per block as in
+ * PDHG (primal tau, dual sigma): the target z~ = proj_Z(z - D F(z)), then
+ * z+ = proj_Z(z - D F(z~)), D = diag(tau I, sigma I).  Four products with
+ * A or A'.  Algorithm 1 averages the targets z~.
+ */
+static void egm_step1(orc_t *o)
+{
+    int64_t n = o->n, m = o->m;
+    /* F at z */
+    mat_tvec(o, o->y, o->aty);
+    mat_vec(o, o->x, o->ax);
+    for (int64_t j = 0; j < n; ++j)
+        o->xt[j] = clampd(o->x[j] - o->tau * (o->c[j] - o->aty[j]), o->l[j], o->u[j]);
+    for (int64_t i = 0; i < m; ++i) {
+        double yy = o->y[i] - o->sigma * (o->ax[i] - o->b[i]);
+        if (o->kind[i] && yy < 0.0) yy = 0.0;
+        o->yt[i] = yy;
+    }
+    /* F at z~, applied from z */
+    mat_tvec(o, o->yt, o->aty);
+    mat_vec(o, o->xt, o->ax);
+    for (int64_t j = 0; j < n; ++j)
+        o->x[j] = clampd(o->x[j] - o->tau * (o->c[j] - o->aty[j]), o->l[j], o->u[j]);
+    for (int64_t i = 0; i < m; ++i) {
+        double yy = o->y[i] - o->sigma * (o->ax[i] - o->b[i]);
+        if (o->kind[i] && yy < 0.0) yy = 0.0;
+        o->y[i] = yy;
+    }
+    for (int64_t j = 0; j < n; ++j) o->sx[j] += o->xt[j];
+    for (int64_t i = 0; i < m; ++i) o->sy[i] += o->yt[i];
+    o->t += 1;
+    o->k += 1;
+}
+
+/* 0: PDHG (eq. PDHG-update), 1: extragradient (eq. extra-gradient-update) */
+void orc_set_method(orc_t *o, int32_t method)
+{
+    o->method = method == ORC_METHOD_EGM ? ORC_METHOD_EGM : ORC_METHOD_PDHG;
+}
+
 /* Inner iterations of Algorithm 1.  With fixed-length restarts
  * (eq. define:t-star) the outer loop restarts as soon as t reaches the
  * length, at any iteration. */
 void orc_step(orc_t *o, int64_t iters)
 {
     for (int64_t s = 0; s < iters; ++s) {
-        pdhg_step1(o);
+        if (o->method == ORC_METHOD_EGM) egm_step1(o);
+        else pdhg_step1(o);
         if (o->mode == ORC_MODE_FIXED && o->fixed_len > 0 && o->t >= o->fixed_len) {
             average(o, o->xa, o->ya);
             restart_to(o, o->xa, o->ya, 0.0);
