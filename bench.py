@@ -13,9 +13,12 @@ Default workload: the large sparse LP, 1,000,000 x 2,000,000 with power-law
 column counts (exponent 2, 1..1000 per column, ~9.1M entries), random-sign
 log-uniform values in [1e-3, 1e3], planted optimum, seed 3.
 
-The roofline figure is for the dominant kernel (the larger of the two
-half-step SpMV kernels), timed with HIP events on the handle's stream right
-after the timed region; algorithmic bytes per launch are
+The roofline figure is for the dominant half-step (A'y with the primal
+update, or A x+ with the dual update), timed with HIP events on the
+handle's stream right after the timed region.  A half-step is one SpMV
+kernel with the update fused, or, where the gathered vector is split into
+column slabs, the slab SpMV kernel plus the kernel that sums its partials
+and applies the update.  Algorithmic bytes per half-step are
     primal: 12 nnz + 60 n + 8 m     dual: 12 nnz + 61 m + 8 n
 (values + int32 indices of A' or A, row pointers, the vector reads and
 writes of the epilogue, and one compulsory read of the gathered vector).
@@ -189,6 +192,9 @@ def main():
     ap.add_argument("--chunk", type=int, default=30_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=200)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB elementwise copy (y = -x, FP64) five times, "
+                         "the yardstick for the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no "
@@ -201,6 +207,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        log("copy calibration: 5 launches, 1073741824 bytes read and written each")
+        return
     _lib.load(build_if_missing=True)
     if args.workload == "batch":
         run_batch(args)

@@ -64,6 +64,12 @@ extern "C" {
 #define PDHG_RESTART_FIXED 3    /* eq. define:t-star with t* = fixed_len          */
 
 /* which KKT error the stopping test uses */
+/* The primal-dual step inside Algorithm 1 (Section 2).  The batched solver
+ * and the unrolled forward/backward passes run PDHG only. */
+#define PDHG_METHOD_PDHG 0 /* eq. PDHG-update: two products per iteration      */
+#define PDHG_METHOD_EGM 1  /* eq. extra-gradient-update: four products; the
+                              window average is over the target points        */
+
 #define PDHG_KKT_RELATIVE 0  /* max of the three relative residuals            */
 #define PDHG_KKT_PAPER_ABS 1 /* ||(h - Kz)^+||_2, eq. define:K-and-h-for-lp    */
 #define PDHG_KKT_MAX_ABS 2   /* max abs primal residual, dual residual, gap    */
@@ -99,6 +105,7 @@ typedef struct pdhg_params {
     int32_t kkt_kind;     /* PDHG_KKT_*                                             */
     int32_t power_iters;  /* power-iteration cap (1000)                             */
     double power_tol;     /* power-iteration relative stop (1e-10)                  */
+    int32_t method;       /* PDHG_METHOD_*: the iteration inside Algorithm 1 (PDHG) */
 } pdhg_params;
 
 typedef struct pdhg_kkt {
@@ -145,12 +152,16 @@ typedef struct pdhg_handle pdhg_t;
 
 /* Fill *p with the defaults above (eta auto, omega 1, beta exp(-1),
  * check_period 30, tau0 1, adaptive restarts, relative KKT,
- * 1000 power iterations, power_tol 1e-10). */
+ * 1000 power iterations, power_tol 1e-10, method PDHG). */
 void pdhg_default_params(pdhg_params *p);
 
 /* Device workspace (bytes, 256-byte aligned start required) that
  * pdhg_create needs for an LP of this size.  Returns 0 for sizes it
- * rejects (negative, n < 1, above int32 range). */
+ * rejects (negative, n < 1, above int32 range).  When the vector a product
+ * gathers is larger than one XCD's L2 (4 MiB; the environment variable
+ * PDHG_SLAB_BYTES overrides the target), the workspace also holds a copy
+ * of A or A' split into column slabs: keep that variable unchanged between
+ * this call and pdhg_create. */
 size_t pdhg_workspace_bytes(int64_t m, int64_t n, int64_t nnz);
 
 /*
@@ -227,11 +238,41 @@ int pdhg_get_transpose(pdhg_t *h, int32_t *t_row_ptr, int32_t *t_col_idx,
                        double *t_vals, int32_t *perm);
 
 /* Run `iters` PDHG iterations exactly as pdhg_step does (no fixed-length
- * restarts) with a HIP event recorded around every kernel on the handle's
- * stream, and return the mean duration in milliseconds of the primal
- * half-step kernel (x+ from A'y, eq. PDHG-update) and of the dual half-step
- * kernel (y+ from A x+).  For throughput measurement.  Syncs. */
+ * restarts) with a HIP event recorded around every half-step on the
+ * handle's stream, and return the mean duration in milliseconds of the
+ * primal half-step (x+ from A'y, eq. PDHG-update) and of the dual half-step
+ * (y+ from A x+); each is one kernel, or two where the product runs over
+ * column slabs (partial sums, then their sum with the update).  For
+ * throughput measurement.  Syncs. */
 int pdhg_time_iterations(pdhg_t *h, int64_t iters, double *ms_primal, double *ms_dual);
+
+/* Primal-weight search of Section 7 (experimental setup).  For each of the
+ * `count` weights omega[w] (host array; every omega > 0; 1 <= count <= 16)
+ * run `iters` (>= 0) iterations of the handle's method (PDHG or
+ * extragradient) without restarts from the initial point, with primal step
+ * eta/omega[w] and dual step eta*omega[w] (eta of the handle).  The copies run side by side: each product streams A or A'
+ * once for all of them.  Then the KKT error of every copy's last iterate
+ * goes to kkt[w] (host array of count; kkt[w].kkt = kkt_paper_abs, the
+ * criterion of Section 7), and *best (host, may be NULL) gets the w with
+ * the smallest kkt_paper_abs (NaN counts as +inf, ties go to the smaller
+ * w; -1 when every copy broke down).  x_out (device, count*n, copy w at
+ * offset w*n) and y_out (device, count*m) receive the last iterates and may
+ * be NULL.  workspace: device, 256-byte aligned, at least
+ * pdhg_weight_search_workspace_bytes(m, n, count) bytes, owned by the
+ * caller and free again on return.  The handle's own iterates, counters
+ * and weight are untouched.  Synchronizes.  Errors: PDHG_E_INVALID for a
+ * bad argument, PDHG_E_WORKSPACE, PDHG_E_HIP. */
+size_t pdhg_weight_search_workspace_bytes(int64_t m, int64_t n, int32_t count);
+int pdhg_weight_search(pdhg_t *h, const double *omega, int32_t count, int64_t iters,
+                       void *workspace, size_t workspace_bytes, pdhg_kkt *kkt,
+                       int32_t *best, double *x_out, double *y_out);
+
+/* Set the primal weight omega (> 0, finite) of the handle (Section 7:
+ * primal step eta/omega, dual step eta*omega, and the omega-weighted norm
+ * of the normalized duality gap), then start the method again from the
+ * initial point: iterates, running sums, counters, restart state and the
+ * check log are reset.  No sync. */
+int pdhg_set_primal_weight(pdhg_t *h, double omega);
 
 /* Release the host handle and its graphs (does not touch caller memory).
  * Synchronizes the stream first.  NULL is ignored. */

@@ -21,6 +21,7 @@ OK, NOT_CONVERGED = 0, 1
 E_INVALID, E_WORKSPACE, E_HIP, E_NUMERICAL = -1, -2, -3, -4
 RESTART_NONE, RESTART_ADAPTIVE, RESTART_FLEXIBLE, RESTART_FIXED = 0, 1, 2, 3
 KKT_RELATIVE, KKT_PAPER_ABS, KKT_MAX_ABS = 0, 1, 2
+METHOD_PDHG, METHOD_EGM = 0, 1
 POINT_CURRENT, POINT_AVERAGE, POINT_ANCHOR, POINT_SOLUTION = 0, 1, 2, 3
 
 
@@ -42,7 +43,7 @@ class Params(C.Structure):
                 ("check_period", C.c_int32), ("tau0", C.c_int32),
                 ("restart_mode", C.c_int32), ("fixed_len", C.c_int32),
                 ("kkt_kind", C.c_int32), ("power_iters", C.c_int32),
-                ("power_tol", C.c_double)]
+                ("power_tol", C.c_double), ("method", C.c_int32)]
 
 
 class KKT(C.Structure):
@@ -121,6 +122,12 @@ def load(build_if_missing: bool = True):
     L.pdhg_get_transpose.restype = C.c_int
     L.pdhg_time_iterations.argtypes = [P, i64, C.POINTER(d), C.POINTER(d)]
     L.pdhg_time_iterations.restype = C.c_int
+    L.pdhg_weight_search_workspace_bytes.argtypes = [i64, i64, i32]
+    L.pdhg_weight_search_workspace_bytes.restype = sz
+    L.pdhg_weight_search.argtypes = [P, P, i32, i64, P, sz, P, C.POINTER(i32), P, P]
+    L.pdhg_weight_search.restype = C.c_int
+    L.pdhg_set_primal_weight.argtypes = [P, d]
+    L.pdhg_set_primal_weight.restype = C.c_int
     L.pdhg_destroy.argtypes = [P]
     L.pdhg_destroy.restype = None
     L.pdhg_trust_region_workspace_bytes.argtypes = [i64]
@@ -202,7 +209,7 @@ class Solver:
     def __init__(self, lp, eta=0.0, omega=1.0, beta=float(np.exp(-1.0)),
                  check_period=30, tau0=1, restart_mode=RESTART_ADAPTIVE,
                  fixed_len=0, kkt_kind=KKT_RELATIVE, power_iters=1000,
-                 power_tol=1e-10, device="cuda:0", stream=None):
+                 power_tol=1e-10, device="cuda:0", stream=None, method=METHOD_PDHG):
         import torch
         L = load()
         self._L = L
@@ -227,7 +234,7 @@ class Solver:
                       self.row_kind.data_ptr() if self.row_kind is not None else None)
         self.params = Params(float(eta), float(omega), float(beta), int(check_period),
                              int(tau0), int(restart_mode), int(fixed_len), int(kkt_kind),
-                             int(power_iters), float(power_tol))
+                             int(power_iters), float(power_tol), int(method))
         nbytes = L.pdhg_workspace_bytes(self.m, self.n, self.nnz)
         if nbytes == 0:
             raise PdhgError(E_INVALID, "pdhg_workspace_bytes")
@@ -325,6 +332,39 @@ class Solver:
         _check(self._L.pdhg_time_iterations(self.h, int(iters), C.byref(a), C.byref(b)),
                "pdhg_time_iterations")
         return a.value, b.value
+
+    # -- primal weight (Section 7) ---------------------------------------
+    def weight_search(self, omegas, iters=5000, want_iterates=False):
+        """Non-restarted PDHG for `iters` iterations at every weight in
+        `omegas` (one pass over A or A' per product for all of them).
+        Returns (list of KKT dicts, index of the smallest kkt_paper_abs,
+        x [count, n] and y [count, m] tensors or None)."""
+        import torch
+        om = np.ascontiguousarray(omegas, dtype=np.float64)
+        cnt = int(om.size)
+        nbytes = self._L.pdhg_weight_search_workspace_bytes(self.m, self.n, cnt)
+        if nbytes == 0:
+            raise PdhgError(E_INVALID, "pdhg_weight_search_workspace_bytes")
+        _own, ws = _dev_workspace(nbytes, self.device)
+        kk = (KKT * cnt)()
+        best = C.c_int32()
+        x = y = None
+        if want_iterates:
+            x = torch.empty(cnt * self.n, dtype=torch.float64, device=self.device)
+            y = torch.empty(max(cnt * self.m, 1), dtype=torch.float64, device=self.device)
+        rc = self._L.pdhg_weight_search(
+            self.h, om.ctypes.data_as(C.c_void_p), cnt, int(iters), _ptr(ws), nbytes,
+            C.cast(kk, C.c_void_p), C.byref(best), _ptr(x) if x is not None else None,
+            _ptr(y) if y is not None else None)
+        _check(rc, "pdhg_weight_search")
+        out = [{k: getattr(kk[w], k) for k, _ in KKT._fields_} for w in range(cnt)]
+        if want_iterates:
+            x = x.view(cnt, self.n)
+            y = y[: cnt * self.m].view(cnt, self.m)
+        return out, int(best.value), x, y
+
+    def set_primal_weight(self, omega):
+        _check(self._L.pdhg_set_primal_weight(self.h, float(omega)), "pdhg_set_primal_weight")
 
     def transpose_csr(self):
         import torch

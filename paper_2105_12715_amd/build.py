@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdhg.so")
-SOURCES = ["pdhg_kernels.hip", "pdhg_tr.hip", "pdhg_api.hip", "pdhg_batch.hip"]
+SOURCES = ["pdhg_kernels.hip", "pdhg_tr.hip", "pdhg_api.hip", "pdhg_batch.hip",
+           "pdhg_weights.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

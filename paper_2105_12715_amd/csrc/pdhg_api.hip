@@ -6,6 +6,7 @@
 // `check_period` iterations plus its check can be recorded once as a HIP
 // graph and replayed; the host reads one status word per batch of replays.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
@@ -37,6 +38,18 @@ namespace pdhg {
 
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Target bytes of the gathered vector per column slab: one XCD's L2 (4 MiB)
+// unless PDHG_SLAB_BYTES overrides it (a tuning knob; read at every
+// workspace-size query and create, so keep it fixed between the two).
+static int64_t slab_slice_bytes() {
+    const char *e = getenv("PDHG_SLAB_BYTES");
+    if (e && *e) {
+        const long long v = atoll(e);
+        if (v >= (64ll << 10) && v <= (1ll << 30)) return v;
+    }
+    return 4ll << 20;
+}
+
 size_t tr_work_bytes(int64_t N) {
     size_t b = 0;
     b += al(sizeof(unsigned int) * 2 * kBuckets);
@@ -46,6 +59,9 @@ size_t tr_work_bytes(int64_t N) {
     size_t n1 = (size_t)(N > 0 ? N : 1) + (size_t)kRedBlocks * kWG;
     b += al(sizeof(unsigned long long) * n1);
     b += al(sizeof(double) * n1) * 2;
+    b += al(sizeof(unsigned int));
+    b += al(sizeof(unsigned long long) * kFinishMax);
+    b += al(sizeof(double) * kFinishMax) * 2;
     return b;
 }
 
@@ -69,6 +85,14 @@ void carve_tr(char *base, int64_t N, TRWork *w) {
     w->ca = (double *)(base + o);
     o += al(sizeof(double) * n1);
     w->cd = (double *)(base + o);
+    o += al(sizeof(double) * n1);
+    w->fcount = (unsigned int *)(base + o);
+    o += al(sizeof(unsigned int));
+    w->fkey = (unsigned long long *)(base + o);
+    o += al(sizeof(unsigned long long) * kFinishMax);
+    w->fa = (double *)(base + o);
+    o += al(sizeof(double) * kFinishMax);
+    w->fd = (double *)(base + o);
 }
 
 bool make_layout(int64_t m, int64_t n, int64_t nnz, Layout *L) {
@@ -106,6 +130,10 @@ bool make_layout(int64_t m, int64_t n, int64_t nnz, Layout *L) {
         L->o_vec_m[k] = o;
         o += al(sizeof(double) * m1);
     }
+    L->o_xt = o;
+    o += al(sizeof(double) * n1);
+    L->o_yt = o;
+    o += al(sizeof(double) * m1);
     L->o_part = o;
     o += al(sizeof(double) * kRedBlocks * kKktSums);
     L->o_log = o;
@@ -113,6 +141,22 @@ bool make_layout(int64_t m, int64_t n, int64_t nnz, Layout *L) {
     for (int sidx = 0; sidx < kTrSlots; ++sidx) {
         L->o_tr[sidx] = o;
         o += tr_work_bytes((int64_t)n1 + (int64_t)(m > 0 ? m : 0));
+    }
+    // column slabs of A and of A' (empty regions when one slab covers the
+    // gathered vector)
+    const int64_t rows_of[2] = {m, n}, gath_of[2] = {n, m};
+    for (int t = 0; t < 2; ++t) {
+        const int S = slab_count_for(rows_of[t], gath_of[t], n, slab_slice_bytes());
+        const size_t Ss = S > 1 ? (size_t)S : 0, zS = S > 1 ? z1 : 0;
+        const size_t r1 = (size_t)(rows_of[t] > 0 ? rows_of[t] : 1);
+        const int nb = t == 0 ? nbA : nbT;
+        const size_t sz[6] = {sizeof(int) * Ss * (r1 + 1), sizeof(int) * zS, sizeof(double) * zS,
+                              sizeof(int) * Ss * ((size_t)nb + 1), sizeof(long long) * 4 * Ss,
+                              sizeof(double) * Ss * r1};
+        for (int k = 0; k < 6; ++k) {
+            L->o_slab[t][k] = o;
+            o += al(sz[k]);
+        }
     }
     L->total = o;
     return true;
@@ -130,6 +174,8 @@ static int gap_slots_for(int mode) {
 static void enqueue_check(pdhg_t *h, double tol, hipStream_t s) {
     const Dev &d = h->d;
     const int *gate = &d.st->done;
+    // the extragradient iterations leave no A x of the current point behind
+    if (h->prm.method == PDHG_METHOD_EGM) launch_spmv_A(d, d.x, d.q, s, gate);
     launch_average(d, s);
     launch_spmv_A(d, d.xbar, d.axb, s, gate);
     launch_spmv_T(d, d.ybar, d.atyb, s, gate);
@@ -145,8 +191,12 @@ static void enqueue_check(pdhg_t *h, double tol, hipStream_t s) {
 
 static void enqueue_iters(pdhg_t *h, int64_t iters, hipStream_t s) {
     for (int64_t i = 0; i < iters; ++i) {
-        launch_primal(h->d, h->tau, s);
-        launch_dual(h->d, h->sigma, s);
+        if (h->prm.method == PDHG_METHOD_EGM) {
+            launch_egm(h->d, h->tau, h->sigma, -1, s);
+        } else {
+            launch_primal(h->d, h->tau, s);
+            launch_dual(h->d, h->sigma, s);
+        }
     }
 }
 
@@ -175,6 +225,7 @@ void pdhg_default_params(pdhg_params *p) {
     p->kkt_kind = PDHG_KKT_RELATIVE;
     p->power_iters = 1000;
     p->power_tol = 1e-10;
+    p->method = PDHG_METHOD_PDHG;
 }
 
 size_t pdhg_workspace_bytes(int64_t m, int64_t n, int64_t nnz) {
@@ -195,6 +246,42 @@ const char *pdhg_strerror(int code) {
     }
 }
 
+// Split the CSR (rp, ci, v) with nblk merge-path blocks into sb.S column
+// slabs (see slab_count_for); one host round trip for the entry count of
+// every slab.
+static int build_slabs(Slabs &sb, const int *rp, const int *ci, const double *v, int nnz,
+                       int nblk, int *scratch, hipStream_t s) {
+    launch_slab_count(sb, rp, ci, scratch, s);
+    int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int q = 0; q < sb.S; ++q)
+        CK(hipMemcpyAsync(&cnt[q], sb.srp + (size_t)q * (sb.rows + 1) + sb.rows, sizeof(int),
+                          hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    long long meta[32];
+    long long eoff = 0, boff = 0;
+    int nbmax = 0;
+    for (int q = 0; q < sb.S; ++q) {
+        const int nb = nblocks_for(sb.rows, cnt[q]);
+        meta[4 * q + 0] = (long long)q * (sb.rows + 1);
+        meta[4 * q + 1] = eoff;
+        meta[4 * q + 2] = boff;
+        meta[4 * q + 3] = nb;
+        eoff += cnt[q];
+        boff += nb + 1;
+        if (nb > nbmax) nbmax = nb;
+    }
+    // every entry lands in exactly one slab; the block tables fit their region
+    if (eoff != nnz || boff > (long long)sb.S * (nblk + 1)) return PDHG_E_INVALID;
+    CK(hipMemcpyAsync(sb.smeta, meta, sizeof(long long) * 4 * sb.S, hipMemcpyHostToDevice, s));
+    CK(hipStreamSynchronize(s));
+    sb.nbmax = nbmax;
+    launch_slab_fill(sb, rp, ci, v, s);
+    for (int q = 0; q < sb.S; ++q)
+        launch_rowsplit(sb.srp + meta[4 * q], sb.rows, cnt[q], (int)meta[4 * q + 3],
+                        sb.sbr + meta[4 * q + 2], s);
+    return last_error();
+}
+
 int pdhg_create(const pdhg_lp *lp, const pdhg_params *prm_in, void *workspace,
                 size_t workspace_bytes, void *stream, pdhg_t **out) {
     if (!out) return PDHG_E_INVALID;
@@ -206,7 +293,8 @@ int pdhg_create(const pdhg_lp *lp, const pdhg_params *prm_in, void *workspace,
     if (!(prm.omega > 0.0) || !isfinite(prm.omega) || !(prm.beta > 0.0) || !(prm.beta < 1.0) ||
         prm.check_period < 1 || prm.tau0 < 1 || prm.restart_mode < 0 || prm.restart_mode > 3 ||
         (prm.restart_mode == PDHG_RESTART_FIXED && prm.fixed_len < 1) || prm.kkt_kind < 0 ||
-        prm.kkt_kind > 2 || isnan(prm.eta) || isinf(prm.eta))
+        prm.kkt_kind > 2 || isnan(prm.eta) || isinf(prm.eta) ||
+        (prm.method != PDHG_METHOD_PDHG && prm.method != PDHG_METHOD_EGM))
         return PDHG_E_INVALID;
     if (prm.power_iters < 1) prm.power_iters = 1000;
     if (!(prm.power_tol > 0.0)) prm.power_tol = 1e-10;
@@ -260,11 +348,28 @@ int pdhg_create(const pdhg_lp *lp, const pdhg_params *prm_in, void *workspace,
     d.atyb = vn[4]; d.aty = vn[5]; d.gx = vn[6]; d.gaty = vn[7];
     d.y = vm[0]; d.y0 = vm[1]; d.sy = vm[2]; d.q = vm[3];
     d.ybar = vm[4]; d.axb = vm[5]; d.gy = vm[6]; d.gax = vm[7];
+    d.xt = (double *)(ws + L.o_xt);
+    d.yt = (double *)(ws + L.o_yt);
     d.part = (double *)(ws + L.o_part);
     d.log = (double *)(ws + L.o_log);
     for (int sidx = 0; sidx < kTrSlots; ++sidx)
         carve_tr(ws + L.o_tr[sidx], (int64_t)d.n + d.m, &d.tr[sidx]);
     d.omega = prm.omega;
+    Slabs *sl[2] = {&d.slA, &d.slT};
+    const int rows_of[2] = {d.m, d.n}, gath_of[2] = {d.n, d.m};
+    for (int t = 0; t < 2; ++t) {
+        Slabs &sb = *sl[t];
+        sb.S = slab_count_for(rows_of[t], gath_of[t], d.n, slab_slice_bytes());
+        sb.W = (int)(((long long)gath_of[t] + sb.S - 1) / sb.S);
+        sb.rows = rows_of[t];
+        sb.nbmax = 0;
+        sb.srp = (int *)(ws + L.o_slab[t][0]);
+        sb.sci = (int *)(ws + L.o_slab[t][1]);
+        sb.sv = (double *)(ws + L.o_slab[t][2]);
+        sb.sbr = (int *)(ws + L.o_slab[t][3]);
+        sb.smeta = (long long *)(ws + L.o_slab[t][4]);
+        sb.spart = (double *)(ws + L.o_slab[t][5]);
+    }
 
     int rc = PDHG_OK;
     do {
@@ -288,6 +393,12 @@ int pdhg_create(const pdhg_lp *lp, const pdhg_params *prm_in, void *workspace,
         launch_rowsplit(d.rp, d.m, d.nnz, d.nblkA, d.brA, s);
         launch_transpose(d, s);
         launch_rowsplit(d.trp, d.n, d.nnz, d.nblkT, d.brT, s);
+        if (d.slA.S > 1 && (rc = build_slabs(d.slA, d.rp, d.ci, d.v, d.nnz, d.nblkA,
+                                             d.long_rows, s)) != PDHG_OK)
+            break;
+        if (d.slT.S > 1 && (rc = build_slabs(d.slT, d.trp, d.tci, d.tv, d.nnz, d.nblkT,
+                                             d.long_rows, s)) != PDHG_OK)
+            break;
         launch_norms(d, s);
         launch_init_point(d, s);
         if ((rc = last_error()) != PDHG_OK) break;
@@ -544,6 +655,103 @@ int pdhg_set_iterate(pdhg_t *h, const double *x, const double *y) {
     return last_error();
 }
 
+size_t pdhg_weight_search_workspace_bytes(int64_t m, int64_t n, int32_t count) {
+    if (m < 0 || n < 1 || count < 1 || count > kWMax) return 0;
+    return wsearch_bytes(m, n, count);
+}
+
+int pdhg_weight_search(pdhg_t *h, const double *omega, int32_t count, int64_t iters,
+                       void *workspace, size_t workspace_bytes, pdhg_kkt *kkt,
+                       int32_t *best, double *x_out, double *y_out) {
+    if (!h || !omega || !kkt || count < 1 || count > kWMax || iters < 0) return PDHG_E_INVALID;
+    for (int w = 0; w < count; ++w)
+        if (!(omega[w] > 0.0) || !isfinite(omega[w])) return PDHG_E_INVALID;
+    const Dev &d = h->d;
+    if (!workspace || ((uintptr_t)workspace & 255u) ||
+        workspace_bytes < wsearch_bytes(d.m, d.n, count))
+        return PDHG_E_WORKSPACE;
+    WArgs a;
+    memset(&a, 0, sizeof(a));
+    a.m = d.m;
+    a.n = d.n;
+    a.W = count;
+    a.egm = h->prm.method == PDHG_METHOD_EGM ? 1 : 0;
+    a.rp = d.rp;
+    a.ci = d.ci;
+    a.v = d.v;
+    a.trp = d.trp;
+    a.tci = d.tci;
+    a.tv = d.tv;
+    a.c = d.c;
+    a.b = d.b;
+    a.l = d.l;
+    a.u = d.u;
+    a.kind = d.kind;
+    a.st = d.st;
+    wsearch_carve((char *)workspace, d.m, d.n, count, &a);
+    for (int w = 0; w < count; ++w) {
+        a.tau[w] = h->eta / omega[w];
+        a.sigma[w] = h->eta * omega[w];
+    }
+    hipStream_t s = h->stream;
+    launch_w_init(a, s);
+    int rc = last_error();
+    if (rc) return rc;
+    // blocks of iterations replayed as one graph, the rest launched directly
+    const int64_t blk = 50;
+    if (iters >= 2 * blk) {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        CK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+        for (int64_t i = 0; i < blk; ++i) launch_w_iter(a, h->cap);
+        CK(hipStreamEndCapture(h->cap, &g));
+        hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return PDHG_E_HIP;
+        for (int64_t i = 0; i + blk <= iters && e == hipSuccess; i += blk)
+            e = hipGraphLaunch(ge, s);
+        (void)hipStreamSynchronize(s);
+        (void)hipGraphExecDestroy(ge);
+        if (e != hipSuccess) return PDHG_E_HIP;
+        for (int64_t i = iters - iters % blk; i < iters; ++i) launch_w_iter(a, s);
+    } else {
+        for (int64_t i = 0; i < iters; ++i) launch_w_iter(a, s);
+    }
+    launch_w_kkt(a, s);
+    if (x_out || y_out) launch_w_extract(a, x_out, d.m > 0 ? y_out : nullptr, s);
+    if ((rc = last_error())) return rc;
+    double out[kWMax * 8];
+    CK(hipMemcpyAsync(out, a.out, sizeof(double) * 8 * count, hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    int32_t bw = -1;
+    for (int w = 0; w < count; ++w) {
+        const double *o = out + 8 * w;
+        pdhg_kkt &k = kkt[w];
+        k.kkt_rel = o[0];
+        k.primal_res = o[1];
+        k.dual_res = o[2];
+        k.pobj = o[3];
+        k.dobj = o[4];
+        k.kkt_paper_abs = o[5];
+        k.kkt_max_abs = o[6];
+        k.kkt = o[5];
+        if (!isnan(o[5]) && (bw < 0 || o[5] < out[8 * bw + 5])) bw = w;
+    }
+    if (best) *best = bw;
+    return PDHG_OK;
+}
+
+int pdhg_set_primal_weight(pdhg_t *h, double omega) {
+    if (!h || !(omega > 0.0) || !isfinite(omega)) return PDHG_E_INVALID;
+    h->prm.omega = omega;
+    h->d.omega = omega;
+    h->tau = h->eta / omega;
+    h->sigma = h->eta * omega;
+    h->g_valid = false;  // the recorded block holds the old step sizes
+    launch_init_point(h->d, h->stream);
+    return last_error();
+}
+
 int pdhg_get_info(pdhg_t *h, pdhg_info *out) {
     if (!h || !out) return PDHG_E_INVALID;
     DevState hs;
@@ -609,7 +817,10 @@ int pdhg_get_transpose(pdhg_t *h, int32_t *t_row_ptr, int32_t *t_col_idx, double
 int pdhg_time_iterations(pdhg_t *h, int64_t iters, double *ms_primal, double *ms_dual) {
     if (!h || iters < 1 || iters > 100000) return PDHG_E_INVALID;
     launch_reset_done(h->d, h->stream);
-    const int64_t ne = 2 * iters + 1;
+    // products per iteration: A'y then A x (PDHG); A'y, A x, A'y~, A x~ (EGM)
+    const bool egm = h->prm.method == PDHG_METHOD_EGM;
+    const int nseg = egm ? 4 : 2;
+    const int64_t ne = nseg * iters + 1;
     hipEvent_t *ev = new (std::nothrow) hipEvent_t[ne];
     if (!ev) return PDHG_E_HIP;
     int64_t made = 0;
@@ -623,21 +834,21 @@ int pdhg_time_iterations(pdhg_t *h, int64_t iters, double *ms_primal, double *ms
         hipStream_t s = h->stream;
         if (hipEventRecord(ev[0], s) != hipSuccess) rc = PDHG_E_HIP;
         for (int64_t i = 0; i < iters && rc == PDHG_OK; ++i) {
-            launch_primal(h->d, h->tau, s);
-            if (hipEventRecord(ev[2 * i + 1], s) != hipSuccess) rc = PDHG_E_HIP;
-            launch_dual(h->d, h->sigma, s);
-            if (hipEventRecord(ev[2 * i + 2], s) != hipSuccess) rc = PDHG_E_HIP;
+            for (int p = 0; p < nseg && rc == PDHG_OK; ++p) {
+                if (egm) launch_egm(h->d, h->tau, h->sigma, p, s);
+                else if (p == 0) launch_primal(h->d, h->tau, s);
+                else launch_dual(h->d, h->sigma, s);
+                if (hipEventRecord(ev[nseg * i + p + 1], s) != hipSuccess) rc = PDHG_E_HIP;
+            }
         }
         if (rc == PDHG_OK) rc = last_error();
         if (rc == PDHG_OK && hipStreamSynchronize(s) != hipSuccess) rc = PDHG_E_HIP;
         double tp = 0.0, td = 0.0;
-        for (int64_t i = 0; i < iters && rc == PDHG_OK; ++i) {
-            float a = 0.f, b = 0.f;
-            if (hipEventElapsedTime(&a, ev[2 * i], ev[2 * i + 1]) != hipSuccess ||
-                hipEventElapsedTime(&b, ev[2 * i + 1], ev[2 * i + 2]) != hipSuccess)
-                rc = PDHG_E_HIP;
-            tp += a;
-            td += b;
+        for (int64_t q = 0; q + 1 < ne && rc == PDHG_OK; ++q) {
+            float a = 0.f;
+            if (hipEventElapsedTime(&a, ev[q], ev[q + 1]) != hipSuccess) rc = PDHG_E_HIP;
+            if ((q % nseg) % 2 == 0) tp += a;
+            else td += a;
         }
         if (rc == PDHG_OK) {
             if (ms_primal) *ms_primal = tp / (double)iters;

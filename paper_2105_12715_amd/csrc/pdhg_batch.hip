@@ -19,6 +19,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -28,6 +29,7 @@
 namespace pdhg {
 
 constexpr int kChunk = 2048;  // elements per block of the per-LP passes
+constexpr int kXcds = 8;      // accelerator dies; workgroup i runs on die i mod 8
 constexpr int kBLog = 512;    // check records kept per LP
 
 struct BLP {
@@ -62,6 +64,8 @@ struct BDev {
     int *cursor, *long_rows;
     int *brA, *brT;
     int nblkA, nblkT;
+    int *xpA, *xpT;        // workgroup -> merge-path block (XCD placement), -1: none
+    int nslotA, nslotT;    // workgroups of the SpMV launches
     int *lp_row, *lp_col;
     double *tau_col, *sigma_row;  // step of each column / row's LP, 0 once it converged
     int *blk_lp, *blk_first;
@@ -89,15 +93,20 @@ __device__ __forceinline__ bool elem_is_x(const BLP &L, int e) { return e < L.n;
 // ---------------------------------------------------------------------
 // SpMV over the block-diagonal matrix; blocks of converged LPs exit
 // ---------------------------------------------------------------------
+// Workgroup i runs on XCD i mod 8; xp maps it to a merge-path block so that
+// all blocks of one LP share an XCD (and its L2 holds that LP's gathered
+// vector), or to -1 for padding.
 template <class Epi>
 __global__ __launch_bounds__(kWG) void k_bspmv(const int *__restrict__ rp, const int *__restrict__ ci,
                                                const double *__restrict__ v,
                                                const double *__restrict__ xin,
                                                const int *__restrict__ br, Epi epi,
                                                const int *__restrict__ lp_of, const BLP *lps,
-                                               int gate_kind) {
+                                               int gate_kind, const int *__restrict__ xp) {
     __shared__ double lds[kLdsProducts];
-    const int r0 = br[blockIdx.x], r1 = br[blockIdx.x + 1];
+    const int c = xp[blockIdx.x];
+    if (c < 0) return;
+    const int r0 = br[c], r1 = br[c + 1];
     if (r0 >= r1) return;
     const int a = lp_of[r0], z = lp_of[r1 - 1];
     if (a == z) {
@@ -138,23 +147,23 @@ struct EpiDualB {
 
 static void bspmv_A(const BDev &d, const double *in, double *out, int gate_kind, hipStream_t s) {
     EpiStore e{out};
-    hipLaunchKernelGGL(k_bspmv<EpiStore>, dim3(d.nblkA), dim3(kWG), 0, s, d.rp, d.ci, d.v, in,
-                       d.brA, e, d.lp_row, d.lp, gate_kind);
+    hipLaunchKernelGGL(k_bspmv<EpiStore>, dim3(d.nslotA), dim3(kWG), 0, s, d.rp, d.ci, d.v, in,
+                       d.brA, e, d.lp_row, d.lp, gate_kind, d.xpA);
 }
 
 static void bspmv_T(const BDev &d, const double *in, double *out, int gate_kind, hipStream_t s) {
     EpiStore e{out};
-    hipLaunchKernelGGL(k_bspmv<EpiStore>, dim3(d.nblkT), dim3(kWG), 0, s, d.trp, d.tci, d.tv, in,
-                       d.brT, e, d.lp_col, d.lp, gate_kind);
+    hipLaunchKernelGGL(k_bspmv<EpiStore>, dim3(d.nslotT), dim3(kWG), 0, s, d.trp, d.tci, d.tv, in,
+                       d.brT, e, d.lp_col, d.lp, gate_kind, d.xpT);
 }
 
 static void b_iteration(const BDev &d, hipStream_t s) {
     EpiPrimalB ep{d.c, d.l, d.u, d.x, d.sx, d.tau_col};
-    hipLaunchKernelGGL(k_bspmv<EpiPrimalB>, dim3(d.nblkT), dim3(kWG), 0, s, d.trp, d.tci, d.tv, d.y,
-                       d.brT, ep, d.lp_col, d.lp, 0);
+    hipLaunchKernelGGL(k_bspmv<EpiPrimalB>, dim3(d.nslotT), dim3(kWG), 0, s, d.trp, d.tci, d.tv,
+                       d.y, d.brT, ep, d.lp_col, d.lp, 0, d.xpT);
     EpiDualB ed{d.b, d.kind, d.y, d.sy, d.q, d.sigma_row};
-    hipLaunchKernelGGL(k_bspmv<EpiDualB>, dim3(d.nblkA), dim3(kWG), 0, s, d.rp, d.ci, d.v, d.x,
-                       d.brA, ed, d.lp_row, d.lp, 0);
+    hipLaunchKernelGGL(k_bspmv<EpiDualB>, dim3(d.nslotA), dim3(kWG), 0, s, d.rp, d.ci, d.v, d.x,
+                       d.brA, ed, d.lp_row, d.lp, 0, d.xpA);
 }
 
 // iteration counters of Algorithm 1 for the LPs still running (every LP
@@ -1268,6 +1277,7 @@ __global__ void k_bgather_tv(BDev d) {
 struct BLayout {
     size_t total;
     size_t o_lp, o_err, o_rp, o_ci, o_v, o_c, o_b, o_l, o_u, o_kind, o_trp, o_tci, o_perm, o_tv;
+    size_t o_xpA, o_xpT;
     size_t o_cursor, o_long, o_brA, o_brT, o_lprow, o_lpcol, o_tau, o_sig, o_blklp, o_blkfirst, o_vn, o_vm;
     size_t o_part, o_log, o_hcnt, o_hD, o_hA, o_tpart, o_ccount, o_coff, o_ckey, o_ca, o_cd;
     int M, N, NNZ, nblk, nblkA, nblkT;
@@ -1319,6 +1329,8 @@ static bool b_layout(int count, const int64_t *m, const int64_t *n, const int64_
     put(L->o_long, sizeof(int) * N1);
     put(L->o_brA, sizeof(int) * ((size_t)L->nblkA + 1));
     put(L->o_brT, sizeof(int) * ((size_t)L->nblkT + 1));
+    put(L->o_xpA, sizeof(int) * kXcds * ((size_t)L->nblkA + 1));
+    put(L->o_xpT, sizeof(int) * kXcds * ((size_t)L->nblkT + 1));
     put(L->o_lprow, sizeof(int) * M1);
     put(L->o_lpcol, sizeof(int) * N1);
     put(L->o_tau, sizeof(double) * N1);
@@ -1340,6 +1352,42 @@ static bool b_layout(int count, const int64_t *m, const int64_t *n, const int64_
     put(L->o_cd, sizeof(double) * kTrSlots * (size_t)nblk * kChunk);
     L->total = o;
     return true;
+}
+
+// Placement of merge-path blocks on XCDs.  br (host copy, nblk + 1 row
+// starts) and off (LP row starts, count + 1) give each non-empty block the
+// LP of its first row; LPs go to XCDs largest first, each to the XCD with
+// the fewest blocks so far; workgroup 8 j + x then runs the j-th block of
+// XCD x (-1 past the end of its list).  Returns the workgroup count.
+static int place_blocks(const std::vector<int> &br, const std::vector<int> &off, int count,
+                        std::vector<int> &xp) {
+    const int nblk = (int)br.size() - 1;
+    std::vector<std::vector<int>> of_lp((size_t)count);
+    for (int c = 0, lp = 0; c < nblk; ++c) {
+        const int r0 = br[c];
+        if (r0 >= br[c + 1]) continue;
+        while (lp + 1 < count && off[lp + 1] <= r0) ++lp;
+        of_lp[lp].push_back(c);
+    }
+    std::vector<int> order((size_t)count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return of_lp[a].size() > of_lp[b].size();
+    });
+    std::vector<std::vector<int>> lists(kXcds);
+    for (int i : order) {
+        int best = 0;
+        for (int x = 1; x < kXcds; ++x)
+            if (lists[x].size() < lists[best].size()) best = x;
+        lists[best].insert(lists[best].end(), of_lp[i].begin(), of_lp[i].end());
+    }
+    size_t len = 0;
+    for (const auto &l : lists) len = l.size() > len ? l.size() : len;
+    if (len == 0) len = 1;
+    xp.assign(len * kXcds, -1);
+    for (int x = 0; x < kXcds; ++x)
+        for (size_t j = 0; j < lists[x].size(); ++j) xp[j * kXcds + x] = lists[x][j];
+    return (int)xp.size();
 }
 
 }  // namespace pdhg
@@ -1408,7 +1456,8 @@ int pdhg_batch_create(int32_t count, const pdhg_lp *lps, const pdhg_params *prm,
         const pdhg_params &p = P[i];
         if (!(p.omega > 0.0) || !isfinite(p.omega) || !(p.beta > 0.0) || !(p.beta < 1.0) ||
             p.check_period < 1 || p.tau0 < 1 || p.kkt_kind < 0 || p.kkt_kind > 2 ||
-            isnan(p.eta) || isinf(p.eta) || p.restart_mode < 0 || p.restart_mode > 2)
+            isnan(p.eta) || isinf(p.eta) || p.restart_mode < 0 || p.restart_mode > 2 ||
+            p.method != PDHG_METHOD_PDHG)
             return PDHG_E_INVALID;
         if (p.restart_mode != P[0].restart_mode || p.check_period != P[0].check_period ||
             p.kkt_kind != P[0].kkt_kind)
@@ -1456,6 +1505,8 @@ int pdhg_batch_create(int32_t count, const pdhg_lp *lps, const pdhg_params *prm,
     d.long_rows = (int *)(ws + L.o_long);
     d.brA = (int *)(ws + L.o_brA);
     d.brT = (int *)(ws + L.o_brT);
+    d.xpA = (int *)(ws + L.o_xpA);
+    d.xpT = (int *)(ws + L.o_xpT);
     d.lp_row = (int *)(ws + L.o_lprow);
     d.lp_col = (int *)(ws + L.o_lpcol);
     d.tau_col = (double *)(ws + L.o_tau);
@@ -1577,6 +1628,28 @@ int pdhg_batch_create(int32_t count, const pdhg_lp *lps, const pdhg_params *prm,
         launch_rowsplit(d.rp, d.M, d.NNZ, d.nblkA, d.brA, s);
         launch_transpose(td, s);
         launch_rowsplit(d.trp, d.N, d.NNZ, d.nblkT, d.brT, s);
+        {
+            std::vector<int> hbrA((size_t)d.nblkA + 1), hbrT((size_t)d.nblkT + 1);
+            std::vector<int> roffs((size_t)count + 1), coffs((size_t)count + 1);
+            for (int i = 0; i < count; ++i) {
+                roffs[i] = hl[i].row_off;
+                coffs[i] = hl[i].col_off;
+            }
+            roffs[count] = d.M;
+            coffs[count] = d.N;
+            if (hipMemcpyAsync(hbrA.data(), d.brA, sizeof(int) * hbrA.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipMemcpyAsync(hbrT.data(), d.brT, sizeof(int) * hbrT.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) { rc = PDHG_E_HIP; break; }
+            std::vector<int> xa, xt;
+            d.nslotA = place_blocks(hbrA, roffs, count, xa);
+            d.nslotT = place_blocks(hbrT, coffs, count, xt);
+            // the lists hold each block at most once: within kXcds (nblk + 1) slots
+            if ((size_t)d.nslotA > (size_t)kXcds * ((size_t)d.nblkA + 1) ||
+                (size_t)d.nslotT > (size_t)kXcds * ((size_t)d.nblkT + 1)) { rc = PDHG_E_INVALID; break; }
+            if (hipMemcpyAsync(d.xpA, xa.data(), sizeof(int) * xa.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+                hipMemcpyAsync(d.xpT, xt.data(), sizeof(int) * xt.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) { rc = PDHG_E_HIP; break; }
+        }
         hipLaunchKernelGGL(k_bnorm_partials, dim3(d.nblk), dim3(kWG), 0, s, d);
         hipLaunchKernelGGL(k_bnorm_final, dim3(count), dim3(kWG), 0, s, d);
         const long long NM = (long long)d.N + d.M;

@@ -73,6 +73,24 @@ struct TRWork {
     unsigned int *coff;    // [kRedBlocks + 1] their exclusive prefix
     unsigned long long *ckey;  // [N + kRedBlocks * kWG] compacted keys, one region per block
     double *ca, *cd;       // same length
+    unsigned int *fcount;  // members of the bracket gathered for the last levels
+    unsigned long long *fkey;  // [kFinishMax] their keys
+    double *fa, *fd;       // [kFinishMax]
+};
+// bracket size from which the last levels run in one workgroup
+constexpr unsigned int kFinishMax = 65536;
+
+// A sparse matrix (CSR, rows x cols) split into S column slabs of width W:
+// slab s holds the entries with column in [s W, (s+1) W), in CSR of its own
+// with local column indices, and its own merge-path block table.
+struct Slabs {
+    int S, W, nbmax, rows;
+    int *srp;                  // [S][rows + 1] row starts within each slab
+    int *sci;                  // [nnz] local column index
+    double *sv;                // [nnz]
+    int *sbr;                  // block row starts of every slab
+    long long *smeta;          // [S][4]: row-start offset, entry offset, block offset, blocks
+    double *spart;             // [S][rows] partial row sums
 };
 
 // Device-side view of one LP and its solver state.
@@ -94,19 +112,62 @@ struct Dev {
     double *x, *y, *x0, *y0, *sx, *sy, *q;
     double *xbar, *ybar, *axb, *atyb, *aty;
     double *gx, *gy, *gax, *gaty;   // scratch point of the stand-alone gap
+    double *xt, *yt;           // extragradient target point z~
     double *part;              // [kRedBlocks][kKktSums]
     double *log;               // [kLogCap][kRec]
     DevState *st;
     TRWork tr[kTrSlots];
     int *err;                  // validation flags; err[1] counts long A' rows
     double omega;              // primal weight (norm of the gap and radii)
+    Slabs slA;                 // A by column slabs (gathers x), for A x
+    Slabs slT;                 // A' by column slabs (gathers y), for A' y
 };
+
+// Column slabs: each slab's slice of the gathered vector is meant to stay in
+// one XCD's 4 MB L2 (workgroup i runs on XCD i mod 8 and block i of a slab
+// launch works on slab i mod S, so slab s stays on XCDs s, s+S, ...).
+// S = 1 (plain merge-path SpMV) when the gathered vector fits one L2 or the
+// set-up scan of the slab row starts would not fit its n-int scratch.
+inline int slab_count_for(int64_t rows, int64_t gathered, int64_t scratch_ints,
+                          int64_t slice_bytes = 4ll << 20) {
+    const int64_t bytes = gathered * 8;
+    if (rows < 1 || (rows + 1 + 2047) / 2048 > scratch_ints) return 1;
+    int S = 1;
+    while (S < 8 && (int64_t)S * slice_bytes < bytes) S <<= 1;
+    return S;
+}
+
+// Primal-weight search: W <= kWMax copies of non-restarted PDHG sharing A
+constexpr int kWMax = 16;
+constexpr int kWSums = 5;      // |p|^2, |d|^2, pobj, dobj, bound violation^2
+struct WArgs {
+    int m, n, W;
+    int egm;                   // 1: extragradient copies, 0: PDHG
+    const int *rp, *ci, *trp, *tci;
+    const double *v, *tv, *c, *b, *l, *u;
+    const signed char *kind;
+    const DevState *st;        // |b|^2 and |c|^2 of the LP
+    double *x, *aty;           // [n][W]
+    double *y, *q;             // [m][W]; q = A x of the latest x
+    double *xt, *yt;           // [n][W], [m][W]: extragradient targets
+    double *part;              // [W][kRedBlocks][kWSums]
+    double *out;               // [W][8] KKT parts
+    double tau[kWMax], sigma[kWMax];
+};
+size_t wsearch_bytes(int64_t m, int64_t n, int W);
+void wsearch_carve(char *ws, int64_t m, int64_t n, int W, WArgs *a);
+void launch_w_init(const WArgs &a, hipStream_t s);
+void launch_w_iter(const WArgs &a, hipStream_t s);
+void launch_w_kkt(const WArgs &a, hipStream_t s);
+void launch_w_extract(const WArgs &a, double *xo, double *yo, hipStream_t s);
 
 // Workspace layout: offsets (bytes) of every region for given sizes.
 struct Layout {
     size_t total;
     size_t o_state, o_err, o_trp, o_tci, o_perm, o_tv, o_cursor, o_long;
     size_t o_brA, o_brT, o_vec_n[8], o_vec_m[8], o_part, o_log;
+    size_t o_slab[2][6];       // srp, sci, sv, sbr, smeta, spart of slA, slT
+    size_t o_xt, o_yt;
     size_t o_tr[kTrSlots];
 };
 bool make_layout(int64_t m, int64_t n, int64_t nnz, Layout *L);
@@ -123,11 +184,20 @@ void launch_validate(const Dev &d, hipStream_t s);
 void launch_transpose(const Dev &d, hipStream_t s);
 void launch_rowsplit(const int *rp, int rows, int nnz, int nblk, int *br, hipStream_t s);
 void launch_init_point(const Dev &d, hipStream_t s);
+// column slabs (when sb.S > 1) of the CSR (rp, ci, v): row starts of every
+// slab (scan scratch: div_up(rows + 1, 2048) ints), then the entries
+void launch_slab_count(const Slabs &sb, const int *rp, const int *ci, int *scratch,
+                       hipStream_t s);
+void launch_slab_fill(const Slabs &sb, const int *rp, const int *ci, const double *v,
+                      hipStream_t s);
 void launch_norms(const Dev &d, hipStream_t s);   // |b|^2, |c|^2 into part[0..1]
 
 // iteration
 void launch_primal(const Dev &d, double tau, hipStream_t s);
 void launch_dual(const Dev &d, double sigma, hipStream_t s);
+// one extragradient iteration (part < 0), or one of its four products
+// (0: target x~, 1: target y~, 2: x+, 3: y+), for timing
+void launch_egm(const Dev &d, double tau, double sigma, int part, hipStream_t s);
 // out = A in / A' in; skip (device flag, may be null) turns the launch into a no-op
 void launch_spmv_A(const Dev &d, const double *in, double *out, hipStream_t s,
                    const int *skip = nullptr);

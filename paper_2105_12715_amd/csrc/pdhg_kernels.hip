@@ -1,14 +1,13 @@
 // HIP kernels of the restarted-PDHG library for gfx950 (MI355X).
 //
-// Hot path (two launches per iteration, eq. PDHG-update):
-//   k_spmv<EpiPrimal> over the explicit A' :  x+ = clamp(x - tau (c - A'y)),
-//                                             sx += x+
-//   k_spmv<EpiDual>   over A               :  q = A x+,
-//                                             y+ = proj(y + sigma (b - (2q - q_prev))),
-//                                             sy += y+, q_prev = q
+// Hot path (two products per iteration, eq. PDHG-update):
+//   over the explicit A' :  x+ = clamp(x - tau (c - A'y)), sx += x+
+//   over A               :  q = A x+, y+ = proj(y + sigma (b - (2q - q_prev))),
+//                           sy += y+, q_prev = q
 // A(2x+ - x) is formed as 2 A x+ - A x from the cached A x of the previous
 // half-step, so each iteration streams A and A' once and gathers x+ and y
-// once per stored entry.
+// once per stored entry.  The extragradient method (eq.
+// extra-gradient-update) uses the same products four times per iteration.
 //
 // SpMV schedule: rows are cut into merge-path blocks of kUnits (1024)
 // rows+entries (a row belongs to the block its start falls in), so each
@@ -19,6 +18,13 @@
 // row each with a fixed butterfly.  Every sum has a fixed order, so results
 // are reproducible run to run.  Blocks whose entries exceed the LDS stage
 // fall back to one wave per row straight from HBM.
+//
+// Column slabs: when the gathered vector is larger than one XCD's L2, the
+// matrix is also kept split by column into S slabs whose slice of the
+// vector fits an L2; workgroup i works on slab i mod S, and since workgroup
+// i runs on XCD i mod 8, every XCD gathers from one slice only.  The slab
+// partial sums of a row are then added in slab order and the epilogue
+// applied in a second, streaming pass.
 //
 // The normalized duality gap (eq. rhorz) needs the multiplier lambda* of the
 // linear trust region of Section 6.3.1.  The GPU finds it by bisection on
@@ -68,6 +74,72 @@ struct EpiDual {
     }
 };
 
+// Extragradient step (eq. extra-gradient-update) with F(z) = (c - A'y, Ax - b):
+// the target z~ = proj_Z(z - D F(z)) (first two products), then
+// z+ = proj_Z(z - D F(z~)) (last two); the sums of Algorithm 1 take z~.
+struct EpiEgmTargetX {
+    const double *__restrict__ c, *__restrict__ l, *__restrict__ u;
+    const double *__restrict__ x;
+    double *__restrict__ xt;
+    double tau;
+    __device__ __forceinline__ void operator()(int j, double aty) const {
+        double v = x[j] - tau * (c[j] - aty);
+        const double lo = l[j], hi = u[j];
+        if (v < lo) v = lo;
+        if (v > hi) v = hi;
+        xt[j] = v;
+    }
+};
+
+struct EpiEgmTargetY {
+    const double *__restrict__ b;
+    const signed char *__restrict__ kind;
+    const double *__restrict__ y;
+    double *__restrict__ yt;
+    double sigma;
+    __device__ __forceinline__ void operator()(int i, double ax) const {
+        double v = y[i] - sigma * (ax - b[i]);
+        if (kind && kind[i] && v < 0.0) v = 0.0;
+        yt[i] = v;
+    }
+};
+
+struct EpiEgmX {
+    const double *__restrict__ c, *__restrict__ l, *__restrict__ u;
+    double *__restrict__ x;
+    const double *__restrict__ xt;
+    double *__restrict__ sx;
+    double tau;
+    DevState *st;
+    __device__ __forceinline__ void operator()(int j, double aty) const {
+        double v = x[j] - tau * (c[j] - aty);
+        const double lo = l[j], hi = u[j];
+        if (v < lo) v = lo;
+        if (v > hi) v = hi;
+        x[j] = v;
+        sx[j] += xt[j];
+        if (j == 0) {  // iteration counters of Algorithm 1
+            st->k += 1;
+            st->t += 1;
+        }
+    }
+};
+
+struct EpiEgmY {
+    const double *__restrict__ b;
+    const signed char *__restrict__ kind;
+    double *__restrict__ y;
+    const double *__restrict__ yt;
+    double *__restrict__ sy;
+    double sigma;
+    __device__ __forceinline__ void operator()(int i, double ax) const {
+        double v = y[i] - sigma * (ax - b[i]);
+        if (kind && kind[i] && v < 0.0) v = 0.0;
+        y[i] = v;
+        sy[i] += yt[i];
+    }
+};
+
 int nblocks_for(int rows, int nnz) {
     long long u = (long long)rows + nnz;
     int nb = div_up(u, kUnits);
@@ -97,32 +169,147 @@ void launch_rowsplit(const int *rp, int rows, int nnz, int nblk, int *br, hipStr
     hipLaunchKernelGGL(k_rowsplit, dim3(div_up(nblk + 1, kWG)), dim3(kWG), 0, s, rp, rows, nblk, br);
 }
 
+// Column-slab SpMV: partial sums per slab, then a fixed-order sum per row.
+// Which (0: A, 1: A') only tells the two instances apart in profiles.
+template <int Which>
+__global__ __launch_bounds__(kWG) void k_slab_spmv(Slabs sb, const double *__restrict__ xin,
+                                                   const int *skip) {
+    if (skip && *skip) return;
+    __shared__ double lds[kLdsProducts];
+    const int sl = blockIdx.x % sb.S, b = blockIdx.x / sb.S;
+    const long long *me = sb.smeta + 4 * sl;
+    if (b >= (int)me[3]) return;
+    const int *br = sb.sbr + me[2];
+    const int r0 = br[b], r1 = br[b + 1];
+    if (r0 >= r1) return;
+    EpiStore e{sb.spart + (size_t)sl * sb.rows};
+    spmv_rows(sb.srp + me[0], sb.sci + me[1], sb.sv + me[1], xin + (size_t)sl * sb.W, r0, r1, e,
+              lds);
+}
+
+__device__ __forceinline__ double slab_sum(const Slabs &sb, int i) {
+    double q = 0.0;
+    for (int sl = 0; sl < sb.S; ++sl)
+        q += __builtin_nontemporal_load(sb.spart + (size_t)sl * sb.rows + i);
+    return q;
+}
+
+// sum of the slab partials of row i, then the row's epilogue
+template <class Epi>
+__global__ void k_slab_apply(Slabs sb, Epi epi, const int *skip) {
+    if (skip && *skip) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < sb.rows) epi(i, slab_sum(sb, i));
+}
+
+static void slab_partials(const Dev &d, const Slabs &sb, const double *in, const int *skip,
+                          hipStream_t s) {
+    if (&sb == &d.slA)
+        hipLaunchKernelGGL(k_slab_spmv<0>, dim3(sb.S * sb.nbmax), dim3(kWG), 0, s, sb, in, skip);
+    else
+        hipLaunchKernelGGL(k_slab_spmv<1>, dim3(sb.S * sb.nbmax), dim3(kWG), 0, s, sb, in, skip);
+}
+
+// out_i = epi(i, (A in)_i) over the rows of A: one merge-path SpMV with the
+// epilogue fused, or the column-slab SpMV and a pass that sums and applies
+template <class Epi>
+static void product_A(const Dev &d, const double *in, const Epi &e, const int *skip,
+                      hipStream_t s) {
+    if (d.m == 0) return;
+    if (d.slA.S > 1) {
+        slab_partials(d, d.slA, in, skip, s);
+        hipLaunchKernelGGL(k_slab_apply<Epi>, dim3(div_up(d.m, kWG)), dim3(kWG), 0, s, d.slA, e,
+                           skip);
+        return;
+    }
+    hipLaunchKernelGGL(k_spmv<Epi>, dim3(d.nblkA), dim3(kWG), 0, s, d.rp, d.ci, d.v, in, d.brA,
+                       e, skip);
+}
+
+// the same over the rows of A' (explicit transpose)
+template <class Epi>
+static void product_T(const Dev &d, const double *in, const Epi &e, const int *skip,
+                      hipStream_t s) {
+    if (d.slT.S > 1) {
+        slab_partials(d, d.slT, in, skip, s);
+        hipLaunchKernelGGL(k_slab_apply<Epi>, dim3(div_up(d.n, kWG)), dim3(kWG), 0, s, d.slT, e,
+                           skip);
+        return;
+    }
+    hipLaunchKernelGGL(k_spmv<Epi>, dim3(d.nblkT), dim3(kWG), 0, s, d.trp, d.tci, d.tv, in,
+                       d.brT, e, skip);
+}
+
 void launch_primal(const Dev &d, double tau, hipStream_t s) {
-    EpiPrimal e{d.c, d.l, d.u, d.x, d.sx, tau, d.st};
-    hipLaunchKernelGGL(k_spmv<EpiPrimal>, dim3(d.nblkT), dim3(kWG), 0, s, d.trp, d.tci, d.tv,
-                       d.y, d.brT, e, &d.st->done);
+    product_T(d, d.y, EpiPrimal{d.c, d.l, d.u, d.x, d.sx, tau, d.st}, &d.st->done, s);
 }
 
 void launch_dual(const Dev &d, double sigma, hipStream_t s) {
-    if (d.m == 0) return;
-    EpiDual e{d.b, d.kind, d.y, d.sy, d.q, sigma};
-    hipLaunchKernelGGL(k_spmv<EpiDual>, dim3(d.nblkA), dim3(kWG), 0, s, d.rp, d.ci, d.v, d.x,
-                       d.brA, e, &d.st->done);
+    product_A(d, d.x, EpiDual{d.b, d.kind, d.y, d.sy, d.q, sigma}, &d.st->done, s);
+}
+
+void launch_egm(const Dev &d, double tau, double sigma, int part, hipStream_t s) {
+    const int *gate = &d.st->done;
+    if (part < 0 || part == 0)
+        product_T(d, d.y, EpiEgmTargetX{d.c, d.l, d.u, d.x, d.xt, tau}, gate, s);
+    if (part < 0 || part == 1)
+        product_A(d, d.x, EpiEgmTargetY{d.b, d.kind, d.y, d.yt, sigma}, gate, s);
+    if (part < 0 || part == 2)
+        product_T(d, d.yt, EpiEgmX{d.c, d.l, d.u, d.x, d.xt, d.sx, tau, d.st}, gate, s);
+    if (part < 0 || part == 3)
+        product_A(d, d.xt, EpiEgmY{d.b, d.kind, d.y, d.yt, d.sy, sigma}, gate, s);
 }
 
 static void spmv_A_gated(const Dev &d, const double *in, double *out, const int *skip,
                          hipStream_t s) {
-    if (d.m == 0) return;
-    EpiStore e{out};
-    hipLaunchKernelGGL(k_spmv<EpiStore>, dim3(d.nblkA), dim3(kWG), 0, s, d.rp, d.ci, d.v, in,
-                       d.brA, e, skip);
+    product_A(d, in, EpiStore{out}, skip, s);
+}
+
+// --- building the slabs (once, at create) ---------------------------------
+// srp[s][i + 1] = entries of row i that fall in slab s (scanned afterwards)
+__global__ void k_slab_count(Slabs sb, const int *__restrict__ rp, const int *__restrict__ ci) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sb.rows) return;
+    int cnt[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) cnt[q] = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        const int sl = ci[p] / sb.W;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cnt[q] += (sl == q) ? 1 : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        if (q < sb.S) {
+            sb.srp[(size_t)q * (sb.rows + 1) + i + 1] = cnt[q];
+            if (i == 0) sb.srp[(size_t)q * (sb.rows + 1)] = 0;
+        }
+}
+
+// place every entry of row i in its slab, keeping the row's order
+__global__ void k_slab_scatter(Slabs sb, const int *__restrict__ rp, const int *__restrict__ ci,
+                               const double *__restrict__ v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sb.rows) return;
+    int run[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) run[q] = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        const int c = ci[p];
+        const int sl = c / sb.W;
+        int r = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (sl == q) r = run[q]++;
+        const long long pos = sb.smeta[4 * sl + 1] + sb.srp[(size_t)sl * (sb.rows + 1) + i] + r;
+        sb.sci[pos] = c - sl * sb.W;
+        sb.sv[pos] = v[p];
+    }
 }
 
 static void spmv_T_gated(const Dev &d, const double *in, double *out, const int *skip,
                          hipStream_t s) {
-    EpiStore e{out};
-    hipLaunchKernelGGL(k_spmv<EpiStore>, dim3(d.nblkT), dim3(kWG), 0, s, d.trp, d.tci, d.tv, in,
-                       d.brT, e, skip);
+    product_T(d, in, EpiStore{out}, skip, s);
 }
 
 void launch_spmv_A(const Dev &d, const double *in, double *out, hipStream_t s,
@@ -433,6 +620,25 @@ void launch_transpose(const Dev &d, hipStream_t s) {
                        nlong, scratch, d.perm, d.tci);
     hipLaunchKernelGGL(k_gather_vals, dim3(div_up(nnz, kWG)), dim3(kWG), 0, s, d.perm, d.v, nnz,
                        d.tv);
+}
+
+void launch_slab_count(const Slabs &sb, const int *rp, const int *ci, int *scratch,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_slab_count, dim3(div_up(sb.rows, kWG)), dim3(kWG), 0, s, sb, rp, ci);
+    // inclusive scan of each slab's rows + 1 counts gives its row starts
+    const long long len = (long long)sb.rows + 1;
+    const int nchunk = div_up(len, kScanChunk);
+    for (int q = 0; q < sb.S; ++q) {
+        int *a = sb.srp + (size_t)q * (sb.rows + 1);
+        hipLaunchKernelGGL(k_scan_chunks, dim3(nchunk), dim3(kWG), 0, s, a, len, scratch);
+        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kWG), 0, s, scratch, nchunk);
+        hipLaunchKernelGGL(k_scan_add, dim3(div_up(len, kWG)), dim3(kWG), 0, s, a, len, scratch);
+    }
+}
+
+void launch_slab_fill(const Slabs &sb, const int *rp, const int *ci, const double *v,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_slab_scatter, dim3(div_up(sb.rows, kWG)), dim3(kWG), 0, s, sb, rp, ci, v);
 }
 
 // x = proj_X(0), x0 = x, y = y0 = 0, sums 0, counters 0

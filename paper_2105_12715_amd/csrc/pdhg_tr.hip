@@ -142,7 +142,10 @@ __global__ __launch_bounds__(kWG) void k_tr_decide0(TRState *ts, TRWork w, int n
     __shared__ ChooseShared cs;
     __shared__ double sh[4 * 4];
     __shared__ int go;
-    if (threadIdx.x == 0) sts = *ts;
+    if (threadIdx.x == 0) {
+        sts = *ts;
+        *w.fcount = 0u;  // the gather before the last levels starts empty
+    }
     double tot[4];
     reduce_partials<4>(w.part, nb, 4, tot, sh);
     if (threadIdx.x == 0) {
@@ -272,7 +275,6 @@ __global__ __launch_bounds__(kWG) void k_tr_decide1(TRState *ts, TRWork w, int n
 
 // Levels 2 and 3 across all blocks while the bracket is still large: block b
 // histograms the members of its own compaction region.
-constexpr unsigned int kFinishMax = 65536;
 
 __global__ __launch_bounds__(kWG) void k_tr_cpass(TRState *ts, TRWork w, const int *gate, int cap,
                                                   int level) {
@@ -327,7 +329,43 @@ __global__ __launch_bounds__(kWG) void k_tr_cdecide(TRState *ts, TRWork w, const
     if (threadIdx.x == 0) *ts = sts;
 }
 
-// remaining levels on the compacted list, one workgroup
+// The bracket's members, copied from the compaction regions into one dense
+// list (up to kFinishMax; the count keeps growing past it) for the last levels.
+__global__ __launch_bounds__(kWG) void k_tr_gather(TRState *ts, TRWork w, const int *gate,
+                                                   int cap) {
+    if (gate && !*gate) return;
+    if (ts->mode != TR_SEARCH) return;
+    __shared__ unsigned int nloc, base, fill;
+    const int above = shift_of(ts->level - 1);
+    const unsigned long long want = ts->prefix >> above;
+    const size_t region = (size_t)blockIdx.x * (size_t)cap;
+    unsigned int cnt = w.ccount[blockIdx.x];
+    if (cnt > (unsigned int)cap) cnt = (unsigned int)cap;
+    if (threadIdx.x == 0) {
+        nloc = 0u;
+        fill = 0u;
+    }
+    __syncthreads();
+    for (unsigned int q = threadIdx.x; q < cnt; q += kWG)
+        if ((w.ckey[region + q] >> above) == want) atomicAdd(&nloc, 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) base = nloc ? atomicAdd(w.fcount, nloc) : 0u;
+    __syncthreads();
+    if (nloc == 0u || base >= kFinishMax) return;
+    for (unsigned int q = threadIdx.x; q < cnt; q += kWG) {
+        const unsigned long long key = w.ckey[region + q];
+        if ((key >> above) != want) continue;
+        const unsigned int at = base + atomicAdd(&fill, 1u);
+        if (at < kFinishMax) {
+            w.fkey[at] = key;
+            w.fa[at] = w.ca[region + q];
+            w.fd[at] = w.cd[region + q];
+        }
+    }
+}
+
+// remaining levels on the gathered list (or, past kFinishMax members, on
+// the compaction regions), one workgroup
 __global__ __launch_bounds__(kWG) void k_tr_finish(TRState *ts, TRWork w, const int *gate, int cap,
                                                    int nb) {
     if (gate && !*gate) return;
@@ -340,10 +378,12 @@ __global__ __launch_bounds__(kWG) void k_tr_finish(TRState *ts, TRWork w, const 
     if (threadIdx.x == 0) sts = *ts;
     for (int b = threadIdx.x; b <= nb; b += kWG) off[b] = w.coff[b];
     __syncthreads();
+    const unsigned int nf = *w.fcount;
+    const bool dense = nf <= kFinishMax;
     // never walk past the compaction buffer, whatever the counts say
-    unsigned int total = off[nb];
+    unsigned int total = dense ? nf : off[nb];
     const unsigned long long room = (unsigned long long)nb * (unsigned long long)cap;
-    if ((unsigned long long)total > room) total = (unsigned int)room;
+    if (!dense && (unsigned long long)total > room) total = (unsigned int)room;
     while (sts.mode == TR_SEARCH) {
         const int level = sts.level;
         const int shift = shift_of(level);
@@ -357,20 +397,30 @@ __global__ __launch_bounds__(kWG) void k_tr_finish(TRState *ts, TRWork w, const 
         }
         __syncthreads();
         for (unsigned int idx = threadIdx.x; idx < total; idx += kWG) {
-            // region holding the idx-th compacted element: last b with off[b] <= idx
-            int lo = 0, hi = nb - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (off[mid] <= idx) lo = mid;
-                else hi = mid - 1;
+            unsigned long long key;
+            double a, d;
+            if (dense) {
+                key = w.fkey[idx];
+                if ((key >> above) != want) continue;
+                a = w.fa[idx];
+                d = w.fd[idx];
+            } else {
+                // region holding the idx-th compacted element: last b with off[b] <= idx
+                int lo = 0, hi = nb - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (off[mid] <= idx) lo = mid;
+                    else hi = mid - 1;
+                }
+                const unsigned int within = idx - off[lo];
+                if (within >= (unsigned int)cap) continue;
+                const size_t at = (size_t)lo * (size_t)cap + within;
+                key = w.ckey[at];
+                if ((key >> above) != want) continue;
+                a = w.ca[at];
+                d = w.cd[at];
             }
-            const unsigned int within = idx - off[lo];
-            if (within >= (unsigned int)cap) continue;
-            const size_t at = (size_t)lo * (size_t)cap + within;
-            const unsigned long long key = w.ckey[at];
-            if ((key >> above) != want) continue;
             const int b = (int)((key >> shift) & (unsigned long long)(nbuck - 1));
-            const double a = w.ca[at], d = w.cd[at];
             atomicAdd(&scnt[b], 1u);
             atomicAdd(&sD[b], d * d);
             atomicAdd(&sA[b], a * a);
@@ -450,6 +500,7 @@ static void run_tr(const E &e, long long N, TRState *ts, const TRWork &w, const 
         hipLaunchKernelGGL(k_tr_cpass, dim3(g), dim3(kWG), 0, s, ts, w, gate, cap, level);
         hipLaunchKernelGGL(k_tr_cdecide, dim3(1), dim3(kWG), 0, s, ts, w, gate, level);
     }
+    hipLaunchKernelGGL(k_tr_gather, dim3(g), dim3(kWG), 0, s, ts, w, gate, cap);
     hipLaunchKernelGGL(k_tr_finish, dim3(1), dim3(kWG), 0, s, ts, w, gate, cap, g);
     hipLaunchKernelGGL(k_tr_final_partials<E>, dim3(g), dim3(kWG), 0, s, e, ts, w, gate);
     hipLaunchKernelGGL(k_tr_final, dim3(1), dim3(kWG), 0, s, ts, w, g, gate);

@@ -1,0 +1,134 @@
+"""GPU parity at the full size of the large sparse workload (1M x 2M,
+power-law column counts, about 9M nonzeros) and for every column-slab count
+of the A x and A' y products.
+
+At this size the oracle still runs a few dozen iterations in seconds, so
+the comparison is element by element, as in the small cases: iterates to a
+relative 1e-10, integer fields of the check records exactly, float fields
+of the records to 1e-9.  The step size is fixed from the bound
+|A|_2 <= sqrt(|A|_1 |A|_inf) so that no power iteration runs on the CPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_12715_amd import lpgen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2105_12715_amd import _lib
+    _lib.load(build_if_missing=False)
+    return _lib
+
+
+@pytest.fixture(scope="module")
+def large():
+    return lpgen.large_powerlaw()
+
+
+def rel(a, b):
+    a = np.asarray(a, float)
+    b = np.asarray(b, float)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def assert_within_sum_bound(got, ref, lp, v, transpose=False):
+    """Row sums of A v (or A' v) summed in different orders agree within
+    the bound of any summation order: |a - b| <= 2 k u sum_j |a_ij v_j|
+    for a row of k entries, u = 2^-53."""
+    A = lp.scipy_csr()
+    if transpose:
+        A = A.T.tocsr()
+    k = np.diff(A.indptr).astype(float)
+    mag = abs(A) @ np.abs(v)
+    bound = 2.0 * k * 2.0 ** -53 * mag
+    err = np.abs(np.asarray(got) - np.asarray(ref))
+    assert np.all(err <= bound), float(np.max(err - bound))
+
+
+def norm_bound_eta(lp):
+    A = abs(lp.scipy_csr())
+    n1 = float(A.sum(axis=0).max())
+    ninf = float(A.sum(axis=1).max())
+    return 0.9 / np.sqrt(n1 * ninf)
+
+
+def test_large_matvec(lib, large):
+    lp = large
+    _say("large matvec", lp.name)
+    s = lib.Solver(lp, eta=norm_bound_eta(lp))
+    o = oracle.Oracle(lp, eta=1.0)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(lp.n)
+    y = rng.standard_normal(lp.m)
+    assert_within_sum_bound(to_np(s.matvec(x)), o.matvec(x), lp, x)
+    assert_within_sum_bound(to_np(s.matvec(y, transpose=True)), o.matvec_t(y), lp, y, True)
+
+
+def test_large_iterates_and_checks(lib, large):
+    """Two check periods of the restarted method at full size: the iterates,
+    averages and anchors, and both check records."""
+    lp = large
+    eta = norm_bound_eta(lp)
+    _say("large iterates", lp.name, eta)
+    o = oracle.Oracle(lp, eta=eta, mode=oracle.MODE_ADAPTIVE)
+    s = lib.Solver(lp, eta=eta, restart_mode=oracle.MODE_ADAPTIVE)
+    done = 0
+    for k in (1, 30, 60):
+        o.solve(k - done, 0.0)
+        s.solve(k - done, 0.0)
+        done = k
+        _say("  compared at", k)
+        for which in (0, 1, 2):
+            xo, yo = o.get(which)
+            xg, yg = (to_np(t) for t in s.get_iterate(which))
+            assert rel(np.concatenate([xg, yg]), np.concatenate([xo, yo])) <= 1e-10, (k, which)
+    lo, lg = o.log(), s.check_log()
+    assert lo.shape == lg.shape == (2, 14)
+    np.testing.assert_array_equal(lg[:, [0, 1, 2, 9, 10, 11]], lo[:, [0, 1, 2, 9, 10, 11]])
+    for col in (3, 4, 5, 6, 7, 8, 12):
+        np.testing.assert_allclose(lg[:, col], lo[:, col], rtol=1e-9, atol=1e-300)
+
+
+@pytest.mark.parametrize("m,n,per_col", [
+    (3000, 600_000, 2),      # two slabs
+    (5000, 1_100_000, 1),    # four slabs
+    (20_000, 4_300_000, 1),  # eight slabs
+    (1, 700_000, 1),         # one row
+    (600_000, 700_000, 2),   # two slabs of A and two of A'
+])
+def test_slab_counts_matvec_and_steps(lib, m, n, per_col):
+    lp = lpgen.column_count_lp(17, m, n, per_col=per_col, bounds="mix")
+    _say("slabs", m, n, per_col)
+    eta = norm_bound_eta(lp)
+    s = lib.Solver(lp, eta=eta)
+    o = oracle.Oracle(lp, eta=eta)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(n)
+    y = rng.standard_normal(m)
+    assert_within_sum_bound(to_np(s.matvec(x)), o.matvec(x), lp, x)
+    assert_within_sum_bound(to_np(s.matvec(y, transpose=True)), o.matvec_t(y), lp, y, True)
+    o.solve(31, 0.0)
+    s.solve(31, 0.0)
+    for which in (0, 1):
+        xo, yo = o.get(which)
+        xg, yg = (to_np(t) for t in s.get_iterate(which))
+        assert rel(np.concatenate([xg, yg]), np.concatenate([xo, yo])) <= 1e-10

@@ -133,7 +133,11 @@ def _tr_case(seed, N, inf_frac, zero_frac=0.1, atb=0.1, dup=False):
     a[rng.random(N) < zero_frac] = 0.0
     d[rng.random(N) < inf_frac] = np.inf
     d[rng.random(N) < atb] = 0.0
-    if dup:
+    if dup == "all":
+        # one breakpoint shared by every coordinate: the bracket never narrows
+        a = np.where(a > 0, 2.0, 0.0)
+        d = np.where(np.isfinite(d), 3.0, d)
+    elif dup:
         d = np.round(d, 1)
         a = np.where(a > 0, 1.0, 0.0)
     return a, d
@@ -142,7 +146,8 @@ def _tr_case(seed, N, inf_frac, zero_frac=0.1, atb=0.1, dup=False):
 @pytest.mark.parametrize("seed,N,inf_frac,dup", [
     (0, 1, 0.0, False), (1, 7, 0.3, False), (2, 1000, 0.0, False), (3, 1000, 0.5, False),
     (4, 5000, 0.1, True), (5, 100_000, 0.2, False), (6, 1_000_000, 0.05, False),
-    (7, 300_000, 0.0, True), (8, 3, 1.0, False),
+    (7, 300_000, 0.0, True), (8, 3, 1.0, False), (9, 200_000, 0.0, "all"),
+    (10, 200_000, 0.3, "all"),
 ])
 def test_trust_region_parity(lib, seed, N, inf_frac, dup):
     a, d = _tr_case(seed, N, inf_frac, dup=dup)
