@@ -180,18 +180,88 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_table2(args):
+    """Planted LPs with the sizes of the four Table 2 instances (qap10,
+    qap15, nug08-3rd, nug20; the instances themselves are not available):
+    the primal-weight search of Section 7 (11 weights 4^-5..4^5, 5000
+    iterations without restarts), then the iterations each restart scheme
+    needs to bring the KKT error of Table 3 (the largest of the absolute
+    primal residual, dual residual and gap) to 1e-6, checked every 30
+    iterations with Table 3's limit: no restarts, fixed lengths 4^k (the
+    best one reported), adaptive and flexible restarts; for PDHG and the
+    extragradient method.  Prints one JSON line with a row per LP and
+    method."""
+    import torch
+    from paper_2105_12715_amd import _lib, lpgen
+
+    names = args.t2_lps.split(",") if args.t2_lps else list(lpgen.TABLE2)
+    methods = args.t2_methods.split(",")
+    fixed = [int(k) for k in args.t2_fixed.split(",")] if args.t2_fixed else []
+    om = [4.0 ** k for k in range(-5, 6)]
+    rows = []
+    for name in names:
+        lp = lpgen.paper_shaped(name)
+        for meth in methods:
+            mcode = _lib.METHOD_EGM if meth == "egm" else _lib.METHOD_PDHG
+            s = _lib.Solver(lp, method=mcode)
+            eta = s.info()["eta"]
+            t0 = time.perf_counter()
+            kk, best, _, _ = s.weight_search(om, 5000)
+            torch.cuda.synchronize()
+            t_ws = time.perf_counter() - t0
+            s.close()
+            omega = om[best]
+            log(f"{name} {meth}: m={lp.m} n={lp.n} nnz={lp.nnz} eta={eta:.4g}, weight search "
+                f"{t_ws:.2f}s -> omega = 4^{best - 5}")
+            schemes = [("none", _lib.RESTART_NONE, 0)]
+            schemes += [(f"fixed 4^{k}", _lib.RESTART_FIXED, 4 ** k) for k in fixed]
+            schemes += [("adaptive", _lib.RESTART_ADAPTIVE, 0),
+                        ("flexible", _lib.RESTART_FLEXIBLE, 0)]
+            res = {}
+            for label, mode, length in schemes:
+                s = _lib.Solver(lp, eta=eta, omega=omega, restart_mode=mode, fixed_len=length,
+                                kkt_kind=_lib.KKT_MAX_ABS, method=mcode)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = s.solve(args.t2_limit, 1e-6)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                res[label] = {"iterations": r["k"] if r["status"] == 0 else None,
+                              "seconds": round(dt, 3), "restarts": r["restarts"]}
+                log(f"  {label}: {res[label]}")
+                s.close()
+            fx = [(v["iterations"], k) for k, v in res.items()
+                  if k.startswith("fixed") and v["iterations"] is not None]
+            best_fixed = min(fx) if fx else None
+            rows.append({"lp": name, "method": meth, "m": lp.m, "n": lp.n, "nnz": lp.nnz,
+                         "omega": omega, "weight_search_s": round(t_ws, 3),
+                         "no_restarts": res["none"]["iterations"],
+                         "best_fixed": best_fixed[0] if best_fixed else None,
+                         "best_fixed_length": best_fixed[1] if best_fixed else None,
+                         "adaptive": res["adaptive"]["iterations"],
+                         "flexible": res["flexible"]["iterations"], "runs": res})
+    print(json.dumps({"metric": "iterations to KKT (max abs) <= 1e-6, Table 2 shaped LPs",
+                      "unit": "iterations", "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+                      "limit": args.t2_limit, "check_period": 30, "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=167, help="timed blocks of 30 iterations")
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="large", choices=["large", "medium", "small", "batch"])
+    ap.add_argument("--workload", default="large",
+                    choices=["large", "medium", "small", "batch", "table2"])
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--budget", type=int, default=1_500_000)
     ap.add_argument("--chunk", type=int, default=30_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=200)
+    ap.add_argument("--t2-lps", default="", help="table2: comma list of Table 2 names")
+    ap.add_argument("--t2-methods", default="pdhg,egm")
+    ap.add_argument("--t2-fixed", default="1,2,3,4,5,6,7,8,9", help="table2: exponents k of 4^k")
+    ap.add_argument("--t2-limit", type=int, default=500_000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB elementwise copy (y = -x, FP64) five times, "
                          "the yardstick for the HBM byte counters")
@@ -218,6 +288,9 @@ def main():
     _lib.load(build_if_missing=True)
     if args.workload == "batch":
         run_batch(args)
+        return
+    if args.workload == "table2":
+        run_table2(args)
         return
     t0 = time.perf_counter()
     lp, wdesc = make_workload(args.workload)
