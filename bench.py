@@ -237,7 +237,8 @@ def run_table2(args):
                          "omega": omega, "weight_search_s": round(t_ws, 3),
                          "no_restarts": res["none"]["iterations"],
                          "best_fixed": best_fixed[0] if best_fixed else None,
-                         "best_fixed_length": best_fixed[1] if best_fixed else None,
+                         "best_fixed_length": (4 ** int(best_fixed[1].split("^")[1])
+                                               if best_fixed else None),
                          "adaptive": res["adaptive"]["iterations"],
                          "flexible": res["flexible"]["iterations"], "runs": res})
     print(json.dumps({"metric": "iterations to KKT (max abs) <= 1e-6, Table 2 shaped LPs",
