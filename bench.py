@@ -246,19 +246,95 @@ def run_table2(args):
                       "limit": args.t2_limit, "check_period": 30, "rows": rows}), flush=True)
 
 
+def run_to_tol(args, lp, wdesc):
+    """Time to relative KKT <= tol from the initial point (pdhg_solve with
+    checks every 30 iterations), with the oracle's time for the same
+    iteration count projected from a bounded sample of its iterations."""
+    import torch
+    from paper_2105_12715_amd import _lib
+    s = _lib.Solver(lp, restart_mode=_lib.RESTART_ADAPTIVE)
+    torch.cuda.synchronize()
+    eta = s.info()["eta"]
+    t0 = time.perf_counter()
+    r = s.solve(args.budget, args.tol)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"{wdesc}: status {r['status']} after {r['k']} iterations, {r['restarts']} restarts, "
+        f"KKT {r['kkt']:.3e}, {dt:.3f}s")
+    cpu = None
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(lp, eta)
+        proj = r["k"] / cb["value"]
+        cpu = {**cb, "value": round(proj, 2), "unit": "s",
+               "sample": cb["sample"] + f"; projected to {r['k']} iterations at that rate"}
+    out = {"metric": f"time to {args.tol:g} rel KKT", "value": round(dt, 4), "unit": "s",
+           "n_gpus": 1, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+           "scaling": "weak", "vs_baseline": None,
+           "config": {"workload": wdesc, "m": lp.m, "n": lp.n, "nnz": lp.nnz, "tol": args.tol,
+                      "check_period": 30, "restart": "adaptive"},
+           "converged": r["status"] == 0, "iterations": r["k"], "restarts": r["restarts"],
+           "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+def run_adjoint(args):
+    """Differentiation workload: 32 planted LPs of 5000 x 10000 (5 per
+    column), K = 2000 unrolled iterations, loss |x_K - x_target|^2; times of
+    the forward pass (with its checkpoints) and of the reverse pass, and the
+    oracle's forward + reverse time for one member, times 32."""
+    import numpy as np
+    import torch
+    from paper_2105_12715_amd import _lib, lpgen
+    K = args.adj_k
+    lps = [lpgen.diff_member(i) for i in range(32)]
+    b = _lib.BatchSolver(lps)
+    xt = torch.as_tensor(np.concatenate([lpgen.x_target(i, lp.n) for i, lp in enumerate(lps)]),
+                         device="cuda:0")
+    b.unrolled_forward(60)  # warm-up of the kernels
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xk, tape = b.unrolled_forward(K)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    gc, gb, gA = b.unrolled_backward(tape, 2.0 * (xk - xt))
+    torch.cuda.synchronize()
+    t_rev = time.perf_counter() - t0
+    log(f"forward {t_fwd:.3f}s, reverse {t_rev:.3f}s for 32 LPs, K = {K}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        o = oracle.Oracle(lps[0], eta=b.info(0)["eta"])
+        t0 = time.perf_counter()
+        o.unrolled_grad(K, lpgen.x_target(0, lps[0].n))
+        one = time.perf_counter() - t0
+        cpu = {"value": round(32 * one, 2), "unit": "s", "cores": 1, "kind": "oracle",
+               "sample": f"forward + reverse of member 0 on one core ({one:.1f} s), times 32"}
+    out = {"metric": "time of K unrolled iterations and their reverse pass", "value":
+           round(t_fwd + t_rev, 4), "unit": "s", "n_gpus": 1, "higher_is_better": False,
+           "dtype": "f64", "data": "synthetic", "scaling": "weak", "vs_baseline": None,
+           "config": {"workload": "32 planted LPs 5000 x 10000, 5 per column, [0,1] "
+                                  "(seeds 5000+i)", "K": K, "loss": "|x_K - x_target|^2"},
+           "forward_s": round(t_fwd, 4), "reverse_s": round(t_rev, 4), "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=167, help="timed blocks of 30 iterations")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="large",
-                    choices=["large", "medium", "small", "batch", "table2"])
+                    choices=["large", "medium", "small", "batch", "table2", "adjoint"])
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--budget", type=int, default=1_500_000)
     ap.add_argument("--chunk", type=int, default=30_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=200)
+    ap.add_argument("--to-tol", action="store_true",
+                    help="large/medium/small: time to --tol instead of iterations per second")
+    ap.add_argument("--adj-k", type=int, default=2000)
     ap.add_argument("--t2-lps", default="", help="table2: comma list of Table 2 names")
     ap.add_argument("--t2-methods", default="pdhg,egm")
     ap.add_argument("--t2-fixed", default="1,2,3,4,5,6,7,8,9", help="table2: exponents k of 4^k")
@@ -293,10 +369,16 @@ def main():
     if args.workload == "table2":
         run_table2(args)
         return
+    if args.workload == "adjoint":
+        run_adjoint(args)
+        return
     t0 = time.perf_counter()
     lp, wdesc = make_workload(args.workload)
     log(f"workload {wdesc}: m={lp.m} n={lp.n} nnz={lp.nnz} generated in "
         f"{time.perf_counter() - t0:.1f}s")
+    if args.to_tol:
+        run_to_tol(args, lp, wdesc)
+        return
     t0 = time.perf_counter()
     s = _lib.Solver(lp, restart_mode=_lib.RESTART_ADAPTIVE)
     torch.cuda.synchronize()

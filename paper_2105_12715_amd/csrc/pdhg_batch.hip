@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kWG) void k_bspmv(const int *__restrict__ rp, const
                                                const int *__restrict__ br, Epi epi,
                                                const int *__restrict__ lp_of, const BLP *lps,
                                                int gate_kind, const int *__restrict__ xp) {
-    __shared__ double lds[kLdsProducts];
+    __shared__ SpmvShared lds;
     const int c = xp[blockIdx.x];
     if (c < 0) return;
     const int r0 = br[c], r1 = br[c + 1];

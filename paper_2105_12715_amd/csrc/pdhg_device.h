@@ -54,21 +54,58 @@ __host__ __device__ inline int div_up(long long a, long long b) { return (int)((
 // ---------------------------------------------------------------------
 // SpMV core
 // ---------------------------------------------------------------------
+// LDS of one SpMV block: the staged products and the block's row starts
+// relative to its first entry (at most kLdsProducts, so 16 bits suffice).
+struct SpmvShared {
+    double prod[kLdsProducts];
+    unsigned short rows[kUnits + 1];
+};
+constexpr int kPerThread = kLdsProducts / kWG;
+
+// matrix loads: non-temporal unless built with PDHG_MATRIX_TEMPORAL
+template <class T>
+__device__ __forceinline__ T ld_matrix(const T *p) {
+#ifdef PDHG_MATRIX_TEMPORAL
+    return *p;
+#else
+    return __builtin_nontemporal_load(p);
+#endif
+}
+
 template <class Epi>
 __device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const int *__restrict__ ci,
                                           const double *__restrict__ v,
                                           const double *__restrict__ xin, int r0, int r1,
-                                          const Epi &epi, double *lds) {
+                                          const Epi &epi, SpmvShared &sm) {
     const int tid = threadIdx.x;
     const int p0 = rp[r0], p1 = rp[r1];
     const int nb = p1 - p0;
-    const int R = r1 - r0;
+    const int R = r1 - r0;  // <= kUnits: every row start takes one unit of the block
     if (nb <= kLdsProducts) {
-        // matrix streams are read once per launch: non-temporal loads keep
-        // them from evicting the gathered vector from L2 and the MALL
-        for (int e = tid; e < nb; e += kWG)
-            lds[e] = __builtin_nontemporal_load(v + p0 + e) *
-                     xin[__builtin_nontemporal_load(ci + p0 + e)];
+        // Every global load of a thread is issued before the first is used:
+        // row starts and matrix entries together, then all gathers, so one
+        // block waits on three memory round trips instead of one per entry.
+        // The matrix is read once per launch: non-temporal loads keep it
+        // from evicting the gathered vector from L2 and the MALL.
+        for (int i = tid; i <= R; i += kWG) sm.rows[i] = (unsigned short)(rp[r0 + i] - p0);
+        int col[kPerThread];
+        double val[kPerThread], g[kPerThread];
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+            const int e = tid + k * kWG;
+            if (e < nb) {
+                col[k] = ld_matrix(ci + p0 + e);
+                val[k] = ld_matrix(v + p0 + e);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k)
+            if (tid + k * kWG < nb) g[k] = xin[col[k]];
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+            const int e = tid + k * kWG;
+            if (e < nb) sm.prod[e] = val[k] * g[k];
+        }
         __syncthreads();
         const int avg = nb / R;
         int L = 1;
@@ -76,19 +113,18 @@ __device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const int 
         const int G = kWG / L;
         const int lane = tid & (L - 1), grp = tid / L;
         for (int rr = grp; rr < R; rr += G) {
-            const int row = r0 + rr;
-            const int s0 = rp[row] - p0, s1 = rp[row + 1] - p0;
+            const int s0 = sm.rows[rr], s1 = sm.rows[rr + 1];
             double s = 0.0;
-            for (int e = s0 + lane; e < s1; e += L) s += lds[e];
+            for (int e = s0 + lane; e < s1; e += L) s += sm.prod[e];
             for (int off = L >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
-            if (lane == 0) epi(row, s);
+            if (lane == 0) epi(r0 + rr, s);
         }
     } else {
         const int wave = tid >> 6, lane = tid & 63;
         for (int row = r0 + wave; row < r1; row += kWG / 64) {
             double s = 0.0;
             for (int p = rp[row] + lane; p < rp[row + 1]; p += 64)
-                s += __builtin_nontemporal_load(v + p) * xin[__builtin_nontemporal_load(ci + p)];
+                s += ld_matrix(v + p) * xin[ld_matrix(ci + p)];
             s = wave_sum(s);
             if (lane == 0) epi(row, s);
         }
@@ -103,7 +139,7 @@ __global__ __launch_bounds__(kWG) void k_spmv(const int *__restrict__ rp,
                                               const int *__restrict__ br, Epi epi,
                                               const int *skip) {
     if (skip && *skip) return;
-    __shared__ double lds[kLdsProducts];
+    __shared__ SpmvShared lds;
     const int r0 = br[blockIdx.x], r1 = br[blockIdx.x + 1];
     if (r0 >= r1) return;
     spmv_rows(rp, ci, v, xin, r0, r1, epi, lds);

@@ -9,8 +9,13 @@
 namespace pdhg {
 
 constexpr int kWG = 256;             // threads per workgroup (4 wave64)
-constexpr int kUnits = 1024;         // SpMV block size in rows + nnz
-constexpr int kLdsProducts = 2048;   // products staged in LDS per SpMV block
+// SpMV block size in rows + nnz (a build parameter for tuning sweeps)
+#ifndef PDHG_SPMV_UNITS
+#define PDHG_SPMV_UNITS 1024
+#endif
+constexpr int kUnits = PDHG_SPMV_UNITS;
+constexpr int kLdsProducts = 2 * kUnits;  // products staged in LDS per SpMV block
+static_assert(kLdsProducts <= 65535, "row starts are staged as 16-bit offsets");
 constexpr int kRedBlocks = 1024;     // max blocks of a partial-sum reduction
 constexpr int kKktSums = 14;         // partial sums of the KKT / radius pass
 constexpr int kBuckets = 2048;       // radix buckets of the multiplier search

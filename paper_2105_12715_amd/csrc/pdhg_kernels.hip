@@ -175,7 +175,7 @@ template <int Which>
 __global__ __launch_bounds__(kWG) void k_slab_spmv(Slabs sb, const double *__restrict__ xin,
                                                    const int *skip) {
     if (skip && *skip) return;
-    __shared__ double lds[kLdsProducts];
+    __shared__ SpmvShared lds;
     const int sl = blockIdx.x % sb.S, b = blockIdx.x / sb.S;
     const long long *me = sb.smeta + 4 * sl;
     if (b >= (int)me[3]) return;
