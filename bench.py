@@ -137,6 +137,9 @@ def run_batch(args):
     t_batch = time.perf_counter() - t0
     ks = np.array([r["k"] for r in res])
     conv = np.array([r["status"] == 0 for r in res])
+    if args.batch_only:
+        log(f"batched {t_batch:.1f}s for {done_k} iterations")
+        return
     # per-LP single-solve iteration time (3000 iterations incl. 100 checks)
     rates = []
     for i, lp in enumerate(lps):
@@ -327,6 +330,8 @@ def main():
     ap.add_argument("--workload", default="large",
                     choices=["large", "medium", "small", "batch", "table2", "adjoint"])
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="batch: skip the sequential single-LP timings (for profiling)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--budget", type=int, default=1_500_000)
     ap.add_argument("--chunk", type=int, default=30_000)

@@ -112,13 +112,33 @@ __device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const int 
         while (L < 64 && 2 * L <= avg) L <<= 1;
         const int G = kWG / L;
         const int lane = tid & (L - 1), grp = tid / L;
-        for (int rr = grp; rr < R; rr += G) {
-            const int s0 = sm.rows[rr], s1 = sm.rows[rr + 1];
-            double s = 0.0;
-            for (int e = s0 + lane; e < s1; e += L) s += sm.prod[e];
-            for (int off = L >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
-            if (lane == 0) epi(r0 + rr, s);
+        // A group reduces at most kLdsProducts / kWG rows: L = 1 when the
+        // mean row length avg = nb / R is below 2 (and R <= kUnits), else
+        // L <= avg, so R L <= nb <= kLdsProducts and R / G = R L / kWG.
+        constexpr int kRounds = kLdsProducts / kWG;
+        double mine[kRounds];
+#pragma unroll
+        for (int t = 0; t < kRounds; ++t) {
+            const int rr = grp + t * G;
+            if (rr < R) {
+                const int s0 = sm.rows[rr], s1 = sm.rows[rr + 1];
+                double s = 0.0;
+                for (int e = s0 + lane; e < s1; e += L) s += sm.prod[e];
+                for (int off = L >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
+                mine[t] = s;
+            }
         }
+        // row sums back to LDS, then the epilogue on consecutive rows with
+        // every lane active, so its loads and stores are coalesced and in
+        // flight together
+        __syncthreads();
+        if (lane == 0) {
+#pragma unroll
+            for (int t = 0; t < kRounds; ++t)
+                if (grp + t * G < R) sm.prod[grp + t * G] = mine[t];
+        }
+        __syncthreads();
+        for (int rr = tid; rr < R; rr += kWG) epi(r0 + rr, sm.prod[rr]);
     } else {
         const int wave = tid >> 6, lane = tid & 63;
         for (int row = r0 + wave; row < r1; row += kWG / 64) {
