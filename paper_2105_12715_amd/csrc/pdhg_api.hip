@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "pdhg.h"
 #include "pdhg_internal.h"
@@ -134,6 +135,19 @@ bool make_layout(int64_t m, int64_t n, int64_t nnz, Layout *L) {
     o += al(sizeof(double) * n1);
     L->o_yt = o;
     o += al(sizeof(double) * m1);
+    // column order: reordered col_idx, the permutation both ways, c, l, u
+    L->o_ci2 = o;
+    o += al(sizeof(int) * z1);
+    L->o_cperm = o;
+    o += al(sizeof(int) * n1);
+    L->o_cinv = o;
+    o += al(sizeof(int) * n1);
+    L->o_c2 = o;
+    o += al(sizeof(double) * n1);
+    L->o_l2 = o;
+    o += al(sizeof(double) * n1);
+    L->o_u2 = o;
+    o += al(sizeof(double) * n1);
     L->o_part = o;
     o += al(sizeof(double) * kRedBlocks * kKktSums);
     L->o_log = o;
@@ -282,6 +296,59 @@ static int build_slabs(Slabs &sb, const int *rp, const int *ci, const double *v,
     return last_error();
 }
 
+// Sort the columns by entry count, largest first (a stable counting sort
+// on the host), and switch the device view to the reordered copies.  With
+// most entries in the first columns, the x that the A x products gather is
+// mostly one L2-sized region; when that region holds at least 60% of the
+// entries, A x skips its column slabs.
+static int order_columns(Dev &d, const Layout &L, char *ws, hipStream_t s) {
+    d.permuted = 0;
+    if (d.n < 2 || d.nnz == 0) return PDHG_OK;
+    const int n = d.n;
+    int *cnt_dev = d.trp;  // n + 1 ints, rebuilt by the transpose afterwards
+    launch_col_counts(d.ci, d.nnz, n, cnt_dev, s);
+    std::vector<int> cnt((size_t)n + 1);
+    CK(hipMemcpyAsync(cnt.data(), cnt_dev, sizeof(int) * ((size_t)n + 1), hipMemcpyDeviceToHost,
+                      s));
+    CK(hipStreamSynchronize(s));
+    int cmax = 0;
+    for (int j = 0; j < n; ++j) cmax = cnt[j + 1] > cmax ? cnt[j + 1] : cmax;
+    // buckets by count, largest count first
+    std::vector<int> start((size_t)cmax + 2, 0);
+    for (int j = 0; j < n; ++j) start[(size_t)(cmax - cnt[j + 1]) + 1] += 1;
+    for (int k = 0; k <= cmax; ++k) start[k + 1] += start[k];
+    std::vector<int> order((size_t)n), inv((size_t)n);
+    bool ident = true;
+    for (int j = 0; j < n; ++j) {
+        const int q = start[(size_t)(cmax - cnt[j + 1])]++;
+        order[q] = j;
+        inv[j] = q;
+        ident &= (q == j);
+    }
+    if (ident) return PDHG_OK;
+    int *ci2 = (int *)(ws + L.o_ci2);
+    int *cperm = (int *)(ws + L.o_cperm), *cinv = (int *)(ws + L.o_cinv);
+    double *c2 = (double *)(ws + L.o_c2), *l2 = (double *)(ws + L.o_l2);
+    double *u2 = (double *)(ws + L.o_u2);
+    CK(hipMemcpyAsync(cperm, order.data(), sizeof(int) * (size_t)n, hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(cinv, inv.data(), sizeof(int) * (size_t)n, hipMemcpyHostToDevice, s));
+    launch_permute_cols(d.ci, d.nnz, cinv, ci2, d.c, d.l, d.u, cperm, n, c2, l2, u2, s);
+    CK(hipStreamSynchronize(s));  // the host vectors above leave scope
+    d.ci = ci2;
+    d.c = c2;
+    d.l = l2;
+    d.u = u2;
+    d.cperm = cperm;
+    d.cinv = cinv;
+    d.permuted = 1;
+    // share of the entries in the first L2-sized run of columns
+    const long long w0 = slab_slice_bytes() / 8;
+    long long hot = 0;
+    for (long long q = 0; q < n && q < w0; ++q) hot += cnt[(size_t)order[q] + 1];
+    if (d.slA.S > 1 && 10 * hot >= 6 * (long long)d.nnz) d.slA.S = 1;
+    return last_error();
+}
+
 int pdhg_create(const pdhg_lp *lp, const pdhg_params *prm_in, void *workspace,
                 size_t workspace_bytes, void *stream, pdhg_t **out) {
     if (!out) return PDHG_E_INVALID;
@@ -390,6 +457,7 @@ int pdhg_create(const pdhg_lp *lp, const pdhg_params *prm_in, void *workspace,
             rc = PDHG_E_INVALID;
             break;
         }
+        if ((rc = order_columns(d, L, ws, s)) != PDHG_OK) break;
         launch_rowsplit(d.rp, d.m, d.nnz, d.nblkA, d.brA, s);
         launch_transpose(d, s);
         launch_rowsplit(d.trp, d.n, d.nnz, d.nblkT, d.brT, s);
@@ -645,13 +713,25 @@ int pdhg_solve(pdhg_t *h, int64_t max_iters, double tol, pdhg_result *out) {
 
 int pdhg_get_iterate(pdhg_t *h, int32_t which, double *x, double *y) {
     if (!h || which < 0 || which > 3 || !x || (h->d.m > 0 && !y)) return PDHG_E_INVALID;
-    launch_copy_point(h->d, which, x, y, h->stream);
+    const Dev &d = h->d;
+    if (d.permuted) {
+        launch_copy_point(d, which, d.gx, y, h->stream);
+        launch_gather(d.gx, d.cinv, d.n, x, h->stream);
+    } else {
+        launch_copy_point(d, which, x, y, h->stream);
+    }
     return last_error();
 }
 
 int pdhg_set_iterate(pdhg_t *h, const double *x, const double *y) {
     if (!h || !x || (h->d.m > 0 && !y)) return PDHG_E_INVALID;
-    launch_set_point(h->d, x, y, h->stream);
+    const Dev &d = h->d;
+    if (d.permuted) {
+        launch_gather(x, d.cperm, d.n, d.gx, h->stream);
+        launch_set_point(d, d.gx, y, h->stream);
+    } else {
+        launch_set_point(d, x, y, h->stream);
+    }
     return last_error();
 }
 
@@ -688,6 +768,7 @@ int pdhg_weight_search(pdhg_t *h, const double *omega, int32_t count, int64_t it
     a.u = d.u;
     a.kind = d.kind;
     a.st = d.st;
+    a.cinv = d.permuted ? d.cinv : nullptr;
     wsearch_carve((char *)workspace, d.m, d.n, count, &a);
     for (int w = 0; w < count; ++w) {
         a.tau[w] = h->eta / omega[w];
@@ -789,8 +870,17 @@ int pdhg_get_check_log(pdhg_t *h, pdhg_check_record *out, int64_t max, int64_t *
 
 int pdhg_matvec(pdhg_t *h, int32_t transpose, const double *in, double *out) {
     if (!h || !in || !out || (transpose != 0 && transpose != 1)) return PDHG_E_INVALID;
-    if (transpose) launch_spmv_T(h->d, in, out, h->stream);
-    else launch_spmv_A(h->d, in, out, h->stream);
+    const Dev &d = h->d;
+    if (!d.permuted) {
+        if (transpose) launch_spmv_T(d, in, out, h->stream);
+        else launch_spmv_A(d, in, out, h->stream);
+    } else if (transpose) {
+        launch_spmv_T(d, in, d.gaty, h->stream);
+        launch_gather(d.gaty, d.cinv, d.n, out, h->stream);
+    } else {
+        launch_gather(in, d.cperm, d.n, d.gx, h->stream);
+        launch_spmv_A(d, d.gx, out, h->stream);
+    }
     return last_error();
 }
 
@@ -798,6 +888,10 @@ int pdhg_get_transpose(pdhg_t *h, int32_t *t_row_ptr, int32_t *t_col_idx, double
                        int32_t *perm) {
     if (!h || !t_row_ptr) return PDHG_E_INVALID;
     const Dev &d = h->d;
+    if (d.permuted) {
+        launch_transpose_out(d, t_row_ptr, t_col_idx, t_vals, perm, h->stream);
+        return last_error();
+    }
     CK(hipMemcpyAsync(t_row_ptr, d.trp, sizeof(int) * ((size_t)d.n + 1), hipMemcpyDeviceToDevice,
                       h->stream));
     if (d.nnz > 0) {

@@ -126,6 +126,14 @@ struct Dev {
     double omega;              // primal weight (norm of the gap and radii)
     Slabs slA;                 // A by column slabs (gathers x), for A x
     Slabs slT;                 // A' by column slabs (gathers y), for A' y
+    // Column order.  Columns are kept sorted by entry count (largest first,
+    // ties in the caller's order), so the most gathered entries of x share
+    // cache lines and blocks of A' hold rows of similar length.  ci, c, l, u
+    // above are then the reordered copies; iterates cross the API in the
+    // caller's order.
+    int permuted;              // 0: the caller's order is already sorted
+    const int *cperm;          // [n] internal column q -> caller's column
+    const int *cinv;           // [n] caller's column j -> internal column
 };
 
 // Column slabs: each slab's slice of the gathered vector is meant to stay in
@@ -152,6 +160,7 @@ struct WArgs {
     const double *v, *tv, *c, *b, *l, *u;
     const signed char *kind;
     const DevState *st;        // |b|^2 and |c|^2 of the LP
+    const int *cinv;           // caller's column -> internal column, or null
     double *x, *aty;           // [n][W]
     double *y, *q;             // [m][W]; q = A x of the latest x
     double *xt, *yt;           // [n][W], [m][W]: extragradient targets
@@ -173,6 +182,7 @@ struct Layout {
     size_t o_brA, o_brT, o_vec_n[8], o_vec_m[8], o_part, o_log;
     size_t o_slab[2][6];       // srp, sci, sv, sbr, smeta, spart of slA, slT
     size_t o_xt, o_yt;
+    size_t o_ci2, o_cperm, o_cinv, o_c2, o_l2, o_u2;
     size_t o_tr[kTrSlots];
 };
 bool make_layout(int64_t m, int64_t n, int64_t nnz, Layout *L);
@@ -196,6 +206,17 @@ void launch_slab_count(const Slabs &sb, const int *rp, const int *ci, int *scrat
 void launch_slab_fill(const Slabs &sb, const int *rp, const int *ci, const double *v,
                       hipStream_t s);
 void launch_norms(const Dev &d, hipStream_t s);   // |b|^2, |c|^2 into part[0..1]
+// column counts of the caller's A into cnt[1..n] (cnt[0] = 0)
+void launch_col_counts(const int *ci, int nnz, int n, int *cnt, hipStream_t s);
+// ci2 = cinv[ci]; c2, l2, u2 = c, l, u in the internal column order
+void launch_permute_cols(const int *ci, int nnz, const int *cinv, int *ci2, const double *c,
+                         const double *l, const double *u, const int *cperm, int n, double *c2,
+                         double *l2, double *u2, hipStream_t s);
+// out[q] = in[idx[q]], q < n
+void launch_gather(const double *in, const int *idx, long long n, double *out, hipStream_t s);
+// A' in the caller's column order from the internal one (row j <- row cinv[j])
+void launch_transpose_out(const Dev &d, int *orp, int *oci, double *ov, int *operm,
+                          hipStream_t s);
 
 // iteration
 void launch_primal(const Dev &d, double tau, hipStream_t s);

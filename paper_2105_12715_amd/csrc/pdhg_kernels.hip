@@ -641,6 +641,88 @@ void launch_slab_fill(const Slabs &sb, const int *rp, const int *ci, const doubl
     hipLaunchKernelGGL(k_slab_scatter, dim3(div_up(sb.rows, kWG)), dim3(kWG), 0, s, sb, rp, ci, v);
 }
 
+// --- column order (set-up and the API's conversions) ----------------------
+void launch_col_counts(const int *ci, int nnz, int n, int *cnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_int, dim3(div_up(n + 1, kWG)), dim3(kWG), 0, s, cnt,
+                       (long long)n + 1, 0);
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_count_cols, dim3(div_up(nnz, kWG)), dim3(kWG), 0, s, ci, nnz, cnt);
+}
+
+__global__ void k_permute_cols(const int *__restrict__ ci, int nnz, const int *__restrict__ cinv,
+                               int *ci2, const double *__restrict__ c,
+                               const double *__restrict__ l, const double *__restrict__ u,
+                               const int *__restrict__ cperm, int n, double *c2, double *l2,
+                               double *u2) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nnz) ci2[i] = cinv[ci[i]];
+    if (i < n) {
+        const int j = cperm[i];
+        c2[i] = c[j];
+        l2[i] = l[j];
+        u2[i] = u[j];
+    }
+}
+
+void launch_permute_cols(const int *ci, int nnz, const int *cinv, int *ci2, const double *c,
+                         const double *l, const double *u, const int *cperm, int n, double *c2,
+                         double *l2, double *u2, hipStream_t s) {
+    const long long mx = nnz > n ? nnz : n;
+    hipLaunchKernelGGL(k_permute_cols, dim3(div_up(mx, kWG)), dim3(kWG), 0, s, ci, nnz, cinv, ci2,
+                       c, l, u, cperm, n, c2, l2, u2);
+}
+
+__global__ void k_gather(const double *__restrict__ in, const int *__restrict__ idx, long long n,
+                         double *out) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) out[q] = in[idx[q]];
+}
+
+void launch_gather(const double *in, const int *idx, long long n, double *out, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_gather, dim3(div_up(n, kWG)), dim3(kWG), 0, s, in, idx, n, out);
+}
+
+// row lengths of A' in the caller's column order: orp[j + 1] (orp[0] = 0)
+__global__ void k_tout_counts(const int *__restrict__ trp, const int *__restrict__ cinv, int n,
+                              int *orp) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j == 0) orp[0] = 0;
+    if (j < n) {
+        const int q = cinv[j];
+        orp[j + 1] = trp[q + 1] - trp[q];
+    }
+}
+
+__global__ void k_tout_copy(const int *__restrict__ trp, const int *__restrict__ tci,
+                            const double *__restrict__ tv, const int *__restrict__ tperm,
+                            const int *__restrict__ cinv, int n, const int *__restrict__ orp,
+                            int *oci, double *ov, int *operm) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int q = cinv[j];
+    const int src = trp[q], len = trp[q + 1] - trp[q], dst = orp[j];
+    for (int k = 0; k < len; ++k) {
+        if (oci) oci[dst + k] = tci[src + k];
+        if (ov) ov[dst + k] = tv[src + k];
+        if (operm) operm[dst + k] = tperm[src + k];
+    }
+}
+
+void launch_transpose_out(const Dev &d, int *orp, int *oci, double *ov, int *operm,
+                          hipStream_t s) {
+    const int n = d.n;
+    hipLaunchKernelGGL(k_tout_counts, dim3(div_up(n, kWG)), dim3(kWG), 0, s, d.trp, d.cinv, n, orp);
+    const long long len = (long long)n + 1;
+    const int nchunk = div_up(len, kScanChunk);
+    int *bsum = d.long_rows;  // n >= nchunk
+    hipLaunchKernelGGL(k_scan_chunks, dim3(nchunk), dim3(kWG), 0, s, orp, len, bsum);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kWG), 0, s, bsum, nchunk);
+    hipLaunchKernelGGL(k_scan_add, dim3(div_up(len, kWG)), dim3(kWG), 0, s, orp, len, bsum);
+    if (d.nnz > 0)
+        hipLaunchKernelGGL(k_tout_copy, dim3(div_up(n, kWG)), dim3(kWG), 0, s, d.trp, d.tci, d.tv,
+                           d.perm, d.cinv, n, orp, oci, ov, operm);
+}
+
 // x = proj_X(0), x0 = x, y = y0 = 0, sums 0, counters 0
 __global__ void k_init_point(Dev d) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;

@@ -247,13 +247,15 @@ void launch_w_kkt(const WArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_w_kkt_final, dim3(a.W), dim3(kWG), 0, s, a, g);
 }
 
-// copy w of the interleaved iterates into plain vectors (x_out[w n + j])
+// copy w of the interleaved iterates into plain vectors (x_out[w n + j]),
+// columns back in the caller's order
 __global__ void k_w_extract(WArgs a, double *xo, double *yo) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long nx = (long long)a.n * a.W, ny = (long long)a.m * a.W;
     if (xo && i < nx) {
         const long long w = i / a.n, j = i % a.n;
-        xo[i] = a.x[j * a.W + w];
+        const long long q = a.cinv ? a.cinv[j] : j;
+        xo[i] = a.x[q * a.W + w];
     }
     if (yo && i < ny) {
         const long long w = i / a.m, r = i % a.m;

@@ -155,13 +155,16 @@ def column_count_lp(seed: int, m: int, n: int, counts=None, per_col: int = 0,
                     ge_frac: float = 0.0, name: str = "") -> LP:
     """Each column gets a fixed or drawn number of distinct uniform rows.
 
-    ``counts`` may be "powerlaw2" (P(k) proportional to k^-2 on 1..1000).
+    ``counts`` may be "powerlaw2" (P(k) proportional to k^-2 on 1..1000) or
+    an array of n column counts.
     ``values``: "normal" (N(0,1)) or "loguniform" (random sign, 10^U(-3,3)).
     ``bounds``: "box01" (all [0,1]), "mix" (half [0,inf), half [0,10]) or
     "mixed_inf" (a mix of every bound class, for edge-case tests).
     """
     rng = np.random.default_rng(seed)
-    if counts == "powerlaw2":
+    if isinstance(counts, np.ndarray):
+        cnt = counts.astype(np.int64)
+    elif counts == "powerlaw2":
         k = np.arange(1, 1001, dtype=np.float64)
         p = k ** -2.0
         p /= p.sum()

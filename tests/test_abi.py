@@ -23,8 +23,11 @@ def test_host_only_entry_points():
     assert _lib.workspace_bytes(10, 0, 5) == 0
     assert _lib.workspace_bytes(0, 1, 0) > 0
     assert _lib.workspace_bytes(10, 2**31, 5) == 0
+    # A' (16 B/entry), column slabs of A and A' (12 B/entry each plus
+    # partial sums), the reordered col_idx, 16 m- and n-vectors, the
+    # trust-region buffers: about 1 GB for 1M x 2M with 10M entries
     big = _lib.workspace_bytes(1_000_000, 2_000_000, 10_000_000)
-    assert 300e6 < big < 1e9
+    assert 300e6 < big < 1.5e9
     assert "workspace" in _lib.strerror(_lib.E_WORKSPACE)
     assert _lib.load().pdhg_trust_region_workspace_bytes(-1) == 0
 
