@@ -166,7 +166,7 @@ bool make_layout(int64_t m, int64_t n, int64_t nnz, Layout *L) {
         const int nb = t == 0 ? nbA : nbT;
         const size_t sz[6] = {sizeof(int) * Ss * (r1 + 1), sizeof(int) * zS, sizeof(double) * zS,
                               sizeof(int) * Ss * ((size_t)nb + 1), sizeof(long long) * 4 * Ss,
-                              sizeof(double) * Ss * r1};
+                              sizeof(double) * (S > 1 ? r1 : 0)};
         for (int k = 0; k < 6; ++k) {
             L->o_slab[t][k] = o;
             o += al(sz[k]);

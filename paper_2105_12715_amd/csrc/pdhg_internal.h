@@ -95,7 +95,7 @@ struct Slabs {
     double *sv;                // [nnz]
     int *sbr;                  // block row starts of every slab
     long long *smeta;          // [S][4]: row-start offset, entry offset, block offset, blocks
-    double *spart;             // [S][rows] partial row sums
+    double *spart;             // [rows] running sum of the slabs done so far
 };
 
 // Device-side view of one LP and its solver state.
@@ -136,9 +136,8 @@ struct Dev {
     const int *cinv;           // [n] caller's column j -> internal column
 };
 
-// Column slabs: each slab's slice of the gathered vector is meant to stay in
-// one XCD's 4 MB L2 (workgroup i runs on XCD i mod 8 and block i of a slab
-// launch works on slab i mod S, so slab s stays on XCDs s, s+S, ...).
+// Column slabs: each slab's slice of the gathered vector is meant to fit
+// one XCD's 4 MB L2; the slabs run one launch after the other.
 // S = 1 (plain merge-path SpMV) when the gathered vector fits one L2 or the
 // set-up scan of the slab row starts would not fit its n-int scratch.
 inline int slab_count_for(int64_t rows, int64_t gathered, int64_t scratch_ints,

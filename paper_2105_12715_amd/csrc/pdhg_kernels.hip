@@ -21,10 +21,10 @@
 //
 // Column slabs: when the gathered vector is larger than one XCD's L2, the
 // matrix is also kept split by column into S slabs whose slice of the
-// vector fits an L2; workgroup i works on slab i mod S, and since workgroup
-// i runs on XCD i mod 8, every XCD gathers from one slice only.  The slab
-// partial sums of a row are then added in slab order and the epilogue
-// applied in a second, streaming pass.
+// vector fits an L2, and the product runs one slab per launch: every XCD
+// then gathers from the same 4 MB slice.  The first slabs leave their row
+// sums in an accumulator (added in slab order), and the last slab's launch
+// applies the epilogue to the full sum.
 //
 // The normalized duality gap (eq. rhorz) needs the multiplier lambda* of the
 // linear trust region of Section 6.3.1.  The GPU finds it by bisection on
@@ -35,6 +35,7 @@
 #include "pdhg_device.h"
 
 #include <math.h>
+#include <stdlib.h>
 
 namespace pdhg {
 
@@ -169,57 +170,57 @@ void launch_rowsplit(const int *rp, int rows, int nnz, int nblk, int *br, hipStr
     hipLaunchKernelGGL(k_rowsplit, dim3(div_up(nblk + 1, kWG)), dim3(kWG), 0, s, rp, rows, nblk, br);
 }
 
-// Column-slab SpMV: partial sums per slab, then a fixed-order sum per row.
-// Which (0: A, 1: A') only tells the two instances apart in profiles.
-template <int Which>
-__global__ __launch_bounds__(kWG) void k_slab_spmv(Slabs sb, const double *__restrict__ xin,
-                                                   const int *skip) {
+// One slab at a time: the sums of slab sl go to acc (slab 0) or are added
+// to it in slab order, and the last slab applies the epilogue to the full
+// sum.
+struct EpiSlabAcc {
+    double *acc;
+    int first;
+    __device__ __forceinline__ void operator()(int r, double s) const {
+        acc[r] = first ? s : acc[r] + s;
+    }
+};
+
+template <class Epi>
+struct EpiSlabLast {
+    Epi inner;
+    const double *acc;
+    __device__ __forceinline__ void operator()(int r, double s) const { inner(r, acc[r] + s); }
+};
+
+template <class Epi>
+__global__ __launch_bounds__(kWG) void k_slab_one(Slabs sb, int sl, const double *__restrict__ xin,
+                                                  Epi epi, const int *skip) {
     if (skip && *skip) return;
     __shared__ SpmvShared lds;
-    const int sl = blockIdx.x % sb.S, b = blockIdx.x / sb.S;
     const long long *me = sb.smeta + 4 * sl;
+    const int b = blockIdx.x;
     if (b >= (int)me[3]) return;
     const int *br = sb.sbr + me[2];
     const int r0 = br[b], r1 = br[b + 1];
     if (r0 >= r1) return;
-    EpiStore e{sb.spart + (size_t)sl * sb.rows};
-    spmv_rows(sb.srp + me[0], sb.sci + me[1], sb.sv + me[1], xin + (size_t)sl * sb.W, r0, r1, e,
+    spmv_rows(sb.srp + me[0], sb.sci + me[1], sb.sv + me[1], xin + (size_t)sl * sb.W, r0, r1, epi,
               lds);
 }
 
-__device__ __forceinline__ double slab_sum(const Slabs &sb, int i) {
-    double q = 0.0;
-    for (int sl = 0; sl < sb.S; ++sl)
-        q += __builtin_nontemporal_load(sb.spart + (size_t)sl * sb.rows + i);
-    return q;
-}
-
-// sum of the slab partials of row i, then the row's epilogue
+// the slabs one after the other, the last with the epilogue fused
 template <class Epi>
-__global__ void k_slab_apply(Slabs sb, Epi epi, const int *skip) {
-    if (skip && *skip) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < sb.rows) epi(i, slab_sum(sb, i));
-}
-
-static void slab_partials(const Dev &d, const Slabs &sb, const double *in, const int *skip,
+static void slabs_in_turn(const Slabs &sb, const double *in, const Epi &e, const int *skip,
                           hipStream_t s) {
-    if (&sb == &d.slA)
-        hipLaunchKernelGGL(k_slab_spmv<0>, dim3(sb.S * sb.nbmax), dim3(kWG), 0, s, sb, in, skip);
-    else
-        hipLaunchKernelGGL(k_slab_spmv<1>, dim3(sb.S * sb.nbmax), dim3(kWG), 0, s, sb, in, skip);
+    double *acc = sb.spart;
+    for (int sl = 0; sl + 1 < sb.S; ++sl)
+        hipLaunchKernelGGL(k_slab_one<EpiSlabAcc>, dim3(sb.nbmax), dim3(kWG), 0, s, sb, sl, in,
+                           EpiSlabAcc{acc, sl == 0 ? 1 : 0}, skip);
+    hipLaunchKernelGGL(k_slab_one<EpiSlabLast<Epi>>, dim3(sb.nbmax), dim3(kWG), 0, s, sb, sb.S - 1,
+                       in, EpiSlabLast<Epi>{e, acc}, skip);
 }
 
-// out_i = epi(i, (A in)_i) over the rows of A: one merge-path SpMV with the
-// epilogue fused, or the column-slab SpMV and a pass that sums and applies
 template <class Epi>
 static void product_A(const Dev &d, const double *in, const Epi &e, const int *skip,
                       hipStream_t s) {
     if (d.m == 0) return;
     if (d.slA.S > 1) {
-        slab_partials(d, d.slA, in, skip, s);
-        hipLaunchKernelGGL(k_slab_apply<Epi>, dim3(div_up(d.m, kWG)), dim3(kWG), 0, s, d.slA, e,
-                           skip);
+        slabs_in_turn(d.slA, in, e, skip, s);
         return;
     }
     hipLaunchKernelGGL(k_spmv<Epi>, dim3(d.nblkA), dim3(kWG), 0, s, d.rp, d.ci, d.v, in, d.brA,
@@ -231,9 +232,7 @@ template <class Epi>
 static void product_T(const Dev &d, const double *in, const Epi &e, const int *skip,
                       hipStream_t s) {
     if (d.slT.S > 1) {
-        slab_partials(d, d.slT, in, skip, s);
-        hipLaunchKernelGGL(k_slab_apply<Epi>, dim3(div_up(d.n, kWG)), dim3(kWG), 0, s, d.slT, e,
-                           skip);
+        slabs_in_turn(d.slT, in, e, skip, s);
         return;
     }
     hipLaunchKernelGGL(k_spmv<Epi>, dim3(d.nblkT), dim3(kWG), 0, s, d.trp, d.tci, d.tv, in,
