@@ -17,8 +17,8 @@ The roofline figure is for the dominant half-step (A'y with the primal
 update, or A x+ with the dual update), timed with HIP events on the
 handle's stream right after the timed region.  A half-step is one SpMV
 kernel with the update fused, or, where the gathered vector is split into
-column slabs, the slab SpMV kernel plus the kernel that sums its partials
-and applies the update.  Algorithmic bytes per half-step are
+column slabs, one launch per slab, the last adding up the slabs' row sums
+and applying the update.  Algorithmic bytes per half-step are
     primal: 12 nnz + 60 n + 8 m     dual: 12 nnz + 61 m + 8 n
 (values + int32 indices of A' or A, row pointers, the vector reads and
 writes of the epilogue, and one compulsory read of the gathered vector).

@@ -241,17 +241,18 @@ int pdhg_get_transpose(pdhg_t *h, int32_t *t_row_ptr, int32_t *t_col_idx,
  * restarts) with a HIP event recorded around every half-step on the
  * handle's stream, and return the mean duration in milliseconds of the
  * primal half-step (x+ from A'y, eq. PDHG-update) and of the dual half-step
- * (y+ from A x+); each is one kernel, or two where the product runs over
- * column slabs (partial sums, then their sum with the update).  For
- * throughput measurement.  Syncs. */
+ * (y+ from A x+); each is one kernel, or one per column slab where the
+ * product runs over slabs (the last one adds the slabs' row sums and
+ * applies the update).  For throughput measurement.  Syncs. */
 int pdhg_time_iterations(pdhg_t *h, int64_t iters, double *ms_primal, double *ms_dual);
 
 /* Primal-weight search of Section 7 (experimental setup).  For each of the
  * `count` weights omega[w] (host array; every omega > 0; 1 <= count <= 16)
  * run `iters` (>= 0) iterations of the handle's method (PDHG or
  * extragradient) without restarts from the initial point, with primal step
- * eta/omega[w] and dual step eta*omega[w] (eta of the handle).  The copies run side by side: each product streams A or A'
- * once for all of them.  Then the KKT error of every copy's last iterate
+ * eta/omega[w] and dual step eta*omega[w] (eta of the handle).  The
+ * copies run side by side: each product streams A or A' once for all of
+ * them.  Then the KKT error of every copy's last iterate
  * goes to kkt[w] (host array of count; kkt[w].kkt = kkt_paper_abs, the
  * criterion of Section 7), and *best (host, may be NULL) gets the w with
  * the smallest kkt_paper_abs (NaN counts as +inf, ties go to the smaller
