@@ -280,6 +280,25 @@ def test_kkt_and_gap_parity(lib, name):
 
 # ------------------------------------------------------------- solves ---
 
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_small_workload_10000_iterations(lib, seed):
+    """The 50 x 100 workload as the benchmark runs it: 10,000 iterations of
+    the solve loop (checks every 30, no stopping test).  Every restart
+    decision matches the oracle's; iterates, averages and anchors agree to
+    1e-9 relative after 10,000 iterations (1e-10 is the bar over the first
+    1,000, checked above; rounding differences may grow slowly after that)."""
+    lp = lpgen.small_dense(seed)
+    _say("small 10000", seed)
+    o, s = _pair(lp, oracle.MODE_ADAPTIVE)
+    o.solve(10_000, 0.0)
+    s.solve(10_000, 0.0)
+    _compare_points(o, s, tol=1e-9)
+    lo, lg = o.log(), s.check_log()
+    assert lo.shape == lg.shape == (333, 14)
+    np.testing.assert_array_equal(lg[:, [0, 1, 2, 9, 10, 11]], lo[:, [0, 1, 2, 9, 10, 11]])
+    assert s.info()["restarts"] == o.info()["restarts"]
+
+
 @pytest.mark.parametrize("name,budget", [("small50x100", 200_000), ("ge_rows", 200_000),
                                          ("mixed_inf", 400_000)])
 def test_solve_to_1e8_matches_oracle(lib, name, budget):
