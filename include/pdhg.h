@@ -137,6 +137,16 @@ typedef struct pdhg_info {
     double rho_prev;          /* rho of the last restart point                 */
     int64_t checks;           /* checks so far                                 */
     int64_t power_iters_used; /* products used by the power iteration          */
+    int32_t one_workgroup;    /* nonzero: pdhg_solve runs whole check periods
+                                 of this LP in one workgroup (method PDHG,
+                                 restarts other than fixed length, n + m <= 1024
+                                 and the iteration vectors within 148 KiB of
+                                 LDS); 1: every lane holds its matrix entries
+                                 in registers, 2: the matrix is in LDS too.
+                                 0: one launch per product and check step.
+                                 Environment: PDHG_TINY=0 at pdhg_create turns
+                                 the path off, PDHG_TINY=lds asks for 2 */
+    int32_t reserved;
 } pdhg_info;
 
 /* One check, in the order the library performs it (14 doubles):

@@ -63,7 +63,8 @@ class Info(C.Structure):
     _fields_ = [("eta", C.c_double), ("tau", C.c_double), ("sigma", C.c_double),
                 ("sigma_max", C.c_double), ("k", C.c_int64), ("t", C.c_int64),
                 ("restarts", C.c_int64), ("rho_prev", C.c_double),
-                ("checks", C.c_int64), ("power_iters_used", C.c_int64)]
+                ("checks", C.c_int64), ("power_iters_used", C.c_int64),
+                ("one_workgroup", C.c_int32), ("reserved", C.c_int32)]
 
 
 class CheckRecord(C.Structure):

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdhg.so")
 SOURCES = ["pdhg_kernels.hip", "pdhg_tr.hip", "pdhg_api.hip", "pdhg_batch.hip",
-           "pdhg_weights.hip"]
+           "pdhg_weights.hip", "pdhg_tiny.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

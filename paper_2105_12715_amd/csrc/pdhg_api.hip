@@ -27,6 +27,7 @@ struct pdhg_handle {
     hipGraphExec_t gexec;   // one block of iterations plus its check
     double g_tol;
     bool g_valid;
+    TinyPlan tiny;          // one-workgroup solver, when the LP fits one CU's LDS
 };
 
 #define CK(expr)                                   \
@@ -491,6 +492,7 @@ int pdhg_create(const pdhg_lp *lp, const pdhg_params *prm_in, void *workspace,
         }
         h->tau = h->eta / prm.omega;
         h->sigma = h->eta * prm.omega;
+        h->tiny = tiny_plan(d, s);
         if (hipStreamSynchronize(s) != hipSuccess) {
             rc = PDHG_E_HIP;
             break;
@@ -679,12 +681,35 @@ int pdhg_solve(pdhg_t *h, int64_t max_iters, double tol, pdhg_result *out) {
         int64_t to_check = P - (k % P);
         if (use_graph && k % P == 0 && k_end - k >= P) {
             // replay whole blocks; the device skips everything after convergence
-            if ((rc = build_graph(h, tol))) return rc;
+            const bool tiny = h->tiny.ok && h->prm.method == PDHG_METHOD_PDHG && P <= INT32_MAX;
+            TinyArgs ta{};
+            if (tiny) {
+                ta.tau = h->tau;
+                ta.sigma = h->sigma;
+                ta.tol = tol;
+                ta.beta = h->prm.beta;
+                ta.omega = h->d.omega;
+                ta.sw = sqrt(h->d.omega);
+                ta.P = (int)P;
+                ta.tau0 = h->prm.tau0;
+                ta.kkt_kind = h->prm.kkt_kind;
+                ta.gap_slots = gap_slots_for(h->prm.restart_mode);
+                ta.Lp = h->tiny.Lp;
+                ta.Ld = h->tiny.Ld;
+            } else if ((rc = build_graph(h, tol))) {
+                return rc;
+            }
             int64_t blocks = (k_end - k) / P;
             int64_t batch = 1;
             while (blocks > 0 && !conv) {
                 int64_t nb = batch < blocks ? batch : blocks;
-                for (int64_t q = 0; q < nb; ++q) CK(hipGraphLaunch(h->gexec, h->stream));
+                if (tiny) {
+                    ta.blocks = (int)nb;
+                    launch_tiny_blocks(h->d, ta, h->tiny, h->stream);
+                    if ((rc = last_error())) return rc;
+                } else {
+                    for (int64_t q = 0; q < nb; ++q) CK(hipGraphLaunch(h->gexec, h->stream));
+                }
                 if ((rc = read_state(h, &hs))) return rc;
                 if (hs.numerr) return PDHG_E_NUMERICAL;
                 blocks -= nb;
@@ -848,6 +873,11 @@ int pdhg_get_info(pdhg_t *h, pdhg_info *out) {
     out->rho_prev = hs.rho_prev;
     out->checks = hs.checks;
     out->power_iters_used = h->pw_used;
+    out->one_workgroup = 0;
+    if (h->tiny.ok && h->prm.method == PDHG_METHOD_PDHG &&
+        h->prm.restart_mode != PDHG_RESTART_FIXED)
+        out->one_workgroup = h->tiny.reg ? 1 : 2;
+    out->reserved = 0;
     return PDHG_OK;
 }
 

@@ -8,15 +8,42 @@ namespace pdhg {
 // ---------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+// a double from another lane of the same row of 16 (DPP lane pattern CTRL);
+// a source lane outside the row or switched off gives 0
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Deterministic block sums of K values; result valid in thread 0.
-template <int K>
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over a whole wave (every lane active), the same value in every lane
+// and a fixed order: a butterfly inside each row of 16 lanes (DPP quad
+// permutations for lane ^ 1 and lane ^ 2; once the lanes of each quad
+// agree, the mirrors inside 8 and 16 lanes pair each quad with the other
+// of its half and each half with the other), then the four row sums.
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+}
+
+// Deterministic block sums of K <= 64 values over a workgroup of NW full
+// waves (sh holds NW * K doubles): lane k of wave 0 adds the wave sums of
+// value k in wave order; result valid in wave 0 (so in thread 0).
+template <int K, int NW = kWG / 64>
 __device__ __forceinline__ void block_sums(double (&v)[K], double *sh) {
+    static_assert(K <= 64, "one lane per value");
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
@@ -25,13 +52,14 @@ __device__ __forceinline__ void block_sums(double (&v)[K], double *sh) {
         for (int k = 0; k < K; ++k) sh[w * K + k] = v[k];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (w == 0) {
+        double s = 0.0;
+        if (lane < K) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            double s = 0.0;
-            for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i * K + k];
-            v[k] = s;
+            for (int i = 0; i < NW; ++i) s += sh[i * K + lane];
         }
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = lane_f64(s, k);
     }
     __syncthreads();
 }
@@ -291,5 +319,321 @@ __device__ void choose_bucket(TRState &ts, const unsigned int *cnt, const double
     }
     __syncthreads();
 }
+
+
+// ---------------------------------------------------------------------
+// PDHG half-step epilogues
+// ---------------------------------------------------------------------
+// x+ = proj_[l,u](x - tau (c - A'y)); sx += x+   (eq. PDHG-update, primal)
+struct EpiPrimal {
+    const double *__restrict__ c, *__restrict__ l, *__restrict__ u;
+    double *__restrict__ x, *__restrict__ sx;
+    double tau;
+    DevState *st;
+    __device__ __forceinline__ void operator()(int j, double aty) const {
+        double g = c[j] - aty;
+        double xn = x[j] - tau * g;
+        const double lo = l[j], hi = u[j];
+        if (xn < lo) xn = lo;
+        if (xn > hi) xn = hi;
+        x[j] = xn;
+        sx[j] += xn;
+        if (j == 0) {  // iteration counters of Algorithm 1
+            st->k += 1;
+            st->t += 1;
+        }
+    }
+};
+
+// y+ = proj_Y(y + sigma (b - (2 A x+ - A x))); sy += y+; q = A x+
+struct EpiDual {
+    const double *__restrict__ b;
+    const signed char *__restrict__ kind;
+    double *__restrict__ y, *__restrict__ sy, *__restrict__ q;
+    double sigma;
+    __device__ __forceinline__ void operator()(int i, double ax) const {
+        double yv = y[i] + sigma * (b[i] - (2.0 * ax - q[i]));
+        if (kind && kind[i] && yv < 0.0) yv = 0.0;
+        y[i] = yv;
+        sy[i] += yv;
+        q[i] = ax;
+    }
+};
+
+// ---------------------------------------------------------------------
+// check steps shared by the multi-kernel check and the one-workgroup path
+// ---------------------------------------------------------------------
+// z-bar = S / t at coordinate i (x first, then y); the empty window
+// averages to z itself
+__device__ __forceinline__ void average_at(const Dev &d, long long i, long long t) {
+    const double tt = (double)t;
+    if (i < d.n) d.xbar[i] = t ? d.sx[i] / tt : d.x[i];
+    else if (i < (long long)d.n + d.m) {
+        const long long r = i - d.n;
+        d.ybar[r] = t ? d.sy[r] / tt : d.y[r];
+    }
+}
+
+// KKT sums of coordinate i (x coordinates first, then y) at the points of
+// P2 (slot 0: the current point, slot 1: the average) and the squared
+// distances of both to the anchor (eq. define:K-and-h-for-lp rows).
+__device__ __forceinline__ void kkt_elem(const Dev &d, const KktPoints &P2, long long i,
+                                         double (&v)[kKktSums]) {
+    // squared distances to the anchor, added after the branch (one of the
+    // pairs is zero) so that the two branches write different slots
+    double rxa = 0.0, rxc = 0.0, rya = 0.0, ryc = 0.0;
+    if (i < d.n) {
+        const int j = (int)i;
+        const double cj = d.c[j], lj = d.l[j], uj = d.u[j], x0 = d.x0[j];
+        const bool lf = isfinite(lj), uf = isfinite(uj);
+        const double xs[2] = {P2.x[0][j], P2.x[1][j]};
+        const double ats[2] = {P2.aty[0][j], P2.aty[1][j]};
+#pragma unroll
+        for (int P = 0; P < 2; ++P) {
+            const double xp = xs[P];
+            const double rc = cj - ats[P];
+            double lam;
+            if (lf && uf) lam = rc;
+            else if (lf) lam = rc > 0.0 ? rc : 0.0;
+            else if (uf) lam = rc < 0.0 ? rc : 0.0;
+            else lam = 0.0;
+            const double dr = rc - lam;
+            v[S_DRES2_C + P] += dr * dr;
+            double dob = 0.0;
+            if (lam > 0.0) dob += lj * lam;
+            if (lam < 0.0) dob += uj * lam;
+            v[S_DOBJ_C + P] += dob;
+            v[S_POBJ_C + P] += cj * xp;
+            double bv = 0.0;
+            if (xp < lj) bv = lj - xp;
+            if (xp > uj) bv = xp - uj;
+            v[S_BV2_C + P] += bv * bv;
+        }
+        const double da = xs[1] - x0, dc = xs[0] - x0;
+        rxa = da * da;
+        rxc = dc * dc;
+    } else {
+        const int r = (int)(i - d.n);
+        const double br = d.b[r], y0 = d.y0[r];
+        const bool ge = d.kind && d.kind[r];
+        const double ys[2] = {P2.y[0][r], P2.y[1][r]};
+        const double axs[2] = {P2.ax[0][r], P2.ax[1][r]};
+#pragma unroll
+        for (int P = 0; P < 2; ++P) {
+            double p = br - axs[P];
+            if (ge && p < 0.0) p = 0.0;
+            v[S_PRES2_C + P] += p * p;
+            v[S_DOBJ_C + P] += br * ys[P];
+            const double yneg = (ge && ys[P] < 0.0) ? ys[P] : 0.0;
+            v[S_BV2_C + P] += yneg * yneg;
+        }
+        const double da = ys[1] - y0, dc = ys[0] - y0;
+        rya = da * da;
+        ryc = dc * dc;
+    }
+    v[S_RX2_A] += rxa;
+    v[S_RX2_C] += rxc;
+    v[S_RY2_A] += rya;
+    v[S_RY2_C] += ryc;
+}
+
+__device__ __forceinline__ void kkt_point(const Dev &d, const double *S, int P, double *out) {
+    const double pres2 = S[S_PRES2_C + P], dres2 = S[S_DRES2_C + P];
+    const double pobj = S[S_POBJ_C + P], dobj = S[S_DOBJ_C + P], bv2 = S[S_BV2_C + P];
+    const double pres = sqrt(pres2), dres = sqrt(dres2);
+    const double gap = pobj - dobj;
+    const double rel_p = pres / (1.0 + sqrt(d.st->nb2));
+    const double rel_d = dres / (1.0 + sqrt(d.st->nc2));
+    const double rel_g = fabs(gap) / (1.0 + fabs(pobj) + fabs(dobj));
+    double rel = rel_p;
+    if (rel_d > rel) rel = rel_d;
+    if (rel_g > rel) rel = rel_g;
+    const double gpos = gap > 0.0 ? gap : 0.0;
+    double mx = pres;
+    if (dres > mx) mx = dres;
+    if (fabs(gap) > mx) mx = fabs(gap);
+    out[1] = rel;
+    out[2] = pres;
+    out[3] = dres;
+    out[4] = pobj;
+    out[5] = dobj;
+    out[6] = sqrt(bv2 + pres2 + dres2 + gpos * gpos);
+    out[7] = mx;
+}
+
+__device__ __forceinline__ double kkt_pick(const double *k8, int kind) {
+    if (kind == 1) return k8[6];
+    if (kind == 2) return k8[7];
+    return k8[1];
+}
+// The stopping test of a check from the 14 KKT sums S: KKT at z and z-bar,
+// the converged flag (termination first), the radii, and the trust-region
+// slots armed for the restart test.  Returns the armed slots.
+__device__ __forceinline__ int kkt_conclude(const Dev &d, const double *S, double tol, int kkt_kind,
+                                            double omega, int gap_slots) {
+    DevState *st = d.st;
+    st->in_check = 1;
+    st->restarted = 0;
+    st->cand = 0;
+    kkt_point(d, S, 0, st->kkt_cur);
+    kkt_point(d, S, 1, st->kkt_avg);
+    const double kc = kkt_pick(st->kkt_cur, kkt_kind), ka = kkt_pick(st->kkt_avg, kkt_kind);
+    st->kkt_cur[0] = kc;
+    st->kkt_avg[0] = ka;
+    bool bad = false;
+    for (int k = 0; k < kKktSums; ++k) bad |= !isfinite(S[k]);
+    st->numerr = bad ? 1 : 0;
+    int conv = (tol > 0.0 && (kc <= tol || ka <= tol)) ? 1 : 0;
+    st->conv_which = -1;
+    if (conv) {
+        st->done = 1;
+        st->conv_which = (ka <= kc) ? 1 : 0;
+        st->conv_k = st->k;
+    }
+    st->r_avg = sqrt(omega * S[S_RX2_A] + S[S_RY2_A] / omega);
+    st->r_cur = sqrt(omega * S[S_RX2_C] + S[S_RY2_C] / omega);
+    int slots = 0;
+    if (!conv && !bad && st->t > 0) slots = gap_slots;
+    st->gap_slots = slots;
+    for (int sidx = 0; sidx < kTrSlots; ++sidx) {
+        TRState &ts = st->tr[sidx];
+        ts.mode = TR_IDLE;
+        ts.rho = 0.0;
+        ts.lam = 0.0;
+        if (slots & (1 << sidx)) {
+            ts.mode = TR_SEARCH;
+            ts.r = sidx == 0 ? st->r_avg : st->r_cur;
+            ts.r2 = ts.r * ts.r;
+            ts.F_acc = 0.0;
+            ts.A_acc = 0.0;
+            ts.prefix = 0ull;
+            ts.klo = 0ull;
+            ts.level = 0;
+            ts.count = 0;
+            ts.ncomp = 0;
+            ts.nan_seen = 0;
+        }
+    }
+    return slots;
+}
+
+// The restart test of a check (eq. adaptive-restart-scheme, Remark
+// rem:flexible) from the trust-region results, the restart bookkeeping,
+// and the check record.  One thread.
+__device__ __forceinline__ void decide_restart(const Dev &d, double beta, int tau0) {
+    DevState *st = d.st;
+    double rec[kRec];
+    rec[0] = (double)st->k;
+    rec[1] = (double)st->t;
+    rec[2] = (double)st->restarts;
+    rec[3] = st->kkt_cur[0];
+    rec[4] = st->kkt_avg[0];
+    rec[5] = 0.0;
+    rec[6] = 0.0;
+    rec[7] = 0.0;
+    rec[8] = -1.0;
+    rec[9] = 0.0;
+    rec[10] = 0.0;
+    rec[11] = (double)st->conv_which;
+    rec[12] = st->rho_prev;
+    rec[13] = 0.0;
+    const int slots = st->gap_slots;
+    if (slots & 1) {
+        rec[5] = st->r_avg;
+        rec[6] = st->tr[0].rho;
+        rec[13] = st->tr[0].lam;
+        if (st->tr[0].nan_seen) st->numerr = 1;
+    }
+    if (slots & 2) {
+        rec[7] = st->r_cur;
+        rec[8] = st->tr[1].rho;
+        if (st->tr[1].nan_seen) st->numerr = 1;
+    }
+    if ((slots & 1) && !st->done && !st->numerr) {
+        const double rho_a = st->tr[0].rho;
+        double rho_c = rho_a;
+        int cand = 0;
+        if ((slots & 2) && st->tr[1].rho < rho_a) {  // strict, as in Remark rem:flexible
+            cand = 1;
+            rho_c = st->tr[1].rho;
+        }
+        bool restart;
+        if (st->restarts == 0) restart = st->t >= (long long)tau0;
+        else restart = rho_c <= beta * st->rho_prev;
+        rec[10] = (double)cand;
+        if (restart) {
+            rec[9] = 1.0;
+            st->restarted = 1;
+            st->cand = cand;
+            st->restarts += 1;
+            st->t = 0;
+            st->rho_prev = rho_c;
+        }
+    }
+    double *dst = d.log + (size_t)(st->checks % kLogCap) * kRec;
+    for (int q = 0; q < kRec; ++q) dst[q] = rec[q];
+    st->checks += 1;
+    st->in_check = 0;
+}
+
+// The restart of Algorithm 1 at coordinate i: the anchor and the current
+// point become the candidate (z-bar, or z itself when cand = 1), with
+// q = A x kept consistent, and the running sums restart.
+__device__ __forceinline__ void apply_restart_at(const Dev &d, long long i, int cand) {
+    if (i < d.n) {
+        if (cand == 0) {
+            const double v = d.xbar[i];
+            d.x[i] = v;
+            d.x0[i] = v;
+        } else {
+            d.x0[i] = d.x[i];
+        }
+        d.sx[i] = 0.0;
+    }
+    if (i < d.m) {
+        if (cand == 0) {
+            const double v = d.ybar[i];
+            d.y[i] = v;
+            d.y0[i] = v;
+            d.q[i] = d.axb[i];
+        } else {
+            d.y0[i] = d.y[i];
+        }
+        d.sy[i] = 0.0;
+    }
+}
+
+// coordinates (|g_i|, distance to the bound g_i points at) of the linear
+// trust region at a point (x, y) with A x and A'y, in the omega-weighted norm
+struct GapElems {
+    int n, m;
+    const double *c, *b, *l, *u;
+    const signed char *kind;
+    const double *x, *y, *ax, *aty;
+    double sw;  // sqrt(omega): the norm is omega |x|^2 + |y|^2 / omega
+    __device__ __forceinline__ long long size() const { return (long long)n + m; }
+    __device__ __forceinline__ void get(long long i, double &a, double &d) const {
+        if (i < n) {
+            const int j = (int)i;
+            const double g = c[j] - aty[j];
+            double dist = 0.0;
+            if (g > 0.0) dist = x[j] - l[j];
+            else if (g < 0.0) dist = u[j] - x[j];
+            if (dist < 0.0) dist = 0.0;
+            a = fabs(g) / sw;
+            d = dist * sw;
+        } else {
+            const int r = (int)(i - n);
+            const double g = ax[r] - b[r];
+            const double lo = (kind && kind[r]) ? 0.0 : -INFINITY;
+            double dist = 0.0;
+            if (g > 0.0) dist = y[r] - lo;
+            else if (g < 0.0) dist = INFINITY;
+            if (dist < 0.0) dist = 0.0;
+            a = fabs(g) * sw;
+            d = dist / sw;
+        }
+    }
+};
 
 }  // namespace pdhg

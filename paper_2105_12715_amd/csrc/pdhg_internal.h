@@ -263,4 +263,41 @@ int red_grid(long long N);
 void launch_tr_raw(int64_t N, const double *a, const double *dd, double r,
                    const TRWork &w, TRState *st, hipStream_t s);
 
+// ---------------------------------------------------------------------
+// One-workgroup solver for LPs whose iteration vectors (and, unless every
+// row fits the registers of its lanes, the matrix) fit one CU's LDS: whole
+// blocks of iterations plus their checks in one launch.
+// ---------------------------------------------------------------------
+constexpr int kTinyWG = 512;                 // threads of the one workgroup
+constexpr int kTinyMaxCoords = 1024;         // n + m
+constexpr int kTinyK = 8;                    // matrix entries per lane held in registers
+constexpr size_t kTinyLdsMax = 148u << 10;   // dynamic LDS bytes (static LDS + this <= 160 KB)
+struct TinyPlan {
+    int ok;                // the LP fits
+    int reg;               // 1: matrix rows in registers, 0: matrix in LDS
+    int Lp, Ld;            // lanes per row of A' (primal) and of A (dual)
+    size_t lds;            // dynamic LDS bytes
+};
+struct TinyArgs {
+    double tau, sigma, tol, beta, omega, sw;  // sw = sqrt(omega)
+    int P, tau0, kkt_kind, gap_slots, blocks;
+    int Lp, Ld;
+};
+// LDS bytes of the one-workgroup solver: doubles x, x-bar (n + 1 each, the
+// last a zero that padded matrix entries point at), sx, c, l, u, A'y,
+// A'y-bar (n each), y, y-bar (m + 1 each), sy, q, b, A x-bar (m each);
+// trust-region keys, d^2, a^2 and a d (n + m each); m bytes of row kinds; and,
+// with the matrix in LDS, the values of A and A' (nnz doubles each), their
+// row starts (ints) and 16-bit column indices
+__host__ __device__ inline size_t tiny_lds_bytes(long long n, long long m, long long nnz,
+                                                 int reg) {
+    long long b = 8 * (8 * n + 6 * m + 4) + 32 * (n + m) + m;
+    b = (b + 7) & ~7ll;
+    if (!reg) b += 16 * nnz + 4 * (n + m + 2) + 4 * nnz;
+    return (size_t)((b + 15) & ~15ll);
+}
+// plan for an LP already on the device (reads its row starts)
+TinyPlan tiny_plan(const Dev &d, hipStream_t s);
+void launch_tiny_blocks(const Dev &d, const TinyArgs &a, const TinyPlan &p, hipStream_t s);
+
 }  // namespace pdhg

@@ -39,42 +39,6 @@
 
 namespace pdhg {
 
-// x+ = proj_[l,u](x - tau (c - A'y)); sx += x+   (eq. PDHG-update, primal)
-struct EpiPrimal {
-    const double *__restrict__ c, *__restrict__ l, *__restrict__ u;
-    double *__restrict__ x, *__restrict__ sx;
-    double tau;
-    DevState *st;
-    __device__ __forceinline__ void operator()(int j, double aty) const {
-        double g = c[j] - aty;
-        double xn = x[j] - tau * g;
-        const double lo = l[j], hi = u[j];
-        if (xn < lo) xn = lo;
-        if (xn > hi) xn = hi;
-        x[j] = xn;
-        sx[j] += xn;
-        if (j == 0) {  // iteration counters of Algorithm 1
-            st->k += 1;
-            st->t += 1;
-        }
-    }
-};
-
-// y+ = proj_Y(y + sigma (b - (2 A x+ - A x))); sy += y+; q = A x+
-struct EpiDual {
-    const double *__restrict__ b;
-    const signed char *__restrict__ kind;
-    double *__restrict__ y, *__restrict__ sy, *__restrict__ q;
-    double sigma;
-    __device__ __forceinline__ void operator()(int i, double ax) const {
-        double yv = y[i] + sigma * (b[i] - (2.0 * ax - q[i]));
-        if (kind && kind[i] && yv < 0.0) yv = 0.0;
-        y[i] = yv;
-        sy[i] += yv;
-        q[i] = ax;
-    }
-};
-
 // Extragradient step (eq. extra-gradient-update) with F(z) = (c - A'y, Ax - b):
 // the target z~ = proj_Z(z - D F(z)) (first two products), then
 // z+ = proj_Z(z - D F(z~)) (last two); the sums of Algorithm 1 take z~.
@@ -816,42 +780,12 @@ __global__ void k_reset_done(DevState *st) {
 
 __global__ void k_average(Dev d) {
     if (d.st->done) return;
-    const long long t = d.st->t;
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const double tt = (double)t;
-    if (i < d.n) d.xbar[i] = t ? d.sx[i] / tt : d.x[i];
-    else if (i < (long long)d.n + d.m) {
-        long long r = i - d.n;
-        d.ybar[r] = t ? d.sy[r] / tt : d.y[r];
-    }
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    average_at(d, i, d.st->t);
 }
 
 void launch_average(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_average, dim3(div_up((long long)d.n + d.m, kWG)), dim3(kWG), 0, s, d);
-}
-
-__device__ void kkt_point(const Dev &d, const double *S, int P, double *out) {
-    const double pres2 = S[S_PRES2_C + P], dres2 = S[S_DRES2_C + P];
-    const double pobj = S[S_POBJ_C + P], dobj = S[S_DOBJ_C + P], bv2 = S[S_BV2_C + P];
-    const double pres = sqrt(pres2), dres = sqrt(dres2);
-    const double gap = pobj - dobj;
-    const double rel_p = pres / (1.0 + sqrt(d.st->nb2));
-    const double rel_d = dres / (1.0 + sqrt(d.st->nc2));
-    const double rel_g = fabs(gap) / (1.0 + fabs(pobj) + fabs(dobj));
-    double rel = rel_p;
-    if (rel_d > rel) rel = rel_d;
-    if (rel_g > rel) rel = rel_g;
-    const double gpos = gap > 0.0 ? gap : 0.0;
-    double mx = pres;
-    if (dres > mx) mx = dres;
-    if (fabs(gap) > mx) mx = fabs(gap);
-    out[1] = rel;
-    out[2] = pres;
-    out[3] = dres;
-    out[4] = pobj;
-    out[5] = dobj;
-    out[6] = sqrt(bv2 + pres2 + dres2 + gpos * gpos);
-    out[7] = mx;
 }
 
 __global__ __launch_bounds__(kWG) void k_kkt_partials(Dev d, KktPoints P2, int gated) {
@@ -862,56 +796,8 @@ __global__ __launch_bounds__(kWG) void k_kkt_partials(Dev d, KktPoints P2, int g
     for (int k = 0; k < kKktSums; ++k) v[k] = 0.0;
     const long long N = (long long)d.n + d.m;
     const long long stride = (long long)gridDim.x * kWG;
-    for (long long i = (long long)blockIdx.x * kWG + threadIdx.x; i < N; i += stride) {
-        if (i < d.n) {
-            const int j = (int)i;
-            const double cj = d.c[j], lj = d.l[j], uj = d.u[j], x0 = d.x0[j];
-            const bool lf = isfinite(lj), uf = isfinite(uj);
-            const double xs[2] = {P2.x[0][j], P2.x[1][j]};
-            const double ats[2] = {P2.aty[0][j], P2.aty[1][j]};
-#pragma unroll
-            for (int P = 0; P < 2; ++P) {
-                const double xp = xs[P];
-                const double rc = cj - ats[P];
-                double lam;
-                if (lf && uf) lam = rc;
-                else if (lf) lam = rc > 0.0 ? rc : 0.0;
-                else if (uf) lam = rc < 0.0 ? rc : 0.0;
-                else lam = 0.0;
-                const double dr = rc - lam;
-                v[S_DRES2_C + P] += dr * dr;
-                double dob = 0.0;
-                if (lam > 0.0) dob += lj * lam;
-                if (lam < 0.0) dob += uj * lam;
-                v[S_DOBJ_C + P] += dob;
-                v[S_POBJ_C + P] += cj * xp;
-                double bv = 0.0;
-                if (xp < lj) bv = lj - xp;
-                if (xp > uj) bv = xp - uj;
-                v[S_BV2_C + P] += bv * bv;
-            }
-            const double da = xs[1] - x0, dc = xs[0] - x0;
-            v[S_RX2_A] += da * da;
-            v[S_RX2_C] += dc * dc;
-        } else {
-            const int r = (int)(i - d.n);
-            const double br = d.b[r], y0 = d.y0[r];
-            const bool ge = d.kind && d.kind[r];
-            const double ys[2] = {P2.y[0][r], P2.y[1][r]};
-            const double axs[2] = {P2.ax[0][r], P2.ax[1][r]};
-#pragma unroll
-            for (int P = 0; P < 2; ++P) {
-                double p = br - axs[P];
-                if (ge && p < 0.0) p = 0.0;
-                v[S_PRES2_C + P] += p * p;
-                v[S_DOBJ_C + P] += br * ys[P];
-                if (ge && ys[P] < 0.0) v[S_BV2_C + P] += ys[P] * ys[P];
-            }
-            const double da = ys[1] - y0, dc = ys[0] - y0;
-            v[S_RY2_A] += da * da;
-            v[S_RY2_C] += dc * dc;
-        }
-    }
+    for (long long i = (long long)blockIdx.x * kWG + threadIdx.x; i < N; i += stride)
+        kkt_elem(d, P2, i, v);
     block_sums<kKktSums>(v, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
@@ -943,11 +829,6 @@ void launch_kkt_eval(const Dev &d, int which, hipStream_t s) {
     hipLaunchKernelGGL(k_kkt_eval, dim3(1), dim3(kWG), 0, s, d, g);
 }
 
-__device__ __forceinline__ double kkt_pick(const double *k8, int kind) {
-    if (kind == 1) return k8[6];
-    if (kind == 2) return k8[7];
-    return k8[1];
-}
 
 // Stopping test and the radii; arms the trust-region slots.
 __global__ __launch_bounds__(kWG) void k_kkt_final(Dev d, int nb, double tol, int kkt_kind,
@@ -958,51 +839,7 @@ __global__ __launch_bounds__(kWG) void k_kkt_final(Dev d, int nb, double tol, in
     __shared__ int armed;
     double S[kKktSums];
     reduce_partials<kKktSums>(d.part, nb, kKktSums, S, sh);
-    if (threadIdx.x == 0) {
-        st->in_check = 1;
-        st->restarted = 0;
-        st->cand = 0;
-        kkt_point(d, S, 0, st->kkt_cur);
-        kkt_point(d, S, 1, st->kkt_avg);
-        const double kc = kkt_pick(st->kkt_cur, kkt_kind), ka = kkt_pick(st->kkt_avg, kkt_kind);
-        st->kkt_cur[0] = kc;
-        st->kkt_avg[0] = ka;
-        bool bad = false;
-        for (int k = 0; k < kKktSums; ++k) bad |= !isfinite(S[k]);
-        st->numerr = bad ? 1 : 0;
-        int conv = (tol > 0.0 && (kc <= tol || ka <= tol)) ? 1 : 0;
-        st->conv_which = -1;
-        if (conv) {
-            st->done = 1;
-            st->conv_which = (ka <= kc) ? 1 : 0;
-            st->conv_k = st->k;
-        }
-        st->r_avg = sqrt(omega * S[S_RX2_A] + S[S_RY2_A] / omega);
-        st->r_cur = sqrt(omega * S[S_RX2_C] + S[S_RY2_C] / omega);
-        int slots = 0;
-        if (!conv && !bad && st->t > 0) slots = gap_slots;
-        st->gap_slots = slots;
-        for (int sidx = 0; sidx < kTrSlots; ++sidx) {
-            TRState &ts = st->tr[sidx];
-            ts.mode = TR_IDLE;
-            ts.rho = 0.0;
-            ts.lam = 0.0;
-            if (slots & (1 << sidx)) {
-                ts.mode = TR_SEARCH;
-                ts.r = sidx == 0 ? st->r_avg : st->r_cur;
-                ts.r2 = ts.r * ts.r;
-                ts.F_acc = 0.0;
-                ts.A_acc = 0.0;
-                ts.prefix = 0ull;
-                ts.klo = 0ull;
-                ts.level = 0;
-                ts.count = 0;
-                ts.ncomp = 0;
-                ts.nan_seen = 0;
-            }
-        }
-        armed = slots;
-    }
+    if (threadIdx.x == 0) armed = kkt_conclude(d, S, tol, kkt_kind, omega, gap_slots);
     __syncthreads();
     // clear level-0 histograms of the armed slots
     for (int sidx = 0; sidx < kTrSlots; ++sidx) {

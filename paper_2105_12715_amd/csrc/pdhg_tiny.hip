@@ -1,0 +1,671 @@
+// Restarted PDHG in one workgroup, for LPs whose iteration vectors fit one
+// CU's LDS.
+//
+// A tiny LP leaves the chip idle: every half-step of the multi-kernel path
+// is a launch of a few blocks, and the check of Section 7 is a dozen more.
+// Here one workgroup of kTinyWG threads runs whole blocks of the check
+// period: the iterations of eq. (PDHG-update), then the check (averages,
+// KKT, radii, the restart test of eq. adaptive-restart-scheme and the
+// restart of Algorithm 1), with barriers between the phases.  The host
+// launches a batch of blocks and polls the state between launches.
+//
+// Rows of A' (primal half-step) and of A (dual half-step) go to aligned
+// groups of L lanes.  When every row has at most kTinyK L entries and each
+// group holds one row, every lane keeps its entries (value, column) in
+// registers and the row's owner keeps its coordinate of the iterate, its
+// running sum and its LP data there too: a half-step is one gather from
+// LDS, a fused multiply-add chain, a butterfly and a barrier.  Otherwise
+// the matrix sits in LDS in CSR with 16-bit column indices.
+//
+// The trust region of the normalized duality gap (Section 6.3.1) has the
+// same answer as in the multi-kernel path: with breakpoints
+// lambda_i = d_i / a_i (compared as IEEE key bits),
+//     f(lambda_p) = sum_{key_i <= key_p} d_i^2 + lambda_p^2 sum_{key_i > key_p} a_i^2
+// is evaluated directly at every breakpoint with a finite key (at most
+// n + m <= 1024 of them, compacted in coordinate order; one pass over the
+// keys per breakpoint by a few lanes, LDS broadcast reads), the clamped set
+// is every key up to the largest breakpoint with f <= r^2, and the closing
+// formula of Algorithm 2 takes the sums in a fixed order.
+#include "pdhg_device.h"
+
+#include <math.h>
+#include <stdlib.h>
+
+#include <vector>
+
+namespace pdhg {
+
+namespace {
+
+constexpr int WG = kTinyWG;
+constexpr int kWaves = WG / 64;
+constexpr int K = kTinyK;
+constexpr unsigned long long kNoKey = ~0ull;  // inactive coordinate (above every key)
+
+// LDS arrays of one launch, carved in the order tiny_lds_bytes counts them
+struct TinyLds {
+    double *x, *xb;                                // n + 1
+    double *sx, *c, *l, *u, *aty, *atyb;           // n
+    double *y, *yb;                                // m + 1
+    double *sy, *q, *b, *axb;                      // m
+    unsigned long long *tkey;                      // n + m
+    double *td2, *ta2, *tad;                       // n + m
+    signed char *kind;                             // m
+    double *av, *tv;                               // nnz (matrix in LDS)
+    int *arp, *trp;                                // m + 1, n + 1
+    unsigned short *aci, *tci;                     // nnz
+};
+
+__device__ TinyLds carve(unsigned char *base, int n, int m, int nnz, bool reg) {
+    TinyLds t;
+    double *dp = (double *)base;
+    t.x = dp; dp += n + 1;
+    t.xb = dp; dp += n + 1;
+    t.sx = dp; dp += n;
+    t.c = dp; dp += n;
+    t.l = dp; dp += n;
+    t.u = dp; dp += n;
+    t.aty = dp; dp += n;
+    t.atyb = dp; dp += n;
+    t.y = dp; dp += m + 1;
+    t.yb = dp; dp += m + 1;
+    t.sy = dp; dp += m;
+    t.q = dp; dp += m;
+    t.b = dp; dp += m;
+    t.axb = dp; dp += m;
+    t.tkey = (unsigned long long *)dp;
+    dp += n + m;
+    t.td2 = dp; dp += n + m;
+    t.ta2 = dp; dp += n + m;
+    t.tad = dp; dp += n + m;
+    unsigned char *cp = (unsigned char *)dp;
+    t.kind = (signed char *)cp;
+    cp += m;
+    cp = (unsigned char *)(((size_t)cp + 7) & ~(size_t)7);
+    t.av = t.tv = nullptr;
+    t.arp = t.trp = nullptr;
+    t.aci = t.tci = nullptr;
+    if (!reg) {
+        dp = (double *)cp;
+        t.av = dp; dp += nnz;
+        t.tv = dp; dp += nnz;
+        int *ip = (int *)dp;
+        t.arp = ip; ip += m + 1;
+        t.trp = ip; ip += n + 1;
+        unsigned short *sp = (unsigned short *)ip;
+        t.aci = sp; sp += nnz;
+        t.tci = sp;
+    }
+    return t;
+}
+
+// Sum over an aligned group of L lanes (L a power of two <= 64); every
+// lane of the group ends with the same sum.  Pairs, then quads exchange by
+// DPP quad permutations; once all lanes of a quad (of 8) agree, the mirror
+// inside 8 (16) lanes pairs each with the other quad (half); the steps
+// across rows of 16 go through the LDS crossbar.
+__device__ __forceinline__ double group_sum(double s, int L) {
+    if (L >= 2) s += dpp_f64<0xB1>(s);   // quad_perm [1,0,3,2]: lane ^ 1
+    if (L >= 4) s += dpp_f64<0x4E>(s);   // quad_perm [2,3,0,1]: lane ^ 2
+    if (L >= 8) s += dpp_f64<0x141>(s);  // row_half_mirror: 7 - lane within 8
+    if (L >= 16) s += dpp_f64<0x140>(s); // row_mirror: 15 - lane within 16
+    if (L >= 32) s += __shfl_xor(s, 16, 64);
+    if (L >= 64) s += __shfl_xor(s, 32, 64);
+    return s;
+}
+
+// Row r of a CSR matrix in LDS times the LDS vector v, by the L lanes of
+// its group: lane-strided partial sums, then the group sum.
+__device__ __forceinline__ double row_dot(const int *rp, const unsigned short *ci,
+                                          const double *val, const double *v, int r, int lane,
+                                          int L) {
+    double s = 0.0;
+    const int e1 = rp[r + 1];
+    for (int e = rp[r] + lane; e < e1; e += L) s += val[e] * v[ci[e]];
+    return group_sum(s, L);
+}
+
+// the same product from the lane's entries held in registers (padding
+// entries have value 0 and point at the zero after the vector's end)
+__device__ __forceinline__ double reg_dot(const int (&col)[K], const double (&val)[K],
+                                          const double *v, int L) {
+    double g[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) g[k] = v[col[k]];
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) s += val[k] * g[k];
+    return group_sum(s, L);
+}
+
+// A lane's share of one row (CSR rp, ci, v in global memory) into registers
+__device__ __forceinline__ void load_row(const int *rp, const int *ci, const double *v, int r,
+                                         int rows, int lane, int L, int pad, int (&col)[K],
+                                         double (&val)[K]) {
+    int e0 = 0, e1 = 0;
+    if (r < rows) {
+        e0 = rp[r];
+        e1 = rp[r + 1];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int e = e0 + lane + k * L;
+        if (e < e1) {
+            col[k] = ci[e];
+            val[k] = v[e];
+        } else {
+            col[k] = pad;
+            val[k] = 0.0;
+        }
+    }
+}
+
+struct TrShared {
+    double red[kWaves * 5];
+    unsigned long long best;  // largest key with f <= r^2, plus one (0: none)
+    int go;
+    int nf;                   // breakpoints with a finite key
+    int woff[2][kWaves];      // compaction offsets of each wave's finite keys
+};
+
+constexpr unsigned long long kInfKey = 0x7FF0000000000000ull;  // key of lambda = inf
+
+// The trust region of one slot (ts armed with r, r^2) over the N = n + m
+// (<= 2 WG) coordinates of e.  Called by the whole workgroup.
+template <class E>
+__device__ void tiny_trust_region(const E &e, TRState &ts, const TinyLds &t, TrShared &sh) {
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int N = (int)e.size();
+    // keys and squares of this thread's (at most two) coordinates, and the
+    // sums of the full-box test (first line of Algorithm 2)
+    unsigned long long key[2];
+    double d2[2], a2[2], ad[2];
+    bool fin[2];
+    double v5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // sum d^2 (finite d), #inf d, sum a d, #bad,
+                                               // sum a^2 of infinite keys
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int p = r * WG + tid;
+        key[r] = kNoKey;
+        d2[r] = a2[r] = ad[r] = 0.0;
+        if (p < N) {
+            double a, d;
+            e.get(p, a, d);
+            if (bad_pair(a, d)) {
+                v5[3] += 1.0;
+            } else if (a > 0.0) {
+                key[r] = key_of(a, d);
+                d2[r] = d * d;
+                a2[r] = a * a;
+                ad[r] = a * d;
+                if (d < INFINITY) {
+                    v5[0] += d2[r];
+                    v5[2] += ad[r];
+                } else {
+                    v5[1] += 1.0;
+                }
+                if (key[r] >= kInfKey) v5[4] += a2[r];
+            }
+        }
+        // a breakpoint with an infinite key is never clamped: f there is
+        // the whole box, larger than r^2 once the full-box test failed
+        fin[r] = key[r] < kInfKey;
+        const unsigned long long bal = __ballot(fin[r]);
+        if (lane == 0) sh.woff[r][w] = __popcll(bal);
+    }
+    block_sums<5, kWaves>(v5, sh.red);
+    if (tid == 0) {
+        int o = 0;
+        for (int r = 0; r < 2; ++r)
+            for (int q = 0; q < kWaves; ++q) {
+                const int c = sh.woff[r][q];
+                sh.woff[r][q] = o;
+                o += c;
+            }
+        sh.nf = o;
+        sh.go = 0;
+        sh.best = 0ull;
+        if (v5[3] > 0.0) {
+            ts.nan_seen = 1;
+            ts.mode = TR_ZERO;
+            ts.rho = NAN;
+            ts.lam = NAN;
+            ts.value = NAN;
+        } else if (!(ts.r > 0.0)) {
+            ts.mode = TR_ZERO;
+            ts.rho = 0.0;
+            ts.lam = 0.0;
+            ts.value = 0.0;
+        } else if (v5[1] == 0.0 && v5[0] <= ts.r2) {
+            ts.mode = TR_FULLBOX;
+            ts.value = v5[2];
+            ts.rho = v5[2] / ts.r;
+            ts.lam = INFINITY;
+        } else {
+            sh.go = 1;
+            ts.value = v5[4];  // sum a^2 over infinite keys, until the final pass
+        }
+    }
+    __syncthreads();
+    if (!sh.go) return;
+    // the finite keys, compacted in coordinate order
+    const unsigned long long lt = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const unsigned long long bal = __ballot(fin[r]);
+        if (fin[r]) {
+            const int at = sh.woff[r][w] + __popcll(bal & lt);
+            t.tkey[at] = key[r];
+            t.td2[at] = d2[r];
+            t.ta2[at] = a2[r];
+            t.tad[at] = ad[r];
+        }
+    }
+    __syncthreads();
+    const int Nf = sh.nf;
+    const double Ainf = ts.value;
+
+    // f at every finite breakpoint (equal keys give equal sums, so no
+    // grouping), T lanes per breakpoint splitting the pass over the keys
+    const double r2 = ts.r2;
+    int T = 1;
+    while (T < 64 && (long long)Nf * (2 * T) <= WG) T <<= 1;
+    const int part = tid & (T - 1);
+    for (int p = tid / T; p < Nf; p += WG / T) {
+        const unsigned long long kp = t.tkey[p];
+        double F = 0.0, A = 0.0;
+        int q = part;
+        for (; q + 3 * T < Nf; q += 4 * T) {
+            unsigned long long kq[4];
+            double dq[4], aq[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                kq[u] = t.tkey[q + u * T];
+                dq[u] = t.td2[q + u * T];
+                aq[u] = t.ta2[q + u * T];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                F += kq[u] <= kp ? dq[u] : 0.0;
+                A += kq[u] <= kp ? 0.0 : aq[u];
+            }
+        }
+        for (; q < Nf; q += T) {
+            const unsigned long long kq = t.tkey[q];
+            F += kq <= kp ? t.td2[q] : 0.0;
+            A += kq <= kp ? 0.0 : t.ta2[q];
+        }
+        F = group_sum(F, T);
+        A = group_sum(A, T) + Ainf;
+        if (part == 0) {
+            const double lam = __longlong_as_double((long long)kp);
+            const double f = F + lam * lam * A;
+            if (f <= r2) atomicMax(&sh.best, kp + 1ull);
+        }
+    }
+    __syncthreads();
+    const unsigned long long bk = sh.best;
+    const bool has = bk != 0ull;
+    const unsigned long long klo = bk - 1ull;
+
+    // F = sum d^2 (clamped), A = sum a^2 (free), AD = sum a d (clamped)
+    double v3[3] = {0.0, 0.0, 0.0};
+    for (int i = tid; i < Nf; i += WG) {
+        if (has && t.tkey[i] <= klo) {
+            v3[0] += t.td2[i];
+            v3[2] += t.tad[i];
+        } else {
+            v3[1] += t.ta2[i];
+        }
+    }
+    block_sums<3, kWaves>(v3, sh.red);
+    if (tid == 0) {
+        const double Fs = v3[0], As = v3[1] + Ainf, AD = v3[2];
+        double lam, val;
+        if (As > 0.0) {
+            double num = ts.r2 - Fs;
+            if (num < 0.0) num = 0.0;
+            lam = sqrt(num / As);
+            val = AD + lam * As;
+        } else {
+            lam = INFINITY;
+            val = AD;
+        }
+        ts.klo = has ? klo : 0ull;
+        ts.lam = lam;
+        ts.value = val;
+        ts.rho = val / ts.r;
+        ts.mode = TR_RESOLVED;
+    }
+    __syncthreads();
+}
+
+template <bool REG>
+__global__ __launch_bounds__(WG) void k_tiny_blocks(Dev d, TinyArgs a) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ DevState sst;
+    __shared__ TrShared trs;
+    __shared__ double red[kWaves * kKktSums];
+    __shared__ int armed;
+    const int tid = threadIdx.x;
+    const int n = d.n, m = d.m, nnz = d.nnz;
+    const TinyLds t = carve(lds, n, m, nnz, REG);
+    if (tid == 0) sst = *d.st;
+    for (int j = tid; j < n; j += WG) {
+        t.x[j] = d.x[j];
+        t.sx[j] = d.sx[j];
+        t.c[j] = d.c[j];
+        t.l[j] = d.l[j];
+        t.u[j] = d.u[j];
+    }
+    for (int i = tid; i < m; i += WG) {
+        t.y[i] = d.y[i];
+        t.sy[i] = d.sy[i];
+        t.q[i] = d.q[i];
+        t.b[i] = d.b[i];
+        t.kind[i] = d.kind ? d.kind[i] : (signed char)0;
+    }
+    if (tid == 0) {
+        t.x[n] = 0.0;
+        t.xb[n] = 0.0;
+        t.y[m] = 0.0;
+        t.yb[m] = 0.0;
+    }
+    if (!REG) {
+        for (int e = tid; e < nnz; e += WG) {
+            t.av[e] = d.v[e];
+            t.aci[e] = (unsigned short)d.ci[e];
+            t.tv[e] = d.tv[e];
+            t.tci[e] = (unsigned short)d.tci[e];
+        }
+        for (int i = tid; i <= m; i += WG) t.arp[i] = d.rp[i];
+        for (int j = tid; j <= n; j += WG) t.trp[j] = d.trp[j];
+    }
+
+    const int Lp = a.Lp, Ld = a.Ld;
+    const int lp = tid & (Lp - 1), gp = tid / Lp, Gp = WG / Lp;
+    const int ld = tid & (Ld - 1), gd = tid / Ld, Gd = WG / Ld;
+    const double tau = a.tau, sigma = a.sigma;
+
+    // register mode: this lane's entries of row gp of A' and row gd of A
+    int pc[K], dc[K];
+    double pv[K], dv[K];
+    if (REG) {
+        load_row(d.trp, d.tci, d.tv, gp, n, lp, Lp, m, pc, pv);
+        load_row(d.rp, d.ci, d.v, gd, m, ld, Ld, n, dc, dv);
+    }
+    const bool pown = REG && gp < n && lp == 0;  // owner of primal row gp
+    const bool down = REG && gd < m && ld == 0;  // owner of dual row gd
+    double xj = 0.0, sxj = 0.0, cj = 0.0, lj = 0.0, uj = 0.0;
+    double yi = 0.0, syi = 0.0, qi = 0.0, bi = 0.0;
+    int ki = 0;
+    __syncthreads();
+    if (pown) {
+        xj = t.x[gp];
+        sxj = t.sx[gp];
+        cj = t.c[gp];
+        lj = t.l[gp];
+        uj = t.u[gp];
+    }
+    if (down) {
+        yi = t.y[gd];
+        syi = t.sy[gd];
+        qi = t.q[gd];
+        bi = t.b[gd];
+        ki = t.kind[gd];
+    }
+
+    // the solver state as the shared check steps see it: LDS copies of
+    // everything but the anchor and the check log
+    Dev L = d;
+    L.x = t.x;
+    L.sx = t.sx;
+    L.c = t.c;
+    L.l = t.l;
+    L.u = t.u;
+    L.xbar = t.xb;
+    L.aty = t.aty;
+    L.atyb = t.atyb;
+    L.y = t.y;
+    L.sy = t.sy;
+    L.q = t.q;
+    L.b = t.b;
+    L.ybar = t.yb;
+    L.axb = t.axb;
+    L.kind = t.kind;
+    L.st = &sst;
+
+    for (int blk = 0; blk < a.blocks; ++blk) {
+        if (sst.done) break;  // uniform: every write to sst precedes a barrier
+        for (int it = 0; it < a.P; ++it) {
+            // x+ = proj_[l,u](x - tau (c - A'y)); sx += x+
+            if (REG) {
+                if (gp < n) {
+                    const double aty = reg_dot(pc, pv, t.y, Lp);
+                    if (lp == 0) {
+                        const double g = cj - aty;
+                        double xn = xj - tau * g;
+                        if (xn < lj) xn = lj;
+                        if (xn > uj) xn = uj;
+                        xj = xn;
+                        sxj += xn;
+                        t.x[gp] = xn;
+                    }
+                }
+            } else {
+                for (int j = gp; j < n; j += Gp) {
+                    const double aty = row_dot(t.trp, t.tci, t.tv, t.y, j, lp, Lp);
+                    if (lp == 0) {
+                        const double g = t.c[j] - aty;
+                        double xn = t.x[j] - tau * g;
+                        const double lo = t.l[j], hi = t.u[j];
+                        if (xn < lo) xn = lo;
+                        if (xn > hi) xn = hi;
+                        t.x[j] = xn;
+                        t.sx[j] += xn;
+                    }
+                }
+            }
+            __syncthreads();
+            // y+ = proj_Y(y + sigma (b - (2 A x+ - A x))); sy += y+; q = A x+
+            if (REG) {
+                if (gd < m) {
+                    const double ax = reg_dot(dc, dv, t.x, Ld);
+                    if (ld == 0) {
+                        double yv = yi + sigma * (bi - (2.0 * ax - qi));
+                        if (ki && yv < 0.0) yv = 0.0;
+                        yi = yv;
+                        syi += yv;
+                        qi = ax;
+                        t.y[gd] = yv;
+                    }
+                }
+            } else {
+                for (int i = gd; i < m; i += Gd) {
+                    const double ax = row_dot(t.arp, t.aci, t.av, t.x, i, ld, Ld);
+                    if (ld == 0) {
+                        double yv = t.y[i] + sigma * (t.b[i] - (2.0 * ax - t.q[i]));
+                        if (t.kind[i] && yv < 0.0) yv = 0.0;
+                        t.y[i] = yv;
+                        t.sy[i] += yv;
+                        t.q[i] = ax;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (pown) t.sx[gp] = sxj;
+        if (down) {
+            t.sy[gd] = syi;
+            t.q[gd] = qi;
+        }
+        if (tid == 0) {
+            sst.k += a.P;
+            sst.t += a.P;
+        }
+        __syncthreads();
+
+        // the check: averages, then A x-bar, A'y-bar and A'y
+        const long long tt = sst.t;
+        for (int i = tid; i < n + m; i += WG) average_at(L, i, tt);
+        __syncthreads();
+        if (REG) {
+            if (gd < m) {
+                const double s = reg_dot(dc, dv, t.xb, Ld);
+                if (ld == 0) t.axb[gd] = s;
+            }
+            if (gp < n) {
+                const double s1 = reg_dot(pc, pv, t.yb, Lp);
+                const double s2 = reg_dot(pc, pv, t.y, Lp);
+                if (lp == 0) {
+                    t.atyb[gp] = s1;
+                    t.aty[gp] = s2;
+                }
+            }
+        } else {
+            for (int i = gd; i < m; i += Gd) {
+                const double s = row_dot(t.arp, t.aci, t.av, t.xb, i, ld, Ld);
+                if (ld == 0) t.axb[i] = s;
+            }
+            for (int j = gp; j < n; j += Gp) {
+                const double s1 = row_dot(t.trp, t.tci, t.tv, t.yb, j, lp, Lp);
+                const double s2 = row_dot(t.trp, t.tci, t.tv, t.y, j, lp, Lp);
+                if (lp == 0) {
+                    t.atyb[j] = s1;
+                    t.aty[j] = s2;
+                }
+            }
+        }
+        __syncthreads();
+        // KKT at z and z-bar, distances to the anchor, stopping test
+        double v[kKktSums];
+#pragma unroll
+        for (int k = 0; k < kKktSums; ++k) v[k] = 0.0;
+        const KktPoints P2{{t.x, t.xb}, {t.y, t.yb}, {t.q, t.axb}, {t.aty, t.atyb}};
+        for (int i = tid; i < n + m; i += WG) kkt_elem(L, P2, i, v);
+        block_sums<kKktSums, kWaves>(v, red);
+        if (tid == 0) armed = kkt_conclude(L, v, a.tol, a.kkt_kind, a.omega, a.gap_slots);
+        __syncthreads();
+        const int slots = armed;
+        for (int sidx = 0; sidx < kTrSlots; ++sidx) {
+            if (!(slots & (1 << sidx))) continue;
+            GapElems e;
+            e.n = n;
+            e.m = m;
+            e.c = t.c;
+            e.b = t.b;
+            e.l = t.l;
+            e.u = t.u;
+            e.kind = t.kind;
+            e.x = sidx == 0 ? t.xb : t.x;
+            e.y = sidx == 0 ? t.yb : t.y;
+            e.ax = sidx == 0 ? t.axb : t.q;
+            e.aty = sidx == 0 ? t.atyb : t.aty;
+            e.sw = a.sw;
+            tiny_trust_region(e, sst.tr[sidx], t, trs);
+        }
+        if (tid == 0) decide_restart(L, a.beta, a.tau0);
+        __syncthreads();
+        if (sst.restarted) {
+            const int cand = sst.cand;
+            const int mx = n > m ? n : m;
+            for (int i = tid; i < mx; i += WG) apply_restart_at(L, i, cand);
+            __syncthreads();
+            if (pown) {
+                xj = t.x[gp];
+                sxj = t.sx[gp];
+            }
+            if (down) {
+                yi = t.y[gd];
+                syi = t.sy[gd];
+                qi = t.q[gd];
+            }
+        }
+        __syncthreads();
+    }
+
+    for (int j = tid; j < n; j += WG) {
+        d.x[j] = t.x[j];
+        d.sx[j] = t.sx[j];
+        d.xbar[j] = t.xb[j];
+        d.aty[j] = t.aty[j];
+        d.atyb[j] = t.atyb[j];
+    }
+    for (int i = tid; i < m; i += WG) {
+        d.y[i] = t.y[i];
+        d.sy[i] = t.sy[i];
+        d.q[i] = t.q[i];
+        d.ybar[i] = t.yb[i];
+        d.axb[i] = t.axb[i];
+    }
+    if (tid == 0) *d.st = sst;
+}
+
+// lanes per row with the matrix in LDS: about four entries per lane
+int lanes_lds(long long nnz, long long rows) {
+    const long long avg = rows > 0 ? (nnz + rows - 1) / rows : 0;
+    int L = 1;
+    while (L < 64 && 4ll * L < avg) L <<= 1;
+    return L;
+}
+
+// lanes per row with rows in registers: the fewest that hold the longest
+// row in K entries each, or 0 when one row per group does not fit
+int lanes_reg(long long maxlen, long long rows) {
+    int L = 1;
+    while (L < 64 && (long long)K * L < maxlen) L <<= 1;
+    if ((long long)K * L < maxlen || rows * L > WG) return 0;
+    return L;
+}
+
+}  // namespace
+
+TinyPlan tiny_plan(const Dev &d, hipStream_t s) {
+    TinyPlan p{};
+    p.ok = 0;
+    // PDHG_TINY=0 turns the path off, PDHG_TINY=lds keeps the matrix in LDS
+    const char *env = getenv("PDHG_TINY");
+    if (env && env[0] == '0') return p;
+    const bool force_lds = env && env[0] == 'l';
+    const int n = d.n, m = d.m;
+    if (m < 1 || n < 1 || (long long)n + m > kTinyMaxCoords) return p;
+    std::vector<int> rp(m + 1), trp(n + 1);
+    if (hipMemcpyAsync(rp.data(), d.rp, sizeof(int) * (m + 1), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(trp.data(), d.trp, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return p;
+    int amax = 0, tmax = 0;
+    for (int i = 0; i < m; ++i) amax = rp[i + 1] - rp[i] > amax ? rp[i + 1] - rp[i] : amax;
+    for (int j = 0; j < n; ++j) tmax = trp[j + 1] - trp[j] > tmax ? trp[j + 1] - trp[j] : tmax;
+    const int Lp = lanes_reg(tmax, n), Ld = lanes_reg(amax, m);
+    if (Lp > 0 && Ld > 0 && !force_lds) {
+        p.reg = 1;
+        p.Lp = Lp;
+        p.Ld = Ld;
+    } else {
+        p.reg = 0;
+        p.Lp = lanes_lds(d.nnz, n);
+        p.Ld = lanes_lds(d.nnz, m);
+    }
+    p.lds = tiny_lds_bytes(n, m, d.nnz, p.reg);
+    if (p.lds > kTinyLdsMax) return p;
+    const void *fn = p.reg ? (const void *)k_tiny_blocks<true> : (const void *)k_tiny_blocks<false>;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return p;
+    }
+    p.ok = 1;
+    return p;
+}
+
+void launch_tiny_blocks(const Dev &d, const TinyArgs &a, const TinyPlan &p, hipStream_t s) {
+    if (p.reg)
+        hipLaunchKernelGGL(k_tiny_blocks<true>, dim3(1), dim3(WG), p.lds, s, d, a);
+    else
+        hipLaunchKernelGGL(k_tiny_blocks<false>, dim3(1), dim3(WG), p.lds, s, d, a);
+}
+
+}  // namespace pdhg

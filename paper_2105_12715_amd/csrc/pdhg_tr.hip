@@ -31,37 +31,6 @@ namespace pdhg {
 // ---------------------------------------------------------------------
 // coordinate providers
 // ---------------------------------------------------------------------
-struct GapElems {
-    int n, m;
-    const double *c, *b, *l, *u;
-    const signed char *kind;
-    const double *x, *y, *ax, *aty;
-    double sw;  // sqrt(omega): the norm is omega |x|^2 + |y|^2 / omega
-    __device__ __forceinline__ long long size() const { return (long long)n + m; }
-    __device__ __forceinline__ void get(long long i, double &a, double &d) const {
-        if (i < n) {
-            const int j = (int)i;
-            const double g = c[j] - aty[j];
-            double dist = 0.0;
-            if (g > 0.0) dist = x[j] - l[j];
-            else if (g < 0.0) dist = u[j] - x[j];
-            if (dist < 0.0) dist = 0.0;
-            a = fabs(g) / sw;
-            d = dist * sw;
-        } else {
-            const int r = (int)(i - n);
-            const double g = ax[r] - b[r];
-            const double lo = (kind && kind[r]) ? 0.0 : -INFINITY;
-            double dist = 0.0;
-            if (g > 0.0) dist = y[r] - lo;
-            else if (g < 0.0) dist = INFINITY;
-            if (dist < 0.0) dist = 0.0;
-            a = fabs(g) * sw;
-            d = dist / sw;
-        }
-    }
-};
-
 struct RawElems {
     long long N;
     const double *a, *d;
@@ -571,62 +540,10 @@ void launch_tr_raw(int64_t N, const double *a, const double *dd, double r, const
 // the restart itself (Algorithm 1: z^{n+1,0} = candidate, window cleared)
 // ---------------------------------------------------------------------
 __global__ void k_decide(Dev d, int mode, double beta, int tau0) {
-    DevState *st = d.st;
-    if (!st->in_check) return;
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double rec[kRec];
-    rec[0] = (double)st->k;
-    rec[1] = (double)st->t;
-    rec[2] = (double)st->restarts;
-    rec[3] = st->kkt_cur[0];
-    rec[4] = st->kkt_avg[0];
-    rec[5] = 0.0;
-    rec[6] = 0.0;
-    rec[7] = 0.0;
-    rec[8] = -1.0;
-    rec[9] = 0.0;
-    rec[10] = 0.0;
-    rec[11] = (double)st->conv_which;
-    rec[12] = st->rho_prev;
-    rec[13] = 0.0;
-    const int slots = st->gap_slots;
-    if (slots & 1) {
-        rec[5] = st->r_avg;
-        rec[6] = st->tr[0].rho;
-        rec[13] = st->tr[0].lam;
-        if (st->tr[0].nan_seen) st->numerr = 1;
-    }
-    if (slots & 2) {
-        rec[7] = st->r_cur;
-        rec[8] = st->tr[1].rho;
-        if (st->tr[1].nan_seen) st->numerr = 1;
-    }
     (void)mode;
-    if ((slots & 1) && !st->done && !st->numerr) {
-        const double rho_a = st->tr[0].rho;
-        double rho_c = rho_a;
-        int cand = 0;
-        if ((slots & 2) && st->tr[1].rho < rho_a) {  // strict, as in Remark rem:flexible
-            cand = 1;
-            rho_c = st->tr[1].rho;
-        }
-        bool restart;
-        if (st->restarts == 0) restart = st->t >= (long long)tau0;
-        else restart = rho_c <= beta * st->rho_prev;
-        rec[10] = (double)cand;
-        if (restart) {
-            rec[9] = 1.0;
-            st->restarted = 1;
-            st->cand = cand;
-            st->restarts += 1;
-            st->t = 0;
-            st->rho_prev = rho_c;
-        }
-    }
-    double *dst = d.log + (size_t)(st->checks % kLogCap) * kRec;
-    for (int q = 0; q < kRec; ++q) dst[q] = rec[q];
-    st->checks += 1;
-    st->in_check = 0;
+    if (!d.st->in_check) return;
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    decide_restart(d, beta, tau0);
 }
 
 void launch_decide(const Dev &d, int mode, double beta, int tau0, hipStream_t s) {
@@ -638,27 +555,7 @@ __global__ void k_apply(Dev d, int force) {
     if (!force && !st->restarted) return;
     const int cand = force ? 0 : st->cand;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < d.n) {
-        if (cand == 0) {
-            const double v = d.xbar[i];
-            d.x[i] = v;
-            d.x0[i] = v;
-        } else {
-            d.x0[i] = d.x[i];
-        }
-        d.sx[i] = 0.0;
-    }
-    if (i < d.m) {
-        if (cand == 0) {
-            const double v = d.ybar[i];
-            d.y[i] = v;
-            d.y0[i] = v;
-            d.q[i] = d.axb[i];
-        } else {
-            d.y0[i] = d.y[i];
-        }
-        d.sy[i] = 0.0;
-    }
+    apply_restart_at(d, i, cand);
 }
 
 void launch_apply(const Dev &d, hipStream_t s) {

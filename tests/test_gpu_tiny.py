@@ -1,0 +1,194 @@
+"""GPU parity of the one-workgroup solver (whole check periods of eq.
+PDHG-update plus the check of Algorithm 1 in one launch, trust region by
+evaluating f at every breakpoint), with the matrix rows in registers and
+with the matrix in LDS, against the oracle and against the multi-kernel
+path on the same LP: iterates, averages and anchors to a relative 1e-10
+over the first 1000 iterations, check records (integer fields exactly,
+float fields to 1e-9) and iteration counts of solves to 1e-8.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_12715_amd import lpgen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2105_12715_amd import _lib
+    _lib.load(build_if_missing=False)
+    return _lib
+
+
+def rel(a, b):
+    a = np.asarray(a, float)
+    b = np.asarray(b, float)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+CASES = {
+    # 50 x 100, Bernoulli(0.1): lanes per row 2 (A') and 4 (A)
+    "small50x100": lambda: lpgen.small_dense(1),
+    # >= rows and [0,1] boxes
+    "ge_rows": lambda: lpgen.bernoulli_lp(11, 30, 60, 0.15, lpgen.BOX01, ge_frac=0.4),
+    # infinite bounds of every kind, half the rows >=
+    "mixed_inf": lambda: lpgen.column_count_lp(13, 120, 260, per_col=3,
+                                               bounds="mixed_inf", ge_frac=0.5),
+    # dense rows: 8 lanes per row of A, 4 per row of A' (rows in registers)
+    "dense40x90": lambda: lpgen.bernoulli_lp(21, 40, 90, 0.5, lpgen.BOX01),
+    # n + m = 520 > 512 threads: two trust-region coordinates per thread
+    "two_per_thread": lambda: lpgen.column_count_lp(23, 170, 350, per_col=1, bounds="box01"),
+    # 72 KiB of LDS with rows in registers
+    "reg_72k": lambda: lpgen.column_count_lp(25, 400, 500, per_col=1, bounds="mix"),
+    # n + m = 1024: 724 rows of A' (more than one per group), matrix in
+    # LDS whatever is asked, 118 KiB
+    "max_coords": lambda: lpgen.column_count_lp(27, 300, 724, per_col=2, bounds="mix",
+                                                ge_frac=0.3),
+}
+# cases whose rows cannot all sit in registers
+LDS_ONLY = {"max_coords"}
+
+
+def _solver(lib, lp, env=None, **kw):
+    """A solver created with PDHG_TINY=env (None: unset)."""
+    if env is not None:
+        os.environ["PDHG_TINY"] = env
+    try:
+        return lib.Solver(lp, **kw)
+    finally:
+        os.environ.pop("PDHG_TINY", None)
+
+
+def _pair(lib, lp, mode, eta=None, tiny="reg", name=None, **kw):
+    if eta is None:
+        eta = oracle.Oracle(lp).info()["eta"]
+    o = oracle.Oracle(lp, eta=eta, mode=mode, **kw)
+    s = _solver(lib, lp, "lds" if tiny == "lds" else None, eta=eta, restart_mode=mode, **kw)
+    want = 2 if (tiny == "lds" or name in LDS_ONLY) else 1
+    assert s.info()["one_workgroup"] == want
+    return o, s
+
+
+def _multi_kernel(lib, lp, **kw):
+    s = _solver(lib, lp, "0", **kw)
+    assert s.info()["one_workgroup"] == 0
+    return s
+
+
+def _compare_points(o_get, s, tol=1e-10):
+    for which in (0, 1, 2):
+        xo, yo = o_get(which)
+        xg, yg = (t.cpu().numpy() for t in s.get_iterate(which))
+        r = rel(np.concatenate([xg, yg]), np.concatenate([xo, yo]))
+        assert r <= tol, (which, r)
+
+
+def _compare_logs(lo, lg, nrec):
+    assert lo.shape == lg.shape == (nrec, 14)
+    np.testing.assert_array_equal(lg[:, [0, 1, 2, 9, 10, 11]], lo[:, [0, 1, 2, 9, 10, 11]])
+    for col in (3, 4, 5, 6, 7, 8, 12, 13):
+        np.testing.assert_allclose(lg[:, col], lo[:, col], rtol=1e-9, atol=1e-300)
+
+
+def test_plan_eligibility(lib):
+    """The path applies to PDHG with adaptive, flexible or no restarts on
+    LPs that fit; not to fixed-length restarts, extragradient, LPs without
+    rows or LPs too large for the LDS budget."""
+    for name, mk in CASES.items():
+        want = 2 if name in LDS_ONLY else 1
+        assert lib.Solver(mk(), eta=0.1).info()["one_workgroup"] == want, name
+        assert _solver(lib, mk(), "lds", eta=0.1).info()["one_workgroup"] == 2, name
+    lp = CASES["small50x100"]()
+    assert lib.Solver(lp, eta=0.1, restart_mode=lib.RESTART_FLEXIBLE).info()["one_workgroup"] == 1
+    assert lib.Solver(lp, eta=0.1, restart_mode=lib.RESTART_NONE).info()["one_workgroup"] == 1
+    assert lib.Solver(lp, eta=0.1, restart_mode=lib.RESTART_FIXED,
+                      fixed_len=64).info()["one_workgroup"] == 0
+    assert lib.Solver(lp, eta=0.1, method=lib.METHOD_EGM).info()["one_workgroup"] == 0
+    big = lpgen.column_count_lp(13, 600, 1300, per_col=5, bounds="mixed_inf", ge_frac=0.5)
+    assert lib.Solver(big, eta=0.1).info()["one_workgroup"] == 0
+    _multi_kernel(lib, lp, eta=0.1)
+
+
+@pytest.mark.parametrize("tiny", ["reg", "lds"])
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("mode", [oracle.MODE_ADAPTIVE, oracle.MODE_FLEXIBLE, oracle.MODE_NONE])
+def test_iterates_and_checks(lib, name, mode, tiny):
+    lp = CASES[name]()
+    _say("tiny", name, mode, tiny)
+    o, s = _pair(lib, lp, mode, tiny=tiny, name=name)
+    done = 0
+    # pieces that start off and on the check period mix both paths
+    for k in [30, 61, 300, 1000]:
+        o.solve(k - done, 0.0)
+        s.solve(k - done, 0.0)
+        done = k
+        _compare_points(o.get, s)
+    _compare_logs(o.log(), s.check_log(), 33)
+    if mode != oracle.MODE_NONE:
+        assert o.log()[:, 9].sum() >= 1
+
+
+@pytest.mark.parametrize("tiny", ["reg", "lds"])
+@pytest.mark.parametrize("name", ["small50x100", "ge_rows", "mixed_inf", "dense40x90"])
+def test_solve_to_1e8_matches_oracle(lib, name, tiny):
+    lp = CASES[name]()
+    _say("tiny solve", name, tiny)
+    o, s = _pair(lib, lp, oracle.MODE_ADAPTIVE, tiny=tiny, name=name)
+    ro = o.solve(400_000, 1e-8)
+    rg = s.solve(400_000, 1e-8)
+    assert ro["status"] == 0 and rg["status"] == 0
+    assert rg["k"] == ro["k"] and rg["restarts"] == ro["restarts"] and rg["which"] == ro["which"]
+    np.testing.assert_allclose(rg["kkt"], ro["kkt"], rtol=1e-6)
+    # a converged handle stays put: the next solve returns at once
+    rg2 = s.solve(3000, 1e-8)
+    assert rg2["status"] == 0 and s.info()["k"] >= rg["k"]
+
+
+@pytest.mark.parametrize("name", ["small50x100", "mixed_inf", "two_per_thread", "max_coords"])
+def test_matches_multi_kernel_path(lib, name):
+    """The same 3000 iterations on the one-workgroup and the multi-kernel
+    path: same restarts, iterates within 1e-10 (the row sums are taken in
+    another order), and a state either side can continue from."""
+    lp = CASES[name]()
+    _say("tiny vs multi", name)
+    eta = oracle.Oracle(lp).info()["eta"]
+    a = lib.Solver(lp, eta=eta)
+    b = _multi_kernel(lib, lp, eta=eta)
+    a.solve(3000, 0.0)
+    b.solve(3000, 0.0)
+    _compare_points(lambda w: tuple(t.cpu().numpy() for t in b.get_iterate(w)), a)
+    la, lb = a.check_log(), b.check_log()
+    np.testing.assert_array_equal(la[:, [0, 1, 2, 9, 10, 11]], lb[:, [0, 1, 2, 9, 10, 11]])
+    assert a.info()["restarts"] == b.info()["restarts"]
+    # eager steps and checks continue from the one-workgroup state
+    a.step(30)
+    a.check(0.0)
+    b.step(30)
+    b.check(0.0)
+    _compare_points(lambda w: tuple(t.cpu().numpy() for t in b.get_iterate(w)), a)
+
+
+def test_repeated_solves_and_determinism(lib):
+    lp = CASES["dense40x90"]()
+    eta = oracle.Oracle(lp).info()["eta"]
+    outs = []
+    for _ in range(2):
+        s = lib.Solver(lp, eta=eta)
+        for _ in range(5):
+            s.solve(600, 0.0)
+        outs.append([t.clone() for t in s.get_iterate(0)])
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
