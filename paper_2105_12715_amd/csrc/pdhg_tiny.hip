@@ -10,12 +10,13 @@
 // launches a batch of blocks and polls the state between launches.
 //
 // Rows of A' (primal half-step) and of A (dual half-step) go to aligned
-// groups of L lanes.  When every row has at most kTinyK L entries and each
-// group holds one row, every lane keeps its entries (value, column) in
-// registers and the row's owner keeps its coordinate of the iterate, its
-// running sum and its LP data there too: a half-step is one gather from
-// LDS, a fused multiply-add chain, a butterfly and a barrier.  Otherwise
-// the matrix sits in LDS in CSR with 16-bit column indices.
+// groups of L lanes.  When every row has at most kTinyK L entries for one
+// L in {1, 2, 4, 8} (a compile-time constant of the kernel) and each group
+// holds one row, every lane keeps its entries (value, column) in registers
+// and the row's owner keeps its coordinate of the iterate, its running sum
+// and its LP data there too: a half-step is one gather from LDS, a tree
+// of products, a butterfly and a barrier.  Otherwise the matrix sits in
+// LDS in CSR with 16-bit column indices.
 //
 // The trust region of the normalized duality gap (Section 6.3.1) has the
 // same answer as in the multi-kernel path: with breakpoints
@@ -49,7 +50,8 @@ struct TinyLds {
     double *y, *yb;                                // m + 1
     double *sy, *q, *b, *axb;                      // m
     unsigned long long *tkey;                      // n + m
-    double *td2, *ta2, *tad;                       // n + m
+    double2 *tda;                                  // n + m: (d^2, a^2)
+    double *tad;                                   // n + m: a d
     signed char *kind;                             // m
     double *av, *tv;                               // nnz (matrix in LDS)
     int *arp, *trp;                                // m + 1, n + 1
@@ -75,8 +77,8 @@ __device__ TinyLds carve(unsigned char *base, int n, int m, int nnz, bool reg) {
     t.axb = dp; dp += m;
     t.tkey = (unsigned long long *)dp;
     dp += n + m;
-    t.td2 = dp; dp += n + m;
-    t.ta2 = dp; dp += n + m;
+    t.tda = (double2 *)dp;
+    dp += 2 * (n + m);
     t.tad = dp; dp += n + m;
     unsigned char *cp = (unsigned char *)dp;
     t.kind = (signed char *)cp;
@@ -125,17 +127,30 @@ __device__ __forceinline__ double row_dot(const int *rp, const unsigned short *c
     return group_sum(s, L);
 }
 
+// group sum with the group size known at compile time
+template <int LL>
+__device__ __forceinline__ double group_sum_c(double s) {
+    if (LL >= 2) s += dpp_f64<0xB1>(s);
+    if (LL >= 4) s += dpp_f64<0x4E>(s);
+    if (LL >= 8) s += dpp_f64<0x141>(s);
+    return s;
+}
+
 // the same product from the lane's entries held in registers (padding
-// entries have value 0 and point at the zero after the vector's end)
+// entries have value 0 and point at the zero after the vector's end):
+// all gathers first, then the products summed as a balanced tree
+template <int LL>
 __device__ __forceinline__ double reg_dot(const int (&col)[K], const double (&val)[K],
-                                          const double *v, int L) {
+                                          const double *v) {
+    static_assert(K == 8, "the tree below adds eight products");
     double g[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) g[k] = v[col[k]];
-    double s = 0.0;
+    double p[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) s += val[k] * g[k];
-    return group_sum(s, L);
+    for (int k = 0; k < K; ++k) p[k] = val[k] * g[k];
+    const double s = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+    return group_sum_c<LL>(s);
 }
 
 // A lane's share of one row (CSR rp, ci, v in global memory) into registers
@@ -158,6 +173,12 @@ __device__ __forceinline__ void load_row(const int *rp, const int *ci, const dou
             val[k] = 0.0;
         }
     }
+}
+
+// v when c, else +0.0, as a bit mask (keeps the loads of both branches
+// unconditional)
+__device__ __forceinline__ double keep_if(double v, bool c) {
+    return __longlong_as_double(__double_as_longlong(v) & -(long long)c);
 }
 
 struct TrShared {
@@ -256,8 +277,7 @@ __device__ void tiny_trust_region(const E &e, TRState &ts, const TinyLds &t, TrS
         if (fin[r]) {
             const int at = sh.woff[r][w] + __popcll(bal & lt);
             t.tkey[at] = key[r];
-            t.td2[at] = d2[r];
-            t.ta2[at] = a2[r];
+            t.tda[at] = make_double2(d2[r], a2[r]);
             t.tad[at] = ad[r];
         }
     }
@@ -277,23 +297,25 @@ __device__ void tiny_trust_region(const E &e, TRState &ts, const TinyLds &t, TrS
         int q = part;
         for (; q + 3 * T < Nf; q += 4 * T) {
             unsigned long long kq[4];
-            double dq[4], aq[4];
+            double2 da[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 kq[u] = t.tkey[q + u * T];
-                dq[u] = t.td2[q + u * T];
-                aq[u] = t.ta2[q + u * T];
+                da[u] = t.tda[q + u * T];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                F += kq[u] <= kp ? dq[u] : 0.0;
-                A += kq[u] <= kp ? 0.0 : aq[u];
+                const bool c = kq[u] <= kp;
+                F += keep_if(da[u].x, c);
+                A += keep_if(da[u].y, !c);
             }
         }
         for (; q < Nf; q += T) {
             const unsigned long long kq = t.tkey[q];
-            F += kq <= kp ? t.td2[q] : 0.0;
-            A += kq <= kp ? 0.0 : t.ta2[q];
+            const double2 da = t.tda[q];
+            const bool c = kq <= kp;
+            F += keep_if(da.x, c);
+            A += keep_if(da.y, !c);
         }
         F = group_sum(F, T);
         A = group_sum(A, T) + Ainf;
@@ -311,12 +333,12 @@ __device__ void tiny_trust_region(const E &e, TRState &ts, const TinyLds &t, TrS
     // F = sum d^2 (clamped), A = sum a^2 (free), AD = sum a d (clamped)
     double v3[3] = {0.0, 0.0, 0.0};
     for (int i = tid; i < Nf; i += WG) {
-        if (has && t.tkey[i] <= klo) {
-            v3[0] += t.td2[i];
-            v3[2] += t.tad[i];
-        } else {
-            v3[1] += t.ta2[i];
-        }
+        const double2 da = t.tda[i];
+        const double adi = t.tad[i];
+        const bool c = has && t.tkey[i] <= klo;
+        v3[0] += keep_if(da.x, c);
+        v3[1] += keep_if(da.y, !c);
+        v3[2] += keep_if(adi, c);
     }
     block_sums<3, kWaves>(v3, sh.red);
     if (tid == 0) {
@@ -340,7 +362,7 @@ __device__ void tiny_trust_region(const E &e, TRState &ts, const TinyLds &t, TrS
     __syncthreads();
 }
 
-template <bool REG>
+template <bool REG, int LP, int LD>
 __global__ __launch_bounds__(WG) void k_tiny_blocks(Dev d, TinyArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ DevState sst;
@@ -382,7 +404,8 @@ __global__ __launch_bounds__(WG) void k_tiny_blocks(Dev d, TinyArgs a) {
         for (int j = tid; j <= n; j += WG) t.trp[j] = d.trp[j];
     }
 
-    const int Lp = a.Lp, Ld = a.Ld;
+    // rows in registers: LP lanes per row of A', LD per row of A
+    const int Lp = REG ? LP : a.Lp, Ld = REG ? LD : a.Ld;
     const int lp = tid & (Lp - 1), gp = tid / Lp, Gp = WG / Lp;
     const int ld = tid & (Ld - 1), gd = tid / Ld, Gd = WG / Ld;
     const double tau = a.tau, sigma = a.sigma;
@@ -441,7 +464,7 @@ __global__ __launch_bounds__(WG) void k_tiny_blocks(Dev d, TinyArgs a) {
             // x+ = proj_[l,u](x - tau (c - A'y)); sx += x+
             if (REG) {
                 if (gp < n) {
-                    const double aty = reg_dot(pc, pv, t.y, Lp);
+                    const double aty = reg_dot<LP>(pc, pv, t.y);
                     if (lp == 0) {
                         const double g = cj - aty;
                         double xn = xj - tau * g;
@@ -470,7 +493,7 @@ __global__ __launch_bounds__(WG) void k_tiny_blocks(Dev d, TinyArgs a) {
             // y+ = proj_Y(y + sigma (b - (2 A x+ - A x))); sy += y+; q = A x+
             if (REG) {
                 if (gd < m) {
-                    const double ax = reg_dot(dc, dv, t.x, Ld);
+                    const double ax = reg_dot<LD>(dc, dv, t.x);
                     if (ld == 0) {
                         double yv = yi + sigma * (bi - (2.0 * ax - qi));
                         if (ki && yv < 0.0) yv = 0.0;
@@ -511,12 +534,12 @@ __global__ __launch_bounds__(WG) void k_tiny_blocks(Dev d, TinyArgs a) {
         __syncthreads();
         if (REG) {
             if (gd < m) {
-                const double s = reg_dot(dc, dv, t.xb, Ld);
+                const double s = reg_dot<LD>(dc, dv, t.xb);
                 if (ld == 0) t.axb[gd] = s;
             }
             if (gp < n) {
-                const double s1 = reg_dot(pc, pv, t.yb, Lp);
-                const double s2 = reg_dot(pc, pv, t.y, Lp);
+                const double s1 = reg_dot<LP>(pc, pv, t.yb);
+                const double s2 = reg_dot<LP>(pc, pv, t.y);
                 if (lp == 0) {
                     t.atyb[gp] = s1;
                     t.aty[gp] = s2;
@@ -609,13 +632,33 @@ int lanes_lds(long long nnz, long long rows) {
     return L;
 }
 
-// lanes per row with rows in registers: the fewest that hold the longest
-// row in K entries each, or 0 when one row per group does not fit
-int lanes_reg(long long maxlen, long long rows) {
+// lanes per row with rows in registers: the fewest (1, 2, 4 or 8) that
+// hold the longest row in K entries each, or 0 when none does
+int lanes_reg(long long maxlen) {
     int L = 1;
-    while (L < 64 && (long long)K * L < maxlen) L <<= 1;
-    if ((long long)K * L < maxlen || rows * L > WG) return 0;
-    return L;
+    while (L < 8 && (long long)K * L < maxlen) L <<= 1;
+    return (long long)K * L < maxlen ? 0 : L;
+}
+
+// kernels by (LP, LD), both in {1, 2, 4, 8}
+template <int LP>
+const void *tiny_fn_ld(int Ld) {
+    switch (Ld) {
+    case 1: return (const void *)k_tiny_blocks<true, LP, 1>;
+    case 2: return (const void *)k_tiny_blocks<true, LP, 2>;
+    case 4: return (const void *)k_tiny_blocks<true, LP, 4>;
+    default: return (const void *)k_tiny_blocks<true, LP, 8>;
+    }
+}
+
+const void *tiny_kernel(const TinyPlan &p) {
+    if (!p.reg) return (const void *)k_tiny_blocks<false, 0, 0>;
+    switch (p.Lp) {
+    case 1: return tiny_fn_ld<1>(p.Ld);
+    case 2: return tiny_fn_ld<2>(p.Ld);
+    case 4: return tiny_fn_ld<4>(p.Ld);
+    default: return tiny_fn_ld<8>(p.Ld);
+    }
 }
 
 }  // namespace
@@ -639,8 +682,9 @@ TinyPlan tiny_plan(const Dev &d, hipStream_t s) {
     int amax = 0, tmax = 0;
     for (int i = 0; i < m; ++i) amax = rp[i + 1] - rp[i] > amax ? rp[i + 1] - rp[i] : amax;
     for (int j = 0; j < n; ++j) tmax = trp[j + 1] - trp[j] > tmax ? trp[j + 1] - trp[j] : tmax;
-    const int Lp = lanes_reg(tmax, n), Ld = lanes_reg(amax, m);
-    if (Lp > 0 && Ld > 0 && !force_lds) {
+    // one row per group of lanes
+    const int Lp = lanes_reg(tmax), Ld = lanes_reg(amax);
+    if (Lp > 0 && Ld > 0 && (long long)n * Lp <= WG && (long long)m * Ld <= WG && !force_lds) {
         p.reg = 1;
         p.Lp = Lp;
         p.Ld = Ld;
@@ -651,7 +695,7 @@ TinyPlan tiny_plan(const Dev &d, hipStream_t s) {
     }
     p.lds = tiny_lds_bytes(n, m, d.nnz, p.reg);
     if (p.lds > kTinyLdsMax) return p;
-    const void *fn = p.reg ? (const void *)k_tiny_blocks<true> : (const void *)k_tiny_blocks<false>;
+    const void *fn = tiny_kernel(p);
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds) !=
         hipSuccess) {
         (void)hipGetLastError();
@@ -662,10 +706,9 @@ TinyPlan tiny_plan(const Dev &d, hipStream_t s) {
 }
 
 void launch_tiny_blocks(const Dev &d, const TinyArgs &a, const TinyPlan &p, hipStream_t s) {
-    if (p.reg)
-        hipLaunchKernelGGL(k_tiny_blocks<true>, dim3(1), dim3(WG), p.lds, s, d, a);
-    else
-        hipLaunchKernelGGL(k_tiny_blocks<false>, dim3(1), dim3(WG), p.lds, s, d, a);
+    const void *fn = tiny_kernel(p);
+    void *args[] = {(void *)&d, (void *)&a};
+    (void)hipLaunchKernel(fn, dim3(1), dim3(WG), args, p.lds, s);
 }
 
 }  // namespace pdhg
