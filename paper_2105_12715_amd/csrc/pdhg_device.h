@@ -437,13 +437,20 @@ __device__ __forceinline__ void kkt_elem(const Dev &d, const KktPoints &P2, long
     v[S_RY2_C] += ryc;
 }
 
-__device__ __forceinline__ void kkt_point(const Dev &d, const double *S, int P, double *out) {
-    const double pres2 = S[S_PRES2_C + P], dres2 = S[S_DRES2_C + P];
-    const double pobj = S[S_POBJ_C + P], dobj = S[S_DOBJ_C + P], bv2 = S[S_BV2_C + P];
+// KKT parts at z (avg false) or z-bar (avg true) from the 14 sums S:
+// o[1..7] = relative KKT, |primal residual|, |dual residual|, primal and
+// dual objective, the paper's absolute form, the max form
+__device__ __forceinline__ void kkt_parts(const DevState *st, const double *S, bool avg,
+                                          double (&o)[8]) {
+    const double pres2 = avg ? S[S_PRES2_A] : S[S_PRES2_C];
+    const double dres2 = avg ? S[S_DRES2_A] : S[S_DRES2_C];
+    const double pobj = avg ? S[S_POBJ_A] : S[S_POBJ_C];
+    const double dobj = avg ? S[S_DOBJ_A] : S[S_DOBJ_C];
+    const double bv2 = avg ? S[S_BV2_A] : S[S_BV2_C];
     const double pres = sqrt(pres2), dres = sqrt(dres2);
     const double gap = pobj - dobj;
-    const double rel_p = pres / (1.0 + sqrt(d.st->nb2));
-    const double rel_d = dres / (1.0 + sqrt(d.st->nc2));
+    const double rel_p = pres / (1.0 + sqrt(st->nb2));
+    const double rel_d = dres / (1.0 + sqrt(st->nc2));
     const double rel_g = fabs(gap) / (1.0 + fabs(pobj) + fabs(dobj));
     double rel = rel_p;
     if (rel_d > rel) rel = rel_d;
@@ -452,66 +459,92 @@ __device__ __forceinline__ void kkt_point(const Dev &d, const double *S, int P, 
     double mx = pres;
     if (dres > mx) mx = dres;
     if (fabs(gap) > mx) mx = fabs(gap);
-    out[1] = rel;
-    out[2] = pres;
-    out[3] = dres;
-    out[4] = pobj;
-    out[5] = dobj;
-    out[6] = sqrt(bv2 + pres2 + dres2 + gpos * gpos);
-    out[7] = mx;
+    o[0] = 0.0;
+    o[1] = rel;
+    o[2] = pres;
+    o[3] = dres;
+    o[4] = pobj;
+    o[5] = dobj;
+    o[6] = sqrt(bv2 + pres2 + dres2 + gpos * gpos);
+    o[7] = mx;
 }
 
-__device__ __forceinline__ double kkt_pick(const double *k8, int kind) {
-    if (kind == 1) return k8[6];
-    if (kind == 2) return k8[7];
-    return k8[1];
+__device__ __forceinline__ void kkt_point(const Dev &d, const double *S, int P, double *out) {
+    double o[8];
+    kkt_parts(d.st, S, P != 0, o);
+#pragma unroll
+    for (int k = 1; k < 8; ++k) out[k] = o[k];
 }
+
 // The stopping test of a check from the 14 KKT sums S: KKT at z and z-bar,
 // the converged flag (termination first), the radii, and the trust-region
-// slots armed for the restart test.  Returns the armed slots.
+// slots armed for the restart test.  Called by every lane of one whole
+// wave with S in each lane: lane 0 takes z and lane 1 z-bar (KKT parts and
+// radius side by side), lane 0 writes the state.  Returns the armed slots
+// in every lane.
 __device__ __forceinline__ int kkt_conclude(const Dev &d, const double *S, double tol, int kkt_kind,
                                             double omega, int gap_slots) {
     DevState *st = d.st;
-    st->in_check = 1;
-    st->restarted = 0;
-    st->cand = 0;
-    kkt_point(d, S, 0, st->kkt_cur);
-    kkt_point(d, S, 1, st->kkt_avg);
-    const double kc = kkt_pick(st->kkt_cur, kkt_kind), ka = kkt_pick(st->kkt_avg, kkt_kind);
-    st->kkt_cur[0] = kc;
-    st->kkt_avg[0] = ka;
-    bool bad = false;
-    for (int k = 0; k < kKktSums; ++k) bad |= !isfinite(S[k]);
-    st->numerr = bad ? 1 : 0;
-    int conv = (tol > 0.0 && (kc <= tol || ka <= tol)) ? 1 : 0;
-    st->conv_which = -1;
-    if (conv) {
-        st->done = 1;
-        st->conv_which = (ka <= kc) ? 1 : 0;
-        st->conv_k = st->k;
+    const int lane = threadIdx.x & 63;
+    const bool odd = (lane & 1) != 0;
+    double o[8];
+    kkt_parts(st, S, odd, o);
+    const double rad = sqrt(odd ? omega * S[S_RX2_A] + S[S_RY2_A] / omega
+                                : omega * S[S_RX2_C] + S[S_RY2_C] / omega);
+    double cur[8], avg[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        cur[k] = lane_f64(o[k], 0);
+        avg[k] = lane_f64(o[k], 1);
     }
-    st->r_avg = sqrt(omega * S[S_RX2_A] + S[S_RY2_A] / omega);
-    st->r_cur = sqrt(omega * S[S_RX2_C] + S[S_RY2_C] / omega);
+    const double r_cur = lane_f64(rad, 0), r_avg = lane_f64(rad, 1);
+    const double kc = kkt_kind == 1 ? cur[6] : (kkt_kind == 2 ? cur[7] : cur[1]);
+    const double ka = kkt_kind == 1 ? avg[6] : (kkt_kind == 2 ? avg[7] : avg[1]);
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < kKktSums; ++k) bad |= !isfinite(S[k]);
+    const int conv = (tol > 0.0 && (kc <= tol || ka <= tol)) ? 1 : 0;
     int slots = 0;
     if (!conv && !bad && st->t > 0) slots = gap_slots;
-    st->gap_slots = slots;
-    for (int sidx = 0; sidx < kTrSlots; ++sidx) {
-        TRState &ts = st->tr[sidx];
-        ts.mode = TR_IDLE;
-        ts.rho = 0.0;
-        ts.lam = 0.0;
-        if (slots & (1 << sidx)) {
-            ts.mode = TR_SEARCH;
-            ts.r = sidx == 0 ? st->r_avg : st->r_cur;
-            ts.r2 = ts.r * ts.r;
-            ts.F_acc = 0.0;
-            ts.A_acc = 0.0;
-            ts.prefix = 0ull;
-            ts.klo = 0ull;
-            ts.level = 0;
-            ts.count = 0;
-            ts.ncomp = 0;
-            ts.nan_seen = 0;
+    if (lane == 0) {
+        st->in_check = 1;
+        st->restarted = 0;
+        st->cand = 0;
+#pragma unroll
+        for (int k = 1; k < 8; ++k) {
+            st->kkt_cur[k] = cur[k];
+            st->kkt_avg[k] = avg[k];
+        }
+        st->kkt_cur[0] = kc;
+        st->kkt_avg[0] = ka;
+        st->numerr = bad ? 1 : 0;
+        st->conv_which = -1;
+        if (conv) {
+            st->done = 1;
+            st->conv_which = (ka <= kc) ? 1 : 0;
+            st->conv_k = st->k;
+        }
+        st->r_avg = r_avg;
+        st->r_cur = r_cur;
+        st->gap_slots = slots;
+        for (int sidx = 0; sidx < kTrSlots; ++sidx) {
+            TRState &ts = st->tr[sidx];
+            ts.mode = TR_IDLE;
+            ts.rho = 0.0;
+            ts.lam = 0.0;
+            if (slots & (1 << sidx)) {
+                ts.mode = TR_SEARCH;
+                ts.r = sidx == 0 ? r_avg : r_cur;
+                ts.r2 = ts.r * ts.r;
+                ts.F_acc = 0.0;
+                ts.A_acc = 0.0;
+                ts.prefix = 0ull;
+                ts.klo = 0ull;
+                ts.level = 0;
+                ts.count = 0;
+                ts.ncomp = 0;
+                ts.nan_seen = 0;
+            }
         }
     }
     return slots;

@@ -286,12 +286,13 @@ struct TinyArgs {
 // LDS bytes of the one-workgroup solver: doubles x, x-bar (n + 1 each, the
 // last a zero that padded matrix entries point at), sx, c, l, u, A'y,
 // A'y-bar (n each), y, y-bar (m + 1 each), sy, q, b, A x-bar (m each);
-// trust-region keys, d^2, a^2 and a d (n + m each); m bytes of row kinds; and,
+// trust-region keys, d^2, a^2 and a d (n + m each) and candidate indices
+// (n + m ints); m bytes of row kinds; and,
 // with the matrix in LDS, the values of A and A' (nnz doubles each), their
 // row starts (ints) and 16-bit column indices
 __host__ __device__ inline size_t tiny_lds_bytes(long long n, long long m, long long nnz,
                                                  int reg) {
-    long long b = 8 * (8 * n + 6 * m + 4) + 32 * (n + m) + m;
+    long long b = 8 * (8 * n + 6 * m + 4) + 36 * (n + m) + m;
     b = (b + 7) & ~7ll;
     if (!reg) b += 16 * nnz + 4 * (n + m + 2) + 4 * nnz;
     return (size_t)((b + 15) & ~15ll);

@@ -839,7 +839,10 @@ __global__ __launch_bounds__(kWG) void k_kkt_final(Dev d, int nb, double tol, in
     __shared__ int armed;
     double S[kKktSums];
     reduce_partials<kKktSums>(d.part, nb, kKktSums, S, sh);
-    if (threadIdx.x == 0) armed = kkt_conclude(d, S, tol, kkt_kind, omega, gap_slots);
+    if (threadIdx.x < 64) {
+        const int sl = kkt_conclude(d, S, tol, kkt_kind, omega, gap_slots);
+        if (threadIdx.x == 0) armed = sl;
+    }
     __syncthreads();
     // clear level-0 histograms of the armed slots
     for (int sidx = 0; sidx < kTrSlots; ++sidx) {

@@ -22,10 +22,12 @@
 // same answer as in the multi-kernel path: with breakpoints
 // lambda_i = d_i / a_i (compared as IEEE key bits),
 //     f(lambda_p) = sum_{key_i <= key_p} d_i^2 + lambda_p^2 sum_{key_i > key_p} a_i^2
-// is evaluated directly at every breakpoint with a finite key (at most
-// n + m <= 1024 of them, compacted in coordinate order; one pass over the
-// keys per breakpoint by a few lanes, LDS broadcast reads), the clamped set
-// is every key up to the largest breakpoint with f <= r^2, and the closing
+// is nondecreasing in the key.  The breakpoints with a finite key (at most
+// n + m <= 1024, compacted in coordinate order) are evaluated directly:
+// first 64 of them spread over the coordinates, which bracket the answer,
+// then every one strictly inside the bracket (one pass over the keys per
+// breakpoint by a group of lanes, LDS broadcast reads).  The clamped set is
+// every key up to the largest breakpoint with f <= r^2, and the closing
 // formula of Algorithm 2 takes the sums in a fixed order.
 #include "pdhg_device.h"
 
@@ -52,6 +54,7 @@ struct TinyLds {
     unsigned long long *tkey;                      // n + m
     double2 *tda;                                  // n + m: (d^2, a^2)
     double *tad;                                   // n + m: a d
+    int *tcid;                                     // n + m: candidate breakpoints
     signed char *kind;                             // m
     double *av, *tv;                               // nnz (matrix in LDS)
     int *arp, *trp;                                // m + 1, n + 1
@@ -80,7 +83,8 @@ __device__ TinyLds carve(unsigned char *base, int n, int m, int nnz, bool reg) {
     t.tda = (double2 *)dp;
     dp += 2 * (n + m);
     t.tad = dp; dp += n + m;
-    unsigned char *cp = (unsigned char *)dp;
+    t.tcid = (int *)dp;
+    unsigned char *cp = (unsigned char *)(t.tcid + n + m);
     t.kind = (signed char *)cp;
     cp += m;
     cp = (unsigned char *)(((size_t)cp + 7) & ~(size_t)7);
@@ -181,11 +185,44 @@ __device__ __forceinline__ double keep_if(double v, bool c) {
     return __longlong_as_double(__double_as_longlong(v) & -(long long)c);
 }
 
+// This lane's share (keys q = part, part + T, ...) of the two sums of
+// f at key kp: F = sum d^2 over keys <= kp, A = sum a^2 over keys > kp
+__device__ __forceinline__ void f_parts(const TinyLds &t, int Nf, unsigned long long kp, int part,
+                                        int T, double &F, double &A) {
+    F = 0.0;
+    A = 0.0;
+    int q = part;
+    for (; q + 3 * T < Nf; q += 4 * T) {
+        unsigned long long kq[4];
+        double2 da[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            kq[u] = t.tkey[q + u * T];
+            da[u] = t.tda[q + u * T];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool c = kq[u] <= kp;
+            F += keep_if(da[u].x, c);
+            A += keep_if(da[u].y, !c);
+        }
+    }
+    for (; q < Nf; q += T) {
+        const unsigned long long kq = t.tkey[q];
+        const double2 da = t.tda[q];
+        const bool c = kq <= kp;
+        F += keep_if(da.x, c);
+        A += keep_if(da.y, !c);
+    }
+}
+
 struct TrShared {
     double red[kWaves * 5];
     unsigned long long best;  // largest key with f <= r^2, plus one (0: none)
+    unsigned long long hi;    // smallest sampled key with f > r^2 (kNoKey: none)
     int go;
     int nf;                   // breakpoints with a finite key
+    int nc;                   // candidates left after the sampled bracket
     int woff[2][kWaves];      // compaction offsets of each wave's finite keys
 };
 
@@ -246,6 +283,7 @@ __device__ void tiny_trust_region(const E &e, TRState &ts, const TinyLds &t, TrS
         sh.nf = o;
         sh.go = 0;
         sh.best = 0ull;
+        sh.hi = kNoKey;
         if (v5[3] > 0.0) {
             ts.nan_seen = 1;
             ts.mode = TR_ZERO;
@@ -285,44 +323,73 @@ __device__ void tiny_trust_region(const E &e, TRState &ts, const TinyLds &t, TrS
     const int Nf = sh.nf;
     const double Ainf = ts.value;
 
-    // f at every finite breakpoint (equal keys give equal sums, so no
-    // grouping), T lanes per breakpoint splitting the pass over the keys
+    // f is nondecreasing in the key, so the answer is the largest finite
+    // key with f <= r^2 (equal keys give equal sums: no grouping needed).
+    // f at 64 breakpoints spread over the coordinate order brackets it;
+    // then f at every breakpoint strictly inside the bracket.
     const double r2 = ts.r2;
-    int T = 1;
-    while (T < 64 && (long long)Nf * (2 * T) <= WG) T <<= 1;
-    const int part = tid & (T - 1);
-    for (int p = tid / T; p < Nf; p += WG / T) {
+    constexpr int S = 64, TS = WG / S;
+    if (Nf > S) {
+        const int part = tid & (TS - 1);
+        const int p = (int)((long long)(tid / TS) * Nf / S);
         const unsigned long long kp = t.tkey[p];
-        double F = 0.0, A = 0.0;
-        int q = part;
-        for (; q + 3 * T < Nf; q += 4 * T) {
-            unsigned long long kq[4];
-            double2 da[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                kq[u] = t.tkey[q + u * T];
-                da[u] = t.tda[q + u * T];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const bool c = kq[u] <= kp;
-                F += keep_if(da[u].x, c);
-                A += keep_if(da[u].y, !c);
-            }
+        double F, A;
+        f_parts(t, Nf, kp, part, TS, F, A);
+        F = group_sum_c<TS>(F);
+        A = group_sum_c<TS>(A) + Ainf;
+        if (part == 0) {
+            const double lam = __longlong_as_double((long long)kp);
+            if (F + lam * lam * A <= r2) atomicMax(&sh.best, kp + 1ull);
+            else atomicMin(&sh.hi, kp);
         }
-        for (; q < Nf; q += T) {
-            const unsigned long long kq = t.tkey[q];
-            const double2 da = t.tda[q];
-            const bool c = kq <= kp;
-            F += keep_if(da.x, c);
-            A += keep_if(da.y, !c);
+        __syncthreads();
+    }
+    {
+        const unsigned long long b0 = sh.best, hi = sh.hi;
+        bool inc[2];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int p = r * WG + tid;
+            inc[r] = false;
+            if (p < Nf) {
+                const unsigned long long k = t.tkey[p];
+                inc[r] = (b0 == 0ull || k > b0 - 1ull) && k < hi;
+            }
+            const unsigned long long bal = __ballot(inc[r]);
+            if (lane == 0) sh.woff[r][w] = __popcll(bal);
         }
+        __syncthreads();
+        if (tid == 0) {
+            int o = 0;
+            for (int r = 0; r < 2; ++r)
+                for (int q = 0; q < kWaves; ++q) {
+                    const int c = sh.woff[r][q];
+                    sh.woff[r][q] = o;
+                    o += c;
+                }
+            sh.nc = o;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const unsigned long long bal = __ballot(inc[r]);
+            if (inc[r]) t.tcid[sh.woff[r][w] + __popcll(bal & lt)] = r * WG + tid;
+        }
+        __syncthreads();
+    }
+    const int nc = sh.nc;
+    int T = 1;
+    while (T < 64 && (long long)nc * (2 * T) <= WG) T <<= 1;
+    const int part = tid & (T - 1);
+    for (int c = tid / T; c < nc; c += WG / T) {
+        const unsigned long long kp = t.tkey[t.tcid[c]];
+        double F, A;
+        f_parts(t, Nf, kp, part, T, F, A);
         F = group_sum(F, T);
         A = group_sum(A, T) + Ainf;
         if (part == 0) {
             const double lam = __longlong_as_double((long long)kp);
-            const double f = F + lam * lam * A;
-            if (f <= r2) atomicMax(&sh.best, kp + 1ull);
+            if (F + lam * lam * A <= r2) atomicMax(&sh.best, kp + 1ull);
         }
     }
     __syncthreads();
@@ -567,7 +634,10 @@ __global__ __launch_bounds__(WG) void k_tiny_blocks(Dev d, TinyArgs a) {
         const KktPoints P2{{t.x, t.xb}, {t.y, t.yb}, {t.q, t.axb}, {t.aty, t.atyb}};
         for (int i = tid; i < n + m; i += WG) kkt_elem(L, P2, i, v);
         block_sums<kKktSums, kWaves>(v, red);
-        if (tid == 0) armed = kkt_conclude(L, v, a.tol, a.kkt_kind, a.omega, a.gap_slots);
+        if (tid < 64) {
+            const int sl = kkt_conclude(L, v, a.tol, a.kkt_kind, a.omega, a.gap_slots);
+            if (tid == 0) armed = sl;
+        }
         __syncthreads();
         const int slots = armed;
         for (int sidx = 0; sidx < kTrSlots; ++sidx) {
