@@ -305,27 +305,47 @@ static int build_slabs(Slabs &sb, const int *rp, const int *ci, const double *v,
 static int order_columns(Dev &d, const Layout &L, char *ws, hipStream_t s) {
     d.permuted = 0;
     if (d.n < 2 || d.nnz == 0) return PDHG_OK;
-    const int n = d.n;
-    int *cnt_dev = d.trp;  // n + 1 ints, rebuilt by the transpose afterwards
+    const int n = d.n, m = d.m;
+    int *cnt_dev = d.trp;     // n + 1 ints, rebuilt by the transpose afterwards
+    int *first_dev = d.cursor;  // n ints of transpose scratch, free until then
     launch_col_counts(d.ci, d.nnz, n, cnt_dev, s);
-    std::vector<int> cnt((size_t)n + 1);
+    launch_first_rows(d.rp, d.ci, m, n, d.nnz, first_dev, s);
+    std::vector<int> cnt((size_t)n + 1), first((size_t)n);
     CK(hipMemcpyAsync(cnt.data(), cnt_dev, sizeof(int) * ((size_t)n + 1), hipMemcpyDeviceToHost,
                       s));
+    CK(hipMemcpyAsync(first.data(), first_dev, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
+    // Columns by entry count, largest first; equal counts by their first row,
+    // so that rows next to each other gather columns next to each other in
+    // A x, and rows of A' next to each other gather nearby y in A'y (two
+    // stable counting passes: first row, then count).
+    std::vector<int> by_first((size_t)n);
+    {
+        std::vector<int> fstart((size_t)m + 2, 0);
+        for (int j = 0; j < n; ++j) fstart[(size_t)first[j] + 1] += 1;
+        for (int r = 0; r <= m; ++r) fstart[(size_t)r + 1] += fstart[r];
+        for (int j = 0; j < n; ++j) by_first[(size_t)fstart[first[j]]++] = j;
+    }
     int cmax = 0;
     for (int j = 0; j < n; ++j) cmax = cnt[j + 1] > cmax ? cnt[j + 1] : cmax;
-    // buckets by count, largest count first
     std::vector<int> start((size_t)cmax + 2, 0);
     for (int j = 0; j < n; ++j) start[(size_t)(cmax - cnt[j + 1]) + 1] += 1;
     for (int k = 0; k <= cmax; ++k) start[k + 1] += start[k];
     std::vector<int> order((size_t)n), inv((size_t)n);
     bool ident = true;
-    for (int j = 0; j < n; ++j) {
+    for (int t = 0; t < n; ++t) {
+        const int j = by_first[(size_t)t];
         const int q = start[(size_t)(cmax - cnt[j + 1])]++;
         order[q] = j;
         inv[j] = q;
         ident &= (q == j);
     }
+    // share of the entries in the first L2-sized run of columns: when the
+    // hot columns hold most of them, A x gathers from one L2 without slabs
+    const long long w0 = slab_slice_bytes() / 8;
+    long long hot = 0;
+    for (long long q = 0; q < n && q < w0; ++q) hot += cnt[(size_t)order[q] + 1];
+    if (d.slA.S > 1 && 10 * hot >= 6 * (long long)d.nnz) d.slA.S = 1;
     if (ident) return PDHG_OK;
     int *ci2 = (int *)(ws + L.o_ci2);
     int *cperm = (int *)(ws + L.o_cperm), *cinv = (int *)(ws + L.o_cinv);
@@ -342,11 +362,6 @@ static int order_columns(Dev &d, const Layout &L, char *ws, hipStream_t s) {
     d.cperm = cperm;
     d.cinv = cinv;
     d.permuted = 1;
-    // share of the entries in the first L2-sized run of columns
-    const long long w0 = slab_slice_bytes() / 8;
-    long long hot = 0;
-    for (long long q = 0; q < n && q < w0; ++q) hot += cnt[(size_t)order[q] + 1];
-    if (d.slA.S > 1 && 10 * hot >= 6 * (long long)d.nnz) d.slA.S = 1;
     return last_error();
 }
 

@@ -127,8 +127,9 @@ struct Dev {
     Slabs slA;                 // A by column slabs (gathers x), for A x
     Slabs slT;                 // A' by column slabs (gathers y), for A' y
     // Column order.  Columns are kept sorted by entry count (largest first,
-    // ties in the caller's order), so the most gathered entries of x share
-    // cache lines and blocks of A' hold rows of similar length.  ci, c, l, u
+    // ties by the row of their first entry), so the most gathered entries
+    // of x share cache lines, neighbouring rows of A gather neighbouring
+    // columns, and blocks of A' hold rows of similar length.  ci, c, l, u
     // above are then the reordered copies; iterates cross the API in the
     // caller's order.
     int permuted;              // 0: the caller's order is already sorted
@@ -207,6 +208,9 @@ void launch_slab_fill(const Slabs &sb, const int *rp, const int *ci, const doubl
 void launch_norms(const Dev &d, hipStream_t s);   // |b|^2, |c|^2 into part[0..1]
 // column counts of the caller's A into cnt[1..n] (cnt[0] = 0)
 void launch_col_counts(const int *ci, int nnz, int n, int *cnt, hipStream_t s);
+// first[j] = smallest row with an entry in column j (m if none), j < n
+void launch_first_rows(const int *rp, const int *ci, int m, int n, int nnz, int *first,
+                       hipStream_t s);
 // ci2 = cinv[ci]; c2, l2, u2 = c, l, u in the internal column order
 void launch_permute_cols(const int *ci, int nnz, const int *cinv, int *ci2, const double *c,
                          const double *l, const double *u, const int *cperm, int n, double *c2,

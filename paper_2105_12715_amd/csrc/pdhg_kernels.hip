@@ -605,6 +605,29 @@ void launch_slab_fill(const Slabs &sb, const int *rp, const int *ci, const doubl
 }
 
 // --- column order (set-up and the API's conversions) ----------------------
+// first[j] = the smallest row holding an entry of column j (m for an empty
+// column); one thread per entry finds its row by bisection of the row starts
+__global__ void k_first_rows(const int *__restrict__ rp, const int *__restrict__ ci, int m,
+                             int nnz, int *first) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    int lo = 0, hi = m - 1;  // last row r with rp[r] <= e
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rp[mid] <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    atomicMin(&first[ci[e]], lo);
+}
+
+void launch_first_rows(const int *rp, const int *ci, int m, int n, int nnz, int *first,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_int, dim3(div_up(n, kWG)), dim3(kWG), 0, s, first, (long long)n, m);
+    if (nnz > 0 && m > 0)
+        hipLaunchKernelGGL(k_first_rows, dim3(div_up(nnz, kWG)), dim3(kWG), 0, s, rp, ci, m, nnz,
+                           first);
+}
+
 void launch_col_counts(const int *ci, int nnz, int n, int *cnt, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_int, dim3(div_up(n + 1, kWG)), dim3(kWG), 0, s, cnt,
                        (long long)n + 1, 0);

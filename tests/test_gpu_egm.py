@@ -122,8 +122,8 @@ def test_egm_solve_to_1e8_matches_oracle(lib, name):
 
 
 def test_egm_over_column_slabs(lib):
-    """A 600,000 x 700,000 LP splits both products into two slabs."""
-    lp = lpgen.column_count_lp(17, 600_000, 700_000, per_col=2, bounds="mix")
+    """A 600,000 x 1,000,000 LP splits both products into two slabs."""
+    lp = lpgen.column_count_lp(17, 600_000, 1_000_000, per_col=1, bounds="mix")
     _say("egm slabs")
     A = abs(lp.scipy_csr())
     eta = 0.9 / np.sqrt(float(A.sum(axis=0).max()) * float(A.sum(axis=1).max()))

@@ -108,12 +108,14 @@ def test_large_iterates_and_checks(lib, large):
         np.testing.assert_allclose(lg[:, col], lo[:, col], rtol=1e-9, atol=1e-300)
 
 
+# equal column counts: the first 4 MiB of x holds its share of the columns
+# of the entries, under 60% in every case, so A keeps its slabs
 @pytest.mark.parametrize("m,n,per_col", [
-    (3000, 600_000, 2),      # two slabs
+    (3000, 1_000_000, 2),    # two slabs
     (5000, 1_100_000, 1),    # four slabs
     (20_000, 4_300_000, 1),  # eight slabs
-    (1, 700_000, 1),         # one row
-    (600_000, 700_000, 2),   # two slabs of A and two of A'
+    (1, 1_000_000, 1),       # one row, two slabs
+    (600_000, 1_000_000, 1), # two slabs of A and two of A'
 ])
 def test_slab_counts_matvec_and_steps(lib, m, n, per_col):
     lp = lpgen.column_count_lp(17, m, n, per_col=per_col, bounds="mix")
