@@ -322,13 +322,82 @@ def run_adjoint(args):
     print(json.dumps(out), flush=True)
 
 
+def run_many(args):
+    """Many small LPs to --tol: each 50 x 100 LP (seeds 1..N) solved alone
+    one after another, all of them in one pdhg_solve_many call (one
+    workgroup per LP), and all of them through the batched solver
+    (pdhg_batch_*); plus the oracle on a few of them, projected to N."""
+    import numpy as np
+    import torch
+    from paper_2105_12715_amd import _lib, lpgen
+    N = args.many_count
+    lps = [lpgen.small_dense(1 + i) for i in range(N)]
+    wdesc = f"{N} small LPs 50 x 100, Bernoulli(0.1) (seeds 1..{N})"
+    log(f"workload {wdesc}")
+
+    def fresh():
+        return [_lib.Solver(lp) for lp in lps]
+
+    seq = fresh()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r_seq = [s.solve(args.budget, args.tol) for s in seq]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    log(f"one after another: {t_seq:.3f} s")
+    many = fresh()
+    assert all(s.info()["one_workgroup"] for s in many)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r_many = _lib.solve_many(many, args.budget, args.tol)
+    torch.cuda.synchronize()
+    t_many = time.perf_counter() - t0
+    log(f"pdhg_solve_many: {t_many:.3f} s")
+    if r_many != r_seq:
+        raise SystemExit("pdhg_solve_many differs from the single solves")
+    b = _lib.BatchSolver(lps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r_b = b.solve(args.budget, args.tol)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    log(f"batched solver: {t_batch:.3f} s")
+    ks = [r["k"] for r in r_seq]
+    nconv = sum(r["status"] == 0 for r in r_seq)
+    line = {"metric": f"time to {args.tol:g} rel KKT", "value": round(t_many, 4), "unit": "s",
+            "n_gpus": 1, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+            "scaling": "weak", "vs_baseline": None,
+            "config": {"workload": wdesc, "count": N, "tol": args.tol, "budget": args.budget,
+                       "check_period": 30, "restart": "adaptive"},
+            "converged": nconv, "iterations_total": int(sum(ks)),
+            "iterations_median": int(np.median(ks)), "iterations_max": int(max(ks)),
+            "one_after_another_s": round(t_seq, 4), "batched_solver_s": round(t_batch, 4),
+            "batched_solver_converged": int(sum(r["status"] == 0 for r in r_b)),
+            "speedup_vs_one_after_another": round(t_seq / t_many, 2),
+            "lp_iterations_per_s": round(sum(ks) / t_many, 1)}
+    if not args.no_cpu_baseline:
+        import oracle
+        sample = lps[: min(8, N)]
+        t0 = time.perf_counter()
+        for lp in sample:
+            oracle.Oracle(lp, eta=_lib.Solver(lp).info()["eta"]).solve(args.budget, args.tol)
+        t_cpu = (time.perf_counter() - t0) / len(sample) * N
+        line["cpu_baseline"] = {"value": round(t_cpu, 3), "unit": "s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"{len(sample)} of the LPs solved to {args.tol:g} by "
+                                          "the single-threaded FP64 C oracle, scaled to "
+                                          f"{N} LPs"}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=167, help="timed blocks of 30 iterations")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="large",
-                    choices=["large", "medium", "small", "batch", "table2", "adjoint"])
+                    choices=["large", "medium", "small", "batch", "table2", "adjoint", "many"])
+    ap.add_argument("--many-count", type=int, default=256)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-only", action="store_true",
                     help="batch: skip the sequential single-LP timings (for profiling)")
@@ -376,6 +445,9 @@ def main():
         return
     if args.workload == "adjoint":
         run_adjoint(args)
+        return
+    if args.workload == "many":
+        run_many(args)
         return
     t0 = time.perf_counter()
     lp, wdesc = make_workload(args.workload)

@@ -220,6 +220,28 @@ int pdhg_gap(pdhg_t *h, int32_t which, double r, double *rho, double *r_used,
  * per batch of blocks. */
 int pdhg_solve(pdhg_t *h, int64_t max_iters, double tol, pdhg_result *out);
 
+/* Bytes of device workspace pdhg_solve_many needs for `count` handles. */
+size_t pdhg_solve_many_workspace_bytes(int32_t count);
+
+/* pdhg_solve (Algorithm 1 with the Section 7 check schedule) on `count`
+ * independent handles at once.  hs: host array of distinct handles, all
+ * created on the current device.  Handles on the one-workgroup path
+ * (pdhg_info.one_workgroup != 0) advance together: one launch runs whole
+ * blocks of check_period iterations for all of them, one workgroup (one CU)
+ * per LP; each handle follows exactly the iterates and checks of its own
+ * pdhg_solve.  Other handles are solved one after another with pdhg_solve.
+ * workspace: device memory of at least
+ * pdhg_solve_many_workspace_bytes(count) bytes, owned by the caller, not
+ * used by any other call while this one runs.  out: host array of `count`
+ * results (may be NULL).  The shared launches go on the stream of hs[0];
+ * every handle's stream is synchronized first, and the call synchronizes
+ * before returning.  Returns PDHG_OK when every handle converged,
+ * PDHG_NOT_CONVERGED when the budget ran out for at least one,
+ * PDHG_E_INVALID for a bad argument (NULL or repeated handle, workspace
+ * too small), or the first error met. */
+int pdhg_solve_many(pdhg_t *const *hs, int32_t count, int64_t max_iters, double tol,
+                    void *workspace, size_t workspace_bytes, pdhg_result *out);
+
 /* Copy a held point (PDHG_POINT_*) into caller device buffers x (n) and
  * y (m), enqueued on the handle's stream.  Does not synchronize. */
 int pdhg_get_iterate(pdhg_t *h, int32_t which, double *x, double *y);

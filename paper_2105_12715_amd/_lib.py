@@ -109,6 +109,10 @@ def load(build_if_missing: bool = True):
     L.pdhg_gap.restype = C.c_int
     L.pdhg_solve.argtypes = [P, i64, d, C.POINTER(Result)]
     L.pdhg_solve.restype = C.c_int
+    L.pdhg_solve_many_workspace_bytes.argtypes = [i32]
+    L.pdhg_solve_many_workspace_bytes.restype = sz
+    L.pdhg_solve_many.argtypes = [P, i32, i64, d, P, sz, P]
+    L.pdhg_solve_many.restype = C.c_int
     L.pdhg_get_iterate.argtypes = [P, i32, P, P]
     L.pdhg_get_iterate.restype = C.c_int
     L.pdhg_set_iterate.argtypes = [P, P, P]
@@ -401,6 +405,32 @@ class _DeviceLP:
                          self.col_idx.data_ptr(), self.vals.data_ptr(), self.c.data_ptr(),
                          self.b.data_ptr(), self.l.data_ptr(), self.u.data_ptr(),
                          self.row_kind.data_ptr() if self.row_kind is not None else None)
+
+
+def _result_dict(r):
+    return dict(status=int(r.status), k=int(r.iterations), restarts=int(r.restarts),
+                kkt=float(r.kkt), which=int(r.which_point), pobj=float(r.pobj),
+                dobj=float(r.dobj))
+
+
+def solve_many(solvers, max_iters, tol):
+    """pdhg_solve_many on several Solver handles at once: the ones on the
+    one-workgroup path run together, one workgroup per LP.  Returns one
+    result dict per solver, as Solver.solve does."""
+    import torch
+    solvers = list(solvers)
+    if not solvers:
+        return []
+    L = solvers[0]._L
+    n = len(solvers)
+    hs = (C.c_void_p * n)(*[s.h for s in solvers])
+    nbytes = int(L.pdhg_solve_many_workspace_bytes(n))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=solvers[0].device)
+    res = (Result * n)()
+    rc = L.pdhg_solve_many(C.cast(hs, C.c_void_p), n, int(max_iters), float(tol), _ptr(ws),
+                           nbytes, C.cast(res, C.c_void_p))
+    _check(rc, "pdhg_solve_many", allow=(OK, NOT_CONVERGED))
+    return [_result_dict(r) for r in res]
 
 
 class BatchSolver:

@@ -9,6 +9,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -681,6 +682,52 @@ static int finish_result(pdhg_t *h, const DevState &hs, pdhg_result *out) {
     return PDHG_OK;
 }
 
+// Plain iterations up to the next check point (or k_end if sooner), then the
+// check when it falls there: the eager part of pdhg_solve.
+static int solve_eager_step(pdhg_t *h, int64_t *k, int64_t k_end, double tol, int64_t *t_host,
+                            bool *conv) {
+    const int64_t P = h->prm.check_period;
+    const int64_t to_check = P - (*k % P);
+    const int64_t sstep = to_check < k_end - *k ? to_check : k_end - *k;
+    int rc;
+    if ((rc = run_iters(h, sstep, t_host))) return rc;
+    *k += sstep;
+    if (*k % P == 0) {
+        enqueue_check(h, tol, h->stream);
+        if ((rc = last_error())) return rc;
+        DevState hs;
+        if ((rc = read_state(h, &hs))) return rc;
+        if (hs.numerr) return PDHG_E_NUMERICAL;
+        *conv = hs.conv_which >= 0 && hs.done;
+        *t_host = hs.t;
+    }
+    return PDHG_OK;
+}
+
+static bool one_workgroup(const pdhg_t *h) {
+    return h->tiny.ok && h->prm.method == PDHG_METHOD_PDHG &&
+           h->prm.restart_mode != PDHG_RESTART_FIXED && h->prm.check_period <= INT32_MAX;
+}
+
+static TinyArgs tiny_args(const pdhg_t *h, double tol, int blocks) {
+    TinyArgs ta{};
+    ta.tau = h->tau;
+    ta.sigma = h->sigma;
+    ta.tol = tol;
+    ta.beta = h->prm.beta;
+    ta.omega = h->d.omega;
+    ta.sw = sqrt(h->d.omega);
+    ta.P = (int)h->prm.check_period;
+    ta.tau0 = h->prm.tau0;
+    ta.kkt_kind = h->prm.kkt_kind;
+    ta.gap_slots = gap_slots_for(h->prm.restart_mode);
+    ta.blocks = blocks;
+    ta.Lp = h->tiny.Lp;
+    ta.Ld = h->tiny.Ld;
+    ta.summary = nullptr;
+    return ta;
+}
+
 int pdhg_solve(pdhg_t *h, int64_t max_iters, double tol, pdhg_result *out) {
     if (!h || max_iters < 0 || isnan(tol)) return PDHG_E_INVALID;
     int rc;
@@ -693,35 +740,18 @@ int pdhg_solve(pdhg_t *h, int64_t max_iters, double tol, pdhg_result *out) {
     bool conv = false;
     const bool use_graph = h->prm.restart_mode != PDHG_RESTART_FIXED;
     while (k < k_end && !conv) {
-        int64_t to_check = P - (k % P);
         if (use_graph && k % P == 0 && k_end - k >= P) {
             // replay whole blocks; the device skips everything after convergence
-            const bool tiny = h->tiny.ok && h->prm.method == PDHG_METHOD_PDHG && P <= INT32_MAX;
-            TinyArgs ta{};
-            if (tiny) {
-                ta.tau = h->tau;
-                ta.sigma = h->sigma;
-                ta.tol = tol;
-                ta.beta = h->prm.beta;
-                ta.omega = h->d.omega;
-                ta.sw = sqrt(h->d.omega);
-                ta.P = (int)P;
-                ta.tau0 = h->prm.tau0;
-                ta.kkt_kind = h->prm.kkt_kind;
-                ta.gap_slots = gap_slots_for(h->prm.restart_mode);
-                ta.Lp = h->tiny.Lp;
-                ta.Ld = h->tiny.Ld;
-            } else if ((rc = build_graph(h, tol))) {
-                return rc;
-            }
+            const bool tiny = one_workgroup(h);
+            TinyArgs ta = tiny_args(h, tol, 0);
+            if (!tiny && (rc = build_graph(h, tol))) return rc;
             int64_t blocks = (k_end - k) / P;
             int64_t batch = 1;
             while (blocks > 0 && !conv) {
                 int64_t nb = batch < blocks ? batch : blocks;
                 if (tiny) {
                     ta.blocks = (int)nb;
-                    launch_tiny_blocks(h->d, ta, h->tiny, h->stream);
-                    if ((rc = last_error())) return rc;
+                    CK(launch_tiny_blocks(h->d, ta, h->tiny, h->stream));
                 } else {
                     for (int64_t q = 0; q < nb; ++q) CK(hipGraphLaunch(h->gexec, h->stream));
                 }
@@ -734,21 +764,135 @@ int pdhg_solve(pdhg_t *h, int64_t max_iters, double tol, pdhg_result *out) {
             }
             continue;
         }
-        int64_t sstep = to_check < k_end - k ? to_check : k_end - k;
-        if ((rc = run_iters(h, sstep, &t_host))) return rc;
-        k += sstep;
-        if (k % P == 0) {
-            enqueue_check(h, tol, h->stream);
-            if ((rc = last_error())) return rc;
-            if ((rc = read_state(h, &hs))) return rc;
-            if (hs.numerr) return PDHG_E_NUMERICAL;
-            conv = hs.conv_which >= 0 && hs.done;
-            t_host = hs.t;
-        }
+        if ((rc = solve_eager_step(h, &k, k_end, tol, &t_host, &conv))) return rc;
     }
     if ((rc = read_state(h, &hs))) return rc;
     if ((rc = finish_result(h, hs, out))) return rc;
     return conv ? PDHG_OK : PDHG_NOT_CONVERGED;
+}
+
+static size_t many_bytes(int64_t count) {
+    return al(sizeof(Dev) * (size_t)count) + al(sizeof(TinyArgs) * (size_t)count) +
+           al(sizeof(long long) * 2 * (size_t)count);
+}
+
+size_t pdhg_solve_many_workspace_bytes(int32_t count) {
+    return count > 0 ? many_bytes(count) : 0;
+}
+
+int pdhg_solve_many(pdhg_t *const *hs, int32_t count, int64_t max_iters, double tol,
+                    void *workspace, size_t workspace_bytes, pdhg_result *out) {
+    if (count < 0 || (count > 0 && !hs) || max_iters < 0 || isnan(tol)) return PDHG_E_INVALID;
+    if (count == 0) return PDHG_OK;
+    {
+        std::vector<const pdhg_t *> seen(hs, hs + count);
+        std::sort(seen.begin(), seen.end());
+        for (int32_t i = 0; i < count; ++i)
+            if (!seen[i] || (i > 0 && seen[i] == seen[i - 1])) return PDHG_E_INVALID;
+    }
+    if (!workspace || workspace_bytes < many_bytes(count)) return PDHG_E_INVALID;
+    char *ws = (char *)workspace;
+    Dev *ddev = (Dev *)ws;
+    TinyArgs *dargs = (TinyArgs *)(ws + al(sizeof(Dev) * (size_t)count));
+    long long *dsum = (long long *)(ws + al(sizeof(Dev) * (size_t)count) +
+                                    al(sizeof(TinyArgs) * (size_t)count));
+    hipStream_t s = hs[0]->stream;
+    bool all_conv = true;
+    std::vector<int64_t> k(count), kend(count), t_host(count);
+    std::vector<char> conv(count, 0), joint(count, 0);
+    int rc;
+    for (int32_t i = 0; i < count; ++i) {
+        pdhg_t *h = hs[i];
+        if (!one_workgroup(h)) {
+            rc = pdhg_solve(h, max_iters, tol, out ? &out[i] : nullptr);
+            if (rc != PDHG_OK && rc != PDHG_NOT_CONVERGED) return rc;
+            all_conv &= rc == PDHG_OK;
+            continue;
+        }
+        launch_reset_done(h->d, h->stream);
+        DevState st;
+        if ((rc = read_state(h, &st))) return rc;
+        k[i] = st.k;
+        t_host[i] = st.t;
+        kend[i] = k[i] + max_iters;
+        const int64_t P = h->prm.check_period;
+        bool c = false;
+        // up to the first check point, as pdhg_solve does
+        if (k[i] % P != 0 && k[i] < kend[i] &&
+            (rc = solve_eager_step(h, &k[i], kend[i], tol, &t_host[i], &c)))
+            return rc;
+        conv[i] = c;
+        joint[i] = !c && kend[i] - k[i] >= P;
+        CK(hipStreamSynchronize(h->stream));
+    }
+    // whole blocks of every remaining handle, one workgroup each, a group of
+    // handles sharing one kernel per launch; rounds of 1, 2, 4, ... 64 blocks
+    for (int32_t lead = 0; lead < count; ++lead) {
+        if (!joint[lead]) continue;
+        const TinyPlan &pl = hs[lead]->tiny;
+        std::vector<int32_t> g;
+        size_t lds = 0;
+        for (int32_t i = lead; i < count; ++i) {
+            const TinyPlan &q = hs[i]->tiny;
+            if (joint[i] && q.reg == pl.reg && (!pl.reg || (q.Lp == pl.Lp && q.Ld == pl.Ld))) {
+                g.push_back(i);
+                lds = q.lds > lds ? q.lds : lds;
+                joint[i] = 0;
+            }
+        }
+        const int ng = (int)g.size();
+        std::vector<Dev> hdev(ng);
+        std::vector<TinyArgs> harg(ng);
+        std::vector<long long> hsum(2 * (size_t)ng);
+        for (int j = 0; j < ng; ++j) hdev[j] = hs[g[j]]->d;
+        CK(hipMemcpyAsync(ddev, hdev.data(), sizeof(Dev) * ng, hipMemcpyHostToDevice, s));
+        std::vector<char> live(ng, 1);
+        int nlive = ng;
+        int64_t batch = 1;
+        while (nlive > 0) {
+            for (int j = 0; j < ng; ++j) {
+                pdhg_t *h = hs[g[j]];
+                const int64_t P = h->prm.check_period;
+                int64_t nb = live[j] ? (kend[g[j]] - k[g[j]]) / P : 0;
+                if (nb > batch) nb = batch;
+                harg[j] = tiny_args(h, tol, (int)nb);
+                harg[j].summary = dsum + 2 * j;
+            }
+            CK(hipMemcpyAsync(dargs, harg.data(), sizeof(TinyArgs) * ng, hipMemcpyHostToDevice, s));
+            CK(launch_tiny_many(ddev, dargs, ng, pl, lds, s));
+            CK(hipMemcpyAsync(hsum.data(), dsum, sizeof(long long) * 2 * ng,
+                              hipMemcpyDeviceToHost, s));
+            CK(hipStreamSynchronize(s));
+            for (int j = 0; j < ng; ++j) {
+                if (!live[j] || harg[j].blocks == 0) continue;
+                const int32_t i = g[j];
+                const long long f = hsum[2 * (size_t)j + 1];
+                if ((f >> 16) & 1) return PDHG_E_NUMERICAL;
+                // a converged handle stops at the check that converged
+                const bool c = (f & 0xff) && ((f >> 8) & 0xff) > 0;
+                k[i] = hsum[2 * (size_t)j];
+                conv[i] = c;
+                if (c || kend[i] - k[i] < hs[i]->prm.check_period) {
+                    live[j] = 0;
+                    --nlive;
+                }
+            }
+            if (batch < 64) batch *= 2;
+        }
+    }
+    // the iterations after the last whole block, and the results
+    for (int32_t i = 0; i < count; ++i) {
+        pdhg_t *h = hs[i];
+        if (!one_workgroup(h)) continue;
+        bool c = conv[i];
+        while (!c && k[i] < kend[i])
+            if ((rc = solve_eager_step(h, &k[i], kend[i], tol, &t_host[i], &c))) return rc;
+        DevState st;
+        if ((rc = read_state(h, &st))) return rc;
+        if ((rc = finish_result(h, st, out ? &out[i] : nullptr))) return rc;
+        all_conv &= c;
+    }
+    return all_conv ? PDHG_OK : PDHG_NOT_CONVERGED;
 }
 
 int pdhg_get_iterate(pdhg_t *h, int32_t which, double *x, double *y) {

@@ -286,6 +286,7 @@ struct TinyArgs {
     double tau, sigma, tol, beta, omega, sw;  // sw = sqrt(omega)
     int P, tau0, kkt_kind, gap_slots, blocks;
     int Lp, Ld;
+    long long *summary;    // may be null: [0] = k, [1] = done | (conv_which + 1) << 8 | numerr << 16
 };
 // LDS bytes of the one-workgroup solver: doubles x, x-bar (n + 1 each, the
 // last a zero that padded matrix entries point at), sx, c, l, u, A'y,
@@ -303,6 +304,11 @@ __host__ __device__ inline size_t tiny_lds_bytes(long long n, long long m, long 
 }
 // plan for an LP already on the device (reads its row starts)
 TinyPlan tiny_plan(const Dev &d, hipStream_t s);
-void launch_tiny_blocks(const Dev &d, const TinyArgs &a, const TinyPlan &p, hipStream_t s);
+hipError_t launch_tiny_blocks(const Dev &d, const TinyArgs &a, const TinyPlan &p, hipStream_t s);
+// count LPs at once, one workgroup each (devs, args in device memory); all
+// of them planned with the kernel of p (same mode and lanes), lds the
+// largest of their LDS sizes
+hipError_t launch_tiny_many(const Dev *devs, const TinyArgs *args, int count, const TinyPlan &p,
+                            size_t lds, hipStream_t s);
 
 }  // namespace pdhg

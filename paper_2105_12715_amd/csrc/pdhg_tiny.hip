@@ -430,7 +430,7 @@ __device__ void tiny_trust_region(const E &e, TRState &ts, const TinyLds &t, TrS
 }
 
 template <bool REG, int LP, int LD>
-__global__ __launch_bounds__(WG) void k_tiny_blocks(Dev d, TinyArgs a) {
+__device__ __forceinline__ void tiny_body(const Dev &d, const TinyArgs &a) {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ DevState sst;
     __shared__ TrShared trs;
@@ -691,7 +691,28 @@ __global__ __launch_bounds__(WG) void k_tiny_blocks(Dev d, TinyArgs a) {
         d.ybar[i] = t.yb[i];
         d.axb[i] = t.axb[i];
     }
-    if (tid == 0) *d.st = sst;
+    if (tid == 0) {
+        *d.st = sst;
+        if (a.summary) {
+            a.summary[0] = sst.k;
+            a.summary[1] = (long long)sst.done | ((long long)(sst.conv_which + 1) << 8) |
+                           ((long long)sst.numerr << 16);
+        }
+    }
+}
+
+template <bool REG, int LP, int LD>
+__global__ __launch_bounds__(WG) void k_tiny_blocks(Dev d, TinyArgs a) {
+    tiny_body<REG, LP, LD>(d, a);
+}
+
+// one LP per workgroup: the solver view and arguments of LP blockIdx.x
+template <bool REG, int LP, int LD>
+__global__ __launch_bounds__(WG) void k_tiny_many(const Dev *__restrict__ devs,
+                                                  const TinyArgs *__restrict__ args) {
+    const Dev d = devs[blockIdx.x];
+    const TinyArgs a = args[blockIdx.x];
+    if (a.blocks > 0) tiny_body<REG, LP, LD>(d, a);
 }
 
 // lanes per row with the matrix in LDS: about four entries per lane
@@ -710,24 +731,27 @@ int lanes_reg(long long maxlen) {
     return (long long)K * L < maxlen ? 0 : L;
 }
 
-// kernels by (LP, LD), both in {1, 2, 4, 8}
-template <int LP>
+// kernels by (LP, LD), both in {1, 2, 4, 8}; MANY picks the one-LP-per-
+// workgroup form
+template <bool MANY, int LP>
 const void *tiny_fn_ld(int Ld) {
     switch (Ld) {
-    case 1: return (const void *)k_tiny_blocks<true, LP, 1>;
-    case 2: return (const void *)k_tiny_blocks<true, LP, 2>;
-    case 4: return (const void *)k_tiny_blocks<true, LP, 4>;
-    default: return (const void *)k_tiny_blocks<true, LP, 8>;
+    case 1: return MANY ? (const void *)k_tiny_many<true, LP, 1> : (const void *)k_tiny_blocks<true, LP, 1>;
+    case 2: return MANY ? (const void *)k_tiny_many<true, LP, 2> : (const void *)k_tiny_blocks<true, LP, 2>;
+    case 4: return MANY ? (const void *)k_tiny_many<true, LP, 4> : (const void *)k_tiny_blocks<true, LP, 4>;
+    default: return MANY ? (const void *)k_tiny_many<true, LP, 8> : (const void *)k_tiny_blocks<true, LP, 8>;
     }
 }
 
+template <bool MANY>
 const void *tiny_kernel(const TinyPlan &p) {
-    if (!p.reg) return (const void *)k_tiny_blocks<false, 0, 0>;
+    if (!p.reg)
+        return MANY ? (const void *)k_tiny_many<false, 0, 0> : (const void *)k_tiny_blocks<false, 0, 0>;
     switch (p.Lp) {
-    case 1: return tiny_fn_ld<1>(p.Ld);
-    case 2: return tiny_fn_ld<2>(p.Ld);
-    case 4: return tiny_fn_ld<4>(p.Ld);
-    default: return tiny_fn_ld<8>(p.Ld);
+    case 1: return tiny_fn_ld<MANY, 1>(p.Ld);
+    case 2: return tiny_fn_ld<MANY, 2>(p.Ld);
+    case 4: return tiny_fn_ld<MANY, 4>(p.Ld);
+    default: return tiny_fn_ld<MANY, 8>(p.Ld);
     }
 }
 
@@ -765,20 +789,35 @@ TinyPlan tiny_plan(const Dev &d, hipStream_t s) {
     }
     p.lds = tiny_lds_bytes(n, m, d.nnz, p.reg);
     if (p.lds > kTinyLdsMax) return p;
-    const void *fn = tiny_kernel(p);
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds) !=
-        hipSuccess) {
-        (void)hipGetLastError();
-        return p;
+    // the limit belongs to the kernel, shared by every handle that uses it:
+    // raise it to the cap, never to one handle's size
+    for (int many = 0; many < 2; ++many) {
+        const void *fn = many ? tiny_kernel<true>(p) : tiny_kernel<false>(p);
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)kTinyLdsMax) != hipSuccess) {
+            (void)hipGetLastError();
+            return p;
+        }
     }
     p.ok = 1;
     return p;
 }
 
-void launch_tiny_blocks(const Dev &d, const TinyArgs &a, const TinyPlan &p, hipStream_t s) {
-    const void *fn = tiny_kernel(p);
-    void *args[] = {(void *)&d, (void *)&a};
-    (void)hipLaunchKernel(fn, dim3(1), dim3(WG), args, p.lds, s);
+hipError_t launch_tiny_blocks(const Dev &d, const TinyArgs &a, const TinyPlan &p, hipStream_t s) {
+    const void *fn = tiny_kernel<false>(p);
+    Dev dd = d;
+    TinyArgs aa = a;
+    void *args[] = {(void *)&dd, (void *)&aa};
+    return hipLaunchKernel(fn, dim3(1), dim3(WG), args, p.lds, s);
+}
+
+hipError_t launch_tiny_many(const Dev *devs, const TinyArgs *args, int count, const TinyPlan &p,
+                            size_t lds, hipStream_t s) {
+    const void *fn = tiny_kernel<true>(p);
+    const Dev *dv = devs;
+    const TinyArgs *av = args;
+    void *kargs[] = {(void *)&dv, (void *)&av};
+    return hipLaunchKernel(fn, dim3(count), dim3(WG), kargs, lds, s);
 }
 
 }  // namespace pdhg

@@ -465,9 +465,12 @@ static void run_tr(const E &e, long long N, TRState *ts, const TRWork &w, const 
     hipLaunchKernelGGL(k_tr_decide0, dim3(1), dim3(kWG), 0, s, ts, w, g, gate);
     hipLaunchKernelGGL(k_tr_pass1<E>, dim3(g), dim3(kWG), 0, s, e, ts, w, gate, cap);
     hipLaunchKernelGGL(k_tr_decide1, dim3(1), dim3(kWG), 0, s, ts, w, g, gate);
-    // the multi-block levels only run while the bracket holds more than
-    // kFinishMax members, which needs more coordinates than that
-    if (N > (long long)kFinishMax) {
+    // The multi-block levels only work while the bracket holds more than
+    // kFinishMax members.  Up to 4 kFinishMax coordinates they are not
+    // launched at all: the one-workgroup finish then walks the compacted
+    // regions itself in the rare case of a bracket that large, instead of
+    // every check paying four launches that return at once.
+    if (N > 4ll * kFinishMax) {
         for (int level = 2; level <= 3; ++level) {
             hipLaunchKernelGGL(k_tr_cpass, dim3(g), dim3(kWG), 0, s, ts, w, gate, cap, level);
             hipLaunchKernelGGL(k_tr_cdecide, dim3(1), dim3(kWG), 0, s, ts, w, gate, level);

@@ -147,7 +147,7 @@ def _tr_case(seed, N, inf_frac, zero_frac=0.1, atb=0.1, dup=False):
     (0, 1, 0.0, False), (1, 7, 0.3, False), (2, 1000, 0.0, False), (3, 1000, 0.5, False),
     (4, 5000, 0.1, True), (5, 100_000, 0.2, False), (6, 1_000_000, 0.05, False),
     (7, 300_000, 0.0, True), (8, 3, 1.0, False), (9, 200_000, 0.0, "all"),
-    (10, 200_000, 0.3, "all"),
+    (10, 200_000, 0.3, "all"), (11, 400_000, 0.1, "all"),
 ])
 def test_trust_region_parity(lib, seed, N, inf_frac, dup):
     a, d = _tr_case(seed, N, inf_frac, dup=dup)
