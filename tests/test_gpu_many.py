@@ -117,3 +117,22 @@ def test_solve_many_continues_and_rejects_bad_arguments(lib):
                            C.cast(res, C.c_void_p))
     assert rc == lib.E_INVALID  # workspace too small
     assert lib.solve_many([], 10, 0.0) == []
+
+
+def test_solve_many_more_lps_than_compute_units(lib):
+    """300 handles (more workgroups than the chip's 256 CUs), a third of them
+    already converged before the call."""
+    lp = lpgen.bernoulli_lp(11, 30, 60, 0.15, lpgen.BOX01, ge_frac=0.4)
+    eta = 0.9 / _sigma_bound(lp)
+    ref = lib.Solver(lp, eta=eta)
+    r_ref = ref.solve(100_000, 1e-8)
+    handles = [lib.Solver(lp, eta=eta) for _ in range(300)]
+    for s in handles[::3]:
+        s.solve(100_000, 1e-8)
+    got = lib.solve_many(handles, 100_000, 1e-8)
+    for i, g in enumerate(got):
+        assert g["status"] == 0
+        if i % 3:
+            assert g == r_ref, i
+    _same_state(ref, handles[1])
+    _same_state(ref, handles[299])
