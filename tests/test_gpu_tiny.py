@@ -54,6 +54,10 @@ CASES = {
     "two_per_thread": lambda: lpgen.column_count_lp(23, 170, 350, per_col=1, bounds="box01"),
     # 72 KiB of LDS with rows in registers
     "reg_72k": lambda: lpgen.column_count_lp(25, 400, 500, per_col=1, bounds="mix"),
+    # n + m = 1024 with rows in registers: every thread holds two
+    # trust-region coordinates
+    "reg_1024": lambda: lpgen.column_count_lp(29, 512, 512, per_col=1, bounds="mix",
+                                              ge_frac=0.2),
     # n + m = 1024: 724 rows of A' (more than one per group), matrix in
     # LDS whatever is asked, 118 KiB
     "max_coords": lambda: lpgen.column_count_lp(27, 300, 724, per_col=2, bounds="mix",
