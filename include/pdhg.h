@@ -220,6 +220,30 @@ int pdhg_gap(pdhg_t *h, int32_t which, double r, double *rho, double *r_used,
  * per batch of blocks. */
 int pdhg_solve(pdhg_t *h, int64_t max_iters, double tol, pdhg_result *out);
 
+/* Outcome of pdhg_autotune.  A product with slabs gathers one column slab
+ * of its vector per launch (each slab meant to stay in one XCD's L2);
+ * 1 = a single launch over all columns. */
+typedef struct pdhg_tune {
+    int32_t slabs_A, slabs_At;            /* slab counts in use for A x and A'y   */
+    int32_t candidates_A, candidates_At;  /* counts timed (0: fixed or cached)    */
+    int32_t tried_A[4], tried_At[4];      /* the slab counts timed                */
+    double ms_A[4], ms_At[4];             /* mean time of one product each, ms    */
+    int32_t from_cache, reserved;         /* 1: taken from an earlier tuning      */
+} pdhg_tune;
+
+/* Per-matrix choice of the column slabs of A x and A'y (the tiles of the
+ * SpMV launches, Section 7's products): times `iters` products of the
+ * current point for each slab count 1, 2, 4, 8 the workspace has room for
+ * (room exists when the gathered vector is larger than one 4 MiB L2
+ * slice), keeps the fastest for each product, and remembers the choice for
+ * the process under a signature of the matrix (sizes and sampled row
+ * starts); with use_cache != 0 a remembered choice is applied without
+ * timing.  The iterates, averages and counters are left as they are; the
+ * products are written to scratch vectors.  Later solves follow the same
+ * iterates up to the order of floating-point sums.  *out (host, may be
+ * NULL).  Synchronizes.  PDHG_E_INVALID for iters outside 1..10000. */
+int pdhg_autotune(pdhg_t *h, int32_t iters, int32_t use_cache, pdhg_tune *out);
+
 /* Bytes of device workspace pdhg_solve_many needs for `count` handles. */
 size_t pdhg_solve_many_workspace_bytes(int32_t count);
 

@@ -67,6 +67,14 @@ class Info(C.Structure):
                 ("one_workgroup", C.c_int32), ("reserved", C.c_int32)]
 
 
+class Tune(C.Structure):
+    _fields_ = [("slabs_A", C.c_int32), ("slabs_At", C.c_int32),
+                ("candidates_A", C.c_int32), ("candidates_At", C.c_int32),
+                ("tried_A", C.c_int32 * 4), ("tried_At", C.c_int32 * 4),
+                ("ms_A", C.c_double * 4), ("ms_At", C.c_double * 4),
+                ("from_cache", C.c_int32), ("reserved", C.c_int32)]
+
+
 class CheckRecord(C.Structure):
     _fields_ = [("v", C.c_double * 14)]
 
@@ -109,6 +117,8 @@ def load(build_if_missing: bool = True):
     L.pdhg_gap.restype = C.c_int
     L.pdhg_solve.argtypes = [P, i64, d, C.POINTER(Result)]
     L.pdhg_solve.restype = C.c_int
+    L.pdhg_autotune.argtypes = [P, i32, i32, C.POINTER(Tune)]
+    L.pdhg_autotune.restype = C.c_int
     L.pdhg_solve_many_workspace_bytes.argtypes = [i32]
     L.pdhg_solve_many_workspace_bytes.restype = sz
     L.pdhg_solve_many.argtypes = [P, i32, i64, d, P, sz, P]
@@ -280,6 +290,17 @@ class Solver:
         return dict(status=int(res.status), k=int(res.iterations), restarts=int(res.restarts),
                     kkt=float(res.kkt), which=int(res.which_point), pobj=float(res.pobj),
                     dobj=float(res.dobj))
+
+    def autotune(self, iters=20, use_cache=True):
+        """pdhg_autotune: time the column-slab counts of A x and A'y on this
+        matrix and keep the fastest; returns the slab counts in use and the
+        timings (ms per product) of the counts tried."""
+        t = Tune()
+        _check(self._L.pdhg_autotune(self.h, int(iters), 1 if use_cache else 0, C.byref(t)),
+               "pdhg_autotune")
+        return dict(slabs_A=t.slabs_A, slabs_At=t.slabs_At, from_cache=bool(t.from_cache),
+                    A={int(t.tried_A[i]): float(t.ms_A[i]) for i in range(t.candidates_A)},
+                    At={int(t.tried_At[i]): float(t.ms_At[i]) for i in range(t.candidates_At)})
 
     # -- evaluation --------------------------------------------------------
     def kkt(self, which=POINT_CURRENT):

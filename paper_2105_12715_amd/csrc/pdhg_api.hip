@@ -10,6 +10,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -29,6 +31,7 @@ struct pdhg_handle {
     double g_tol;
     bool g_valid;
     TinyPlan tiny;          // one-workgroup solver, when the LP fits one CU's LDS
+    int slab_cap[2];        // slab counts the workspace has room for (A, A')
 };
 
 #define CK(expr)                                   \
@@ -162,7 +165,7 @@ bool make_layout(int64_t m, int64_t n, int64_t nnz, Layout *L) {
     // gathered vector)
     const int64_t rows_of[2] = {m, n}, gath_of[2] = {n, m};
     for (int t = 0; t < 2; ++t) {
-        const int S = slab_count_for(rows_of[t], gath_of[t], n, slab_slice_bytes());
+        const int S = slab_reserve_for(rows_of[t], gath_of[t], n, slab_slice_bytes());
         const size_t Ss = S > 1 ? (size_t)S : 0, zS = S > 1 ? z1 : 0;
         const size_t r1 = (size_t)(rows_of[t] > 0 ? rows_of[t] : 1);
         const int nb = t == 0 ? nbA : nbT;
@@ -445,6 +448,7 @@ int pdhg_create(const pdhg_lp *lp, const pdhg_params *prm_in, void *workspace,
         Slabs &sb = *sl[t];
         sb.S = slab_count_for(rows_of[t], gath_of[t], d.n, slab_slice_bytes());
         sb.W = (int)(((long long)gath_of[t] + sb.S - 1) / sb.S);
+        h->slab_cap[t] = slab_reserve_for(rows_of[t], gath_of[t], d.n, slab_slice_bytes());
         sb.rows = rows_of[t];
         sb.nbmax = 0;
         sb.srp = (int *)(ws + L.o_slab[t][0]);
@@ -893,6 +897,136 @@ int pdhg_solve_many(pdhg_t *const *hs, int32_t count, int64_t max_iters, double 
         all_conv &= c;
     }
     return all_conv ? PDHG_OK : PDHG_NOT_CONVERGED;
+}
+
+// ---------------------------------------------------------------------
+// tuning of the column slabs per matrix
+// ---------------------------------------------------------------------
+// slab count S of A (t = 0) or A' (t = 1), rebuilding the slabs; the
+// recorded graph holds the old launches, so it is dropped
+static int set_slabs(pdhg_t *h, int t, int S) {
+    Dev &d = h->d;
+    Slabs &sb = t == 0 ? d.slA : d.slT;
+    if (S == sb.S) return PDHG_OK;
+    if (S < 1 || S > h->slab_cap[t]) return PDHG_E_INVALID;
+    const int gath = t == 0 ? d.n : d.m;
+    h->g_valid = false;
+    sb.S = S;
+    sb.W = (int)(((long long)gath + S - 1) / S);
+    if (S == 1) return PDHG_OK;
+    return t == 0 ? build_slabs(sb, d.rp, d.ci, d.v, d.nnz, d.nblkA, d.long_rows, h->stream)
+                  : build_slabs(sb, d.trp, d.tci, d.tv, d.nnz, d.nblkT, d.long_rows, h->stream);
+}
+
+// mean time of one product A x (t = 0) or A'y (t = 1) of the current point,
+// written to scratch vectors: the solver state is left alone
+static int time_product(pdhg_t *h, int t, int iters, double *ms) {
+    const Dev &d = h->d;
+    hipStream_t s = h->stream;
+    auto once = [&]() {
+        if (t == 0) launch_spmv_A(d, d.x, d.gax, s);
+        else launch_spmv_T(d, d.y, d.gaty, s);
+    };
+    once();  // warm-up
+    hipEvent_t a = nullptr, b = nullptr;
+    int rc = PDHG_OK;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) rc = PDHG_E_HIP;
+    if (rc == PDHG_OK && hipEventRecord(a, s) != hipSuccess) rc = PDHG_E_HIP;
+    for (int i = 0; i < iters && rc == PDHG_OK; ++i) once();
+    if (rc == PDHG_OK && hipEventRecord(b, s) != hipSuccess) rc = PDHG_E_HIP;
+    if (rc == PDHG_OK) rc = last_error();
+    float el = 0.f;
+    if (rc == PDHG_OK && (hipEventSynchronize(b) != hipSuccess ||
+                          hipEventElapsedTime(&el, a, b) != hipSuccess))
+        rc = PDHG_E_HIP;
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (rc == PDHG_OK) *ms = el / (double)iters;
+    return rc;
+}
+
+// signature of a matrix for the tuning cache: sizes and 32 sampled row
+// starts of A and of A' (FNV-1a)
+static int matrix_signature(pdhg_t *h, uint64_t *sig) {
+    const Dev &d = h->d;
+    uint64_t f = 1469598103934665603ull;
+    auto mix = [&](long long v) {
+        for (int k = 0; k < 8; ++k) {
+            f ^= (uint64_t)((v >> (8 * k)) & 0xff);
+            f *= 1099511628211ull;
+        }
+    };
+    mix(d.m);
+    mix(d.n);
+    mix(d.nnz);
+    const int *arrs[2] = {d.rp, d.trp};
+    const int rows[2] = {d.m, d.n};
+    for (int t = 0; t < 2; ++t) {
+        int v[32];
+        for (int q = 0; q < 32; ++q)
+            CK(hipMemcpyAsync(&v[q], arrs[t] + (long long)rows[t] * q / 31, sizeof(int),
+                              hipMemcpyDeviceToHost, h->stream));
+        CK(hipStreamSynchronize(h->stream));
+        for (int q = 0; q < 32; ++q) mix(v[q]);
+    }
+    *sig = f;
+    return PDHG_OK;
+}
+
+static std::mutex g_tune_mu;
+static std::map<uint64_t, std::pair<int, int>> g_tune_cache;
+
+int pdhg_autotune(pdhg_t *h, int32_t iters, int32_t use_cache, pdhg_tune *out) {
+    if (!h || iters < 1 || iters > 10000) return PDHG_E_INVALID;
+    pdhg_tune r;
+    memset(&r, 0, sizeof(r));
+    int rc;
+    uint64_t sig = 0;
+    if ((rc = matrix_signature(h, &sig))) return rc;
+    bool cached = false;
+    std::pair<int, int> choice(h->d.slA.S, h->d.slT.S);
+    if (use_cache) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(sig);
+        if (it != g_tune_cache.end()) {
+            cached = true;
+            choice = it->second;
+        }
+    }
+    if (cached) {
+        if ((rc = set_slabs(h, 0, choice.first)) || (rc = set_slabs(h, 1, choice.second)))
+            return rc;
+        r.from_cache = 1;
+    } else {
+        int *tried[2] = {r.tried_A, r.tried_At};
+        double *ms[2] = {r.ms_A, r.ms_At};
+        int *ncand[2] = {&r.candidates_A, &r.candidates_At};
+        int best[2] = {h->d.slA.S, h->d.slT.S};
+        for (int t = 0; t < 2; ++t) {
+            if (h->slab_cap[t] <= 1) continue;
+            double bt = 0.0;
+            for (int S = 1; S <= h->slab_cap[t] && *ncand[t] < 4; S <<= 1) {
+                double m = 0.0;
+                if ((rc = set_slabs(h, t, S)) || (rc = time_product(h, t, iters, &m))) return rc;
+                tried[t][*ncand[t]] = S;
+                ms[t][*ncand[t]] = m;
+                ++*ncand[t];
+                if (*ncand[t] == 1 || m < bt) {
+                    bt = m;
+                    best[t] = S;
+                }
+            }
+            if ((rc = set_slabs(h, t, best[t]))) return rc;
+        }
+        choice = std::make_pair(best[0], best[1]);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[sig] = choice;
+    }
+    CK(hipStreamSynchronize(h->stream));
+    r.slabs_A = h->d.slA.S;
+    r.slabs_At = h->d.slT.S;
+    if (out) *out = r;
+    return last_error();
 }
 
 int pdhg_get_iterate(pdhg_t *h, int32_t which, double *x, double *y) {

@@ -150,6 +150,14 @@ inline int slab_count_for(int64_t rows, int64_t gathered, int64_t scratch_ints,
     return S;
 }
 
+// Slab counts the workspace reserves room for when a product uses slabs at
+// all (the tuner may try any power of two up to it)
+constexpr int kSlabMax = 8;
+inline int slab_reserve_for(int64_t rows, int64_t gathered, int64_t scratch_ints,
+                            int64_t slice_bytes) {
+    return slab_count_for(rows, gathered, scratch_ints, slice_bytes) > 1 ? kSlabMax : 1;
+}
+
 // Primal-weight search: W <= kWMax copies of non-restarted PDHG sharing A
 constexpr int kWMax = 16;
 constexpr int kWSums = 5;      // |p|^2, |d|^2, pobj, dobj, bound violation^2

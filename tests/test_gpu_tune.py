@@ -1,0 +1,93 @@
+"""pdhg_autotune: per-matrix choice of the column slabs of A x and A'y.
+The tuner times the products only, so the solver state stays bitwise the
+same; solves after a re-slabbing still match the oracle; a second handle on
+the same matrix takes the remembered choice.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_12715_amd import lpgen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2105_12715_amd import _lib
+    _lib.load(build_if_missing=False)
+    return _lib
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0)
+
+
+def _eta(lp):
+    A = abs(lp.scipy_csr())
+    return 0.9 / np.sqrt(float(A.sum(axis=0).max()) * float(A.sum(axis=1).max()))
+
+
+def test_autotune_keeps_state_and_parity(lib):
+    # x of 8 MB and y of 4.8 MB: both products may use slabs
+    lp = lpgen.column_count_lp(17, 600_000, 1_000_000, per_col=1, bounds="mix")
+    eta = _eta(lp)
+    _say("autotune", lp.nnz)
+    s = lib.Solver(lp, eta=eta)
+    o = oracle.Oracle(lp, eta=eta)
+    s.solve(31, 0.0)
+    o.solve(31, 0.0)
+    before = [t.clone() for w in (0, 1, 2) for t in s.get_iterate(w)]
+    info0 = s.info()
+    r = s.autotune(iters=5, use_cache=False)
+    _say(r)
+    assert not r["from_cache"]
+    assert sorted(r["A"]) == [1, 2, 4, 8] and sorted(r["At"]) == [1, 2, 4, 8]
+    assert all(v > 0 for v in list(r["A"].values()) + list(r["At"].values()))
+    assert r["slabs_A"] == min(r["A"], key=r["A"].get)
+    assert r["slabs_At"] == min(r["At"], key=r["At"].get)
+    after = [t for w in (0, 1, 2) for t in s.get_iterate(w)]
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(before, after))
+    info1 = s.info()
+    for key in ("k", "t", "restarts", "checks"):
+        assert info0[key] == info1[key]
+    # every slab count gives the same products up to rounding
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal(lp.n)
+    y = rng.standard_normal(lp.m)
+    np.testing.assert_allclose(s.matvec(x).cpu().numpy(), o.matvec(x), rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(s.matvec(y, transpose=True).cpu().numpy(), o.matvec_t(y),
+                               rtol=1e-12, atol=1e-9)
+    # iterations after the re-slabbing still follow the oracle
+    s.solve(61, 0.0)
+    o.solve(61, 0.0)
+    for which in (0, 1, 2):
+        xo, yo = o.get(which)
+        xg, yg = (t.cpu().numpy() for t in s.get_iterate(which))
+        assert rel(np.concatenate([xg, yg]), np.concatenate([xo, yo])) <= 1e-10
+    # the same matrix again: the remembered choice, no timing
+    s2 = lib.Solver(lp, eta=eta)
+    r2 = s2.autotune(iters=5)
+    assert r2["from_cache"] and r2["A"] == {} and r2["At"] == {}
+    assert (r2["slabs_A"], r2["slabs_At"]) == (r["slabs_A"], r["slabs_At"])
+
+
+def test_autotune_without_slabs_and_bad_arguments(lib):
+    lp = lpgen.small_dense(1)
+    s = lib.Solver(lp, eta=0.1)
+    r = s.autotune(iters=3, use_cache=False)
+    assert (r["slabs_A"], r["slabs_At"]) == (1, 1) and r["A"] == {} and r["At"] == {}
+    with pytest.raises(lib.PdhgError):
+        s.autotune(iters=0)
