@@ -362,6 +362,9 @@ int pdhg_linear_trust_region(int64_t N, const double *a, const double *d,
  * defaults); restart_mode (none, adaptive or flexible), check_period and
  * kkt_kind must be equal across the batch.  Workspace and stream rules are
  * those of pdhg_create.  Sizes: host arrays m, n, nnz of `count` entries.
+ * Inside each LP's own range the columns are held in an order of the
+ * library's choosing (by entry count, then by first row); every call below
+ * takes and returns column vectors in the caller's order.
  */
 typedef struct pdhg_batch_handle pdhg_batch_t;
 size_t pdhg_batch_workspace_bytes(int32_t count, const int64_t *m, const int64_t *n,

@@ -62,6 +62,9 @@ struct BDev {
     int *trp, *tci, *perm;
     double *tv;
     int *cursor, *long_rows;
+    // column order inside each LP's column range (null: the caller's order)
+    int *cperm;  // [N] internal column -> caller's column
+    int *cinv;   // [N] caller's column -> internal column
     int *brA, *brT;
     int nblkA, nblkT;
     int *xpA, *xpT;        // workgroup -> merge-path block (XCD placement), -1: none
@@ -1079,7 +1082,7 @@ __global__ void k_bget(BDev d, int lpi, int which, double *ox, double *oy) {
     const long long t = L.t;
     const bool sol_avg = L.conv_which == 1;
     if (i < L.n) {
-        const int j = L.col_off + (int)i;
+        const int j = d.cinv ? d.cinv[L.col_off + (int)i] : L.col_off + (int)i;
         double v;
         if (which == 0) v = d.x[j];
         else if (which == 1) v = t ? d.sx[j] / (double)t : d.x[j];
@@ -1117,6 +1120,7 @@ struct Tape {
     long long *evT;         // window length of that restart
     double *sx, *sy;        // recomputed iterates of one window: [(P+1)][N], [(P+1)][M]
     double *xh, *yh, *sxh, *syh, *vh, *uh;
+    double *gc;             // dL/dc in the internal column order (permuted columns only)
     int nwin, P;
     long long K;
 };
@@ -1278,6 +1282,7 @@ struct BLayout {
     size_t total;
     size_t o_lp, o_err, o_rp, o_ci, o_v, o_c, o_b, o_l, o_u, o_kind, o_trp, o_tci, o_perm, o_tv;
     size_t o_xpA, o_xpT;
+    size_t o_cperm, o_cinv;
     size_t o_cursor, o_long, o_brA, o_brT, o_lprow, o_lpcol, o_tau, o_sig, o_blklp, o_blkfirst, o_vn, o_vm;
     size_t o_part, o_log, o_hcnt, o_hD, o_hA, o_tpart, o_ccount, o_coff, o_ckey, o_ca, o_cd;
     int M, N, NNZ, nblk, nblkA, nblkT;
@@ -1325,6 +1330,8 @@ static bool b_layout(int count, const int64_t *m, const int64_t *n, const int64_
     put(L->o_tci, sizeof(int) * Z1);
     put(L->o_perm, sizeof(int) * Z1);
     put(L->o_tv, sizeof(double) * Z1);
+    put(L->o_cperm, sizeof(int) * N1);
+    put(L->o_cinv, sizeof(int) * N1);
     put(L->o_cursor, sizeof(int) * N1);
     put(L->o_long, sizeof(int) * N1);
     put(L->o_brA, sizeof(int) * ((size_t)L->nblkA + 1));
@@ -1388,6 +1395,67 @@ static int place_blocks(const std::vector<int> &br, const std::vector<int> &off,
     for (int x = 0; x < kXcds; ++x)
         for (size_t j = 0; j < lists[x].size(); ++j) xp[j * kXcds + x] = lists[x][j];
     return (int)xp.size();
+}
+
+// Column order of the concatenated matrix, inside each LP's own column
+// range: columns by entry count, largest first, equal counts by the row of
+// their first entry (two stable counting passes per LP), as for a single
+// LP.  Rows next to each other then gather columns next to each other in
+// A x and rows of A' next to each other gather nearby y in A'y.  The
+// block-diagonal structure and every LP's column range stay as they are.
+// Runs after the concatenation and before the transpose, whose scratch
+// (trp, cursor, tci) and the not yet initialised x0, sx, xbar it borrows.
+static int b_order_columns(BDev &d, const std::vector<BLP> &hl, int *cperm, int *cinv,
+                           hipStream_t s) {
+    d.cperm = d.cinv = nullptr;
+    const int N = d.N, M = d.M;
+    if (N < 2 || d.NNZ == 0 || M == 0) return PDHG_OK;
+    launch_col_counts(d.ci, d.NNZ, N, d.trp, s);
+    launch_first_rows(d.rp, d.ci, M, N, d.NNZ, d.cursor, s);
+    std::vector<int> cnt((size_t)N + 1), first((size_t)N);
+    if (hipMemcpyAsync(cnt.data(), d.trp, sizeof(int) * ((size_t)N + 1), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(first.data(), d.cursor, sizeof(int) * (size_t)N, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return PDHG_E_HIP;
+    std::vector<int> order((size_t)N), inv((size_t)N), by_first, fstart, start;
+    bool ident = true;
+    for (const BLP &L : hl) {
+        const int co = L.col_off, n = L.n, ro = L.row_off, m = L.m;
+        // key of a column: its first row inside the LP, m when it is empty
+        auto key = [&](int j) { return first[(size_t)co + j] >= M ? m : first[(size_t)co + j] - ro; };
+        by_first.assign((size_t)n, 0);
+        fstart.assign((size_t)m + 2, 0);
+        for (int j = 0; j < n; ++j) fstart[(size_t)key(j) + 1] += 1;
+        for (int r = 0; r <= m; ++r) fstart[(size_t)r + 1] += fstart[r];
+        for (int j = 0; j < n; ++j) by_first[(size_t)fstart[(size_t)key(j)]++] = j;
+        int cmax = 0;
+        for (int j = 0; j < n; ++j) cmax = cnt[(size_t)co + j + 1] > cmax ? cnt[(size_t)co + j + 1] : cmax;
+        start.assign((size_t)cmax + 2, 0);
+        for (int j = 0; j < n; ++j) start[(size_t)(cmax - cnt[(size_t)co + j + 1]) + 1] += 1;
+        for (int k = 0; k <= cmax; ++k) start[(size_t)k + 1] += start[k];
+        for (int t = 0; t < n; ++t) {
+            const int j = by_first[(size_t)t];
+            const int q = start[(size_t)(cmax - cnt[(size_t)co + j + 1])]++;
+            order[(size_t)co + q] = co + j;
+            inv[(size_t)co + j] = co + q;
+            ident &= (q == j);
+        }
+    }
+    if (ident) return PDHG_OK;
+    if (hipMemcpyAsync(cperm, order.data(), sizeof(int) * (size_t)N, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(cinv, inv.data(), sizeof(int) * (size_t)N, hipMemcpyHostToDevice, s) != hipSuccess)
+        return PDHG_E_HIP;
+    launch_permute_cols(d.ci, d.NNZ, cinv, d.tci, d.c, d.l, d.u, cperm, N, d.x0, d.sx, d.xbar, s);
+    const size_t nb = sizeof(double) * (size_t)N;
+    if (hipMemcpyAsync(d.ci, d.tci, sizeof(int) * (size_t)d.NNZ, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(d.c, d.x0, nb, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(d.l, d.sx, nb, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(d.u, d.xbar, nb, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)  // the host vectors above leave scope
+        return PDHG_E_HIP;
+    d.cperm = cperm;
+    d.cinv = cinv;
+    return hipGetLastError() == hipSuccess ? PDHG_OK : PDHG_E_HIP;
 }
 
 }  // namespace pdhg
@@ -1609,6 +1677,8 @@ int pdhg_batch_create(int32_t count, const pdhg_lp *lps, const pdhg_params *prm,
             nz_off += zs[i];
         }
         hipLaunchKernelGGL(k_bclose_rp, dim3(1), dim3(1), 0, s, d);
+        if ((rc = b_order_columns(d, hl, (int *)(ws + L.o_cperm), (int *)(ws + L.o_cinv), s)) != PDHG_OK)
+            break;
         // explicit A' of the block-diagonal matrix and the SpMV row splits
         Dev td;
         memset(&td, 0, sizeof(td));
@@ -1892,6 +1962,7 @@ static bool tape_carve(const pdhg_batch_t *h, int64_t K, char *base, Tape *t, si
     const size_t oxh = put(sizeof(double) * N), oyh = put(sizeof(double) * M);
     const size_t osxh = put(sizeof(double) * N), osyh = put(sizeof(double) * M);
     const size_t ovh = put(sizeof(double) * M), ouh = put(sizeof(double) * N);
+    const size_t ogc = d.cinv ? put(sizeof(double) * N) : 0;
     *total = o;
     if (base && t) {
         t->cx = (double *)(base + ocx);
@@ -1907,6 +1978,7 @@ static bool tape_carve(const pdhg_batch_t *h, int64_t K, char *base, Tape *t, si
         t->syh = (double *)(base + osyh);
         t->vh = (double *)(base + ovh);
         t->uh = (double *)(base + ouh);
+        t->gc = d.cinv ? (double *)(base + ogc) : nullptr;
         t->nwin = (int)nwin;
         t->P = (int)P;
         t->K = K;
@@ -1927,7 +1999,8 @@ int pdhg_batch_set_data(pdhg_batch_t *h, const double *c, const double *b, const
     if (!h || !c || (h->d.M > 0 && !b) || (h->d.NNZ > 0 && !vals)) return PDHG_E_INVALID;
     const BDev &d = h->d;
     hipStream_t s = h->stream;
-    BCK(hipMemcpyAsync(d.c, c, sizeof(double) * (size_t)d.N, hipMemcpyDeviceToDevice, s));
+    if (d.cperm) launch_gather(c, d.cperm, d.N, d.c, s);
+    else BCK(hipMemcpyAsync(d.c, c, sizeof(double) * (size_t)d.N, hipMemcpyDeviceToDevice, s));
     if (d.M > 0) BCK(hipMemcpyAsync(d.b, b, sizeof(double) * (size_t)d.M, hipMemcpyDeviceToDevice, s));
     if (d.NNZ > 0) {
         BCK(hipMemcpyAsync(d.v, vals, sizeof(double) * (size_t)d.NNZ, hipMemcpyDeviceToDevice, s));
@@ -1972,7 +2045,8 @@ int pdhg_batch_unrolled_forward(pdhg_batch_t *h, int64_t K, void *tape, size_t t
         int rc = b_last_error();
         if (rc) return rc;
     }
-    if (xK) BCK(hipMemcpyAsync(xK, d.x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    if (xK && d.cinv) launch_gather(d.x, d.cinv, d.N, xK, s);
+    else if (xK) BCK(hipMemcpyAsync(xK, d.x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
     return b_last_error();
 }
 
@@ -1987,9 +2061,13 @@ int pdhg_batch_unrolled_backward(pdhg_batch_t *h, int64_t K, void *tape, size_t 
     hipStream_t s = h->stream;
     const size_t N = (size_t)d.N, M = (size_t)d.M;
     const long long NM = (long long)d.N + d.M;
-    BCK(hipMemcpyAsync(t.xh, dLdx, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    // dL/dx in, dL/dc out in the caller's column order; the sweep runs in
+    // the internal one (gA follows the entries, which keep their places)
+    if (d.cperm) launch_gather(dLdx, d.cperm, d.N, t.xh, s);
+    else BCK(hipMemcpyAsync(t.xh, dLdx, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    double *gcw = d.cinv ? t.gc : gc;
     hipLaunchKernelGGL(k_fill_d, dim3(div_up(d.N, kWG)), dim3(kWG), 0, s, t.sxh, (long long)d.N, 0.0);
-    hipLaunchKernelGGL(k_fill_d, dim3(div_up(d.N, kWG)), dim3(kWG), 0, s, gc, (long long)d.N, 0.0);
+    hipLaunchKernelGGL(k_fill_d, dim3(div_up(d.N, kWG)), dim3(kWG), 0, s, gcw, (long long)d.N, 0.0);
     if (M) {
         hipLaunchKernelGGL(k_fill_d, dim3(div_up(d.M, kWG)), dim3(kWG), 0, s, t.yh, (long long)d.M, 0.0);
         hipLaunchKernelGGL(k_fill_d, dim3(div_up(d.M, kWG)), dim3(kWG), 0, s, t.syh, (long long)d.M, 0.0);
@@ -2021,7 +2099,7 @@ int pdhg_batch_unrolled_backward(pdhg_batch_t *h, int64_t K, void *tape, size_t 
             if (M)
                 hipLaunchKernelGGL(k_adj_dual, dim3(div_up(d.M, kWG)), dim3(kWG), 0, s, d, yt,
                                    t.yh, t.syh, t.vh, gb);
-            EpiAdjPrimal ep{xt, d.l, d.u, t.xh, t.sxh, t.uh, gc, d.lp_col, d.lp};
+            EpiAdjPrimal ep{xt, d.l, d.u, t.xh, t.sxh, t.uh, gcw, d.lp_col, d.lp};
             hipLaunchKernelGGL(k_spmv<EpiAdjPrimal>, dim3(d.nblkT), dim3(kWG), 0, s, d.trp, d.tci,
                                d.tv, t.vh, d.brT, ep, (const int *)nullptr);
             if (M)
@@ -2031,6 +2109,7 @@ int pdhg_batch_unrolled_backward(pdhg_batch_t *h, int64_t K, void *tape, size_t 
         int rc = b_last_error();
         if (rc) return rc;
     }
+    if (d.cinv) launch_gather(t.gc, d.cinv, d.N, gc, s);
     return b_last_error();
 }
 
