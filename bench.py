@@ -55,6 +55,20 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def halfstep_bytes(m, n, nnz):
+    """Algorithmic bytes of one primal and one dual half-step, from the
+    byte model of the path.  Both stream their matrix (8-byte value and
+    4-byte index per entry) and row pointers (4 bytes per row) and read the
+    gathered vector once (8 bytes per element).  Primal, per column: x, c,
+    l, u and S_x reads, x and S_x writes (56).  Dual, per row: y, b, q,
+    S_y and row-kind reads, y, S_y and q writes (57).  The kernels move
+    less than this where they can: a class byte per column instead of l and
+    u when the bounds take at most four pairs, and the running sums read and
+    written every other iteration.  The measured traffic is reported next
+    to it."""
+    return 12 * nnz + 60 * n + 8 * m, 12 * nnz + 61 * m + 8 * n
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in ("pdhg_kernels.hip", "pdhg_device.h", "pdhg_internal.h"):
@@ -478,8 +492,7 @@ def main():
 
     ms_p, ms_d = s.time_iterations(args.kernel_iters)
     m, n, nnz = lp.m, lp.n, lp.nnz
-    bytes_p = 12 * nnz + 60 * n + 8 * m
-    bytes_d = 12 * nnz + 61 * m + 8 * n
+    bytes_p, bytes_d = halfstep_bytes(m, n, nnz)
     if ms_p >= ms_d:
         kname, kb, kms = "primal", bytes_p, ms_p
     else:

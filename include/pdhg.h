@@ -146,7 +146,9 @@ typedef struct pdhg_info {
                                  0: one launch per product and check step.
                                  Environment: PDHG_TINY=0 at pdhg_create turns
                                  the path off, PDHG_TINY=lds asks for 2 */
-    int32_t reserved;
+    int32_t bound_classes;    /* distinct (l, u) pairs the primal update reads
+                                 as a one-byte class per column (1..4), or 0:
+                                 it reads l and u */
 } pdhg_info;
 
 /* One check, in the order the library performs it (14 doubles):

@@ -64,7 +64,7 @@ class Info(C.Structure):
                 ("sigma_max", C.c_double), ("k", C.c_int64), ("t", C.c_int64),
                 ("restarts", C.c_int64), ("rho_prev", C.c_double),
                 ("checks", C.c_int64), ("power_iters_used", C.c_int64),
-                ("one_workgroup", C.c_int32), ("reserved", C.c_int32)]
+                ("one_workgroup", C.c_int32), ("bound_classes", C.c_int32)]
 
 
 class Tune(C.Structure):

@@ -153,6 +153,8 @@ bool make_layout(int64_t m, int64_t n, int64_t nnz, Layout *L) {
     o += al(sizeof(double) * n1);
     L->o_u2 = o;
     o += al(sizeof(double) * n1);
+    L->o_bcls = o;
+    o += al(n1);
     L->o_part = o;
     o += al(sizeof(double) * kRedBlocks * kKktSums);
     L->o_log = o;
@@ -213,8 +215,9 @@ static void enqueue_iters(pdhg_t *h, int64_t iters, hipStream_t s) {
         if (h->prm.method == PDHG_METHOD_EGM) {
             launch_egm(h->d, h->tau, h->sigma, -1, s);
         } else {
-            launch_primal(h->d, h->tau, s);
-            launch_dual(h->d, h->sigma, s);
+            const int sm = sum_mode(i, iters);
+            launch_primal(h->d, h->tau, sm, s);
+            launch_dual(h->d, h->sigma, sm, s);
         }
     }
 }
@@ -369,6 +372,45 @@ static int order_columns(Dev &d, const Layout &L, char *ws, hipStream_t s) {
     return last_error();
 }
 
+// Bound classes: when the columns' (l, u) pairs (compared bit for bit)
+// take at most kBoundClasses distinct values, each column gets a one-byte
+// class and the primal update reads that byte instead of 16 bytes of bounds.
+// LPs with more distinct pairs keep reading l and u.
+static int bound_classes(Dev &d, const Layout &L, char *ws, hipStream_t s) {
+    d.bcls = nullptr;
+    d.nbcls = 0;
+    const int n = d.n;
+    std::vector<unsigned long long> lo((size_t)n), hi((size_t)n);
+    CK(hipMemcpyAsync(lo.data(), d.l, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, s));
+    CK(hipMemcpyAsync(hi.data(), d.u, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    std::vector<unsigned char> cls((size_t)n);
+    unsigned long long kl[kBoundClasses], ku[kBoundClasses];
+    int nc = 0;
+    for (int j = 0; j < n; ++j) {
+        int k = 0;
+        while (k < nc && (kl[k] != lo[(size_t)j] || ku[k] != hi[(size_t)j])) ++k;
+        if (k == nc) {
+            if (nc == kBoundClasses) return PDHG_OK;
+            kl[nc] = lo[(size_t)j];
+            ku[nc] = hi[(size_t)j];
+            ++nc;
+        }
+        cls[(size_t)j] = (unsigned char)k;
+    }
+    for (int k = 0; k < kBoundClasses; ++k) {
+        const int q = k < nc ? k : 0;
+        memcpy(&d.blo[k], &kl[q], sizeof(double));
+        memcpy(&d.bhi[k], &ku[q], sizeof(double));
+    }
+    unsigned char *dev = (unsigned char *)(ws + L.o_bcls);
+    CK(hipMemcpyAsync(dev, cls.data(), (size_t)n, hipMemcpyHostToDevice, s));
+    CK(hipStreamSynchronize(s));  // the host vector above leaves scope
+    d.bcls = dev;
+    d.nbcls = nc;
+    return PDHG_OK;
+}
+
 int pdhg_create(const pdhg_lp *lp, const pdhg_params *prm_in, void *workspace,
                 size_t workspace_bytes, void *stream, pdhg_t **out) {
     if (!out) return PDHG_E_INVALID;
@@ -479,6 +521,7 @@ int pdhg_create(const pdhg_lp *lp, const pdhg_params *prm_in, void *workspace,
             break;
         }
         if ((rc = order_columns(d, L, ws, s)) != PDHG_OK) break;
+        if ((rc = bound_classes(d, L, ws, s)) != PDHG_OK) break;
         launch_rowsplit(d.rp, d.m, d.nnz, d.nblkA, d.brA, s);
         launch_transpose(d, s);
         launch_rowsplit(d.trp, d.n, d.nnz, d.nblkT, d.brT, s);
@@ -1170,7 +1213,7 @@ int pdhg_get_info(pdhg_t *h, pdhg_info *out) {
     if (h->tiny.ok && h->prm.method == PDHG_METHOD_PDHG &&
         h->prm.restart_mode != PDHG_RESTART_FIXED)
         out->one_workgroup = h->tiny.reg ? 1 : 2;
-    out->reserved = 0;
+    out->bound_classes = h->d.nbcls;
     return PDHG_OK;
 }
 
@@ -1253,8 +1296,8 @@ int pdhg_time_iterations(pdhg_t *h, int64_t iters, double *ms_primal, double *ms
         for (int64_t i = 0; i < iters && rc == PDHG_OK; ++i) {
             for (int p = 0; p < nseg && rc == PDHG_OK; ++p) {
                 if (egm) launch_egm(h->d, h->tau, h->sigma, p, s);
-                else if (p == 0) launch_primal(h->d, h->tau, s);
-                else launch_dual(h->d, h->sigma, s);
+                else if (p == 0) launch_primal(h->d, h->tau, sum_mode(i, iters), s);
+                else launch_dual(h->d, h->sigma, sum_mode(i, iters), s);
                 if (hipEventRecord(ev[nseg * i + p + 1], s) != hipSuccess) rc = PDHG_E_HIP;
             }
         }

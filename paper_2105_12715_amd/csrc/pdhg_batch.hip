@@ -1912,7 +1912,7 @@ int pdhg_batch_get_info(pdhg_batch_t *h, int32_t index, pdhg_info *out) {
     out->checks = L.checks;
     out->power_iters_used = h->pw_used.empty() ? 0 : h->pw_used[index];
     out->one_workgroup = 0;
-    out->reserved = 0;
+    out->bound_classes = 0;
     return PDHG_OK;
 }
 

@@ -324,20 +324,34 @@ __device__ void choose_bucket(TRState &ts, const unsigned int *cnt, const double
 // ---------------------------------------------------------------------
 // PDHG half-step epilogues
 // ---------------------------------------------------------------------
-// x+ = proj_[l,u](x - tau (c - A'y)); sx += x+   (eq. PDHG-update, primal)
+// x+ = proj_[l,u](x - tau (c - A'y)); sx += x+   (eq. PDHG-update, primal;
+// the running sum of Algorithm 1 in pairs of iterations, see sum_mode)
 struct EpiPrimal {
     const double *__restrict__ c, *__restrict__ l, *__restrict__ u;
     double *__restrict__ x, *__restrict__ sx;
     double tau;
     DevState *st;
+    const unsigned char *__restrict__ cls;  // bound class of each column, or null
+    double blo[kBoundClasses], bhi[kBoundClasses];
+    int smode;  // running sum: 0 add x+, 1 nothing yet, 2 add the previous x, then x+
     __device__ __forceinline__ void operator()(int j, double aty) const {
         double g = c[j] - aty;
-        double xn = x[j] - tau * g;
-        const double lo = l[j], hi = u[j];
+        const double xo = x[j];
+        double xn = xo - tau * g;
+        double lo, hi;
+        if (cls) {
+            const int k = cls[j];
+            lo = (k & 2) ? ((k & 1) ? blo[3] : blo[2]) : ((k & 1) ? blo[1] : blo[0]);
+            hi = (k & 2) ? ((k & 1) ? bhi[3] : bhi[2]) : ((k & 1) ? bhi[1] : bhi[0]);
+        } else {
+            lo = l[j];
+            hi = u[j];
+        }
         if (xn < lo) xn = lo;
         if (xn > hi) xn = hi;
         x[j] = xn;
-        sx[j] += xn;
+        if (smode == 0) sx[j] += xn;
+        else if (smode == 2) sx[j] = (sx[j] + xo) + xn;
         if (j == 0) {  // iteration counters of Algorithm 1
             st->k += 1;
             st->t += 1;
@@ -345,17 +359,21 @@ struct EpiPrimal {
     }
 };
 
-// y+ = proj_Y(y + sigma (b - (2 A x+ - A x))); sy += y+; q = A x+
+// y+ = proj_Y(y + sigma (b - (2 A x+ - A x))); sy += y+ (in pairs as for
+// x); q = A x+
 struct EpiDual {
     const double *__restrict__ b;
     const signed char *__restrict__ kind;
     double *__restrict__ y, *__restrict__ sy, *__restrict__ q;
     double sigma;
+    int smode;
     __device__ __forceinline__ void operator()(int i, double ax) const {
-        double yv = y[i] + sigma * (b[i] - (2.0 * ax - q[i]));
+        const double yo = y[i];
+        double yv = yo + sigma * (b[i] - (2.0 * ax - q[i]));
         if (kind && kind[i] && yv < 0.0) yv = 0.0;
         y[i] = yv;
-        sy[i] += yv;
+        if (smode == 0) sy[i] += yv;
+        else if (smode == 2) sy[i] = (sy[i] + yo) + yv;
         q[i] = ax;
     }
 };

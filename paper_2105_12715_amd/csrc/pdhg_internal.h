@@ -22,6 +22,7 @@ constexpr int kBuckets = 2048;       // radix buckets of the multiplier search
 constexpr int kTrSlots = 2;          // trust-region evaluations per check
 constexpr int kLogCap = 4096;        // check records kept on the device
 constexpr int kRec = 14;             // doubles per check record
+constexpr int kBoundClasses = 4;     // distinct (l, u) pairs held as a class byte
 
 // KKT partial-sum slots
 enum {
@@ -135,6 +136,13 @@ struct Dev {
     int permuted;              // 0: the caller's order is already sorted
     const int *cperm;          // [n] internal column q -> caller's column
     const int *cinv;           // [n] caller's column j -> internal column
+    // Bound classes: when the columns' (l, u) pairs take at most
+    // kBoundClasses distinct values, bcls[j] names column j's pair in
+    // blo/bhi and the primal update reads that byte instead of l and u
+    // (which stay for the checks).  Null otherwise.
+    const unsigned char *bcls;
+    double blo[kBoundClasses], bhi[kBoundClasses];
+    int nbcls;                 // distinct pairs in use (0 with bcls null)
 };
 
 // Column slabs: each slab's slice of the gathered vector is meant to fit
@@ -190,7 +198,7 @@ struct Layout {
     size_t o_brA, o_brT, o_vec_n[8], o_vec_m[8], o_part, o_log;
     size_t o_slab[2][6];       // srp, sci, sv, sbr, smeta, spart of slA, slT
     size_t o_xt, o_yt;
-    size_t o_ci2, o_cperm, o_cinv, o_c2, o_l2, o_u2;
+    size_t o_ci2, o_cperm, o_cinv, o_c2, o_l2, o_u2, o_bcls;
     size_t o_tr[kTrSlots];
 };
 bool make_layout(int64_t m, int64_t n, int64_t nnz, Layout *L);
@@ -230,8 +238,19 @@ void launch_transpose_out(const Dev &d, int *orp, int *oci, double *ov, int *ope
                           hipStream_t s);
 
 // iteration
-void launch_primal(const Dev &d, double tau, hipStream_t s);
-void launch_dual(const Dev &d, double sigma, hipStream_t s);
+// Half-steps of eq. PDHG-update with the running sums of Algorithm 1.
+// smode (sum_mode below): 0 adds the new iterate to S, 1 leaves S for the
+// next iteration, 2 adds the previous iterate and then the new one.
+void launch_primal(const Dev &d, double tau, int smode, hipStream_t s);
+void launch_dual(const Dev &d, double sigma, int smode, hipStream_t s);
+// How iteration i of a run of `iters` iterations updates the running sums:
+// in pairs, so S is read and written every other iteration; a run of odd
+// length ends with a single addition.  Every run leaves S complete, and
+// (S + x_i) + x_{i+1} rounds exactly as two additions one after the other.
+inline int sum_mode(int64_t i, int64_t iters) {
+    if ((i & 1) == 0) return i + 1 < iters ? 1 : 0;
+    return 2;
+}
 // one extragradient iteration (part < 0), or one of its four products
 // (0: target x~, 1: target y~, 2: x+, 3: y+), for timing
 void launch_egm(const Dev &d, double tau, double sigma, int part, hipStream_t s);

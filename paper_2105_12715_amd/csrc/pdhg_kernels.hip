@@ -203,12 +203,17 @@ static void product_T(const Dev &d, const double *in, const Epi &e, const int *s
                        d.brT, e, skip);
 }
 
-void launch_primal(const Dev &d, double tau, hipStream_t s) {
-    product_T(d, d.y, EpiPrimal{d.c, d.l, d.u, d.x, d.sx, tau, d.st}, &d.st->done, s);
+void launch_primal(const Dev &d, double tau, int smode, hipStream_t s) {
+    EpiPrimal e{d.c, d.l, d.u, d.x, d.sx, tau, d.st, d.bcls, {}, {}, smode};
+    for (int k = 0; k < kBoundClasses; ++k) {
+        e.blo[k] = d.blo[k];
+        e.bhi[k] = d.bhi[k];
+    }
+    product_T(d, d.y, e, &d.st->done, s);
 }
 
-void launch_dual(const Dev &d, double sigma, hipStream_t s) {
-    product_A(d, d.x, EpiDual{d.b, d.kind, d.y, d.sy, d.q, sigma}, &d.st->done, s);
+void launch_dual(const Dev &d, double sigma, int smode, hipStream_t s) {
+    product_A(d, d.x, EpiDual{d.b, d.kind, d.y, d.sy, d.q, sigma, smode}, &d.st->done, s);
 }
 
 void launch_egm(const Dev &d, double tau, double sigma, int part, hipStream_t s) {

@@ -238,6 +238,61 @@ def test_iterates_with_restarts_first_1000(lib, name, mode):
     assert lo[:, 9].sum() >= 2
 
 
+_PAIRS5 = [(0.0, 1.0), (0.0, np.inf), (-np.inf, np.inf), (-1.0, 1.0), (0.0, 10.0)]
+
+
+def _with_bound_pairs(k, seed=41):
+    """An LP too large for the one-workgroup path whose columns take k
+    distinct (l, u) pairs."""
+    import dataclasses
+    lp = lpgen.column_count_lp(13, 600, 1300, per_col=5, bounds="box01", ge_frac=0.5)
+    pick = np.random.default_rng(seed).integers(0, k, size=lp.n)
+    pick[:k] = np.arange(k)
+    l = np.array([_PAIRS5[i][0] for i in pick])
+    u = np.array([_PAIRS5[i][1] for i in pick])
+    return dataclasses.replace(lp, l=l, u=u)
+
+
+def test_bound_classes_in_use(lib):
+    """Up to four distinct (l, u) pairs are read as a class byte per column;
+    with more the primal update reads l and u."""
+    want = {"mixed_inf": 0, "powerlaw": 2, "medium20kx50k": 2}
+    for name, k in want.items():
+        assert lib.Solver(get_case(name), eta=0.1).info()["bound_classes"] == k, name
+    for k in (1, 3, 4, 5):
+        got = lib.Solver(_with_bound_pairs(k), eta=0.1).info()["bound_classes"]
+        assert got == (k if k <= 4 else 0), k
+
+
+@pytest.mark.parametrize("k", [4, 5])
+@pytest.mark.parametrize("period", [7, 30])
+def test_bound_classes_and_paired_sums(lib, k, period):
+    """Runs of odd and even length (the running sums are updated in pairs
+    of iterations, a run of odd length ends with a single addition) and an
+    odd check period, with and without bound classes: iterates, averages
+    and check records as the oracle's."""
+    lp = _with_bound_pairs(k)
+    _say("bound classes", k, "period", period)
+    o, s = _pair(lp, oracle.MODE_ADAPTIVE, check_period=period)
+    assert s.info()["one_workgroup"] == 0
+    done = 0
+    for kk in [1, 2, 5, 6, 13, 14, 40, 77]:
+        o.step(kk - done)
+        s.step(kk - done)
+        done = kk
+        _compare_points(o, s)
+    for kk in [100, 157, 400, 1000]:
+        o.solve(kk - done, 0.0)
+        s.solve(kk - done, 0.0)
+        done = kk
+        _compare_points(o, s)
+    lo, lg = o.log(), s.check_log()
+    assert lo.shape == lg.shape and lo.shape[0] >= 10
+    np.testing.assert_array_equal(lg[:, [0, 1, 2, 9, 10, 11]], lo[:, [0, 1, 2, 9, 10, 11]])
+    for col in (3, 4, 5, 6, 7, 8, 12):
+        np.testing.assert_allclose(lg[:, col], lo[:, col], rtol=1e-9, atol=1e-300)
+
+
 def test_fixed_length_restarts(lib):
     lp = get_case("ge_rows")
     _say("fixed restarts")
