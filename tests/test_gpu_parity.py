@@ -2,8 +2,8 @@
 the same seeded inputs.
 
 Tolerances: iterates match to a relative 1e-10 (norm of the difference
-over the norm of the oracle's iterate) over the first 1000 iterations, the
-bar the spec workload sets; scalars that are sums of many rounded
+over the norm of the oracle's iterate) over the first 1000 iterations;
+scalars that are sums of many rounded
 terms (KKT parts, rho) match to 1e-9 relative; integer work (transpose,
 restart decisions, iteration counts) matches exactly.
 """
