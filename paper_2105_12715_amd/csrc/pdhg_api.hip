@@ -124,10 +124,10 @@ bool make_layout(int64_t m, int64_t n, int64_t nnz, Layout *L) {
     L->o_long = o;
     o += al(sizeof(int) * n1);
     const int nbA = nblocks_for((int)m, (int)nnz), nbT = nblocks_for((int)n, (int)nnz);
-    L->o_brA = o;
-    o += al(sizeof(int) * ((size_t)nbA + 1));
+    L->o_brA = o;  // block tables: row starts, then entry starts (k_rowsplit)
+    o += al(sizeof(int) * 2 * ((size_t)nbA + 1));
     L->o_brT = o;
-    o += al(sizeof(int) * ((size_t)nbT + 1));
+    o += al(sizeof(int) * 2 * ((size_t)nbT + 1));
     for (int k = 0; k < 8; ++k) {
         L->o_vec_n[k] = o;
         o += al(sizeof(double) * n1);
@@ -172,7 +172,7 @@ bool make_layout(int64_t m, int64_t n, int64_t nnz, Layout *L) {
         const size_t r1 = (size_t)(rows_of[t] > 0 ? rows_of[t] : 1);
         const int nb = t == 0 ? nbA : nbT;
         const size_t sz[6] = {sizeof(int) * Ss * (r1 + 1), sizeof(int) * zS, sizeof(double) * zS,
-                              sizeof(int) * Ss * ((size_t)nb + 1), sizeof(long long) * 4 * Ss,
+                              sizeof(int) * Ss * 2 * ((size_t)nb + 1), sizeof(long long) * 4 * Ss,
                               sizeof(double) * (S > 1 ? r1 : 0)};
         for (int k = 0; k < 6; ++k) {
             L->o_slab[t][k] = o;
@@ -289,11 +289,11 @@ static int build_slabs(Slabs &sb, const int *rp, const int *ci, const double *v,
         meta[4 * q + 2] = boff;
         meta[4 * q + 3] = nb;
         eoff += cnt[q];
-        boff += nb + 1;
+        boff += 2 * (nb + 1);
         if (nb > nbmax) nbmax = nb;
     }
     // every entry lands in exactly one slab; the block tables fit their region
-    if (eoff != nnz || boff > (long long)sb.S * (nblk + 1)) return PDHG_E_INVALID;
+    if (eoff != nnz || boff > (long long)sb.S * 2 * (nblk + 1)) return PDHG_E_INVALID;
     CK(hipMemcpyAsync(sb.smeta, meta, sizeof(long long) * 4 * sb.S, hipMemcpyHostToDevice, s));
     CK(hipStreamSynchronize(s));
     sb.nbmax = nbmax;

@@ -103,7 +103,7 @@ template <class Epi>
 __global__ __launch_bounds__(kWG) void k_bspmv(const int *__restrict__ rp, const int *__restrict__ ci,
                                                const double *__restrict__ v,
                                                const double *__restrict__ xin,
-                                               const int *__restrict__ br, Epi epi,
+                                               const int *__restrict__ br, int nblk, Epi epi,
                                                const int *__restrict__ lp_of, const BLP *lps,
                                                int gate_kind, const int *__restrict__ xp) {
     __shared__ SpmvShared lds;
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kWG) void k_bspmv(const int *__restrict__ rp, const
         const BLP &L = lps[a];
         if (gate_kind == 0 ? L.done : L.pw_done) return;
     }
-    spmv_rows(rp, ci, v, xin, r0, r1, epi, lds);
+    spmv_rows(rp, ci, v, xin, r0, r1, br[nblk + 1 + c], br[nblk + 2 + c], epi, lds);
 }
 
 struct EpiPrimalB {
@@ -151,22 +151,22 @@ struct EpiDualB {
 static void bspmv_A(const BDev &d, const double *in, double *out, int gate_kind, hipStream_t s) {
     EpiStore e{out};
     hipLaunchKernelGGL(k_bspmv<EpiStore>, dim3(d.nslotA), dim3(kWG), 0, s, d.rp, d.ci, d.v, in,
-                       d.brA, e, d.lp_row, d.lp, gate_kind, d.xpA);
+                       d.brA, d.nblkA, e, d.lp_row, d.lp, gate_kind, d.xpA);
 }
 
 static void bspmv_T(const BDev &d, const double *in, double *out, int gate_kind, hipStream_t s) {
     EpiStore e{out};
     hipLaunchKernelGGL(k_bspmv<EpiStore>, dim3(d.nslotT), dim3(kWG), 0, s, d.trp, d.tci, d.tv, in,
-                       d.brT, e, d.lp_col, d.lp, gate_kind, d.xpT);
+                       d.brT, d.nblkT, e, d.lp_col, d.lp, gate_kind, d.xpT);
 }
 
 static void b_iteration(const BDev &d, hipStream_t s) {
     EpiPrimalB ep{d.c, d.l, d.u, d.x, d.sx, d.tau_col};
     hipLaunchKernelGGL(k_bspmv<EpiPrimalB>, dim3(d.nslotT), dim3(kWG), 0, s, d.trp, d.tci, d.tv,
-                       d.y, d.brT, ep, d.lp_col, d.lp, 0, d.xpT);
+                       d.y, d.brT, d.nblkT, ep, d.lp_col, d.lp, 0, d.xpT);
     EpiDualB ed{d.b, d.kind, d.y, d.sy, d.q, d.sigma_row};
     hipLaunchKernelGGL(k_bspmv<EpiDualB>, dim3(d.nslotA), dim3(kWG), 0, s, d.rp, d.ci, d.v, d.x,
-                       d.brA, ed, d.lp_row, d.lp, 0, d.xpA);
+                       d.brA, d.nblkA, ed, d.lp_row, d.lp, 0, d.xpA);
 }
 
 // iteration counters of Algorithm 1 for the LPs still running (every LP
@@ -1334,8 +1334,8 @@ static bool b_layout(int count, const int64_t *m, const int64_t *n, const int64_
     put(L->o_cinv, sizeof(int) * N1);
     put(L->o_cursor, sizeof(int) * N1);
     put(L->o_long, sizeof(int) * N1);
-    put(L->o_brA, sizeof(int) * ((size_t)L->nblkA + 1));
-    put(L->o_brT, sizeof(int) * ((size_t)L->nblkT + 1));
+    put(L->o_brA, sizeof(int) * 2 * ((size_t)L->nblkA + 1));  // block tables (k_rowsplit)
+    put(L->o_brT, sizeof(int) * 2 * ((size_t)L->nblkT + 1));
     put(L->o_xpA, sizeof(int) * kXcds * ((size_t)L->nblkA + 1));
     put(L->o_xpT, sizeof(int) * kXcds * ((size_t)L->nblkT + 1));
     put(L->o_lprow, sizeof(int) * M1);
@@ -2101,7 +2101,7 @@ int pdhg_batch_unrolled_backward(pdhg_batch_t *h, int64_t K, void *tape, size_t 
                                    t.yh, t.syh, t.vh, gb);
             EpiAdjPrimal ep{xt, d.l, d.u, t.xh, t.sxh, t.uh, gcw, d.lp_col, d.lp};
             hipLaunchKernelGGL(k_spmv<EpiAdjPrimal>, dim3(d.nblkT), dim3(kWG), 0, s, d.trp, d.tci,
-                               d.tv, t.vh, d.brT, ep, (const int *)nullptr);
+                               d.tv, t.vh, d.brT, d.nblkT, ep, (const int *)nullptr);
             if (M)
                 hipLaunchKernelGGL(k_adj_rows, dim3(d.nblkA), dim3(kWG), 0, s, d, t.uh, xt, xp, yp,
                                    t.vh, t.yh, gA);

@@ -104,9 +104,10 @@ template <class Epi>
 __device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const int *__restrict__ ci,
                                           const double *__restrict__ v,
                                           const double *__restrict__ xin, int r0, int r1,
-                                          const Epi &epi, SpmvShared &sm) {
+                                          int p0, int p1, const Epi &epi, SpmvShared &sm) {
+    // rows [r0, r1) hold entries [p0, p1) (from the block table, see
+    // k_rowsplit)
     const int tid = threadIdx.x;
-    const int p0 = rp[r0], p1 = rp[r1];
     const int nb = p1 - p0;
     const int R = r1 - r0;  // <= kUnits: every row start takes one unit of the block
     if (nb <= kLdsProducts) {
@@ -184,13 +185,15 @@ __global__ __launch_bounds__(kWG) void k_spmv(const int *__restrict__ rp,
                                               const int *__restrict__ ci,
                                               const double *__restrict__ v,
                                               const double *__restrict__ xin,
-                                              const int *__restrict__ br, Epi epi,
+                                              const int *__restrict__ br, int nblk, Epi epi,
                                               const int *skip) {
-    if (skip && *skip) return;
     __shared__ SpmvShared lds;
-    const int r0 = br[blockIdx.x], r1 = br[blockIdx.x + 1];
-    if (r0 >= r1) return;
-    spmv_rows(rp, ci, v, xin, r0, r1, epi, lds);
+    // the gate and the block table are loaded together (one round trip)
+    const int b = blockIdx.x;
+    const int r0 = br[b], r1 = br[b + 1], p0 = br[nblk + 1 + b], p1 = br[nblk + 2 + b];
+    const int off = skip ? *skip : 0;
+    if (off || r0 >= r1) return;
+    spmv_rows(rp, ci, v, xin, r0, r1, p0, p1, epi, lds);
 }
 
 struct EpiStore {

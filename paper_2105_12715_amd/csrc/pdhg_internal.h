@@ -94,7 +94,7 @@ struct Slabs {
     int *srp;                  // [S][rows + 1] row starts within each slab
     int *sci;                  // [nnz] local column index
     double *sv;                // [nnz]
-    int *sbr;                  // block row starts of every slab
+    int *sbr;                  // block tables of every slab (k_rowsplit)
     long long *smeta;          // [S][4]: row-start offset, entry offset, block offset, blocks
     double *spart;             // [rows] running sum of the slabs done so far
 };
@@ -112,7 +112,7 @@ struct Dev {
     int *cursor;               // n, setup scratch
     int *long_rows;            // n, setup scratch
     // merge-path block row starts
-    int *brA, *brT;
+    int *brA, *brT;            // block tables: 2 (nblk + 1) ints (k_rowsplit)
     int nblkA, nblkT;
     // vectors
     double *x, *y, *x0, *y0, *sx, *sy, *q;

@@ -111,22 +111,26 @@ int nblocks_for(int rows, int nnz) {
     return nb < 1 ? 1 : nb;
 }
 
-// br[c] = first row i in [0, rows] with i + rp[i] >= c * kUnits; br[nblk] = rows.
+// Block table of a merge-path split, 2 (nblk + 1) ints: br[c] = first row
+// i in [0, rows] with i + rp[i] >= c * kUnits (br[nblk] = rows), and
+// br[nblk + 1 + c] = rp[br[c]], the block's first entry, so that a block
+// finds its rows and its entries in one round of loads.
 __global__ void k_rowsplit(const int *__restrict__ rp, int rows, int nblk, int *br) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c > nblk) return;
-    if (c == nblk) {
-        br[c] = rows;
-        return;
-    }
-    long long target = (long long)c * kUnits;
-    int lo = 0, hi = rows;
-    while (lo < hi) {
-        int mid = lo + ((hi - lo) >> 1);
-        if ((long long)mid + rp[mid] >= target) hi = mid;
-        else lo = mid + 1;
+    int lo = rows;
+    if (c < nblk) {
+        long long target = (long long)c * kUnits;
+        int hi = rows;
+        lo = 0;
+        while (lo < hi) {
+            int mid = lo + ((hi - lo) >> 1);
+            if ((long long)mid + rp[mid] >= target) hi = mid;
+            else lo = mid + 1;
+        }
     }
     br[c] = lo;
+    br[nblk + 1 + c] = rp[lo];
 }
 
 void launch_rowsplit(const int *rp, int rows, int nnz, int nblk, int *br, hipStream_t s) {
@@ -155,16 +159,17 @@ struct EpiSlabLast {
 template <class Epi>
 __global__ __launch_bounds__(kWG) void k_slab_one(Slabs sb, int sl, const double *__restrict__ xin,
                                                   Epi epi, const int *skip) {
-    if (skip && *skip) return;
     __shared__ SpmvShared lds;
+    // the gate and the slab's metadata are loaded together
     const long long *me = sb.smeta + 4 * sl;
-    const int b = blockIdx.x;
-    if (b >= (int)me[3]) return;
+    const int b = blockIdx.x, nb = (int)me[3];
+    const int off = skip ? *skip : 0;
+    if (off || b >= nb) return;
     const int *br = sb.sbr + me[2];
     const int r0 = br[b], r1 = br[b + 1];
     if (r0 >= r1) return;
-    spmv_rows(sb.srp + me[0], sb.sci + me[1], sb.sv + me[1], xin + (size_t)sl * sb.W, r0, r1, epi,
-              lds);
+    spmv_rows(sb.srp + me[0], sb.sci + me[1], sb.sv + me[1], xin + (size_t)sl * sb.W, r0, r1,
+              br[nb + 1 + b], br[nb + 2 + b], epi, lds);
 }
 
 // the slabs one after the other, the last with the epilogue fused
@@ -188,7 +193,7 @@ static void product_A(const Dev &d, const double *in, const Epi &e, const int *s
         return;
     }
     hipLaunchKernelGGL(k_spmv<Epi>, dim3(d.nblkA), dim3(kWG), 0, s, d.rp, d.ci, d.v, in, d.brA,
-                       e, skip);
+                       d.nblkA, e, skip);
 }
 
 // the same over the rows of A' (explicit transpose)
@@ -200,7 +205,7 @@ static void product_T(const Dev &d, const double *in, const Epi &e, const int *s
         return;
     }
     hipLaunchKernelGGL(k_spmv<Epi>, dim3(d.nblkT), dim3(kWG), 0, s, d.trp, d.tci, d.tv, in,
-                       d.brT, e, skip);
+                       d.brT, d.nblkT, e, skip);
 }
 
 void launch_primal(const Dev &d, double tau, int smode, hipStream_t s) {
