@@ -65,6 +65,11 @@ struct BDev {
     // column order inside each LP's column range (null: the caller's order)
     int *cperm;  // [N] internal column -> caller's column
     int *cinv;   // [N] caller's column -> internal column
+    // bound classes over the whole batch, as for a single LP (bcls null: the
+    // primal update reads l and u)
+    const unsigned char *bcls;
+    double blo[kBoundClasses], bhi[kBoundClasses];
+    int nbcls;
     int *brA, *brT;
     int nblkA, nblkT;
     int *xpA, *xpT;        // workgroup -> merge-path block (XCD placement), -1: none
@@ -119,18 +124,34 @@ __global__ __launch_bounds__(kWG) void k_bspmv(const int *__restrict__ rp, const
     spmv_rows(rp, ci, v, xin, r0, r1, br[nblk + 1 + c], br[nblk + 2 + c], epi, lds);
 }
 
+// The batch's half-step epilogues: the single-LP updates with per-element
+// step sizes; bounds as class bytes and the running sums in pairs of
+// iterations as there (smode, sum_mode)
 struct EpiPrimalB {
     const double *__restrict__ c, *__restrict__ l, *__restrict__ u;
     double *__restrict__ x, *__restrict__ sx;
     const double *__restrict__ tau;
+    const unsigned char *__restrict__ cls;
+    double blo[kBoundClasses], bhi[kBoundClasses];
+    int smode;
     __device__ __forceinline__ void operator()(int j, double aty) const {
         double g = c[j] - aty;
-        double xn = x[j] - tau[j] * g;  // tau = 0 leaves a converged LP's x as it is
-        const double lo = l[j], hi = u[j];
+        const double xo = x[j];
+        double xn = xo - tau[j] * g;  // tau = 0 leaves a converged LP's x as it is
+        double lo, hi;
+        if (cls) {
+            const int k = cls[j];
+            lo = (k & 2) ? ((k & 1) ? blo[3] : blo[2]) : ((k & 1) ? blo[1] : blo[0]);
+            hi = (k & 2) ? ((k & 1) ? bhi[3] : bhi[2]) : ((k & 1) ? bhi[1] : bhi[0]);
+        } else {
+            lo = l[j];
+            hi = u[j];
+        }
         if (xn < lo) xn = lo;
         if (xn > hi) xn = hi;
         x[j] = xn;
-        sx[j] += xn;
+        if (smode == 0) sx[j] += xn;
+        else if (smode == 2) sx[j] = (sx[j] + xo) + xn;
     }
 };
 
@@ -139,11 +160,14 @@ struct EpiDualB {
     const signed char *__restrict__ kind;
     double *__restrict__ y, *__restrict__ sy, *__restrict__ q;
     const double *__restrict__ sigma;
+    int smode;
     __device__ __forceinline__ void operator()(int i, double ax) const {
-        double yv = y[i] + sigma[i] * (b[i] - (2.0 * ax - q[i]));
+        const double yo = y[i];
+        double yv = yo + sigma[i] * (b[i] - (2.0 * ax - q[i]));
         if (kind[i] && yv < 0.0) yv = 0.0;
         y[i] = yv;
-        sy[i] += yv;
+        if (smode == 0) sy[i] += yv;
+        else if (smode == 2) sy[i] = (sy[i] + yo) + yv;
         q[i] = ax;
     }
 };
@@ -160,11 +184,15 @@ static void bspmv_T(const BDev &d, const double *in, double *out, int gate_kind,
                        d.brT, d.nblkT, e, d.lp_col, d.lp, gate_kind, d.xpT);
 }
 
-static void b_iteration(const BDev &d, hipStream_t s) {
-    EpiPrimalB ep{d.c, d.l, d.u, d.x, d.sx, d.tau_col};
+static void b_iteration(const BDev &d, int smode, hipStream_t s) {
+    EpiPrimalB ep{d.c, d.l, d.u, d.x, d.sx, d.tau_col, d.bcls, {}, {}, smode};
+    for (int k = 0; k < kBoundClasses; ++k) {
+        ep.blo[k] = d.blo[k];
+        ep.bhi[k] = d.bhi[k];
+    }
     hipLaunchKernelGGL(k_bspmv<EpiPrimalB>, dim3(d.nslotT), dim3(kWG), 0, s, d.trp, d.tci, d.tv,
                        d.y, d.brT, d.nblkT, ep, d.lp_col, d.lp, 0, d.xpT);
-    EpiDualB ed{d.b, d.kind, d.y, d.sy, d.q, d.sigma_row};
+    EpiDualB ed{d.b, d.kind, d.y, d.sy, d.q, d.sigma_row, smode};
     hipLaunchKernelGGL(k_bspmv<EpiDualB>, dim3(d.nslotA), dim3(kWG), 0, s, d.rp, d.ci, d.v, d.x,
                        d.brA, d.nblkA, ed, d.lp_row, d.lp, 0, d.xpA);
 }
@@ -182,7 +210,7 @@ __global__ void k_badvance(BDev d, int iters) {
 
 static void b_iterations(const BDev &d, long long iters, hipStream_t s) {
     if (iters <= 0) return;
-    for (long long i = 0; i < iters; ++i) b_iteration(d, s);
+    for (long long i = 0; i < iters; ++i) b_iteration(d, sum_mode(i, iters), s);
     hipLaunchKernelGGL(k_badvance, dim3(div_up(d.count, kWG)), dim3(kWG), 0, s, d, (int)iters);
 }
 
@@ -1282,7 +1310,7 @@ struct BLayout {
     size_t total;
     size_t o_lp, o_err, o_rp, o_ci, o_v, o_c, o_b, o_l, o_u, o_kind, o_trp, o_tci, o_perm, o_tv;
     size_t o_xpA, o_xpT;
-    size_t o_cperm, o_cinv;
+    size_t o_cperm, o_cinv, o_bcls;
     size_t o_cursor, o_long, o_brA, o_brT, o_lprow, o_lpcol, o_tau, o_sig, o_blklp, o_blkfirst, o_vn, o_vm;
     size_t o_part, o_log, o_hcnt, o_hD, o_hA, o_tpart, o_ccount, o_coff, o_ckey, o_ca, o_cd;
     int M, N, NNZ, nblk, nblkA, nblkT;
@@ -1332,6 +1360,7 @@ static bool b_layout(int count, const int64_t *m, const int64_t *n, const int64_
     put(L->o_tv, sizeof(double) * Z1);
     put(L->o_cperm, sizeof(int) * N1);
     put(L->o_cinv, sizeof(int) * N1);
+    put(L->o_bcls, N1);
     put(L->o_cursor, sizeof(int) * N1);
     put(L->o_long, sizeof(int) * N1);
     put(L->o_brA, sizeof(int) * 2 * ((size_t)L->nblkA + 1));  // block tables (k_rowsplit)
@@ -1456,6 +1485,44 @@ static int b_order_columns(BDev &d, const std::vector<BLP> &hl, int *cperm, int 
     d.cperm = cperm;
     d.cinv = cinv;
     return hipGetLastError() == hipSuccess ? PDHG_OK : PDHG_E_HIP;
+}
+
+// Bound classes of the concatenated columns: at most kBoundClasses distinct
+// (l, u) pairs (bit for bit) over the whole batch give each column a class
+// byte, which the primal update reads instead of l and u.
+static int b_bound_classes(BDev &d, unsigned char *dev, hipStream_t s) {
+    d.bcls = nullptr;
+    const size_t N = (size_t)d.N;
+    std::vector<unsigned long long> lo(N), hi(N);
+    if (hipMemcpyAsync(lo.data(), d.l, sizeof(double) * N, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(hi.data(), d.u, sizeof(double) * N, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return PDHG_E_HIP;
+    std::vector<unsigned char> cls(N);
+    unsigned long long kl[kBoundClasses], ku[kBoundClasses];
+    int nc = 0;
+    for (size_t j = 0; j < N; ++j) {
+        int k = 0;
+        while (k < nc && (kl[k] != lo[j] || ku[k] != hi[j])) ++k;
+        if (k == nc) {
+            if (nc == kBoundClasses) return PDHG_OK;
+            kl[nc] = lo[j];
+            ku[nc] = hi[j];
+            ++nc;
+        }
+        cls[j] = (unsigned char)k;
+    }
+    for (int k = 0; k < kBoundClasses; ++k) {
+        const int q = k < nc ? k : 0;
+        memcpy(&d.blo[k], &kl[q], sizeof(double));
+        memcpy(&d.bhi[k], &ku[q], sizeof(double));
+    }
+    if (hipMemcpyAsync(dev, cls.data(), N, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)  // the host vector above leaves scope
+        return PDHG_E_HIP;
+    d.bcls = dev;
+    d.nbcls = nc;
+    return PDHG_OK;
 }
 
 }  // namespace pdhg
@@ -1679,6 +1746,7 @@ int pdhg_batch_create(int32_t count, const pdhg_lp *lps, const pdhg_params *prm,
         hipLaunchKernelGGL(k_bclose_rp, dim3(1), dim3(1), 0, s, d);
         if ((rc = b_order_columns(d, hl, (int *)(ws + L.o_cperm), (int *)(ws + L.o_cinv), s)) != PDHG_OK)
             break;
+        if ((rc = b_bound_classes(d, (unsigned char *)(ws + L.o_bcls), s)) != PDHG_OK) break;
         // explicit A' of the block-diagonal matrix and the SpMV row splits
         Dev td;
         memset(&td, 0, sizeof(td));
@@ -1912,7 +1980,7 @@ int pdhg_batch_get_info(pdhg_batch_t *h, int32_t index, pdhg_info *out) {
     out->checks = L.checks;
     out->power_iters_used = h->pw_used.empty() ? 0 : h->pw_used[index];
     out->one_workgroup = 0;
-    out->bound_classes = 0;
+    out->bound_classes = h->d.nbcls;
     return PDHG_OK;
 }
 
@@ -2089,7 +2157,7 @@ int pdhg_batch_unrolled_backward(pdhg_batch_t *h, int64_t K, void *tape, size_t 
             BCK(hipMemcpyAsync(t.sy, d.y, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
         }
         for (long long q = 1; q <= len; ++q) {
-            b_iteration(d, s);
+            b_iteration(d, 0, s);
             BCK(hipMemcpyAsync(t.sx + q * N, d.x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
             if (M) BCK(hipMemcpyAsync(t.sy + q * M, d.y, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
         }

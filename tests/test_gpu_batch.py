@@ -57,6 +57,7 @@ def test_batch_iterates_and_logs_match_oracle(lib, mode):
     etas = [oracle.Oracle(lp).info()["eta"] for lp in lps]
     orcs = [oracle.Oracle(lp, eta=e, mode=mode) for lp, e in zip(lps, etas)]
     b = lib.BatchSolver(lps, params=[{"eta": e} for e in etas], restart_mode=mode)
+    assert b.info(0)["bound_classes"] == 0  # six (l, u) pairs in the mixed member
     done = 0
     for k in [30, 31, 90, 300, 1000]:
         b.solve(k - done, 0.0)
@@ -120,7 +121,18 @@ def test_uneven_batch_members(lib):
     etas = [oracle.Oracle(lp).info()["eta"] for lp in lps]
     orcs = [oracle.Oracle(lp, eta=e) for lp, e in zip(lps, etas)]
     b = lib.BatchSolver(lps, params=[{"eta": e} for e in etas])
+    # one (l, u) pair over the batch: the primal update reads a class byte
+    assert b.info(0)["bound_classes"] == 1
     b.solve(300, 0.0)
     for i, o in enumerate(orcs):
         o.solve(300, 0.0)
+        _cmp(o, b, i)
+    # runs of odd length (the running sums are updated in pairs of
+    # iterations; an odd run ends with a single addition), then a solve that
+    # starts between check points
+    b.step(7)
+    b.solve(53, 0.0)
+    for i, o in enumerate(orcs):
+        o.step(7)
+        o.solve(53, 0.0)
         _cmp(o, b, i)
