@@ -117,11 +117,13 @@ __global__ __launch_bounds__(kWG) void k_bspmv(const int *__restrict__ rp, const
     const int r0 = br[c], r1 = br[c + 1];
     if (r0 >= r1) return;
     const int a = lp_of[r0], z = lp_of[r1 - 1];
+    const BLP *one = nullptr;  // the block's LP when it holds rows of one LP only
     if (a == z) {
         const BLP &L = lps[a];
         if (gate_kind == 0 ? L.done : L.pw_done) return;
+        one = &L;
     }
-    spmv_rows(rp, ci, v, xin, r0, r1, br[nblk + 1 + c], br[nblk + 2 + c], epi, lds);
+    spmv_rows(rp, ci, v, xin, r0, r1, br[nblk + 1 + c], br[nblk + 2 + c], for_block(epi, one), lds);
 }
 
 // The batch's half-step epilogues: the single-LP updates with per-element
@@ -134,10 +136,13 @@ struct EpiPrimalB {
     const unsigned char *__restrict__ cls;
     double blo[kBoundClasses], bhi[kBoundClasses];
     int smode;
-    __device__ __forceinline__ void operator()(int j, double aty) const {
+    __device__ __forceinline__ void operator()(int j, double aty) const { apply(j, aty, 0, 0.0); }
+    // one: the block lies in one running LP, whose step is t1
+    __device__ __forceinline__ void apply(int j, double aty, int one, double t1) const {
         double g = c[j] - aty;
         const double xo = x[j];
-        double xn = xo - tau[j] * g;  // tau = 0 leaves a converged LP's x as it is
+        // tau = 0 leaves a converged LP's x as it is
+        double xn = xo - (one ? t1 : tau[j]) * g;
         double lo, hi;
         if (cls) {
             const int k = cls[j];
@@ -161,9 +166,10 @@ struct EpiDualB {
     double *__restrict__ y, *__restrict__ sy, *__restrict__ q;
     const double *__restrict__ sigma;
     int smode;
-    __device__ __forceinline__ void operator()(int i, double ax) const {
+    __device__ __forceinline__ void operator()(int i, double ax) const { apply(i, ax, 0, 0.0); }
+    __device__ __forceinline__ void apply(int i, double ax, int one, double s1) const {
         const double yo = y[i];
-        double yv = yo + sigma[i] * (b[i] - (2.0 * ax - q[i]));
+        double yv = yo + (one ? s1 : sigma[i]) * (b[i] - (2.0 * ax - q[i]));
         if (kind[i] && yv < 0.0) yv = 0.0;
         y[i] = yv;
         if (smode == 0) sy[i] += yv;
@@ -171,6 +177,27 @@ struct EpiDualB {
         q[i] = ax;
     }
 };
+
+// The epilogue for one merge-path block: blocks inside one running LP take
+// that LP's step from its record (the same value the per-element step
+// arrays hold) instead of reading a step per element.
+template <class Epi>
+__device__ __forceinline__ const Epi &for_block(const Epi &e, const BLP *) {
+    return e;
+}
+template <class Epi>
+struct InBlock {  // an epilogue and its block's step (the epilogue is not copied)
+    const Epi &e;
+    int one;
+    double step;
+    __device__ __forceinline__ void operator()(int j, double s) const { e.apply(j, s, one, step); }
+};
+__device__ __forceinline__ InBlock<EpiPrimalB> for_block(const EpiPrimalB &e, const BLP *L) {
+    return InBlock<EpiPrimalB>{e, L ? 1 : 0, L ? L->tau : 0.0};
+}
+__device__ __forceinline__ InBlock<EpiDualB> for_block(const EpiDualB &e, const BLP *L) {
+    return InBlock<EpiDualB>{e, L ? 1 : 0, L ? L->sigma : 0.0};
+}
 
 static void bspmv_A(const BDev &d, const double *in, double *out, int gate_kind, hipStream_t s) {
     EpiStore e{out};
