@@ -77,6 +77,13 @@ struct BDev {
     int *lp_row, *lp_col;
     double *tau_col, *sigma_row;  // step of each column / row's LP, 0 once it converged
     int *blk_lp, *blk_first;
+    // SpMV blocks never span two LPs: LP i owns blocks blkA[i] .. blkA[i+1]-1
+    // of A and blkT[i] .. of A'; lp_r0 / lp_c0 ([count + 1]) are the LPs'
+    // row and column offsets.  When every LP has at most 65,536 rows and
+    // columns, ci16 / tci16 hold A's column and A''s row indices relative to
+    // their LP (null otherwise).
+    int *blkA, *blkT, *lp_r0, *lp_c0;
+    unsigned short *ci16, *tci16;
     double *x, *y, *x0, *y0, *sx, *sy, *q, *xbar, *ybar, *axb, *atyb, *aty;
     double *part;    // [nblk][kKktSums]
     double *log;     // [count][kBLog][kRec]
@@ -110,7 +117,9 @@ __global__ __launch_bounds__(kWG) void k_bspmv(const int *__restrict__ rp, const
                                                const double *__restrict__ xin,
                                                const int *__restrict__ br, int nblk, Epi epi,
                                                const int *__restrict__ lp_of, const BLP *lps,
-                                               int gate_kind, const int *__restrict__ xp) {
+                                               int gate_kind, const int *__restrict__ xp,
+                                               const unsigned short *__restrict__ ci16,
+                                               const int *__restrict__ lp_base) {
     __shared__ SpmvShared lds;
     const int c = xp[blockIdx.x];
     if (c < 0) return;
@@ -123,7 +132,12 @@ __global__ __launch_bounds__(kWG) void k_bspmv(const int *__restrict__ rp, const
         if (gate_kind == 0 ? L.done : L.pw_done) return;
         one = &L;
     }
-    spmv_rows(rp, ci, v, xin, r0, r1, br[nblk + 1 + c], br[nblk + 2 + c], for_block(epi, one), lds);
+    const int p0 = br[nblk + 1 + c], p1 = br[nblk + 2 + c];
+    decltype(auto) eb = for_block(epi, one);
+    // 16-bit indices within the block's LP: the gathered vector is shifted
+    // to the LP's first element
+    if (ci16 && one) spmv_rows(rp, ci16, v, xin + lp_base[a], r0, r1, p0, p1, eb, lds);
+    else spmv_rows(rp, ci, v, xin, r0, r1, p0, p1, eb, lds);
 }
 
 // The batch's half-step epilogues: the single-LP updates with per-element
@@ -202,13 +216,13 @@ __device__ __forceinline__ InBlock<EpiDualB> for_block(const EpiDualB &e, const 
 static void bspmv_A(const BDev &d, const double *in, double *out, int gate_kind, hipStream_t s) {
     EpiStore e{out};
     hipLaunchKernelGGL(k_bspmv<EpiStore>, dim3(d.nslotA), dim3(kWG), 0, s, d.rp, d.ci, d.v, in,
-                       d.brA, d.nblkA, e, d.lp_row, d.lp, gate_kind, d.xpA);
+                       d.brA, d.nblkA, e, d.lp_row, d.lp, gate_kind, d.xpA, d.ci16, d.lp_c0);
 }
 
 static void bspmv_T(const BDev &d, const double *in, double *out, int gate_kind, hipStream_t s) {
     EpiStore e{out};
     hipLaunchKernelGGL(k_bspmv<EpiStore>, dim3(d.nslotT), dim3(kWG), 0, s, d.trp, d.tci, d.tv, in,
-                       d.brT, d.nblkT, e, d.lp_col, d.lp, gate_kind, d.xpT);
+                       d.brT, d.nblkT, e, d.lp_col, d.lp, gate_kind, d.xpT, d.tci16, d.lp_r0);
 }
 
 static void b_iteration(const BDev &d, int smode, hipStream_t s) {
@@ -218,10 +232,10 @@ static void b_iteration(const BDev &d, int smode, hipStream_t s) {
         ep.bhi[k] = d.bhi[k];
     }
     hipLaunchKernelGGL(k_bspmv<EpiPrimalB>, dim3(d.nslotT), dim3(kWG), 0, s, d.trp, d.tci, d.tv,
-                       d.y, d.brT, d.nblkT, ep, d.lp_col, d.lp, 0, d.xpT);
+                       d.y, d.brT, d.nblkT, ep, d.lp_col, d.lp, 0, d.xpT, d.tci16, d.lp_r0);
     EpiDualB ed{d.b, d.kind, d.y, d.sy, d.q, d.sigma_row, smode};
     hipLaunchKernelGGL(k_bspmv<EpiDualB>, dim3(d.nslotA), dim3(kWG), 0, s, d.rp, d.ci, d.v, d.x,
-                       d.brA, d.nblkA, ed, d.lp_row, d.lp, 0, d.xpA);
+                       d.brA, d.nblkA, ed, d.lp_row, d.lp, 0, d.xpA, d.ci16, d.lp_c0);
 }
 
 // iteration counters of Algorithm 1 for the LPs still running (every LP
@@ -282,6 +296,47 @@ __global__ void k_bconcat(BDev d, int lpi, const int *rp, const int *ci, const d
 }
 
 __global__ void k_bclose_rp(BDev d) { d.rp[d.M] = d.NNZ; }
+
+// Block table (the layout of k_rowsplit: row starts, then entry starts) of
+// the concatenated rows rp in which no block spans two LPs: LP i (rows
+// off[i] .. off[i+1]-1) takes blocks blk[i] .. blk[i+1]-1, split by the
+// merge-path rule over its own rows and entries.
+__global__ void k_lpsplit(const int *__restrict__ rp, const int *__restrict__ off,
+                          const int *__restrict__ blk, int count, int nblk, int *br) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > nblk) return;
+    int row = off[count];
+    if (c < nblk) {
+        int lo = 0, hi = count - 1;  // the LP of block c: last i with blk[i] <= c
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (blk[mid] <= c) lo = mid;
+            else hi = mid - 1;
+        }
+        const int r0 = off[lo], rows = off[lo + 1] - r0, e0 = rp[r0];
+        const long long target = (long long)(c - blk[lo]) * kUnits;
+        int a = 0, b = rows;
+        while (a < b) {
+            const int mid = a + ((b - a) >> 1);
+            if ((long long)mid + (rp[r0 + mid] - e0) >= target) b = mid;
+            else a = mid + 1;
+        }
+        row = r0 + a;
+    }
+    br[c] = row;
+    br[nblk + 1 + c] = rp[row];
+}
+
+// indices of a block-diagonal CSR relative to their LP: out[p] = ci[p] -
+// base[lp_of[row of p]] (every LP narrower than 65,537)
+__global__ void k_bidx16(const int *__restrict__ rp, const int *__restrict__ ci, int rows,
+                         const int *__restrict__ lp_of, const int *__restrict__ base,
+                         unsigned short *out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    const int b0 = base[lp_of[r]];
+    for (int p = rp[r]; p < rp[r + 1]; ++p) out[p] = (unsigned short)(ci[p] - b0);
+}
 
 // x = proj_X(0), y = 0, anchors, sums
 __global__ void k_binit(BDev d) {
@@ -1337,7 +1392,7 @@ struct BLayout {
     size_t total;
     size_t o_lp, o_err, o_rp, o_ci, o_v, o_c, o_b, o_l, o_u, o_kind, o_trp, o_tci, o_perm, o_tv;
     size_t o_xpA, o_xpT;
-    size_t o_cperm, o_cinv, o_bcls;
+    size_t o_cperm, o_cinv, o_bcls, o_blkA, o_blkT, o_lpr0, o_lpc0, o_ci16, o_tci16;
     size_t o_cursor, o_long, o_brA, o_brT, o_lprow, o_lpcol, o_tau, o_sig, o_blklp, o_blkfirst, o_vn, o_vm;
     size_t o_part, o_log, o_hcnt, o_hD, o_hA, o_tpart, o_ccount, o_coff, o_ckey, o_ca, o_cd;
     int M, N, NNZ, nblk, nblkA, nblkT;
@@ -1363,8 +1418,15 @@ static bool b_layout(int count, const int64_t *m, const int64_t *n, const int64_
     L->N = (int)N;
     L->NNZ = (int)Z;
     L->nblk = (int)nblk;
-    L->nblkA = nblocks_for((int)M, (int)Z);
-    L->nblkT = nblocks_for((int)N, (int)Z);
+    // blocks per LP (no block spans two LPs)
+    long long nbA = 0, nbT = 0;
+    for (int i = 0; i < count; ++i) {
+        nbA += nblocks_for((int)m[i], (int)nnz[i]);
+        nbT += nblocks_for((int)n[i], (int)nnz[i]);
+    }
+    if (nbA > lim / kUnits || nbT > lim / kUnits) return false;
+    L->nblkA = (int)nbA;
+    L->nblkT = (int)nbT;
     const size_t M1 = (size_t)(M > 0 ? M : 1), N1 = (size_t)N, Z1 = (size_t)(Z > 0 ? Z : 1);
     size_t o = 0;
     auto put = [&](size_t &off, size_t bytes) {
@@ -1388,6 +1450,12 @@ static bool b_layout(int count, const int64_t *m, const int64_t *n, const int64_
     put(L->o_cperm, sizeof(int) * N1);
     put(L->o_cinv, sizeof(int) * N1);
     put(L->o_bcls, N1);
+    put(L->o_blkA, sizeof(int) * ((size_t)count + 1));
+    put(L->o_blkT, sizeof(int) * ((size_t)count + 1));
+    put(L->o_lpr0, sizeof(int) * ((size_t)count + 1));
+    put(L->o_lpc0, sizeof(int) * ((size_t)count + 1));
+    put(L->o_ci16, sizeof(unsigned short) * Z1);
+    put(L->o_tci16, sizeof(unsigned short) * Z1);
     put(L->o_cursor, sizeof(int) * N1);
     put(L->o_long, sizeof(int) * N1);
     put(L->o_brA, sizeof(int) * 2 * ((size_t)L->nblkA + 1));  // block tables (k_rowsplit)
@@ -1675,6 +1743,11 @@ int pdhg_batch_create(int32_t count, const pdhg_lp *lps, const pdhg_params *prm,
     d.sigma_row = (double *)(ws + L.o_sig);
     d.blk_lp = (int *)(ws + L.o_blklp);
     d.blk_first = (int *)(ws + L.o_blkfirst);
+    d.blkA = (int *)(ws + L.o_blkA);
+    d.blkT = (int *)(ws + L.o_blkT);
+    d.lp_r0 = (int *)(ws + L.o_lpr0);
+    d.lp_c0 = (int *)(ws + L.o_lpc0);
+    d.ci16 = d.tci16 = nullptr;
     const size_t sn = al(sizeof(double) * (size_t)L.N), sm = al(sizeof(double) * (size_t)(L.M > 0 ? L.M : 1));
     double **vn[6] = {&d.x, &d.x0, &d.sx, &d.xbar, &d.atyb, &d.aty};
     double **vm[6] = {&d.y, &d.y0, &d.sy, &d.q, &d.ybar, &d.axb};
@@ -1757,6 +1830,32 @@ int pdhg_batch_create(int32_t count, const pdhg_lp *lps, const pdhg_params *prm,
             rc = PDHG_E_HIP;
             break;
         }
+        // per-LP block ranges of the SpMV splits and the LPs' offsets
+        std::vector<int> hblkA((size_t)count + 1), hblkT((size_t)count + 1);
+        std::vector<int> hr0((size_t)count + 1), hc0((size_t)count + 1);
+        long long wide = 0;
+        hblkA[0] = hblkT[0] = 0;
+        for (int i = 0; i < count; ++i) {
+            hblkA[(size_t)i + 1] = hblkA[i] + nblocks_for((int)ms[i], (int)zs[i]);
+            hblkT[(size_t)i + 1] = hblkT[i] + nblocks_for((int)ns[i], (int)zs[i]);
+            hr0[i] = hl[i].row_off;
+            hc0[i] = hl[i].col_off;
+            wide = std::max(wide, (long long)std::max(ms[i], ns[i]));
+        }
+        hr0[count] = L.M;
+        hc0[count] = L.N;
+        if (hblkA[count] != d.nblkA || hblkT[count] != d.nblkT) {
+            rc = PDHG_E_INVALID;
+            break;
+        }
+        if (hipMemcpyAsync(d.blkA, hblkA.data(), sizeof(int) * hblkA.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(d.blkT, hblkT.data(), sizeof(int) * hblkT.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(d.lp_r0, hr0.data(), sizeof(int) * hr0.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(d.lp_c0, hc0.data(), sizeof(int) * hc0.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {  // the host vectors above leave scope
+            rc = PDHG_E_HIP;
+            break;
+        }
         long long nz_off = 0;
         for (int i = 0; i < count; ++i) {
             const BLP &b = hl[i];
@@ -1790,9 +1889,21 @@ int pdhg_batch_create(int32_t count, const pdhg_lp *lps, const pdhg_params *prm,
         td.cursor = d.cursor;
         td.long_rows = d.long_rows;
         td.err = d.err;
-        launch_rowsplit(d.rp, d.M, d.NNZ, d.nblkA, d.brA, s);
+        hipLaunchKernelGGL(k_lpsplit, dim3(div_up(d.nblkA + 1, kWG)), dim3(kWG), 0, s, d.rp, d.lp_r0,
+                           d.blkA, count, d.nblkA, d.brA);
         launch_transpose(td, s);
-        launch_rowsplit(d.trp, d.N, d.NNZ, d.nblkT, d.brT, s);
+        hipLaunchKernelGGL(k_lpsplit, dim3(div_up(d.nblkT + 1, kWG)), dim3(kWG), 0, s, d.trp, d.lp_c0,
+                           d.blkT, count, d.nblkT, d.brT);
+        if (d.NNZ > 0 && wide <= 65536) {
+            unsigned short *a16 = (unsigned short *)(ws + L.o_ci16), *t16 = (unsigned short *)(ws + L.o_tci16);
+            if (d.M > 0)
+                hipLaunchKernelGGL(k_bidx16, dim3(div_up(d.M, kWG)), dim3(kWG), 0, s, d.rp, d.ci, d.M,
+                                   d.lp_row, d.lp_c0, a16);
+            hipLaunchKernelGGL(k_bidx16, dim3(div_up(d.N, kWG)), dim3(kWG), 0, s, d.trp, d.tci, d.N,
+                               d.lp_col, d.lp_r0, t16);
+            d.ci16 = a16;
+            d.tci16 = t16;
+        }
         {
             std::vector<int> hbrA((size_t)d.nblkA + 1), hbrT((size_t)d.nblkT + 1);
             std::vector<int> roffs((size_t)count + 1), coffs((size_t)count + 1);

@@ -100,8 +100,11 @@ __device__ __forceinline__ T ld_matrix(const T *p) {
 #endif
 }
 
-template <class Epi>
-__device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const int *__restrict__ ci,
+// Idx: int column indices, or unsigned short ones relative to the start of
+// xin (a caller that knows a block's columns lie in one 65,536-wide window
+// passes xin shifted to that window)
+template <class Epi, class Idx = int>
+__device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const Idx *__restrict__ ci,
                                           const double *__restrict__ v,
                                           const double *__restrict__ xin, int r0, int r1,
                                           int p0, int p1, const Epi &epi, SpmvShared &sm) {

@@ -136,3 +136,18 @@ def test_uneven_batch_members(lib):
         o.step(7)
         o.solve(53, 0.0)
         _cmp(o, b, i)
+
+
+def test_member_wider_than_16_bit_indices(lib):
+    """A member with more than 65,536 columns: the batch keeps 32-bit
+    indices (smaller batches use 16-bit ones relative to each LP)."""
+    lps = [lpgen.column_count_lp(31, 1200, 70_000, per_col=1, bounds="mix"),
+           lpgen.small_dense(2)]
+    _say("wide member", [(lp.m, lp.n) for lp in lps])
+    etas = [oracle.Oracle(lp).info()["eta"] for lp in lps]
+    orcs = [oracle.Oracle(lp, eta=e) for lp, e in zip(lps, etas)]
+    b = lib.BatchSolver(lps, params=[{"eta": e} for e in etas])
+    b.solve(301, 0.0)
+    for i, o in enumerate(orcs):
+        o.solve(301, 0.0)
+        _cmp(o, b, i)
