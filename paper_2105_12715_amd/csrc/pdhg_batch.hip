@@ -150,6 +150,7 @@ struct EpiPrimalB {
     const unsigned char *__restrict__ cls;
     double blo[kBoundClasses], bhi[kBoundClasses];
     int smode;
+    double *__restrict__ xcopy = nullptr;  // a second copy of x+ (the reverse pass's tape), or null
     __device__ __forceinline__ void operator()(int j, double aty) const { apply(j, aty, 0, 0.0); }
     // one: the block lies in one running LP, whose step is t1
     __device__ __forceinline__ void apply(int j, double aty, int one, double t1) const {
@@ -169,6 +170,7 @@ struct EpiPrimalB {
         if (xn < lo) xn = lo;
         if (xn > hi) xn = hi;
         x[j] = xn;
+        if (xcopy) xcopy[j] = xn;
         if (smode == 0) sx[j] += xn;
         else if (smode == 2) sx[j] = (sx[j] + xo) + xn;
     }
@@ -180,12 +182,14 @@ struct EpiDualB {
     double *__restrict__ y, *__restrict__ sy, *__restrict__ q;
     const double *__restrict__ sigma;
     int smode;
+    double *__restrict__ ycopy = nullptr;
     __device__ __forceinline__ void operator()(int i, double ax) const { apply(i, ax, 0, 0.0); }
     __device__ __forceinline__ void apply(int i, double ax, int one, double s1) const {
         const double yo = y[i];
         double yv = yo + (one ? s1 : sigma[i]) * (b[i] - (2.0 * ax - q[i]));
         if (kind[i] && yv < 0.0) yv = 0.0;
         y[i] = yv;
+        if (ycopy) ycopy[i] = yv;
         if (smode == 0) sy[i] += yv;
         else if (smode == 2) sy[i] = (sy[i] + yo) + yv;
         q[i] = ax;
@@ -225,15 +229,17 @@ static void bspmv_T(const BDev &d, const double *in, double *out, int gate_kind,
                        d.brT, d.nblkT, e, d.lp_col, d.lp, gate_kind, d.xpT, d.tci16, d.lp_r0);
 }
 
-static void b_iteration(const BDev &d, int smode, hipStream_t s) {
-    EpiPrimalB ep{d.c, d.l, d.u, d.x, d.sx, d.tau_col, d.bcls, {}, {}, smode};
+// one iteration; xcopy / ycopy (optional) receive copies of x+ and y+
+static void b_iteration(const BDev &d, int smode, hipStream_t s, double *xcopy = nullptr,
+                        double *ycopy = nullptr) {
+    EpiPrimalB ep{d.c, d.l, d.u, d.x, d.sx, d.tau_col, d.bcls, {}, {}, smode, xcopy};
     for (int k = 0; k < kBoundClasses; ++k) {
         ep.blo[k] = d.blo[k];
         ep.bhi[k] = d.bhi[k];
     }
     hipLaunchKernelGGL(k_bspmv<EpiPrimalB>, dim3(d.nslotT), dim3(kWG), 0, s, d.trp, d.tci, d.tv,
                        d.y, d.brT, d.nblkT, ep, d.lp_col, d.lp, 0, d.xpT, d.tci16, d.lp_r0);
-    EpiDualB ed{d.b, d.kind, d.y, d.sy, d.q, d.sigma_row, smode};
+    EpiDualB ed{d.b, d.kind, d.y, d.sy, d.q, d.sigma_row, smode, ycopy};
     hipLaunchKernelGGL(k_bspmv<EpiDualB>, dim3(d.nslotA), dim3(kWG), 0, s, d.rp, d.ci, d.v, d.x,
                        d.brA, d.nblkA, ed, d.lp_row, d.lp, 0, d.xpA, d.ci16, d.lp_c0);
 }
@@ -1229,7 +1235,8 @@ struct Tape {
     int *ev;                // [nwin][count] restart after the window: 0 none, 1 average, 2 current
     long long *evT;         // window length of that restart
     double *sx, *sy;        // recomputed iterates of one window: [(P+1)][N], [(P+1)][M]
-    double *xh, *yh, *sxh, *syh, *vh, *uh;
+    double *xh, *yh, *sxh, *syh, *vh;
+    double2 *uw;            // per column: (uh, 2 x+ - x) for the A^ entries
     double *gc;             // dL/dc in the internal column order (permuted columns only)
     int nwin, P;
     long long K;
@@ -1299,27 +1306,31 @@ __global__ void k_adj_dual(BDev d, const double *yt, const double *yh, const dou
     gb[i] += L.sigma * v;
 }
 
+// the A' product of the reverse step with the primal adjoint fused; it
+// also leaves (uh_j, 2 x+_j - x_j) side by side for the A rows, which then
+// gather both with one load
 struct EpiAdjPrimal {
-    const double *__restrict__ xt, *__restrict__ l, *__restrict__ u;
-    double *__restrict__ xh, *__restrict__ sxh, *__restrict__ uh, *__restrict__ gc;
+    const double *__restrict__ xt, *__restrict__ xprev, *__restrict__ l, *__restrict__ u;
+    double *__restrict__ xh, *__restrict__ sxh, *__restrict__ gc;
+    double2 *__restrict__ uw;
     const int *__restrict__ lpc;
     const BLP *lp;
     __device__ __forceinline__ void operator()(int j, double atv) const {
         const BLP &L = lp[lpc[j]];
         const double wh = -L.sigma * atv;
         const double tot = xh[j] + sxh[j] + 2.0 * wh;
-        const bool inside = l[j] < xt[j] && xt[j] < u[j];
+        const double xtj = xt[j];
+        const bool inside = l[j] < xtj && xtj < u[j];
         const double uu = inside ? tot : 0.0;
-        uh[j] = uu;
+        uw[j] = make_double2(uu, 2.0 * xtj - xprev[j]);
         gc[j] += -L.tau * uu;
         xh[j] = -wh + uu;
     }
 };
 
 // rows of A: yh_i = vh_i + tau (A uh)_i and the A^ entries of the row
-__global__ __launch_bounds__(kWG) void k_adj_rows(BDev d, const double *__restrict__ uh,
-                                                  const double *__restrict__ xt,
-                                                  const double *__restrict__ xprev,
+// (uw_j = (uh_j, 2 x+_j - x_j))
+__global__ __launch_bounds__(kWG) void k_adj_rows(BDev d, const double2 *__restrict__ uw,
                                                   const double *__restrict__ yprev,
                                                   const double *__restrict__ vh, double *yh,
                                                   double *gA) {
@@ -1331,12 +1342,29 @@ __global__ __launch_bounds__(kWG) void k_adj_rows(BDev d, const double *__restri
     const int tid = threadIdx.x;
     const int p0 = rp[r0], p1 = rp[r1], nb = p1 - p0, R = r1 - r0;
     if (nb <= kLdsProducts) {
-        for (int e = tid; e < nb; e += kWG) {
-            const int j = ci[p0 + e];
-            const double uu = uh[j];
-            sp[e] = v[p0 + e] * uu;
-            sw[e] = 2.0 * xt[j] - xprev[j];
-            su[e] = uu;
+        // all index and value loads of a thread, then all its gathers
+        int col[kPerThread];
+        double val[kPerThread];
+        double2 g[kPerThread];
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+            const int e = tid + k * kWG;
+            if (e < nb) {
+                col[k] = ci[p0 + e];
+                val[k] = v[p0 + e];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k)
+            if (tid + k * kWG < nb) g[k] = uw[col[k]];
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+            const int e = tid + k * kWG;
+            if (e < nb) {
+                sp[e] = val[k] * g[k].x;
+                sw[e] = g[k].y;
+                su[e] = g[k].x;
+            }
         }
         __syncthreads();
         const int avg = nb / R;
@@ -1363,10 +1391,9 @@ __global__ __launch_bounds__(kWG) void k_adj_rows(BDev d, const double *__restri
             const double sig = LP.sigma, tau = LP.tau, vr = vh[row], yr = yprev[row];
             double s = 0.0;
             for (int p = rp[row] + lane; p < rp[row + 1]; p += 64) {
-                const int j = ci[p];
-                const double uu = uh[j];
-                s += v[p] * uu;
-                gA[p] += -sig * vr * (2.0 * xt[j] - xprev[j]) + tau * yr * uu;
+                const double2 g = uw[ci[p]];
+                s += v[p] * g.x;
+                gA[p] += -sig * vr * g.y + tau * yr * g.x;
             }
             s = wave_sum(s);
             if (lane == 0) yh[row] = vr + tau * s;
@@ -2167,7 +2194,7 @@ static bool tape_carve(const pdhg_batch_t *h, int64_t K, char *base, Tape *t, si
     const size_t osy = put(sizeof(double) * M * (size_t)(P + 1));
     const size_t oxh = put(sizeof(double) * N), oyh = put(sizeof(double) * M);
     const size_t osxh = put(sizeof(double) * N), osyh = put(sizeof(double) * M);
-    const size_t ovh = put(sizeof(double) * M), ouh = put(sizeof(double) * N);
+    const size_t ovh = put(sizeof(double) * M), ouw = put(sizeof(double2) * N);
     const size_t ogc = d.cinv ? put(sizeof(double) * N) : 0;
     *total = o;
     if (base && t) {
@@ -2183,7 +2210,7 @@ static bool tape_carve(const pdhg_batch_t *h, int64_t K, char *base, Tape *t, si
         t->sxh = (double *)(base + osxh);
         t->syh = (double *)(base + osyh);
         t->vh = (double *)(base + ovh);
-        t->uh = (double *)(base + ouh);
+        t->uw = (double2 *)(base + ouw);
         t->gc = d.cinv ? (double *)(base + ogc) : nullptr;
         t->nwin = (int)nwin;
         t->P = (int)P;
@@ -2267,6 +2294,15 @@ int pdhg_batch_unrolled_backward(pdhg_batch_t *h, int64_t K, void *tape, size_t 
     hipStream_t s = h->stream;
     const size_t N = (size_t)d.N, M = (size_t)d.M;
     const long long NM = (long long)d.N + d.M;
+    // LPs stopped by an earlier solve skip their SpMV blocks, so their
+    // iterates are copied to the tape whole rather than by the epilogues
+    bool any_done = false;
+    {
+        std::vector<BLP> cur;
+        const int rc0 = b_read_lps(h, cur);
+        if (rc0) return rc0;
+        for (const BLP &L : cur) any_done |= L.done != 0;
+    }
     // dL/dx in, dL/dc out in the caller's column order; the sweep runs in
     // the internal one (gA follows the entries, which keep their places)
     if (d.cperm) launch_gather(dLdx, d.cperm, d.N, t.xh, s);
@@ -2295,9 +2331,14 @@ int pdhg_batch_unrolled_backward(pdhg_batch_t *h, int64_t K, void *tape, size_t 
             BCK(hipMemcpyAsync(t.sy, d.y, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
         }
         for (long long q = 1; q <= len; ++q) {
-            b_iteration(d, 0, s);
-            BCK(hipMemcpyAsync(t.sx + q * N, d.x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-            if (M) BCK(hipMemcpyAsync(t.sy + q * M, d.y, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+            if (any_done) {
+                b_iteration(d, 0, s);
+                BCK(hipMemcpyAsync(t.sx + q * N, d.x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+                if (M) BCK(hipMemcpyAsync(t.sy + q * M, d.y, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+            } else {
+                // every block runs, so the epilogues write the whole iterate
+                b_iteration(d, 0, s, t.sx + q * N, M ? t.sy + q * M : nullptr);
+            }
         }
         for (long long q = len; q >= 1; --q) {
             const double *xt = t.sx + q * N, *xp = t.sx + (q - 1) * N;
@@ -2305,12 +2346,12 @@ int pdhg_batch_unrolled_backward(pdhg_batch_t *h, int64_t K, void *tape, size_t 
             if (M)
                 hipLaunchKernelGGL(k_adj_dual, dim3(div_up(d.M, kWG)), dim3(kWG), 0, s, d, yt,
                                    t.yh, t.syh, t.vh, gb);
-            EpiAdjPrimal ep{xt, d.l, d.u, t.xh, t.sxh, t.uh, gcw, d.lp_col, d.lp};
+            EpiAdjPrimal ep{xt, xp, d.l, d.u, t.xh, t.sxh, gcw, t.uw, d.lp_col, d.lp};
             hipLaunchKernelGGL(k_spmv<EpiAdjPrimal>, dim3(d.nblkT), dim3(kWG), 0, s, d.trp, d.tci,
                                d.tv, t.vh, d.brT, d.nblkT, ep, (const int *)nullptr);
             if (M)
-                hipLaunchKernelGGL(k_adj_rows, dim3(d.nblkA), dim3(kWG), 0, s, d, t.uh, xt, xp, yp,
-                                   t.vh, t.yh, gA);
+                hipLaunchKernelGGL(k_adj_rows, dim3(d.nblkA), dim3(kWG), 0, s, d,
+                                   (const double2 *)t.uw, yp, t.vh, t.yh, gA);
         }
         int rc = b_last_error();
         if (rc) return rc;
