@@ -151,3 +151,30 @@ def test_member_wider_than_16_bit_indices(lib):
     for i, o in enumerate(orcs):
         o.solve(301, 0.0)
         _cmp(o, b, i)
+
+
+def test_members_without_rows_and_with_empty_columns(lib):
+    """A member with no rows, one with empty columns and >= rows, and two
+    ordinary ones: each SpMV block stays inside one member (a member
+    without rows has only an empty block), columns are reordered inside
+    each member, and every member follows its oracle."""
+    from tests.lp_cases import lp_from_dense
+    no_rows = lp_from_dense(np.zeros((0, 4)), [], [1.0, -1.0, 0.5, 0.0], [0, 0, -1, -2],
+                            [1, 1, 1, 2])
+    A = np.array([[1.0, 0, 2.0, 0], [0, 0, -1.0, 0], [3.0, 0, 0, 0]])
+    empty_cols = lp_from_dense(A, [1.0, -0.5, 2.0], [1.0, 1.0, 1.0, -1.0], [0, 0, 0, -1],
+                               [5, 5, 5, 3], kind=[0, 1, 0])
+    lps = [lpgen.small_dense(3), no_rows, empty_cols,
+           lpgen.column_count_lp(41, 900, 2000, per_col=3, bounds="mix", ge_frac=0.3)]
+    _say("edge members", [(lp.m, lp.n) for lp in lps])
+    etas = [0.5 if lp.m == 0 else oracle.Oracle(lp).info()["eta"] for lp in lps]
+    orcs = [oracle.Oracle(lp, eta=e, mode=2) for lp, e in zip(lps, etas)]
+    b = lib.BatchSolver(lps, params=[{"eta": e} for e in etas], restart_mode=2)
+    done = 0
+    for k in [1, 30, 61, 600]:
+        b.solve(k - done, 0.0)
+        for o in orcs:
+            o.solve(k - done, 0.0)
+        done = k
+        for i, o in enumerate(orcs):
+            _cmp(o, b, i)
