@@ -5,9 +5,12 @@
 // half-step of eq. PDHG-update is one SpMV launch over every LP at once
 // with the update fused into the row epilogue.  Each LP keeps its own step
 // sizes, iteration and restart counters, trust-region bracket and done
-// flag (struct BLP); epilogues look the LP of a row or column up in
-// lp_row / lp_col and leave converged LPs untouched, and SpMV blocks whose
-// rows all belong to converged LPs exit at once.
+// flag (struct BLP).  The SpMV blocks are split per LP, so every block
+// belongs to one LP: a block of a converged LP exits at once, and the
+// others take their LP's step sizes from its record.  Inside each LP the
+// columns are held sorted by entry count and first row (the API converts
+// column vectors at the boundary), and A and A' also carry 16-bit indices
+// relative to their LP when every LP is narrow enough.
 //
 // Per-LP reductions (KKT, radii, the normalized duality gap of eq. rhorz,
 // power iteration) run over a block table: the element space of LP i
