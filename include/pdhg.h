@@ -408,9 +408,12 @@ int pdhg_batch_set_data(pdhg_batch_t *h, const double *c, const double *b, const
  * (eq. PDHG-update), the running average and restarts of Algorithm 1 with
  * the restart decisions and projection masks of the forward pass held
  * fixed.  Each window between checkpoints is recomputed from its
- * checkpoint and swept in reverse.  The step sizes are constants.  After
- * the backward call the batch's iterates are those at the first window's
- * end; call the forward or a solve before reading them.
+ * checkpoint and swept in reverse.  The step sizes are constants.  The
+ * backward call takes the tape and K of the last forward call, with no
+ * solve, step or set_data since (else PDHG_E_INVALID); it may be repeated
+ * on one forward.  After the backward call the batch's iterates are those
+ * at the first window's end; call the forward or a solve before reading
+ * them.
  */
 size_t pdhg_batch_tape_bytes(pdhg_batch_t *h, int64_t K);
 int pdhg_batch_unrolled_forward(pdhg_batch_t *h, int64_t K, void *tape, size_t tape_bytes,

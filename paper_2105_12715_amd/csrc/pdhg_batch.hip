@@ -1663,6 +1663,11 @@ struct pdhg_batch_handle {
     double g_tol;
     bool g_valid;
     std::vector<int> pw_used;
+    // the tape of the last unrolled forward call, while nothing has changed
+    // the batch since (the backward recomputes its windows from it)
+    const void *tape_of = nullptr;
+    int64_t tape_K = -1;
+    bool tape_ok = false;
 };
 
 #define BCK(expr)                                  \
@@ -2014,6 +2019,7 @@ void pdhg_batch_destroy(pdhg_batch_t *h) {
 
 int pdhg_batch_step(pdhg_batch_t *h, int64_t iters) {
     if (!h || iters < 0) return PDHG_E_INVALID;
+    h->tape_ok = false;
     b_iterations(h->d, iters, h->stream);
     return b_last_error();
 }
@@ -2043,6 +2049,7 @@ static int b_build_graph(pdhg_batch_t *h, double tol) {
 
 int pdhg_batch_solve(pdhg_batch_t *h, int64_t max_iters, double tol, pdhg_result *results) {
     if (!h || max_iters < 0 || isnan(tol)) return PDHG_E_INVALID;
+    h->tape_ok = false;
     int rc;
     std::vector<BLP> cur;
     hipLaunchKernelGGL(k_breset, dim3(div_up(h->count, kWG)), dim3(kWG), 0, h->stream, h->d);
@@ -2233,6 +2240,7 @@ size_t pdhg_batch_tape_bytes(pdhg_batch_t *h, int64_t K) {
 
 int pdhg_batch_set_data(pdhg_batch_t *h, const double *c, const double *b, const double *vals) {
     if (!h || !c || (h->d.M > 0 && !b) || (h->d.NNZ > 0 && !vals)) return PDHG_E_INVALID;
+    h->tape_ok = false;
     const BDev &d = h->d;
     hipStream_t s = h->stream;
     if (d.cperm) launch_gather(c, d.cperm, d.N, d.c, s);
@@ -2254,6 +2262,7 @@ int pdhg_batch_unrolled_forward(pdhg_batch_t *h, int64_t K, void *tape, size_t t
     size_t need = 0;
     if (!tape_carve(h, K, (char *)tape, &t, &need)) return PDHG_E_INVALID;
     if (!tape || ((uintptr_t)tape & 255u) || tape_bytes < need) return PDHG_E_WORKSPACE;
+    h->tape_ok = false;
     const BDev &d = h->d;
     hipStream_t s = h->stream;
     const long long NM = (long long)d.N + d.M;
@@ -2283,7 +2292,13 @@ int pdhg_batch_unrolled_forward(pdhg_batch_t *h, int64_t K, void *tape, size_t t
     }
     if (xK && d.cinv) launch_gather(d.x, d.cinv, d.N, xK, s);
     else if (xK) BCK(hipMemcpyAsync(xK, d.x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-    return b_last_error();
+    const int rc = b_last_error();
+    if (rc == PDHG_OK) {
+        h->tape_of = tape;
+        h->tape_K = K;
+        h->tape_ok = true;
+    }
+    return rc;
 }
 
 int pdhg_batch_unrolled_backward(pdhg_batch_t *h, int64_t K, void *tape, size_t tape_bytes,
@@ -2293,19 +2308,13 @@ int pdhg_batch_unrolled_backward(pdhg_batch_t *h, int64_t K, void *tape, size_t 
     size_t need = 0;
     if (!tape_carve(h, K, (char *)tape, &t, &need)) return PDHG_E_INVALID;
     if (!tape || ((uintptr_t)tape & 255u) || tape_bytes < need) return PDHG_E_WORKSPACE;
+    // the tape must come from the last forward call, with nothing changed
+    // since: the windows are recomputed from the batch's current data
+    if (!h->tape_ok || tape != h->tape_of || K != h->tape_K) return PDHG_E_INVALID;
     const BDev &d = h->d;
     hipStream_t s = h->stream;
     const size_t N = (size_t)d.N, M = (size_t)d.M;
     const long long NM = (long long)d.N + d.M;
-    // LPs stopped by an earlier solve skip their SpMV blocks, so their
-    // iterates are copied to the tape whole rather than by the epilogues
-    bool any_done = false;
-    {
-        std::vector<BLP> cur;
-        const int rc0 = b_read_lps(h, cur);
-        if (rc0) return rc0;
-        for (const BLP &L : cur) any_done |= L.done != 0;
-    }
     // dL/dx in, dL/dc out in the caller's column order; the sweep runs in
     // the internal one (gA follows the entries, which keep their places)
     if (d.cperm) launch_gather(dLdx, d.cperm, d.N, t.xh, s);
@@ -2333,16 +2342,11 @@ int pdhg_batch_unrolled_backward(pdhg_batch_t *h, int64_t K, void *tape, size_t 
             BCK(hipMemcpyAsync(d.q, t.cq + w * M, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
             BCK(hipMemcpyAsync(t.sy, d.y, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
         }
-        for (long long q = 1; q <= len; ++q) {
-            if (any_done) {
-                b_iteration(d, 0, s);
-                BCK(hipMemcpyAsync(t.sx + q * N, d.x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-                if (M) BCK(hipMemcpyAsync(t.sy + q * M, d.y, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
-            } else {
-                // every block runs, so the epilogues write the whole iterate
-                b_iteration(d, 0, s, t.sx + q * N, M ? t.sy + q * M : nullptr);
-            }
-        }
+        // After the forward call no LP has stopped (its checks have no
+        // stopping test), so every block runs and the epilogues write the
+        // whole iterate into the tape.
+        for (long long q = 1; q <= len; ++q)
+            b_iteration(d, 0, s, t.sx + q * N, M ? t.sy + q * M : nullptr);
         for (long long q = len; q >= 1; --q) {
             const double *xt = t.sx + q * N, *xp = t.sx + (q - 1) * N;
             const double *yt = t.sy + q * M, *yp = t.sy + (q - 1) * M;

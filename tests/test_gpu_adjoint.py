@@ -146,3 +146,31 @@ def test_differentiation_workload_against_finite_differences(lib):
             assert g == pytest.approx(fd, rel=1e-5, abs=1e-7)
             checked += 1
     assert checked >= 10
+
+
+def test_backward_needs_the_tape_of_the_last_forward(lib):
+    """The backward call recomputes its windows from the batch's current
+    data: it runs on the tape of the last forward call (repeatable, same
+    gradients), and is refused after a solve, a step or another forward."""
+    lps = [lpgen.small_dense(1), lpgen.column_count_lp(21, 300, 600, per_col=4, bounds="mix")]
+    b = lib.BatchSolver(lps, params=[{"eta": 0.05}, {"eta": 0.05}])
+    N = sum(lp.n for lp in lps)
+    ones = torch.ones(N, dtype=torch.float64, device="cuda:0")
+    _, tape = b.unrolled_forward(90)
+    g1 = b.unrolled_backward(tape, ones)
+    g2 = b.unrolled_backward(tape, ones)
+    for a, c in zip(g1, g2):
+        assert torch.equal(a, c)
+    b.solve(30, 0.0)
+    with pytest.raises(lib.PdhgError):
+        b.unrolled_backward(tape, ones)
+    _, tape2 = b.unrolled_forward(90)
+    with pytest.raises(lib.PdhgError):
+        b.unrolled_backward(tape, ones)
+    b.step(3)
+    with pytest.raises(lib.PdhgError):
+        b.unrolled_backward(tape2, ones)
+    _, tape3 = b.unrolled_forward(90)
+    g3 = b.unrolled_backward(tape3, ones)
+    for a, c in zip(g1, g3):
+        assert torch.equal(a, c)
