@@ -215,36 +215,44 @@ __device__ __forceinline__ bool bad_pair(double a, double d) {
     return a != a || d != d || a < 0.0 || d < 0.0 || a == INFINITY;
 }
 
-// deterministic exclusive prefix (from the left) and suffix (from the right)
-// of one double per thread
+// Deterministic exclusive prefix (from the left) and suffix (from the
+// right) of one double per thread: a scan inside each wave by shuffles
+// (the exclusive value is the neighbour's inclusive one, so no subtraction
+// enters), then the totals of the waves before (after) added in wave
+// order.  sh holds kWG / 64 doubles; two barriers.
 __device__ double block_excl_prefix(double v, double *sh) {
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int off = 1; off < kWG; off <<= 1) {
-        double o = t >= off ? sh[t - off] : 0.0;
-        __syncthreads();
-        sh[t] += o;
-        __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const double y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
     }
-    double r = t ? sh[t - 1] : 0.0;
+    double ex = __shfl_up(x, 1, 64);
+    if (lane == 0) ex = 0.0;
+    if (lane == 63) sh[w] = x;
     __syncthreads();
-    return r;
+    double base = 0.0;
+    for (int q = 0; q < w; ++q) base += sh[q];
+    __syncthreads();
+    return base + ex;
 }
 
 __device__ double block_excl_suffix(double v, double *sh) {
-    const int p = kWG - 1 - threadIdx.x;
-    sh[p] = v;
-    __syncthreads();
-    for (int off = 1; off < kWG; off <<= 1) {
-        double o = p >= off ? sh[p - off] : 0.0;
-        __syncthreads();
-        sh[p] += o;
-        __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    constexpr int NW = kWG / 64;
+    double x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const double y = __shfl_down(x, off, 64);
+        if (lane + off < 64) x += y;
     }
-    double r = p ? sh[p - 1] : 0.0;
+    double ex = __shfl_down(x, 1, 64);
+    if (lane == 63) ex = 0.0;
+    if (lane == 0) sh[w] = x;
     __syncthreads();
-    return r;
+    double base = 0.0;
+    for (int q = NW - 1; q > w; --q) base += sh[q];
+    __syncthreads();
+    return base + ex;
 }
 
 struct ChooseShared {
