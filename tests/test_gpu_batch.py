@@ -178,3 +178,21 @@ def test_members_without_rows_and_with_empty_columns(lib):
         done = k
         for i, o in enumerate(orcs):
             _cmp(o, b, i)
+
+
+def test_batch_paired_running_sums_are_exact(lib):
+    """As for one LP: sixty one-iteration steps and one sixty-iteration step
+    give bitwise the same iterates and averages."""
+    lps = batch_lps()
+    params = [{"eta": oracle.Oracle(lp).info()["eta"]} for lp in lps]
+    a = lib.BatchSolver(lps, params=params, restart_mode=0)
+    b = lib.BatchSolver(lps, params=params, restart_mode=0)
+    for _ in range(60):
+        a.step(1)
+    b.step(60)
+    for i in range(len(lps)):
+        for which in (0, 1):
+            xa, ya = a.get_iterate(i, which)
+            xb, yb = b.get_iterate(i, which)
+            torch.cuda.synchronize()
+            assert torch.equal(xa, xb) and torch.equal(ya, yb), (i, which)

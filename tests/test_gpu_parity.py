@@ -462,3 +462,25 @@ def test_invalid_lp_is_rejected(lib):
     bad.vals[0] = np.nan
     with pytest.raises(lib.PdhgError):
         lib.Solver(bad, eta=0.1)
+
+
+@pytest.mark.parametrize("name", ["mixed_inf", "powerlaw"])
+def test_paired_running_sums_are_exact(lib, name):
+    """The running sums take two iterates every other iteration, (S + x_k)
+    + x_{k+1}, which rounds exactly as two single additions: sixty
+    one-iteration steps (single additions only) and one sixty-iteration
+    step give bitwise the same iterates and averages."""
+    lp = get_case(name)
+    _say("paired sums", name)
+    eta = oracle.Oracle(lp).info()["eta"]
+    a = lib.Solver(lp, eta=eta, restart_mode=lib.RESTART_NONE)
+    b = lib.Solver(lp, eta=eta, restart_mode=lib.RESTART_NONE)
+    assert a.info()["one_workgroup"] == 0
+    for _ in range(60):
+        a.step(1)
+    b.step(60)
+    for which in (0, 1):
+        xa, ya = a.get_iterate(which)
+        xb, yb = b.get_iterate(which)
+        torch.cuda.synchronize()
+        assert torch.equal(xa, xb) and torch.equal(ya, yb), which
