@@ -389,6 +389,27 @@ int pdhg_batch_get_check_log(pdhg_batch_t *h, int32_t index, pdhg_check_record *
                              int64_t max, int64_t *count);
 void pdhg_batch_destroy(pdhg_batch_t *h);
 
+/* SpMV schedule of the batch's products: `placement` 1 runs the merge-path
+ * blocks of each LP on one XCD (largest LP first onto the least loaded
+ * XCD), 0 runs the blocks in row order; `index16` 1 gathers through 16-bit
+ * indices relative to each LP (available when every LP has at most 65,536
+ * rows and columns), 0 through the 32-bit ones.  Both are set at creation
+ * to (1, 1 when available). */
+typedef struct pdhg_batch_tune {
+    int32_t placement, index16;   /* the schedule in use                        */
+    int32_t candidates, reserved; /* schedules timed                             */
+    int32_t tried_placement[4], tried_index16[4];
+    double ms[4];                 /* mean time of one A'y and one A x, ms       */
+} pdhg_batch_tune;
+/* Times `iters` pairs of products (A'y and A x of the current point, into
+ * scratch vectors; the iterates, averages and counters stay as they are)
+ * for each schedule and keeps the fastest.  *out (host, may be NULL).
+ * Synchronizes.  PDHG_E_INVALID for iters outside 1..10000. */
+int pdhg_batch_autotune(pdhg_batch_t *h, int32_t iters, pdhg_batch_tune *out);
+/* Sets a schedule (see pdhg_batch_tune); PDHG_E_INVALID for a flag other
+ * than 0 or 1, or index16 = 1 when 16-bit indices are not available. */
+int pdhg_batch_set_schedule(pdhg_batch_t *h, int32_t placement, int32_t index16);
+
 /* Replace the problem data of the whole batch with device arrays in the
  * concatenated layout (c: sum n_i, b: sum m_i, vals: sum nnz_i, each LP's
  * entries in its own CSR order); the sparsity pattern and the step sizes

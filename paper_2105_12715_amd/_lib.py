@@ -75,6 +75,13 @@ class Tune(C.Structure):
                 ("from_cache", C.c_int32), ("reserved", C.c_int32)]
 
 
+class BatchTune(C.Structure):
+    _fields_ = [("placement", C.c_int32), ("index16", C.c_int32),
+                ("candidates", C.c_int32), ("reserved", C.c_int32),
+                ("tried_placement", C.c_int32 * 4), ("tried_index16", C.c_int32 * 4),
+                ("ms", C.c_double * 4)]
+
+
 class CheckRecord(C.Structure):
     _fields_ = [("v", C.c_double * 14)]
 
@@ -119,6 +126,10 @@ def load(build_if_missing: bool = True):
     L.pdhg_solve.restype = C.c_int
     L.pdhg_autotune.argtypes = [P, i32, i32, C.POINTER(Tune)]
     L.pdhg_autotune.restype = C.c_int
+    L.pdhg_batch_autotune.argtypes = [P, i32, C.POINTER(BatchTune)]
+    L.pdhg_batch_autotune.restype = C.c_int
+    L.pdhg_batch_set_schedule.argtypes = [P, i32, i32]
+    L.pdhg_batch_set_schedule.restype = C.c_int
     L.pdhg_solve_many_workspace_bytes.argtypes = [i32]
     L.pdhg_solve_many_workspace_bytes.restype = sz
     L.pdhg_solve_many.argtypes = [P, i32, i64, d, P, sz, P]
@@ -530,6 +541,22 @@ class BatchSolver:
         _check(self._L.pdhg_batch_get_info(self.h, int(index), C.byref(out)),
                "pdhg_batch_get_info")
         return {k: getattr(out, k) for k, _ in Info._fields_}
+
+    def autotune(self, iters=20):
+        """pdhg_batch_autotune: time the SpMV schedules (XCD placement or
+        row order; 16-bit or 32-bit indices) and keep the fastest; returns
+        the schedule in use and {(placement, index16): ms per pair of
+        products}."""
+        t = BatchTune()
+        _check(self._L.pdhg_batch_autotune(self.h, int(iters), C.byref(t)),
+               "pdhg_batch_autotune")
+        return dict(placement=t.placement, index16=t.index16,
+                    ms={(int(t.tried_placement[i]), int(t.tried_index16[i])): float(t.ms[i])
+                        for i in range(t.candidates)})
+
+    def set_schedule(self, placement, index16):
+        _check(self._L.pdhg_batch_set_schedule(self.h, int(placement), int(index16)),
+               "pdhg_batch_set_schedule")
 
     # -- differentiation -------------------------------------------------
     @property

@@ -75,7 +75,8 @@ struct BDev {
     int nbcls;
     int *brA, *brT;
     int nblkA, nblkT;
-    int *xpA, *xpT;        // workgroup -> merge-path block (XCD placement), -1: none
+    int *xpA, *xpT;        // workgroup -> merge-path block (XCD placement), -1: none;
+                           // null: workgroup i runs block i
     int nslotA, nslotT;    // workgroups of the SpMV launches
     int *lp_row, *lp_col;
     double *tau_col, *sigma_row;  // step of each column / row's LP, 0 once it converged
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(kWG) void k_bspmv(const int *__restrict__ rp, const
                                                const unsigned short *__restrict__ ci16,
                                                const int *__restrict__ lp_base) {
     __shared__ SpmvShared lds;
-    const int c = xp[blockIdx.x];
+    const int c = xp ? xp[blockIdx.x] : (int)blockIdx.x;  // null: blocks in row order
     if (c < 0) return;
     const int r0 = br[c], r1 = br[c + 1];
     if (r0 >= r1) return;
@@ -1668,6 +1669,12 @@ struct pdhg_batch_handle {
     const void *tape_of = nullptr;
     int64_t tape_K = -1;
     bool tape_ok = false;
+    // the SpMV schedules (pdhg_batch_set_schedule): the XCD placement lists
+    // and the 16-bit indices built at creation
+    int *xpA_x = nullptr, *xpT_x = nullptr;
+    int nslotA_x = 0, nslotT_x = 0;
+    unsigned short *ci16_x = nullptr, *tci16_x = nullptr;
+    int placement = 1, index16 = 0;
 };
 
 #define BCK(expr)                                  \
@@ -1960,6 +1967,14 @@ int pdhg_batch_create(int32_t count, const pdhg_lp *lps, const pdhg_params *prm,
             if (hipMemcpyAsync(d.xpA, xa.data(), sizeof(int) * xa.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
                 hipMemcpyAsync(d.xpT, xt.data(), sizeof(int) * xt.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess) { rc = PDHG_E_HIP; break; }
+            h->xpA_x = d.xpA;
+            h->xpT_x = d.xpT;
+            h->nslotA_x = d.nslotA;
+            h->nslotT_x = d.nslotT;
+            h->ci16_x = d.ci16;
+            h->tci16_x = d.tci16;
+            h->placement = 1;
+            h->index16 = d.ci16 ? 1 : 0;
         }
         hipLaunchKernelGGL(k_bnorm_partials, dim3(d.nblk), dim3(kWG), 0, s, d);
         hipLaunchKernelGGL(k_bnorm_final, dim3(count), dim3(kWG), 0, s, d);
@@ -2136,6 +2151,77 @@ int pdhg_batch_get_iterate(pdhg_batch_t *h, int32_t index, int32_t which, double
     const int mx = L.n > L.m ? L.n : L.m;
     hipLaunchKernelGGL(k_bget, dim3(div_up(mx, kWG)), dim3(kWG), 0, h->stream, h->d, index, which, x, y);
     return b_last_error();
+}
+
+int pdhg_batch_set_schedule(pdhg_batch_t *h, int32_t placement, int32_t index16) {
+    if (!h || (placement != 0 && placement != 1) || (index16 != 0 && index16 != 1) ||
+        (index16 && !h->ci16_x))
+        return PDHG_E_INVALID;
+    BDev &d = h->d;
+    d.xpA = placement ? h->xpA_x : nullptr;
+    d.xpT = placement ? h->xpT_x : nullptr;
+    d.nslotA = placement ? h->nslotA_x : d.nblkA;
+    d.nslotT = placement ? h->nslotT_x : d.nblkT;
+    d.ci16 = index16 ? h->ci16_x : nullptr;
+    d.tci16 = index16 ? h->tci16_x : nullptr;
+    h->placement = placement;
+    h->index16 = index16;
+    h->g_valid = false;  // the recorded graph holds the old launch arguments
+    return PDHG_OK;
+}
+
+int pdhg_batch_autotune(pdhg_batch_t *h, int32_t iters, pdhg_batch_tune *out) {
+    if (!h || iters < 1 || iters > 10000) return PDHG_E_INVALID;
+    pdhg_batch_tune r;
+    memset(&r, 0, sizeof(r));
+    hipStream_t s = h->stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return PDHG_E_HIP;
+    }
+    int rc = PDHG_OK, best_p = h->placement, best_i = h->index16, k = 0;
+    double best = INFINITY;
+    for (int pl = 1; pl >= 0 && rc == PDHG_OK; --pl) {
+        for (int ix = h->ci16_x ? 1 : 0; ix >= 0 && rc == PDHG_OK; --ix) {
+            (void)pdhg_batch_set_schedule(h, pl, ix);
+            const BDev &d = h->d;
+            // A'y and A x of the current point into the check's scratch
+            // vectors (rewritten by every check before use)
+            bspmv_T(d, d.y, d.aty, 0, s);
+            bspmv_A(d, d.x, d.axb, 0, s);
+            float ms = 0.f;
+            if (hipEventRecord(e0, s) != hipSuccess) rc = PDHG_E_HIP;
+            for (int q = 0; q < iters && rc == PDHG_OK; ++q) {
+                bspmv_T(d, d.y, d.aty, 0, s);
+                bspmv_A(d, d.x, d.axb, 0, s);
+            }
+            if (rc == PDHG_OK && (hipEventRecord(e1, s) != hipSuccess ||
+                                  hipEventSynchronize(e1) != hipSuccess ||
+                                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = PDHG_E_HIP;
+            if (rc == PDHG_OK) rc = b_last_error();
+            if (rc != PDHG_OK) break;
+            const double per = (double)ms / iters;
+            r.tried_placement[k] = pl;
+            r.tried_index16[k] = ix;
+            r.ms[k] = per;
+            ++k;
+            if (per < best) {
+                best = per;
+                best_p = pl;
+                best_i = ix;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    r.candidates = k;
+    (void)pdhg_batch_set_schedule(h, best_p, best_i);
+    r.placement = h->placement;
+    r.index16 = h->index16;
+    if (out) *out = r;
+    return rc;
 }
 
 int pdhg_batch_get_info(pdhg_batch_t *h, int32_t index, pdhg_info *out) {

@@ -196,3 +196,49 @@ def test_batch_paired_running_sums_are_exact(lib):
             xb, yb = b.get_iterate(i, which)
             torch.cuda.synchronize()
             assert torch.equal(xa, xb) and torch.equal(ya, yb), (i, which)
+
+
+@pytest.mark.parametrize("placement,index16", [(1, 1), (1, 0), (0, 1), (0, 0)])
+def test_batch_schedules_follow_the_oracle(lib, placement, index16):
+    """Every SpMV schedule of the batch (XCD placement or row order; 16-bit
+    or 32-bit indices) gives the oracle's iterates."""
+    lps = [lpgen.batch_member(2), lpgen.batch_member(3), lpgen.small_dense(5),
+           lpgen.column_count_lp(13, 600, 1300, per_col=5, bounds="mixed_inf", ge_frac=0.5)]
+    etas = [oracle.Oracle(lp).info()["eta"] for lp in lps]
+    orcs = [oracle.Oracle(lp, eta=e) for lp, e in zip(lps, etas)]
+    b = lib.BatchSolver(lps, params=[{"eta": e} for e in etas])
+    b.set_schedule(placement, index16)
+    b.solve(307, 0.0)
+    for i, o in enumerate(orcs):
+        o.solve(307, 0.0)
+        _cmp(o, b, i)
+
+
+def test_batch_autotune(lib):
+    """The tuner times the four schedules on products into scratch vectors:
+    the iterates stay bitwise as they were, the fastest schedule is kept,
+    and the solve goes on like the oracle's."""
+    lps = [lpgen.batch_member(i) for i in range(4)]
+    etas = [oracle.Oracle(lp).info()["eta"] for lp in lps]
+    orcs = [oracle.Oracle(lp, eta=e) for lp, e in zip(lps, etas)]
+    b = lib.BatchSolver(lps, params=[{"eta": e} for e in etas])
+    b.solve(90, 0.0)
+    before = [[t.clone() for t in b.get_iterate(i, w)] for i in range(4) for w in (0, 1)]
+    r = b.autotune(5)
+    _say("batch tune", r)
+    after = [[t.clone() for t in b.get_iterate(i, w)] for i in range(4) for w in (0, 1)]
+    for p, q in zip(before, after):
+        assert torch.equal(p[0], q[0]) and torch.equal(p[1], q[1])
+    assert len(r["ms"]) == 4
+    assert min(r["ms"], key=r["ms"].get) == (r["placement"], r["index16"])
+    b.solve(210, 0.0)
+    for i, o in enumerate(orcs):
+        o.solve(300, 0.0)
+        _cmp(o, b, i)
+    # 16-bit indices need every LP within 65,536 rows and columns
+    wide = lib.BatchSolver([lpgen.column_count_lp(31, 1200, 70_000, per_col=1, bounds="mix")],
+                           params=[{"eta": 0.01}])
+    with pytest.raises(lib.PdhgError):
+        wide.set_schedule(1, 1)
+    wide.set_schedule(0, 0)
+    assert len(wide.autotune(2)["ms"]) == 2
