@@ -407,7 +407,8 @@ typedef struct pdhg_batch_tune {
  * Synchronizes.  PDHG_E_INVALID for iters outside 1..10000. */
 int pdhg_batch_autotune(pdhg_batch_t *h, int32_t iters, pdhg_batch_tune *out);
 /* Sets a schedule (see pdhg_batch_tune); PDHG_E_INVALID for a flag other
- * than 0 or 1, or index16 = 1 when 16-bit indices are not available. */
+ * than 0 or 1, or index16 = 1 when 16-bit indices are not available.  No
+ * schedule changes a result: every row is summed in the same order. */
 int pdhg_batch_set_schedule(pdhg_batch_t *h, int32_t placement, int32_t index16);
 
 /* Replace the problem data of the whole batch with device arrays in the

@@ -242,3 +242,19 @@ def test_batch_autotune(lib):
         wide.set_schedule(1, 1)
     wide.set_schedule(0, 0)
     assert len(wide.autotune(2)["ms"]) == 2
+
+
+def test_batch_schedules_give_bitwise_equal_iterates(lib):
+    """Placement and index width change which workgroup runs a block and how
+    it addresses the gathered vector, not the order of any sum."""
+    lps = [lpgen.batch_member(2), lpgen.small_dense(5), lpgen.batch_member(3)]
+    params = [{"eta": oracle.Oracle(lp).info()["eta"]} for lp in lps]
+    runs = []
+    for placement, index16 in [(1, 1), (0, 0), (1, 0), (0, 1)]:
+        b = lib.BatchSolver(lps, params=params)
+        b.set_schedule(placement, index16)
+        b.solve(331, 0.0)
+        runs.append([[t.clone() for t in b.get_iterate(i, w)] for i in range(3) for w in (0, 1)])
+    for other in runs[1:]:
+        for p, q in zip(runs[0], other):
+            assert torch.equal(p[0], q[0]) and torch.equal(p[1], q[1])
