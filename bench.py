@@ -407,7 +407,9 @@ def run_many(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=167, help="timed blocks of 30 iterations")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed blocks of 30 iterations (default 167; 2000 for the small LP, "
+                         "whose blocks take microseconds)")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="large",
                     choices=["large", "medium", "small", "batch", "table2", "adjoint", "many"])
@@ -477,6 +479,8 @@ def main():
     log(f"setup (validate, transpose, power iteration {info['power_iters_used']} steps) "
         f"{time.perf_counter() - t0:.2f}s, eta={info['eta']:.6g}")
     P = 30
+    if args.steps is None:
+        args.steps = 2000 if args.workload == "small" else 167
     s.solve(args.warmup * P, 0.0)
     torch.cuda.synchronize()
     log("warmup done")
