@@ -18,6 +18,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pdhg_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# the same source with its per-coordinate loops and products on every host
+# core (-DORC_OPENMP); bitwise equal results, used for the all-cores CPU
+# baseline
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 MODE_NONE, MODE_ADAPTIVE, MODE_FLEXIBLE, MODE_FIXED = 0, 1, 2, 3
 METHOD_PDHG, METHOD_EGM = 0, 1
@@ -25,27 +29,45 @@ KKT_RELATIVE, KKT_PAPER_ABS, KKT_MAX_ABS = 0, 1, 2
 REC = 14
 
 _lib = None
+_lib_omp = None
+
+_CFLAGS = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC",
+           "-shared", "-Wall", "-Wno-unused-function"]
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no fused multiply-add, no fast math)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call([
-            "gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
-            "-fPIC", "-shared", "-Wall", "-Wno-unused-function", "-o", tmp,
-            _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile the oracle with gcc (no fused multiply-add, no fast math):
+    the plain sequential build and the OpenMP build of the same source."""
+    for lib, extra in ((_LIB, []), (_LIB_OMP, ["-DORC_OPENMP", "-fopenmp"])):
+        if force or not os.path.exists(lib):
+            tmp = lib + ".tmp"
+            subprocess.check_call([*_CFLAGS, *extra, "-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, lib)
     return _LIB
 
 
-def _load():
-    global _lib
+def threads(parallel=True):
+    """Threads the chosen build runs its parallel loops on (1: plain)."""
+    return int(_load(parallel).orc_threads())
+
+
+def _load(parallel=False):
+    global _lib, _lib_omp
+    if parallel:
+        if _lib_omp is None:
+            if not os.path.exists(_LIB_OMP):
+                build(force=False)
+            _lib_omp = _declare(C.CDLL(_LIB_OMP))
+        return _lib_omp
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB):
-        build()
-    L = C.CDLL(_LIB)
+        build(force=False)
+    _lib = _declare(C.CDLL(_LIB))
+    return _lib
+
+
+def _declare(L):
     P = C.c_void_p
     i64, i32, d = C.c_int64, C.c_int32, C.c_double
     L.orc_create.restype = P
@@ -86,7 +108,8 @@ def _load():
     L.orc_branch_signature.argtypes = [P, i64]
     L.orc_restart_iters.restype = i64
     L.orc_restart_iters.argtypes = [P, i64, P, i64]
-    _lib = L
+    L.orc_threads.restype = i32
+    L.orc_threads.argtypes = []
     return L
 
 
@@ -135,8 +158,9 @@ class Oracle:
     def __init__(self, lp, eta=0.0, omega=1.0, beta=float(np.exp(-1.0)),
                  check_period=30, tau0=1, mode=MODE_ADAPTIVE, fixed_len=0,
                  kkt_kind=KKT_RELATIVE, power_iters=1000, power_tol=1e-10,
-                 method=METHOD_PDHG):
-        L = _load()
+                 method=METHOD_PDHG, parallel=False):
+        # parallel: the OpenMP build (bitwise the same results, all cores)
+        L = _load(parallel)
         self._L = L
         self.m, self.n = int(lp.m), int(lp.n)
         self._keep = [np.ascontiguousarray(lp.row_ptr, dtype=np.int32),

@@ -41,6 +41,14 @@
  *     prop:assumption-one-holds, so the reciprocal is used).
  * Compile with -O2 -ffp-contract=off so that no fused multiply-add changes
  * the rounding of the written formulas.
+ *
+ * Built with -DORC_OPENMP -fopenmp, the same source runs the products and
+ * the per-coordinate loops of an iteration on every host core (for the
+ * CPU baseline): each parallel loop writes only its own outputs, and A'y
+ * is taken row by row of an explicit A' whose rows keep the entries in
+ * increasing row of A, the order in which the plain build accumulates
+ * them.  Every sum (norms, KKT parts, the trust region) stays sequential.
+ * The two builds therefore give bitwise equal results.
  */
 #include <math.h>
 #include <stdint.h>
@@ -54,6 +62,12 @@
 
 #define ORC_METHOD_PDHG 0
 #define ORC_METHOD_EGM 1
+
+#ifdef ORC_OPENMP
+#define ORC_PAR_FOR _Pragma("omp parallel for schedule(static, 2048)")
+#else
+#define ORC_PAR_FOR
+#endif
 
 #define ORC_KKT_RELATIVE 0
 #define ORC_KKT_PAPER_ABS 1
@@ -79,6 +93,9 @@ typedef struct orc {
     /* check log */
     double *log;
     int64_t log_len, log_cap;
+    /* explicit A' for the row-parallel A'y of the ORC_OPENMP build */
+    int32_t *trp, *tci;
+    double *tv;
 } orc_t;
 
 /* ------------------------------------------------------------------ */
@@ -88,6 +105,7 @@ typedef struct orc {
 /* out = A x : (A x)_i = sum_k A_ik x_k over the stored entries of row i. */
 static void mat_vec(const orc_t *o, const double *x, double *out)
 {
+    ORC_PAR_FOR
     for (int64_t i = 0; i < o->m; ++i) {
         double s = 0.0;
         for (int32_t p = o->rp[i]; p < o->rp[i + 1]; ++p)
@@ -99,6 +117,19 @@ static void mat_vec(const orc_t *o, const double *x, double *out)
 /* out = A' y : (A'y)_j = sum_i A_ij y_i, accumulated in increasing i. */
 static void mat_tvec(const orc_t *o, const double *y, double *out)
 {
+#ifdef ORC_OPENMP
+    if (o->trp) {
+        /* the same sums, one row of A' per column j, entries in increasing i */
+        ORC_PAR_FOR
+        for (int64_t j = 0; j < o->n; ++j) {
+            double s = 0.0;
+            for (int32_t q = o->trp[j]; q < o->trp[j + 1]; ++q)
+                s += o->tv[q] * y[o->tci[q]];
+            out[j] = s;
+        }
+        return;
+    }
+#endif
     for (int64_t j = 0; j < o->n; ++j) out[j] = 0.0;
     for (int64_t i = 0; i < o->m; ++i)
         for (int32_t p = o->rp[i]; p < o->rp[i + 1]; ++p)
@@ -439,6 +470,12 @@ orc_t *orc_create(int64_t m, int64_t n, const int32_t *rp, const int32_t *ci,
     o->mode = mode;
     o->fixed_len = fixed_len;
     o->kkt_kind = kkt_kind;
+#ifdef ORC_OPENMP
+    o->trp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    o->tci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    o->tv = dalloc(nnz);
+    orc_transpose(m, n, o->rp, o->ci, o->v, o->trp, o->tci, o->tv, NULL);
+#endif
     o->sigma_max = 0.0;
     if (eta > 0.0) {
         o->eta = eta;
@@ -475,8 +512,17 @@ void orc_destroy(orc_t *o)
     free(o->sx); free(o->sy); free(o->ax); free(o->aty); free(o->xa); free(o->ya);
     free(o->axa); free(o->atya); free(o->xn); free(o->yn); free(o->e);
     free(o->ga); free(o->gd); free(o->xt); free(o->yt); free(o->log);
+    free(o->trp); free(o->tci); free(o->tv);
     free(o);
 }
+
+/* threads the parallel loops use (1 for the plain build) */
+#ifdef ORC_OPENMP
+#include <omp.h>
+int32_t orc_threads(void) { return (int32_t)omp_get_max_threads(); }
+#else
+int32_t orc_threads(void) { return 1; }
+#endif
 
 /* scalar info: eta, tau, sigma, sigma_max, k, t, restarts, rho_prev */
 void orc_info(const orc_t *o, double *out)
@@ -495,7 +541,9 @@ static void average(orc_t *o, double *xa, double *ya)
         return;
     }
     double tt = (double)o->t;
+    ORC_PAR_FOR
     for (int64_t j = 0; j < o->n; ++j) xa[j] = o->sx[j] / tt;
+    ORC_PAR_FOR
     for (int64_t i = 0; i < o->m; ++i) ya[i] = o->sy[i] / tt;
 }
 
@@ -518,10 +566,13 @@ static void pdhg_step1(orc_t *o)
 {
     int64_t n = o->n, m = o->m;
     mat_tvec(o, o->y, o->aty);
+    ORC_PAR_FOR
     for (int64_t j = 0; j < n; ++j)
         o->xn[j] = clampd(o->x[j] - o->tau * (o->c[j] - o->aty[j]), o->l[j], o->u[j]);
+    ORC_PAR_FOR
     for (int64_t j = 0; j < n; ++j) o->e[j] = 2.0 * o->xn[j] - o->x[j];
     mat_vec(o, o->e, o->ax);
+    ORC_PAR_FOR
     for (int64_t i = 0; i < m; ++i) {
         double yy = o->y[i] + o->sigma * (o->b[i] - o->ax[i]);
         if (o->kind[i] && yy < 0.0) yy = 0.0;
@@ -529,7 +580,9 @@ static void pdhg_step1(orc_t *o)
     }
     memcpy(o->x, o->xn, sizeof(double) * (size_t)n);
     memcpy(o->y, o->yn, sizeof(double) * (size_t)m);
+    ORC_PAR_FOR
     for (int64_t j = 0; j < n; ++j) o->sx[j] += o->x[j];
+    ORC_PAR_FOR
     for (int64_t i = 0; i < m; ++i) o->sy[i] += o->y[i];
     o->t += 1;
     o->k += 1;

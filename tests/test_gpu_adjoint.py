@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 from paper_2105_12715_amd import lpgen
+from tests.parity import assert_points_match
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -62,10 +63,10 @@ def test_gradients_match_oracle_reverse_pass(lib, mode, K):
     for i, (lp, e) in enumerate(zip(lps, etas)):
         o = oracle.Oracle(lp, eta=e, mode=mode)
         loss, ogc, ogb, ogA, oxk = o.unrolled_grad(K, xts[i])
-        assert rel(xks[i], oxk) <= 1e-10
-        assert rel(gcs[i], ogc) <= 1e-8, (i, rel(gcs[i], ogc))
-        assert rel(gbs[i], ogb) <= 1e-8, (i, rel(gbs[i], ogb))
-        assert rel(gAs[i], ogA) <= 1e-8, (i, rel(gAs[i], ogA))
+        assert_points_match(xks[i], oxk, 1e-10, f"LP {i} x_K")
+        assert_points_match(gcs[i], ogc, 1e-8, f"LP {i} dL/dc")
+        assert_points_match(gbs[i], ogb, 1e-8, f"LP {i} dL/db")
+        assert_points_match(gAs[i], ogA, 1e-8, f"LP {i} dL/dA")
 
 
 def test_autograd_function_and_set_data(lib):
@@ -88,7 +89,7 @@ def test_autograd_function_and_set_data(lib):
     xk3, _ = b.unrolled_forward(240)
     lp0 = lpgen.LP(**{**lps[0].__dict__, "c": lps[0].c * 1.01})
     o = oracle.Oracle(lp0, eta=etas[0])
-    assert rel(xk3[: lps[0].n].cpu().numpy(), o.unrolled_value(240)) <= 1e-10
+    assert_points_match(xk3[: lps[0].n].cpu().numpy(), o.unrolled_value(240), 1e-10, "x_K")
 
 
 def test_differentiation_workload_against_finite_differences(lib):
@@ -110,7 +111,9 @@ def test_differentiation_workload_against_finite_differences(lib):
     # the oracle's reverse pass on one member
     o = oracle.Oracle(lps[0], eta=etas[0])
     loss, ogc, ogb, ogA, oxk = o.unrolled_grad(K, xts[0])
-    assert rel(gcs[0], ogc) <= 1e-8 and rel(gbs[0], ogb) <= 1e-8 and rel(gAs[0], ogA) <= 1e-8
+    assert_points_match(gcs[0], ogc, 1e-8, "dL/dc")
+    assert_points_match(gbs[0], ogb, 1e-8, "dL/db")
+    assert_points_match(gAs[0], ogA, 1e-8, "dL/dA")
     _say("oracle reverse matches")
     rng = np.random.default_rng(5200)
     picks = [("c", 7), ("b", 7), ("A", 6)]

@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 from paper_2105_12715_amd import lpgen
+from tests.parity import assert_points_match
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -46,8 +47,8 @@ def _cmp(o, b, i, tol=1e-10):
     for which in (0, 1, 2):
         xo, yo = o.get(which)
         xg, yg = (t.cpu().numpy() for t in b.get_iterate(i, which))
-        r = rel(np.concatenate([xg, yg]), np.concatenate([xo, yo]))
-        assert r <= tol, (i, which, r)
+        assert_points_match(np.concatenate([xg, yg]), np.concatenate([xo, yo]), tol,
+                            f"LP {i} point {which}")
 
 
 @pytest.mark.parametrize("mode", [1, 2])
@@ -110,7 +111,8 @@ def test_batch_of_one_equals_single_solver(lib):
     s.solve(600, 0.0)
     xb, yb = (t.cpu().numpy() for t in b.get_iterate(0))
     xs, ys = (t.cpu().numpy() for t in s.get_iterate(0))
-    assert rel(np.concatenate([xb, yb]), np.concatenate([xs, ys])) <= 1e-12
+    assert_points_match(np.concatenate([xb, yb]), np.concatenate([xs, ys]), 1e-12,
+                        "batch member against its single solve")
     assert b.info(0)["restarts"] == s.info()["restarts"]
 
 

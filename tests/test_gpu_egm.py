@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 from paper_2105_12715_amd import lpgen
+from tests.parity import assert_points_match
 
 pytestmark = pytest.mark.gpu
 
@@ -59,8 +60,8 @@ def _compare_points(o, s, tol=1e-10):
     for which in (0, 1, 2):
         xo, yo = o.get(which)
         xg, yg = (t.cpu().numpy() for t in s.get_iterate(which))
-        r = rel(np.concatenate([xg, yg]), np.concatenate([xo, yo]))
-        assert r <= tol, (which, r)
+        assert_points_match(np.concatenate([xg, yg]), np.concatenate([xo, yo]), tol,
+                            f"point {which}")
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -155,7 +156,7 @@ def test_egm_weight_search(lib, name, iters):
     xg, yg = xg.cpu().numpy(), yg.cpu().numpy()
     keys = ["kkt_rel", "primal_res", "dual_res", "pobj", "dobj", "kkt_paper_abs", "kkt_max_abs"]
     for w in range(len(om)):
-        r = rel(np.concatenate([xg[w], yg[w]]), np.concatenate([xo[w], yo[w]]))
-        assert r <= 1e-10, (w, r)
+        assert_points_match(np.concatenate([xg[w], yg[w]]), np.concatenate([xo[w], yo[w]]),
+                            1e-10, f"weight {w}")
         np.testing.assert_allclose([kk[w][k] for k in keys], parts[w], rtol=1e-9, atol=1e-12)
     assert best == obest

@@ -1,11 +1,13 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle on
 the same seeded inputs.
 
-Tolerances: iterates match to a relative 1e-10 (norm of the difference
-over the norm of the oracle's iterate) over the first 1000 iterations;
-scalars that are sums of many rounded
-terms (KKT parts, rho) match to 1e-9 relative; integer work (transpose,
-restart decisions, iteration counts) matches exactly.
+Tolerances: iterates match to 1e-10 over the first 1000 iterations, both
+as a norm (||z_gpu - z_cpu|| <= 1e-10 ||z_cpu||) and coordinate by
+coordinate (|z_gpu,i - z_cpu,i| <= 1e-10 (|z_cpu,i| + ||z_cpu||_inf), see
+tests/parity.py); scalars that are sums of many rounded terms (KKT parts,
+rho) match to 1e-9 relative; products of the matrix match every row within
+the summation-order bound; integer work (transpose, restart decisions,
+iteration counts) matches exactly.
 """
 import sys
 
@@ -14,6 +16,7 @@ import pytest
 
 import oracle
 from paper_2105_12715_amd import lpgen
+from tests.parity import assert_points_match, assert_within_sum_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -111,6 +114,10 @@ def test_matvec_parity(lib, name):
     y = rng.standard_normal(lp.m)
     assert rel(to_np(s.matvec(x)), o.matvec(x)) <= 1e-14
     assert rel(to_np(s.matvec(y, transpose=True)), o.matvec_t(y)) <= 1e-14
+    absA = abs(lp.scipy_csr())
+    assert_within_sum_bound(to_np(s.matvec(x)), o.matvec(x), absA, x, "A x")
+    assert_within_sum_bound(to_np(s.matvec(y, transpose=True)), o.matvec_t(y),
+                            absA.T.tocsr(), y, "A'y")
 
 
 @pytest.mark.parametrize("name", ["small50x100", "mixed_inf", "powerlaw"])
@@ -188,13 +195,14 @@ def _pair(lp, mode, eta=None, **kw):
     return o, s
 
 
-def _compare_points(o, s, tol=1e-10):
+def _compare_points(o, s, tol=1e-10, where=""):
+    """Current point, average and anchor, each by the norm and
+    per-coordinate bounds of tests/parity.py."""
     for which in (0, 1, 2):
         xo, yo = o.get(which)
         xg, yg = (to_np(t) for t in s.get_iterate(which))
-        zo = np.concatenate([xo, yo])
-        zg = np.concatenate([xg, yg])
-        assert rel(zg, zo) <= tol, (which, rel(zg, zo))
+        assert_points_match(np.concatenate([xg, yg]), np.concatenate([xo, yo]), tol,
+                            f"{where} point {which}")
 
 
 @pytest.mark.parametrize("name", ["small50x100", "ge_rows", "mixed_inf", "powerlaw",
@@ -208,7 +216,7 @@ def test_iterates_no_restart_first_1000(lib, name):
         o.step(k - done)
         s.step(k - done)
         done = k
-        _compare_points(o, s)
+        _compare_points(o, s, where=f"k={k}")
     assert s.info()["k"] == 1000 and s.info()["t"] == 1000
 
 
@@ -229,7 +237,7 @@ def test_iterates_with_restarts_first_1000(lib, name, mode):
         o.solve(k - done, 0.0)
         s.solve(k - done, 0.0)
         done = k
-        _compare_points(o, s)
+        _compare_points(o, s, where=f"k={k}")
     lo, lg = o.log(), s.check_log()
     assert lo.shape == lg.shape == (33, 14)
     np.testing.assert_array_equal(lg[:, [0, 1, 2, 9, 10, 11]], lo[:, [0, 1, 2, 9, 10, 11]])
@@ -280,12 +288,12 @@ def test_bound_classes_and_paired_sums(lib, k, period):
         o.step(kk - done)
         s.step(kk - done)
         done = kk
-        _compare_points(o, s)
+        _compare_points(o, s, where=f"k={kk}")
     for kk in [100, 157, 400, 1000]:
         o.solve(kk - done, 0.0)
         s.solve(kk - done, 0.0)
         done = kk
-        _compare_points(o, s)
+        _compare_points(o, s, where=f"k={kk}")
     lo, lg = o.log(), s.check_log()
     assert lo.shape == lg.shape and lo.shape[0] >= 10
     np.testing.assert_array_equal(lg[:, [0, 1, 2, 9, 10, 11]], lo[:, [0, 1, 2, 9, 10, 11]])
@@ -302,7 +310,7 @@ def test_fixed_length_restarts(lib):
         o.solve(k - done, 0.0)
         s.solve(k - done, 0.0)
         done = k
-        _compare_points(o, s)
+        _compare_points(o, s, where=f"k={k}")
     assert s.info()["restarts"] == o.info()["restarts"] == 1000 // 64
 
 
@@ -372,17 +380,33 @@ def test_solve_to_1e8_matches_oracle(lib, name, budget):
 
 
 def test_medium_solve_to_1e8(lib):
-    """The 20,000 x 50,000 workload: iterate until relative KKT <= 1e-8 on
-    both sides; same iteration count and restarts."""
+    """The 20,000 x 50,000 workload solved to relative KKT <= 1e-8 by both
+    the oracle and the GPU (Algorithm 1, checks every 30 iterations):
+    both converge, with the same iteration count, restart count and
+    returned point (current or average); both KKT values are <= 1e-8; the
+    returned points match to 1e-8 (the bar of 1e-10 holds over the first
+    1000 iterations, checked above, and rounding differences grow slowly
+    over a few thousand); the oracle's own KKT at the GPU's answer is
+    <= 1e-8; the objective is the planted optimum's."""
     lp = get_case("medium20kx50k")
     _say("solve medium")
     o, s = _pair(lp, oracle.MODE_ADAPTIVE)
+    ro = o.solve(300_000, 1e-8)
+    _say("oracle", {k: v for k, v in ro.items() if k not in ("x", "y")})
     rg = s.solve(300_000, 1e-8)
     _say("gpu", rg)
-    assert rg["status"] == 0 and rg["kkt"] <= 1e-8
+    assert ro["status"] == 0 and rg["status"] == 0
+    assert rg["kkt"] <= 1e-8 and ro["kkt"] <= 1e-8
+    assert (rg["k"], rg["restarts"], rg["which"]) == (ro["k"], ro["restarts"], ro["which"])
+    assert rg["kkt"] == pytest.approx(ro["kkt"], rel=1e-6)
     x, y = (to_np(t) for t in s.get_iterate(3))
+    assert_points_match(np.concatenate([x, y]), np.concatenate([ro["x"], ro["y"]]), 1e-8,
+                        "returned point")
     assert oracle.Oracle(lp, eta=0.1).kkt_at(x, y)[0] <= 1.0001e-8
     assert rg["pobj"] == pytest.approx(lp.objective_star(), rel=1e-6)
+    lo, lg = o.log(), s.check_log()
+    assert lo.shape == lg.shape
+    np.testing.assert_array_equal(lg[:, [0, 1, 2, 9, 10, 11]], lo[:, [0, 1, 2, 9, 10, 11]])
 
 
 def test_graph_replay_matches_eager(lib):

@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 from paper_2105_12715_amd import lpgen
+from tests.parity import assert_points_match
 
 pytestmark = pytest.mark.gpu
 
@@ -97,8 +98,8 @@ def _compare_points(o_get, s, tol=1e-10):
     for which in (0, 1, 2):
         xo, yo = o_get(which)
         xg, yg = (t.cpu().numpy() for t in s.get_iterate(which))
-        r = rel(np.concatenate([xg, yg]), np.concatenate([xo, yo]))
-        assert r <= tol, (which, r)
+        assert_points_match(np.concatenate([xg, yg]), np.concatenate([xo, yo]), tol,
+                            f"point {which}")
 
 
 def _compare_logs(lo, lg, nrec):

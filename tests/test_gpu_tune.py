@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 from paper_2105_12715_amd import lpgen
+from tests.parity import assert_points_match
 
 pytestmark = pytest.mark.gpu
 
@@ -76,7 +77,8 @@ def test_autotune_keeps_state_and_parity(lib):
     for which in (0, 1, 2):
         xo, yo = o.get(which)
         xg, yg = (t.cpu().numpy() for t in s.get_iterate(which))
-        assert rel(np.concatenate([xg, yg]), np.concatenate([xo, yo])) <= 1e-10
+        assert_points_match(np.concatenate([xg, yg]), np.concatenate([xo, yo]), 1e-10,
+                            f"point {which}")
     # the same matrix again: the remembered choice, no timing
     s2 = lib.Solver(lp, eta=eta)
     r2 = s2.autotune(iters=5)

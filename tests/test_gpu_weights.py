@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 from paper_2105_12715_amd import lpgen
+from tests.parity import assert_points_match
 
 pytestmark = pytest.mark.gpu
 
@@ -58,7 +59,7 @@ def _compare(lp, omegas, iters, s, eta):
     for w in range(len(omegas)):
         zg = np.concatenate([xg[w], yg[w]])
         zo = np.concatenate([xo[w], yo[w]])
-        assert rel(zg, zo) <= 1e-10, (w, rel(zg, zo))
+        assert_points_match(zg, zo, 1e-10, f"weight {w}")
         got = [kk[w][k] for k in KEYS]
         np.testing.assert_allclose(got, parts[w], rtol=1e-9, atol=1e-12)
         assert kk[w]["kkt"] == kk[w]["kkt_paper_abs"]
@@ -104,7 +105,8 @@ def test_set_primal_weight_restarts_from_the_initial_point(lib):
         for which in (0, 1, 2):
             xo, yo = o.get(which)
             xg, yg = (t.cpu().numpy() for t in s.get_iterate(which))
-            assert rel(np.concatenate([xg, yg]), np.concatenate([xo, yo])) <= 1e-10
+            assert_points_match(np.concatenate([xg, yg]), np.concatenate([xo, yo]), 1e-10,
+                                f"point {which}")
     lo, lg = o.log(), s.check_log()
     assert lo.shape == lg.shape
     np.testing.assert_array_equal(lg[:, [0, 1, 2, 9, 10, 11]], lo[:, [0, 1, 2, 9, 10, 11]])
