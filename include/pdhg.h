@@ -276,6 +276,31 @@ int pdhg_get_iterate(pdhg_t *h, int32_t which, double *x, double *y);
  * the averaging window (t = 0).  Restart count and rho_prev are kept. */
 int pdhg_set_iterate(pdhg_t *h, const double *x, const double *y);
 
+/*
+ * Checkpoint and resume (Algorithm 1's state).  The state of a handle is
+ * everything the rest of a run depends on: the current point z^{n,t},
+ * the anchor z^{n,0}, the running sums of the window (the average's
+ * numerator), A x of the current point, the counters k, t, n (restarts)
+ * and checks, rho of the last restart point, the step size eta and primal
+ * weight omega, the last check's results (with the converged point) and
+ * the check log.  pdhg_state_bytes: size of that state for this handle
+ * (0 for NULL).  pdhg_get_state writes it into `state` (device, at least
+ * pdhg_state_bytes bytes, 256-byte aligned, owned by the caller) on the
+ * handle's stream and synchronizes.  pdhg_set_state loads such a state
+ * into a handle created for the same LP (same sizes and matrix, same
+ * method, restart scheme, check period and KKT kind; eta and omega are
+ * taken from the state), synchronizing; the run then continues exactly as
+ * the run it was taken from would have: the same iterates bit for bit.
+ * The contents are opaque (vectors in the library's internal column
+ * order).  Errors: PDHG_E_INVALID (NULL, a state of another LP or solver
+ * configuration, or not written by pdhg_get_state), PDHG_E_WORKSPACE
+ * (buffer too small or misaligned), PDHG_E_HIP.  The handle is unchanged
+ * after an error of pdhg_set_state.
+ */
+size_t pdhg_state_bytes(pdhg_t *h);
+int pdhg_get_state(pdhg_t *h, void *state, size_t bytes);
+int pdhg_set_state(pdhg_t *h, const void *state, size_t bytes);
+
 /* Scalars of the handle into *out (host).  Syncs. */
 int pdhg_get_info(pdhg_t *h, pdhg_info *out);
 
@@ -433,9 +458,11 @@ int pdhg_batch_set_data(pdhg_batch_t *h, const double *c, const double *b, const
  * checkpoint and swept in reverse.  The step sizes are constants.  The
  * backward call takes the tape and K of the last forward call, with no
  * solve, step or set_data since (else PDHG_E_INVALID); it may be repeated
- * on one forward.  After the backward call the batch's iterates are those
- * at the first window's end; call the forward or a solve before reading
- * them.
+ * on one forward.  The backward call recomputes the windows through the
+ * batch's own iterate arrays and then puts back the state the forward call
+ * ended in (x_K, y_K, the running sums and every LP's counters and
+ * restart state; the tape holds a copy), so a later step or solve
+ * continues from K exactly as it would have without the backward call.
  */
 size_t pdhg_batch_tape_bytes(pdhg_batch_t *h, int64_t K);
 int pdhg_batch_unrolled_forward(pdhg_batch_t *h, int64_t K, void *tape, size_t tape_bytes,

@@ -138,6 +138,12 @@ def load(build_if_missing: bool = True):
     L.pdhg_get_iterate.restype = C.c_int
     L.pdhg_set_iterate.argtypes = [P, P, P]
     L.pdhg_set_iterate.restype = C.c_int
+    L.pdhg_state_bytes.argtypes = [P]
+    L.pdhg_state_bytes.restype = C.c_size_t
+    L.pdhg_get_state.argtypes = [P, P, C.c_size_t]
+    L.pdhg_get_state.restype = C.c_int
+    L.pdhg_set_state.argtypes = [P, P, C.c_size_t]
+    L.pdhg_set_state.restype = C.c_int
     L.pdhg_get_info.argtypes = [P, C.POINTER(Info)]
     L.pdhg_get_info.restype = C.c_int
     L.pdhg_get_check_log.argtypes = [P, P, i64, C.POINTER(i64)]
@@ -332,6 +338,21 @@ class Solver:
         _check(self._L.pdhg_get_iterate(self.h, int(which), _ptr(x), _ptr(y)),
                "pdhg_get_iterate")
         return x, y[: self.m]
+
+    # -- checkpoint ------------------------------------------------------
+    def state_bytes(self):
+        return int(self._L.pdhg_state_bytes(self.h))
+
+    def get_state(self):
+        """The handle's solver state as a device byte tensor (opaque)."""
+        nbytes = self.state_bytes()
+        owner, view = _dev_workspace(nbytes, self.device)
+        _check(self._L.pdhg_get_state(self.h, _ptr(view), nbytes), "pdhg_get_state")
+        return (owner, view)
+
+    def set_state(self, state):
+        owner, view = state
+        _check(self._L.pdhg_set_state(self.h, _ptr(view), int(view.numel())), "pdhg_set_state")
 
     def set_iterate(self, x, y):
         import torch

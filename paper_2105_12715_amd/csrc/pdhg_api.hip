@@ -1096,6 +1096,119 @@ int pdhg_set_iterate(pdhg_t *h, const double *x, const double *y) {
     return last_error();
 }
 
+// --- checkpoint of the solver state (Algorithm 1's restart state) ----------
+// Blob layout, each region 256-byte aligned: header, DevState (counters k,
+// t, n, checks, rho_prev and the last check's results), then x, y, x0, y0,
+// S_x, S_y, q = A x, x-bar, y-bar (the solution point when the average
+// converged) in the library's internal column order, then the check log.
+namespace {
+constexpr uint64_t kStateMagic = 0x31415453474844ull;  // "DHGSTA1"
+struct StateHeader {
+    uint64_t magic;
+    int64_t m, n, nnz;
+    uint64_t sig;                 // matrix signature (sizes, sampled row starts)
+    int32_t method, restart_mode, check_period, kkt_kind;
+    double eta, omega;
+    int64_t bytes;
+};
+struct StateLayout {
+    size_t hdr, st, vec[9], log, total;
+};
+StateLayout state_layout(const Dev &d) {
+    StateLayout L;
+    size_t o = 0;
+    L.hdr = o;
+    o += al(sizeof(StateHeader));
+    L.st = o;
+    o += al(sizeof(DevState));
+    const int64_t len[9] = {d.n, d.m, d.n, d.m, d.n, d.m, d.m, d.n, d.m};
+    for (int q = 0; q < 9; ++q) {
+        L.vec[q] = o;
+        o += al(sizeof(double) * (size_t)(len[q] > 0 ? len[q] : 1));
+    }
+    L.log = o;
+    o += al(sizeof(double) * (size_t)kLogCap * kRec);
+    L.total = o;
+    return L;
+}
+}  // namespace
+
+size_t pdhg_state_bytes(pdhg_t *h) { return h ? state_layout(h->d).total : 0; }
+
+int pdhg_get_state(pdhg_t *h, void *state, size_t bytes) {
+    if (!h || !state) return PDHG_E_INVALID;
+    const Dev &d = h->d;
+    const StateLayout L = state_layout(d);
+    if (bytes < L.total || ((uintptr_t)state & 255)) return PDHG_E_WORKSPACE;
+    StateHeader hd{};
+    hd.magic = kStateMagic;
+    hd.m = d.m;
+    hd.n = d.n;
+    hd.nnz = d.nnz;
+    int rc = matrix_signature(h, &hd.sig);
+    if (rc) return rc;
+    hd.method = h->prm.method;
+    hd.restart_mode = h->prm.restart_mode;
+    hd.check_period = h->prm.check_period;
+    hd.kkt_kind = h->prm.kkt_kind;
+    hd.eta = h->eta;
+    hd.omega = d.omega;
+    hd.bytes = (int64_t)L.total;
+    char *b = (char *)state;
+    CK(hipMemcpyAsync(b + L.hdr, &hd, sizeof(hd), hipMemcpyHostToDevice, h->stream));
+    CK(hipMemcpyAsync(b + L.st, d.st, sizeof(DevState), hipMemcpyDeviceToDevice, h->stream));
+    const double *src[9] = {d.x, d.y, d.x0, d.y0, d.sx, d.sy, d.q, d.xbar, d.ybar};
+    const int64_t len[9] = {d.n, d.m, d.n, d.m, d.n, d.m, d.m, d.n, d.m};
+    for (int q = 0; q < 9; ++q)
+        if (len[q] > 0)
+            CK(hipMemcpyAsync(b + L.vec[q], src[q], sizeof(double) * (size_t)len[q],
+                              hipMemcpyDeviceToDevice, h->stream));
+    CK(hipMemcpyAsync(b + L.log, d.log, sizeof(double) * (size_t)kLogCap * kRec,
+                      hipMemcpyDeviceToDevice, h->stream));
+    CK(hipStreamSynchronize(h->stream));  // the header came from host memory
+    return PDHG_OK;
+}
+
+int pdhg_set_state(pdhg_t *h, const void *state, size_t bytes) {
+    if (!h || !state) return PDHG_E_INVALID;
+    Dev &d = h->d;
+    const StateLayout L = state_layout(d);
+    if (bytes < L.total || ((uintptr_t)state & 255)) return PDHG_E_WORKSPACE;
+    const char *b = (const char *)state;
+    StateHeader hd;
+    CK(hipMemcpyAsync(&hd, b + L.hdr, sizeof(hd), hipMemcpyDeviceToHost, h->stream));
+    CK(hipStreamSynchronize(h->stream));
+    uint64_t sig = 0;
+    int rc = matrix_signature(h, &sig);
+    if (rc) return rc;
+    if (hd.magic != kStateMagic || hd.m != d.m || hd.n != d.n || hd.nnz != d.nnz ||
+        hd.sig != sig || hd.method != h->prm.method ||
+        hd.restart_mode != h->prm.restart_mode || hd.check_period != h->prm.check_period ||
+        hd.kkt_kind != h->prm.kkt_kind || hd.bytes != (int64_t)L.total ||
+        !(hd.eta > 0.0) || !(hd.omega > 0.0))
+        return PDHG_E_INVALID;
+    // the step sizes belong to the state: a resumed run takes the same steps
+    if (hd.eta != h->eta || hd.omega != d.omega) {
+        h->eta = hd.eta;
+        h->prm.omega = hd.omega;
+        d.omega = hd.omega;
+        h->tau = hd.eta / hd.omega;
+        h->sigma = hd.eta * hd.omega;
+        h->g_valid = false;  // the recorded block holds the old step sizes
+    }
+    CK(hipMemcpyAsync(d.st, b + L.st, sizeof(DevState), hipMemcpyDeviceToDevice, h->stream));
+    double *dst[9] = {d.x, d.y, d.x0, d.y0, d.sx, d.sy, d.q, d.xbar, d.ybar};
+    const int64_t len[9] = {d.n, d.m, d.n, d.m, d.n, d.m, d.m, d.n, d.m};
+    for (int q = 0; q < 9; ++q)
+        if (len[q] > 0)
+            CK(hipMemcpyAsync(dst[q], b + L.vec[q], sizeof(double) * (size_t)len[q],
+                              hipMemcpyDeviceToDevice, h->stream));
+    CK(hipMemcpyAsync(d.log, b + L.log, sizeof(double) * (size_t)kLogCap * kRec,
+                      hipMemcpyDeviceToDevice, h->stream));
+    CK(hipStreamSynchronize(h->stream));
+    return PDHG_OK;
+}
+
 size_t pdhg_weight_search_workspace_bytes(int64_t m, int64_t n, int32_t count) {
     if (m < 0 || n < 1 || count < 1 || count > kWMax) return 0;
     return wsearch_bytes(m, n, count);

@@ -1242,6 +1242,11 @@ struct Tape {
     double *xh, *yh, *sxh, *syh, *vh;
     double2 *uw;            // per column: (uh, 2 x+ - x) for the A^ entries
     double *gc;             // dL/dc in the internal column order (permuted columns only)
+    // the batch's state at the end of the forward call (x, y, A x, running
+    // sums, per-LP records), put back after the reverse sweep, which
+    // recomputes the windows through the live iterate arrays
+    double *ex, *ey, *eq, *esx, *esy;
+    BLP *elp;
     int nwin, P;
     long long K;
 };
@@ -2292,6 +2297,9 @@ static bool tape_carve(const pdhg_batch_t *h, int64_t K, char *base, Tape *t, si
     const size_t osxh = put(sizeof(double) * N), osyh = put(sizeof(double) * M);
     const size_t ovh = put(sizeof(double) * M), ouw = put(sizeof(double2) * N);
     const size_t ogc = d.cinv ? put(sizeof(double) * N) : 0;
+    const size_t oex = put(sizeof(double) * N), oey = put(sizeof(double) * M);
+    const size_t oeq = put(sizeof(double) * M), oesx = put(sizeof(double) * N);
+    const size_t oesy = put(sizeof(double) * M), oelp = put(sizeof(BLP) * C);
     *total = o;
     if (base && t) {
         t->cx = (double *)(base + ocx);
@@ -2308,6 +2316,12 @@ static bool tape_carve(const pdhg_batch_t *h, int64_t K, char *base, Tape *t, si
         t->vh = (double *)(base + ovh);
         t->uw = (double2 *)(base + ouw);
         t->gc = d.cinv ? (double *)(base + ogc) : nullptr;
+        t->ex = (double *)(base + oex);
+        t->ey = (double *)(base + oey);
+        t->eq = (double *)(base + oeq);
+        t->esx = (double *)(base + oesx);
+        t->esy = (double *)(base + oesy);
+        t->elp = (BLP *)(base + oelp);
         t->nwin = (int)nwin;
         t->P = (int)P;
         t->K = K;
@@ -2316,6 +2330,23 @@ static bool tape_carve(const pdhg_batch_t *h, int64_t K, char *base, Tape *t, si
 }
 
 extern "C" {
+
+// copy the batch's end-of-forward state into the tape (save) or back
+static hipError_t save_end_state(const BDev &d, const Tape &t, bool save, hipStream_t s) {
+    const size_t N = (size_t)d.N, M = (size_t)d.M;
+    struct {
+        double *live, *kept;
+        size_t len;
+    } v[5] = {{d.x, t.ex, N}, {d.y, t.ey, M}, {d.q, t.eq, M}, {d.sx, t.esx, N}, {d.sy, t.esy, M}};
+    for (auto &e : v) {
+        if (!e.len) continue;
+        hipError_t r = hipMemcpyAsync(save ? e.kept : e.live, save ? e.live : e.kept,
+                                      sizeof(double) * e.len, hipMemcpyDeviceToDevice, s);
+        if (r != hipSuccess) return r;
+    }
+    return hipMemcpyAsync(save ? (void *)t.elp : (void *)d.lp, save ? (void *)d.lp : (void *)t.elp,
+                          sizeof(BLP) * (size_t)d.count, hipMemcpyDeviceToDevice, s);
+}
 
 size_t pdhg_batch_tape_bytes(pdhg_batch_t *h, int64_t K) {
     if (!h) return 0;
@@ -2378,6 +2409,7 @@ int pdhg_batch_unrolled_forward(pdhg_batch_t *h, int64_t K, void *tape, size_t t
     }
     if (xK && d.cinv) launch_gather(d.x, d.cinv, d.N, xK, s);
     else if (xK) BCK(hipMemcpyAsync(xK, d.x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    BCK(save_end_state(d, t, true, s));
     const int rc = b_last_error();
     if (rc == PDHG_OK) {
         h->tape_of = tape;
@@ -2450,6 +2482,9 @@ int pdhg_batch_unrolled_backward(pdhg_batch_t *h, int64_t K, void *tape, size_t 
         if (rc) return rc;
     }
     if (d.cinv) launch_gather(t.gc, d.cinv, d.N, gc, s);
+    // the batch is left where the forward call left it (x_K, its running
+    // sums and counters), so later calls continue from there
+    BCK(save_end_state(d, t, false, s));
     return b_last_error();
 }
 

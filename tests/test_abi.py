@@ -49,3 +49,7 @@ def test_create_rejects_bad_arguments_before_touching_the_device():
     assert L.pdhg_solve(None, 1, 1e-8, None) == _lib.E_INVALID
     L.pdhg_destroy(None)
     assert L.pdhg_linear_trust_region(-1, None, None, 1.0, None, 0, None, None, None) == _lib.E_INVALID
+    # checkpoint calls
+    assert L.pdhg_state_bytes(None) == 0
+    assert L.pdhg_get_state(None, None, 0) == _lib.E_INVALID
+    assert L.pdhg_set_state(None, None, 0) == _lib.E_INVALID

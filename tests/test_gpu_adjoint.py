@@ -177,3 +177,48 @@ def test_backward_needs_the_tape_of_the_last_forward(lib):
     g3 = b.unrolled_backward(tape3, ones)
     for a, c in zip(g1, g3):
         assert torch.equal(a, c)
+
+
+@pytest.mark.parametrize("K", [90, 100])
+def test_backward_leaves_the_forward_state(lib, K):
+    """After forward + backward the batch is where the forward call left
+    it: x_K, the running sums, counters and restart state.  A solve then
+    continues exactly as after the forward call alone (bitwise, against a
+    second batch that skips the backward call), and each LP follows the
+    oracle's run of K iterations (Algorithm 1 with checks, no stopping
+    test) continued by its solve to 1e-8."""
+    lps = [lpgen.small_dense(1), lpgen.column_count_lp(21, 300, 600, per_col=4, bounds="mix")]
+    etas = [oracle.Oracle(lp).info()["eta"] for lp in lps]
+    params = [{"eta": e} for e in etas]
+    a = lib.BatchSolver(lps, params=params)
+    b = lib.BatchSolver(lps, params=params)
+    N = sum(lp.n for lp in lps)
+    ones = torch.ones(N, dtype=torch.float64, device="cuda:0")
+    xka, tape = a.unrolled_forward(K)
+    xkb, _ = b.unrolled_forward(K)
+    a.unrolled_backward(tape, ones)
+    for i in range(len(lps)):
+        for which in (0, 1, 2):
+            xa, ya = a.get_iterate(i, which)
+            xb, yb = b.get_iterate(i, which)
+            torch.cuda.synchronize()
+            assert torch.equal(xa, xb) and torch.equal(ya, yb), (i, which)
+        ia, ib = a.info(i), b.info(i)
+        for key in ("k", "t", "restarts", "checks", "rho_prev"):
+            assert ia[key] == ib[key], (i, key)
+    ra = a.solve(200_000, 1e-8)
+    rb = b.solve(200_000, 1e-8)
+    for i, lp in enumerate(lps):
+        assert (ra[i]["k"], ra[i]["restarts"]) == (rb[i]["k"], rb[i]["restarts"])
+        xa, ya = a.get_iterate(i, 3)
+        xb, yb = b.get_iterate(i, 3)
+        torch.cuda.synchronize()
+        assert torch.equal(xa, xb) and torch.equal(ya, yb)
+        o = oracle.Oracle(lp, eta=etas[i])
+        o.solve(K, 0.0)
+        ro = o.solve(200_000, 1e-8)
+        assert ro["status"] == 0 and ra[i]["status"] == 0
+        assert (ra[i]["k"], ra[i]["restarts"], ra[i]["which"]) == (
+            ro["k"], ro["restarts"], ro["which"])
+        assert_points_match(np.concatenate([xa.cpu().numpy(), ya.cpu().numpy()]),
+                            np.concatenate([ro["x"], ro["y"]]), 1e-8, f"LP {i} solution")
