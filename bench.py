@@ -93,23 +93,37 @@ def measured_traffic(workload, kernel):
 
 
 def cpu_baseline(lp, eta, budget_s=12.0):
+    """The oracle on the same LP and schedule (whole blocks of 30 iterations
+    with their restart checks), timed on the host: the plain build on one
+    core, and the OpenMP build of the same source (bitwise the same
+    iterates) on every core the process may use.  About budget_s seconds
+    of CPU work each."""
     import oracle
-    o = oracle.Oracle(lp, eta=eta, mode=oracle.MODE_ADAPTIVE)
-    # calibrate on 2 iterations, then run whole 30-iteration blocks with
-    # their checks for about budget_s seconds (at least one block)
-    t0 = time.perf_counter()
-    o.step(2)
-    per_iter = (time.perf_counter() - t0) / 2
-    blocks = max(1, int(budget_s / (per_iter * 30 * 1.5)))
-    o2 = oracle.Oracle(lp, eta=eta, mode=oracle.MODE_ADAPTIVE)
-    t0 = time.perf_counter()
-    o2.solve(30 * blocks, 0.0)
-    dt = time.perf_counter() - t0
-    o.close()
-    o2.close()
-    return {"value": 30 * blocks / dt, "unit": "iter/s", "cores": 1, "kind": "oracle",
-            "sample": f"{blocks} block(s) of 30 iterations + restart check on the same LP, "
-                      f"single-threaded FP64 C oracle, {dt:.1f} s"}
+
+    def timed(parallel, budget):
+        o = oracle.Oracle(lp, eta=eta, mode=oracle.MODE_ADAPTIVE, parallel=parallel)
+        # calibrate on 2 iterations, then whole blocks for about `budget`
+        t0 = time.perf_counter()
+        o.step(2)
+        per_iter = (time.perf_counter() - t0) / 2
+        blocks = max(1, int(budget / (per_iter * 30 * 1.5)))
+        o.close()
+        o2 = oracle.Oracle(lp, eta=eta, mode=oracle.MODE_ADAPTIVE, parallel=parallel)
+        t0 = time.perf_counter()
+        o2.solve(30 * blocks, 0.0)
+        dt = time.perf_counter() - t0
+        o2.close()
+        return 30 * blocks / dt, blocks, dt
+
+    v1, b1, d1 = timed(False, budget_s)
+    cores = oracle.threads(parallel=True)
+    vp, bp, dp = timed(True, budget_s)
+    return {"value": vp, "unit": "iter/s", "cores": cores, "kind": "oracle",
+            "sample": f"{bp} block(s) of 30 iterations + restart check on the same LP, FP64 C "
+                      f"oracle built with OpenMP (bitwise the plain build's iterates), "
+                      f"{cores} threads, {dp:.1f} s",
+            "one_core": {"value": v1, "unit": "iter/s", "cores": 1,
+                         "sample": f"{b1} block(s), plain single-threaded build, {d1:.1f} s"}}
 
 
 def run_batch(args):
@@ -263,6 +277,75 @@ def run_table2(args):
                       "limit": args.t2_limit, "check_period": 30, "rows": rows}), flush=True)
 
 
+def solver_column_order(lp):
+    """The column order the library works in for a single LP (columns by
+    entry count, largest first, ties by the row of their first entry):
+    returns cinv, the internal index of each of the caller's columns."""
+    import numpy as np
+    A = lp.scipy_csr().tocsc()
+    A.sort_indices()
+    cnt = np.diff(A.indptr)
+    first = np.full(lp.n, lp.m)
+    nz = cnt > 0
+    first[nz] = A.indices[A.indptr[:-1][nz]]
+    order = np.lexsort((first, -cnt))
+    cinv = np.empty(lp.n, np.int64)
+    cinv[order] = np.arange(lp.n)
+    return cinv
+
+
+def run_ceiling(args):
+    """Ceilings of the GPU for the half-steps, measured with the library's
+    own yardstick kernels: a plain streaming copy of 1 GiB (HBM), and plain
+    gathers out[i] = val[i] x[idx[i]] with the index streams of the large
+    LP's two products (A x+: A's column indices in the solver's column
+    order into a 16 MB x; A'y: A''s row indices into an 8 MB y) and with
+    uniform random indices into vectors of 4, 8 and 16 MB, each over the
+    large LP's entry count.  Prints one JSON line."""
+    import numpy as np
+    import torch
+    from paper_2105_12715_amd import _lib, lpgen
+
+    dev = "cuda"
+    n = 1 << 27  # 1 GiB of doubles
+    src = torch.arange(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    ms = _lib.time_copy(src, dst, reps=20)
+    ok = bool(torch.equal(src, dst))
+    copy = {"bytes_each_way": 8 * n, "ms": round(ms, 5),
+            "gbs_read_plus_write": round(2 * 8 * n / ms / 1e6, 1), "result_checked": ok}
+    log(f"copy 1 GiB: {ms:.4f} ms, {copy['gbs_read_plus_write']} GB/s read + write")
+    del src, dst
+    lp = lpgen.large_powerlaw(3)
+    cinv = solver_column_order(lp)
+    A = lp.scipy_csr()
+    nnz = A.nnz
+    At = A.tocsc()
+    At.sort_indices()
+    rng = np.random.default_rng(7)
+    pats = [("A x+ (large LP, x of 16 MB)", cinv[A.indices], lp.n),
+            ("A'y (large LP, y of 8 MB)", At.indices[np.argsort(cinv[np.repeat(
+                np.arange(lp.n), np.diff(At.indptr))], kind="stable")], lp.m)]
+    for mb in (4, 8, 16):
+        ln = mb * (1 << 20) // 8
+        pats.append((f"uniform over {mb} MB", rng.integers(0, ln, nnz), ln))
+    val = torch.as_tensor(np.asarray(A.data), device=dev)
+    out = torch.empty(nnz, dtype=torch.float64, device=dev)
+    gathers = []
+    for name, idx_np, ln in pats:
+        idx = torch.as_tensor(np.ascontiguousarray(idx_np, dtype=np.int32), device=dev)
+        x = torch.as_tensor(rng.standard_normal(ln), device=dev)
+        ms = _lib.time_gather(idx, val, x, out, reps=20)
+        ok = bool(torch.equal(out, val * x[idx.long()]))
+        rate = nnz / (ms * 1e-3) / 1e9
+        gathers.append({"pattern": name, "entries": nnz, "vector_bytes": 8 * ln,
+                        "ms": round(ms, 5), "g_gathers_per_s": round(rate, 1),
+                        "stream_gbs": round(20 * nnz / ms / 1e6, 1), "result_checked": ok})
+        log(f"gather {name}: {ms * 1e3:.1f} us, {rate:.1f} G gathers/s")
+    print(json.dumps({"metric": "yardstick ceilings", "dtype": "f64", "n_gpus": 1,
+                      "copy": copy, "gather": gathers}), flush=True)
+
+
 def run_to_tol(args, lp, wdesc):
     """Time to relative KKT <= tol from the initial point (pdhg_solve with
     checks every 30 iterations), with the oracle's time for the same
@@ -280,10 +363,26 @@ def run_to_tol(args, lp, wdesc):
         f"KKT {r['kkt']:.3e}, {dt:.3f}s")
     cpu = None
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(lp, eta)
-        proj = r["k"] / cb["value"]
-        cpu = {**cb, "value": round(proj, 2), "unit": "s",
-               "sample": cb["sample"] + f"; projected to {r['k']} iterations at that rate"}
+        # the oracle solved to the same tolerance (measured, not projected):
+        # the OpenMP build on every host core and the plain build on one
+        import oracle
+        runs = {}
+        for par in (True, False):
+            o = oracle.Oracle(lp, eta=eta, mode=oracle.MODE_ADAPTIVE, parallel=par)
+            t0 = time.perf_counter()
+            ro = o.solve(args.budget, args.tol)
+            runs[par] = (time.perf_counter() - t0, ro)
+            o.close()
+            log(f"oracle ({'all cores' if par else 'one core'}): status {ro['status']} after "
+                f"{ro['k']} iterations, {ro['restarts']} restarts, {runs[par][0]:.2f}s")
+        (dp, rp_), (d1, r1) = runs[True], runs[False]
+        cpu = {"value": round(dp, 3), "unit": "s", "cores": oracle.threads(parallel=True),
+               "kind": "oracle",
+               "sample": f"the whole solve to {args.tol:g}: {rp_['k']} iterations, "
+                         f"{rp_['restarts']} restarts, OpenMP build (bitwise the plain "
+                         f"build's iterates)",
+               "one_core": {"value": round(d1, 3), "unit": "s", "cores": 1,
+                            "iterations": r1["k"], "restarts": r1["restarts"]}}
     out = {"metric": f"time to {args.tol:g} rel KKT", "value": round(dt, 4), "unit": "s",
            "n_gpus": 1, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
            "scaling": "weak", "vs_baseline": None,
@@ -412,7 +511,8 @@ def main():
                          "whose blocks take microseconds)")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="large",
-                    choices=["large", "medium", "small", "batch", "table2", "adjoint", "many"])
+                    choices=["large", "medium", "small", "batch", "table2", "adjoint", "many",
+                             "ceiling"])
     ap.add_argument("--many-count", type=int, default=256)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-only", action="store_true",
@@ -430,8 +530,8 @@ def main():
     ap.add_argument("--t2-fixed", default="1,2,3,4,5,6,7,8,9", help="table2: exponents k of 4^k")
     ap.add_argument("--t2-limit", type=int, default=500_000)
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="only run a plain 1 GiB elementwise copy (y = -x, FP64) five times, "
-                         "the yardstick for the HBM byte counters")
+                    help="only run the library's plain 1 GiB copy kernel five times, the "
+                         "yardstick for the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no "
@@ -444,15 +544,18 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    _lib.load(build_if_missing=True)
     if args.calibrate_copy:
         x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         y = torch.empty_like(x)
-        for _ in range(5):
-            torch.neg(x, out=y)
+        _lib.time_copy(x, y, reps=4)  # warm-up launch + 4 timed: 5 launches
         torch.cuda.synchronize()
-        log("copy calibration: 5 launches, 1073741824 bytes read and written each")
+        log("copy calibration: 5 launches of the library's copy kernel, 1073741824 bytes "
+            "read and written each")
         return
-    _lib.load(build_if_missing=True)
+    if args.workload == "ceiling":
+        run_ceiling(args)
+        return
     if args.workload == "batch":
         run_batch(args)
         return

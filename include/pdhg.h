@@ -329,6 +329,21 @@ int pdhg_get_transpose(pdhg_t *h, int32_t *t_row_ptr, int32_t *t_col_idx,
  * applies the update).  For throughput measurement.  Syncs. */
 int pdhg_time_iterations(pdhg_t *h, int64_t iters, double *ms_primal, double *ms_dual);
 
+/* Measurement yardsticks for the roofline of the half-steps (no paper
+ * step): the mean time in ms (host *ms) of `reps` (1..1000) launches of
+ *  - pdhg_time_copy: the library's plain streaming copy dst[i] = src[i],
+ *    i < n (device, 16-byte aligned, not overlapping): 16 n bytes of HBM
+ *    traffic per launch when n is large;
+ *  - pdhg_time_gather: a plain gather out[i] = val[i] * x[idx[i]], i < n
+ *    (device; every idx[i] must index x; n < 2^31), the access pattern of a
+ *    product's gathers without its rows and update.
+ * One warm-up launch runs first; enqueued on `stream`, synchronizes.
+ * Errors: PDHG_E_INVALID, PDHG_E_HIP. */
+int pdhg_time_copy(const double *src, double *dst, int64_t n, int32_t reps, void *stream,
+                   double *ms);
+int pdhg_time_gather(const int32_t *idx, const double *val, const double *x, double *out,
+                     int64_t n, int32_t reps, void *stream, double *ms);
+
 /* Primal-weight search of Section 7 (experimental setup).  For each of the
  * `count` weights omega[w] (host array; every omega > 0; 1 <= count <= 16)
  * run `iters` (>= 0) iterations of the handle's method (PDHG or

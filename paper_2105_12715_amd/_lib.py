@@ -166,6 +166,10 @@ def load(build_if_missing: bool = True):
     L.pdhg_trust_region_workspace_bytes.restype = sz
     L.pdhg_linear_trust_region.argtypes = [i64, P, P, d, P, sz, P, C.POINTER(d), C.POINTER(d)]
     L.pdhg_linear_trust_region.restype = C.c_int
+    L.pdhg_time_copy.argtypes = [P, P, i64, i32, P, C.POINTER(d)]
+    L.pdhg_time_copy.restype = C.c_int
+    L.pdhg_time_gather.argtypes = [P, P, P, P, i64, i32, P, C.POINTER(d)]
+    L.pdhg_time_gather.restype = C.c_int
     L.pdhg_batch_workspace_bytes.argtypes = [i32, P, P, P]
     L.pdhg_batch_workspace_bytes.restype = sz
     L.pdhg_batch_create.argtypes = [i32, P, P, P, sz, P, C.POINTER(P)]
@@ -673,6 +677,26 @@ def pdhg_unrolled(c, b, vals, solver, K):
     if _UNROLLED is None:
         _UNROLLED = _make_unrolled()
     return _UNROLLED.apply(c, b, vals, solver, K)
+
+
+def time_copy(src, dst, reps=20, stream=None):
+    """Mean ms of the library's streaming copy dst = src (device float64
+    tensors of equal size)."""
+    L = load()
+    ms = C.c_double()
+    _check(L.pdhg_time_copy(_ptr(src), _ptr(dst), int(src.numel()), int(reps),
+                            _stream_handle(stream), C.byref(ms)), "pdhg_time_copy")
+    return ms.value
+
+
+def time_gather(idx, val, x, out, reps=20, stream=None):
+    """Mean ms of the library's plain gather out = val * x[idx]."""
+    L = load()
+    ms = C.c_double()
+    _check(L.pdhg_time_gather(_ptr(idx), _ptr(val), _ptr(x), _ptr(out), int(idx.numel()),
+                              int(reps), _stream_handle(stream), C.byref(ms)),
+           "pdhg_time_gather")
+    return ms.value
 
 
 def linear_trust_region(a, d, r, device="cuda:0", stream=None):

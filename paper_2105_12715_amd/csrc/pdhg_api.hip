@@ -1433,6 +1433,47 @@ int pdhg_time_iterations(pdhg_t *h, int64_t iters, double *ms_primal, double *ms
     return rc;
 }
 
+// mean time of `reps` launches enqueued on s by `launch`, in ms
+}  // extern "C"
+template <class F>
+static int time_launches(hipStream_t s, int32_t reps, F launch, double *ms) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = PDHG_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = PDHG_E_HIP;
+    if (rc == PDHG_OK) {
+        launch();  // warm-up
+        if (hipEventRecord(e0, s) != hipSuccess) rc = PDHG_E_HIP;
+        for (int32_t r = 0; r < reps && rc == PDHG_OK; ++r) launch();
+        if (rc == PDHG_OK && hipEventRecord(e1, s) != hipSuccess) rc = PDHG_E_HIP;
+        if (rc == PDHG_OK) rc = last_error();
+        if (rc == PDHG_OK && hipEventSynchronize(e1) != hipSuccess) rc = PDHG_E_HIP;
+        float a = 0.f;
+        if (rc == PDHG_OK && hipEventElapsedTime(&a, e0, e1) != hipSuccess) rc = PDHG_E_HIP;
+        if (rc == PDHG_OK && ms) *ms = a / (double)reps;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return rc;
+}
+
+extern "C" {
+int pdhg_time_copy(const double *src, double *dst, int64_t n, int32_t reps, void *stream,
+                   double *ms) {
+    if (!src || !dst || n < 1 || reps < 1 || reps > 1000 || ((uintptr_t)src & 15) ||
+        ((uintptr_t)dst & 15))
+        return PDHG_E_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    return time_launches(s, reps, [&] { launch_copy_yard(src, dst, n, s); }, ms);
+}
+
+int pdhg_time_gather(const int32_t *idx, const double *val, const double *x, double *out,
+                     int64_t n, int32_t reps, void *stream, double *ms) {
+    if (!idx || !val || !x || !out || n < 1 || n > 0x7fffffffLL || reps < 1 || reps > 1000)
+        return PDHG_E_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    return time_launches(s, reps, [&] { launch_gather_yard(idx, val, x, out, n, s); }, ms);
+}
+
 size_t pdhg_trust_region_workspace_bytes(int64_t N) {
     if (N < 0 || N > 0x7fffffffLL) return 0;
     return al(sizeof(TRState)) + tr_work_bytes(N);

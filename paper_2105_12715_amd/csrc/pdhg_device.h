@@ -550,6 +550,9 @@ __device__ __forceinline__ int kkt_conclude(const Dev &d, const double *S, doubl
         st->kkt_cur[0] = kc;
         st->kkt_avg[0] = ka;
         st->numerr = bad ? 1 : 0;
+        // a breakdown ends the run like convergence: the blocks replayed
+        // after this check do nothing, so the iterates stay at this check
+        if (bad) st->done = 1;
         st->conv_which = -1;
         if (conv) {
             st->done = 1;

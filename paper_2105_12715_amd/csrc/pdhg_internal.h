@@ -290,6 +290,12 @@ void launch_power_step(const Dev &d, double tol, int max_iters, hipStream_t s);
 // shared reductions
 int red_grid(long long N);
 
+// measurement yardsticks (plain streaming copy of n doubles; plain gather
+// out[i] = val[i] x[idx[i]], i < n)
+void launch_copy_yard(const double *src, double *dst, long long n, hipStream_t s);
+void launch_gather_yard(const int *idx, const double *val, const double *x, double *out,
+                        long long n, hipStream_t s);
+
 // stand-alone trust region on raw (a, d)
 void launch_tr_raw(int64_t N, const double *a, const double *dd, double r,
                    const TRWork &w, TRState *st, hipStream_t s);

@@ -975,4 +975,62 @@ void launch_power_step(const Dev &d, double tol, int max_iters, hipStream_t s) {
     hipLaunchKernelGGL(k_power_norm, dim3(div_up(d.n, kWG)), dim3(kWG), 0, s, d);
 }
 
+// ---------------------------------------------------------------------
+// measurement yardsticks: a plain streaming copy (the HBM ceiling the
+// half-steps are set against) and a plain gather out[i] = val[i] x[idx[i]]
+// (the access pattern of a product's gathers without its rows)
+// ---------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_copy_yard(const double2 *__restrict__ src,
+                                                   double2 *__restrict__ dst, long long n2,
+                                                   const double *__restrict__ s1,
+                                                   double *__restrict__ d1, int odd) {
+    const long long stride = (long long)gridDim.x * kWG;
+    for (long long i = (long long)blockIdx.x * kWG + threadIdx.x; i < n2; i += stride)
+        dst[i] = src[i];
+    if (odd && blockIdx.x == 0 && threadIdx.x == 0) d1[2 * n2] = s1[2 * n2];
+}
+
+void launch_copy_yard(const double *src, double *dst, long long n, hipStream_t s) {
+    const long long n2 = n / 2;
+    long long g = (n2 + kWG - 1) / kWG;
+    if (g > 16384) g = 16384;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_copy_yard, dim3((unsigned)g), dim3(kWG), 0, s, (const double2 *)src,
+                       (double2 *)dst, n2, src, dst, (int)(n & 1));
+}
+
+constexpr int kYardPer = 8;  // gathers in flight per thread, as in the SpMV stage
+__global__ __launch_bounds__(kWG) void k_gather_yard(const int *__restrict__ idx,
+                                                     const double *__restrict__ val,
+                                                     const double *__restrict__ x,
+                                                     double *__restrict__ out, long long n) {
+    const long long base = (long long)blockIdx.x * kWG * kYardPer + threadIdx.x;
+    int c[kYardPer];
+    double v[kYardPer], g[kYardPer];
+#pragma unroll
+    for (int k = 0; k < kYardPer; ++k) {
+        const long long e = base + (long long)k * kWG;
+        if (e < n) {
+            c[k] = ld_matrix(idx + e);
+            v[k] = ld_matrix(val + e);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kYardPer; ++k)
+        if (base + (long long)k * kWG < n) g[k] = x[c[k]];
+#pragma unroll
+    for (int k = 0; k < kYardPer; ++k) {
+        const long long e = base + (long long)k * kWG;
+        if (e < n) out[e] = v[k] * g[k];
+    }
+}
+
+void launch_gather_yard(const int *idx, const double *val, const double *x, double *out,
+                        long long n, hipStream_t s) {
+    const long long per = (long long)kWG * kYardPer;
+    const long long g = (n + per - 1) / per;
+    if (g < 1) return;
+    hipLaunchKernelGGL(k_gather_yard, dim3((unsigned)g), dim3(kWG), 0, s, idx, val, x, out, n);
+}
+
 }  // namespace pdhg

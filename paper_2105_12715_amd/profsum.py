@@ -128,7 +128,7 @@ def main(argv=None):
     for k in ("fetch", "write", "copy_fetch", "copy_write", "kernels", "source_hash", "cmd"):
         t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
-    t.add_argument("--copy-kernel", default="elementwise")
+    t.add_argument("--copy-kernel", default="k_copy_yard")
     a = ap.parse_args(argv)
     if a.what == "stats":
         sys.stdout.write(stats_markdown(a.dir, a.title, a.cmd))

@@ -194,25 +194,26 @@ def _divergent_lp():
 def test_step_size_too_large_is_a_numerical_error(lib, tiny_off):
     """eta = 3 / sigma_max(A) (the valid range is eta <= 1/sigma_max) on an
     LP whose variables are all free: the PDHG map expands, the iterates
-    overflow, and the next check reports PDHG_E_NUMERICAL."""
+    overflow, and the first check whose KKT sums are not finite (the
+    oracle's KKT values overflow at the same check) ends the solve with
+    PDHG_E_NUMERICAL."""
     lp, smax = _divergent_lp()
     eta = 3.0 / smax
     o = oracle.Oracle(lp, eta=eta)
-    k_bad = None
-    for _ in range(200):
-        o.solve(30, 1e-8)
-        x, y = o.get(0)
-        if not np.all(np.isfinite(np.concatenate([x, y]))):
-            k_bad = int(o.info()["k"])
-            break
-    assert k_bad is not None and k_bad <= 600
+    o.solve(600, 1e-8)
+    lo = o.log()
+    bad = [int(r[0]) for r in lo if not np.all(np.isfinite(r[3:5]))]
+    assert bad, "the oracle's KKT values stay finite"
+    k_bad = bad[0]  # the first check whose KKT sums overflow
     s = _solver(lib, lp, tiny_off, eta=eta)
     assert (s.info()["one_workgroup"] == 0) == tiny_off
     with pytest.raises(lib.PdhgError) as e:
         s.solve(6000, 1e-8)
     assert e.value.code == lib.E_NUMERICAL
-    k_gpu = s.info()["k"]
-    assert k_gpu >= k_bad - 30  # stopped at (or soon after) the check that saw it
+    # the run stops at the check that saw the breakdown
+    assert s.info()["k"] == k_bad
+    lg = s.check_log()
+    np.testing.assert_array_equal(lg[:, 0], lo[: lg.shape[0], 0])
     # the handle stays usable and keeps reporting the breakdown
     s.step(30)
     with pytest.raises(lib.PdhgError) as e:

@@ -75,7 +75,9 @@ def _assert_same_stop(lib, s, ro, rg, tol=TOL):
     assert ro["status"] == 0 and rg["status"] == 0, (ro["status"], rg["status"])
     assert (rg["k"], rg["restarts"], rg["which"]) == (ro["k"], ro["restarts"], ro["which"])
     assert rg["kkt"] <= tol and ro["kkt"] <= tol
-    assert rg["kkt"] == pytest.approx(ro["kkt"], rel=1e-6)
+    # the gap term of the KKT error is a difference of two objectives of
+    # size ~1 that agree to ~1e-7, so its relative rounding is amplified
+    assert rg["kkt"] == pytest.approx(ro["kkt"], rel=1e-4)
     x, y = (t.detach().cpu().numpy() for t in s.get_iterate(lib.POINT_SOLUTION))
     assert_points_match(np.concatenate([x, y]), np.concatenate([ro["x"], ro["y"]]), 1e-8,
                         "returned point")
@@ -134,6 +136,12 @@ def test_one_workgroup_absolute_stop(lib, case, mode, kkt_kind):
     _say(case, "mode", mode, "kkt", kkt_kind)
     o, s, ro, rg = _solve_both(lib, lp, eta, mode, kkt_kind=kkt_kind, limit=200_000)
     assert s.info()["one_workgroup"] != 0
+    if mode == oracle.MODE_NONE and ro["status"] != 0:
+        # without restarts the 50 x 100 LP does not reach 1e-6 in the
+        # budget: both sides run it out and report the same KKT error
+        assert rg["status"] == ro["status"] and rg["k"] == ro["k"] == 200_000
+        assert rg["kkt"] == pytest.approx(ro["kkt"], rel=1e-6)
+        return
     _assert_same_stop(lib, s, ro, rg)
 
 
