@@ -133,7 +133,17 @@ def run_batch(args):
     budget ends), printing progress per chunk.  Each LP of a batch follows
     exactly the iterates of its own single-LP solve (a GPU test checks
     this), so the sequential time is the sum over LPs of its iteration
-    count times the measured per-iteration time of its single-LP solve."""
+    count times the measured per-iteration time of its single-LP solve.
+
+    The model is checked on the three LPs with the fewest iterations (each
+    solved alone to the tolerance) and on the three with the most (each
+    timed alone over a truncated budget).  The time to tolerance is also
+    reported for the converged subset alone: the batch's clock when its
+    last member converged (interpolated inside the chunk) against the sum
+    of the subset's sequential times.  One member that does not converge
+    is run by the oracle for its first --oracle-iters iterations beside
+    its own GPU solve, check by check, to show whether its stall is the
+    method's or a discrepancy of the GPU path."""
     import numpy as np
     import torch
     from paper_2105_12715_amd import _lib, lpgen
@@ -151,14 +161,16 @@ def run_batch(args):
     t0 = time.perf_counter()
     done_k = 0
     res = None
+    clock = [(0, 0.0)]  # (batch iterations, seconds) after every chunk
     while done_k < args.budget:
         chunk = min(args.chunk, args.budget - done_k)
         res = b.solve(chunk, tol)
         done_k += chunk
+        clock.append((done_k, time.perf_counter() - t0))
         conv = sum(r["status"] == 0 for r in res)
         kk = np.array([r["kkt"] for r in res])
         log(f"iteration {done_k}: {conv}/{len(lps)} converged, max KKT {kk.max():.2e}, "
-            f"{time.perf_counter() - t0:.1f}s")
+            f"{clock[-1][1]:.1f}s")
         if conv == len(lps):
             break
     torch.cuda.synchronize()
@@ -183,18 +195,43 @@ def run_batch(args):
     t_seq = float(np.sum(ks * rates))
     log(f"batched {t_batch:.1f}s, sequential (sum k_i x rate_i) {t_seq:.1f}s, "
         f"speedup {t_seq / t_batch:.2f}")
-    # check the sequential model on a few LPs solved alone to the tolerance
+    # the converged subset: the batch clock when its last member converged
+    sub = None
+    if conv.any():
+        kc = int(ks[conv].max())
+        ck = np.array([c[0] for c in clock])
+        ct = np.array([c[1] for c in clock])
+        t_sub = float(np.interp(kc, ck, ct))
+        t_sub_seq = float(np.sum(ks[conv] * rates[conv]))
+        sub = {"lps": int(conv.sum()), "iterations_max": kc,
+               "batched_s": round(t_sub, 3), "sequential_plain_s": round(t_sub_seq, 3),
+               "speedup": round(t_sub_seq / t_sub, 3),
+               "note": "batch clock interpolated inside its chunk of iterations"}
+        log(f"converged subset ({conv.sum()} LPs, last at {kc}): batched {t_sub:.1f}s, "
+            f"sequential {t_sub_seq:.1f}s")
+    # check the sequential model: the three LPs with the fewest iterations
+    # solved alone to the tolerance, the three with the most timed alone
+    # over a truncated budget (the model uses a rate per iteration)
     checks = []
-    for i in np.argsort(ks)[:3]:
-        s = _lib.Solver(lps[i], eta=b.info(int(i))["eta"])
+    order = np.argsort(ks, kind="stable")
+    for i in list(order[:3]) + list(order[-3:]):
+        i = int(i)
+        s = _lib.Solver(lps[i], eta=b.info(i)["eta"])
+        few = i in [int(q) for q in order[:3]]
+        budget = int(ks[i]) + 30 if few else min(int(ks[i]), args.model_iters)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        r = s.solve(int(ks[i]) + 30, tol)
+        r = s.solve(budget, tol)
         torch.cuda.synchronize()
-        checks.append({"lp": int(i), "k": r["k"], "k_batch": int(ks[i]),
+        checks.append({"lp": i, "kind": "fewest" if few else "most (truncated)",
+                       "k": r["k"], "k_batch": int(ks[i]), "converged": r["status"] == 0,
                        "measured_s": round(time.perf_counter() - t1, 3),
-                       "model_s": round(float(ks[i] * rates[i]), 3)})
+                       "model_s": round(float(r["k"] * rates[i]), 3)})
+        log(f"model check {checks[-1]}")
         s.close()
+    oracle_run = None
+    if (~conv).any() and args.oracle_iters > 0:
+        oracle_run = unconverged_against_oracle(lps, b, ks, conv, rates, args)
     out = {
         "metric": "time to 1e-8 rel KKT, batched vs plain", "value": round(t_batch, 3),
         "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f64",
@@ -205,10 +242,46 @@ def run_batch(args):
         "converged": int(conv.sum()), "iterations_max": int(ks.max()),
         "iterations_median": float(np.median(ks)),
         "sequential_plain_s": round(t_seq, 3), "speedup_vs_sequential": round(t_seq / t_batch, 3),
+        "converged_subset": sub,
         "sequential_model_checks": checks,
+        "unconverged_member_vs_oracle": oracle_run,
         "single_iteration_us_median": round(float(np.median(rates)) * 1e6, 2),
     }
     print(json.dumps(out), flush=True)
+
+
+def unconverged_against_oracle(lps, b, ks, conv, rates, args):
+    """The unconverged member with the fewest rows: its own GPU solve and
+    the oracle (OpenMP build) side by side for the first --oracle-iters
+    iterations, check by check: restart decisions, KKT values."""
+    import numpy as np
+    import oracle
+    from paper_2105_12715_amd import _lib
+    cand = [i for i in range(len(lps)) if not conv[i]]
+    i = min(cand, key=lambda q: lps[q].m)
+    lp = lps[i]
+    eta = b.info(i)["eta"]
+    K = int(args.oracle_iters)
+    s = _lib.Solver(lp, eta=eta)
+    rg = s.solve(K, args.tol)
+    lg = s.check_log(max_records=K // 30 + 1)
+    o = oracle.Oracle(lp, eta=eta, mode=oracle.MODE_ADAPTIVE, parallel=True)
+    t1 = time.perf_counter()
+    ro = o.solve(K, args.tol)
+    dt = time.perf_counter() - t1
+    lo = o.log()
+    n = min(len(lo), len(lg))
+    same_int = bool(np.array_equal(lg[:n][:, [0, 1, 2, 9, 10, 11]], lo[:n][:, [0, 1, 2, 9, 10, 11]]))
+    kkt_rel = float(np.max(np.abs(lg[:n, 3:5] - lo[:n, 3:5]) / np.maximum(np.abs(lo[:n, 3:5]),
+                                                                          1e-300)))
+    rep = {"lp": i, "m": lp.m, "n": lp.n, "iterations": K, "checks_compared": n,
+           "restart_decisions_equal": same_int, "kkt_max_rel_diff": kkt_rel,
+           "gpu_restarts": rg["restarts"], "oracle_restarts": ro["restarts"],
+           "gpu_kkt_at_end": rg["kkt"], "oracle_kkt_at_end": ro["kkt"],
+           "kkt_every_3000": [float(min(r[3], r[4])) for r in lo[99::100]],
+           "oracle_s": round(dt, 2), "oracle_threads": oracle.threads(parallel=True)}
+    log(f"unconverged LP {i} against the oracle: {rep}")
+    return rep
 
 
 def run_table2(args):
@@ -520,6 +593,10 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--budget", type=int, default=1_500_000)
     ap.add_argument("--chunk", type=int, default=30_000)
+    ap.add_argument("--model-iters", type=int, default=30_000,
+                    help="batch: truncated budget of the model check on the slowest LPs")
+    ap.add_argument("--oracle-iters", type=int, default=30_000,
+                    help="batch: iterations of the unconverged member run by the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=200)
     ap.add_argument("--to-tol", action="store_true",

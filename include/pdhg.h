@@ -332,7 +332,7 @@ int pdhg_time_iterations(pdhg_t *h, int64_t iters, double *ms_primal, double *ms
 /* Measurement yardsticks for the roofline of the half-steps (no paper
  * step): the mean time in ms (host *ms) of `reps` (1..1000) launches of
  *  - pdhg_time_copy: the library's plain streaming copy dst[i] = src[i],
- *    i < n (device, 16-byte aligned, not overlapping): 16 n bytes of HBM
+ *    i < n (device, 32-byte aligned, not overlapping): 16 n bytes of HBM
  *    traffic per launch when n is large;
  *  - pdhg_time_gather: a plain gather out[i] = val[i] * x[idx[i]], i < n
  *    (device; every idx[i] must index x; n < 2^31), the access pattern of a

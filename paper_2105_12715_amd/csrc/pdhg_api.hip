@@ -1459,8 +1459,8 @@ static int time_launches(hipStream_t s, int32_t reps, F launch, double *ms) {
 extern "C" {
 int pdhg_time_copy(const double *src, double *dst, int64_t n, int32_t reps, void *stream,
                    double *ms) {
-    if (!src || !dst || n < 1 || reps < 1 || reps > 1000 || ((uintptr_t)src & 15) ||
-        ((uintptr_t)dst & 15))
+    if (!src || !dst || n < 1 || reps < 1 || reps > 1000 || ((uintptr_t)src & 31) ||
+        ((uintptr_t)dst & 31))
         return PDHG_E_INVALID;
     hipStream_t s = (hipStream_t)stream;
     return time_launches(s, reps, [&] { launch_copy_yard(src, dst, n, s); }, ms);

@@ -103,6 +103,32 @@ def test_transpose_long_columns(lib):
     np.testing.assert_array_equal(tv, e_v)
 
 
+def test_transpose_huge_columns(lib):
+    """Columns of 1,000,000 and 200,000 entries (and others just above and
+    below the 4096-entry LDS sort) are ordered by a merge sort in setup:
+    A' and perm equal the oracle's, and the setup takes seconds."""
+    import time
+    rng = np.random.default_rng(23)
+    m = 1_200_000
+    cnt = np.concatenate([[1_000_000, 200_000, 8193, 4097, 4096, 4095], np.full(200, 3)])
+    rows, cols = lpgen._distinct_rows_per_column(rng, m, cnt)
+    vals = rng.standard_normal(rows.size)
+    lp = lpgen.planted_lp(rng, m, cnt.size, rows, cols, vals, np.zeros(cnt.size),
+                          np.ones(cnt.size))
+    _say("transpose huge columns", lp.nnz)
+    t0 = time.perf_counter()
+    s = lib.Solver(lp, eta=1e-3)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    trp, tci, tv, perm = (to_np(t) for t in s.transpose_csr())
+    e_rp, e_ci, e_v, e_perm = oracle.transpose(lp.m, lp.n, lp.row_ptr, lp.col_idx, lp.vals)
+    np.testing.assert_array_equal(trp, e_rp)
+    np.testing.assert_array_equal(perm, e_perm)
+    np.testing.assert_array_equal(tci, e_ci)
+    np.testing.assert_array_equal(tv, e_v)
+    assert dt < 20.0, dt
+
+
 @pytest.mark.parametrize("name", ["small50x100", "powerlaw", "medium20kx50k"])
 def test_matvec_parity(lib, name):
     lp = get_case(name)
