@@ -395,6 +395,22 @@ int pdhg_linear_trust_region(int64_t N, const double *a, const double *d,
                              void *stream, double *value, double *lambda);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * stand-alone linear trust region above with its scratch in a static
+ * device array owned by the library (14 MiB on each GPU it runs on, held
+ * until the process ends) instead of a caller workspace.  N is at most
+ * PDHG_TR_STATIC_MAX_N (PDHG_E_INVALID beyond).  The call allocates
+ * nothing.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (several streams or host threads) race and must be
+ * serialized by the caller.  Other arguments, outputs, synchronization and
+ * errors as pdhg_linear_trust_region.
+ */
+#define PDHG_TR_STATIC_MAX_N 262144
+int pdhg_linear_trust_region_static(int64_t N, const double *a, const double *d, double r,
+                                    void *stream, double *value, double *lambda);
+
+/*
  * Batched solver: `count` independent LPs advanced by the same launches
  * (the LPs are concatenated into one block-diagonal system on the device).
  * Each LP keeps its own step sizes (power iteration per LP when its

@@ -170,6 +170,8 @@ def load(build_if_missing: bool = True):
     L.pdhg_time_copy.restype = C.c_int
     L.pdhg_time_gather.argtypes = [P, P, P, P, i64, i32, P, C.POINTER(d)]
     L.pdhg_time_gather.restype = C.c_int
+    L.pdhg_linear_trust_region_static.argtypes = [i64, P, P, d, P, C.POINTER(d), C.POINTER(d)]
+    L.pdhg_linear_trust_region_static.restype = C.c_int
     L.pdhg_batch_workspace_bytes.argtypes = [i32, P, P, P]
     L.pdhg_batch_workspace_bytes.restype = sz
     L.pdhg_batch_create.argtypes = [i32, P, P, P, sz, P, C.POINTER(P)]
@@ -697,6 +699,25 @@ def time_gather(idx, val, x, out, reps=20, stream=None):
                               int(reps), _stream_handle(stream), C.byref(ms)),
            "pdhg_time_gather")
     return ms.value
+
+
+TR_STATIC_MAX_N = 262144
+
+
+def linear_trust_region_static(a, d, r, device="cuda:0", stream=None):
+    """The same trust region through pdhg_linear_trust_region_static (no
+    workspace: the library's static scratch); returns (value, lambda)."""
+    import torch
+    L = load()
+    a = torch.as_tensor(a, dtype=torch.float64).to(device).contiguous()
+    d = torch.as_tensor(d, dtype=torch.float64).to(device).contiguous()
+    N = int(a.numel())
+    val, lam = C.c_double(), C.c_double()
+    rc = L.pdhg_linear_trust_region_static(N, _ptr(a) if N else None, _ptr(d) if N else None,
+                                           float(r), _stream_handle(stream), C.byref(val),
+                                           C.byref(lam))
+    _check(rc, "pdhg_linear_trust_region_static")
+    return val.value, lam.value
 
 
 def linear_trust_region(a, d, r, device="cuda:0", stream=None):

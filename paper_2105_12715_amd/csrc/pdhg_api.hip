@@ -1504,3 +1504,47 @@ int pdhg_linear_trust_region(int64_t N, const double *a, const double *d, double
 }
 
 }  // extern "C"
+
+// --- the same trust region with library-owned scratch ---------------------
+// For callers that cannot allocate device memory.  The scratch lives in a
+// file-scope device array; host code must not pass the array's name to a
+// kernel (in host code it is a stand-in, not a device address): each device
+// holds its own copy, whose address hipGetSymbolAddress gives once per
+// device, with that device current.
+namespace {
+constexpr size_t kTrStaticBytes = 14u << 20;  // holds the scratch of PDHG_TR_STATIC_MAX_N
+static __device__ __align__(256) unsigned char scratch[kTrStaticBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];  // per device: the array's device address
+
+// device address of the current device's copy of `scratch` (nullptr on
+// failure); set up on the first call on each device
+void *device_scratch() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" {
+int pdhg_linear_trust_region_static(int64_t N, const double *a, const double *d, double r,
+                                    void *stream, double *value, double *lambda) {
+    if (N < 0 || N > PDHG_TR_STATIC_MAX_N || isnan(r) || (N > 0 && (!a || !d)))
+        return PDHG_E_INVALID;
+    const size_t need = pdhg_trust_region_workspace_bytes(N);
+    if (need == 0 || need > kTrStaticBytes) return PDHG_E_WORKSPACE;
+    void *ws = device_scratch();
+    if (!ws) return PDHG_E_HIP;
+    // every value the kernels read is written by them first (k_tr_arm
+    // clears the first histograms; the later levels clear their own), so
+    // what an earlier call left in the array does not matter
+    return pdhg_linear_trust_region(N, a, d, r, ws, kTrStaticBytes, stream, value, lambda);
+}
+}  // extern "C"
