@@ -305,8 +305,13 @@ void launch_tr_raw(int64_t N, const double *a, const double *dd, double r,
 // row fits the registers of its lanes, the matrix) fit one CU's LDS: whole
 // blocks of iterations plus their checks in one launch.
 // ---------------------------------------------------------------------
-constexpr int kTinyWG = 512;                 // threads of the one workgroup
-constexpr int kTinyMaxCoords = 1024;         // n + m
+// threads of the one workgroup (a build parameter for tuning sweeps); each
+// thread holds at most two trust-region coordinates
+#ifndef PDHG_TINY_WG
+#define PDHG_TINY_WG 512
+#endif
+constexpr int kTinyWG = PDHG_TINY_WG;
+constexpr int kTinyMaxCoords = 2 * kTinyWG;  // n + m
 constexpr int kTinyK = 8;                    // matrix entries per lane held in registers
 constexpr size_t kTinyLdsMax = 148u << 10;   // dynamic LDS bytes (static LDS + this <= 160 KB)
 struct TinyPlan {
