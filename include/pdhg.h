@@ -231,20 +231,34 @@ typedef struct pdhg_tune {
     int32_t tried_A[4], tried_At[4];      /* the slab counts timed                */
     double ms_A[4], ms_At[4];             /* mean time of one product each, ms    */
     int32_t from_cache, reserved;         /* 1: taken from an earlier tuning      */
+    int32_t lanes_bias_A, lanes_bias_At;  /* lanes per row in use: -1, 0, +1 power
+                                             of two from the block's rule        */
+    double ms_lanes_A[3], ms_lanes_At[3]; /* one product with bias -1, 0, +1, ms
+                                             (not filled when cached)            */
 } pdhg_tune;
 
-/* Per-matrix choice of the column slabs of A x and A'y (the tiles of the
- * SpMV launches, Section 7's products): times `iters` products of the
- * current point for each slab count 1, 2, 4, 8 the workspace has room for
- * (room exists when the gathered vector is larger than one 4 MiB L2
- * slice), keeps the fastest for each product, and remembers the choice for
- * the process under a signature of the matrix (sizes and sampled row
- * starts); with use_cache != 0 a remembered choice is applied without
- * timing.  The iterates, averages and counters are left as they are; the
+/* Per-matrix choice of the SpMV schedule of A x and A'y (Section 7's
+ * products): first the column slabs (the tiles of the launches) -- times
+ * `iters` products of the current point for each slab count 1, 2, 4, 8 the
+ * workspace has room for (room exists when the gathered vector is larger
+ * than one 4 MiB L2 slice) and keeps the fastest -- then the row split:
+ * with that slab count, the lanes that reduce one row (a power of two near
+ * each block's mean row length) one power of two lower, as the rule, and
+ * one higher, keeping the fastest.  The choice is remembered for the
+ * process under a signature of the matrix (sizes and sampled row starts);
+ * with use_cache != 0 a remembered choice is applied without timing.  The iterates, averages and counters are left as they are; the
  * products are written to scratch vectors.  Later solves follow the same
  * iterates up to the order of floating-point sums.  *out (host, may be
  * NULL).  Synchronizes.  PDHG_E_INVALID for iters outside 1..10000. */
 int pdhg_autotune(pdhg_t *h, int32_t iters, int32_t use_cache, pdhg_tune *out);
+
+/* Pins a schedule instead of timing one: slab counts (1, 2, 4 or 8, at
+ * most what the workspace has room for; 1 is always allowed) and lanes-per-
+ * row biases (-1, 0, +1) of A x and A'y.  Every schedule gives the same
+ * iterates up to the order of floating-point sums.  PDHG_E_INVALID for a
+ * value outside those sets.  No sync. */
+int pdhg_set_schedule(pdhg_t *h, int32_t slabs_A, int32_t slabs_At, int32_t lanes_bias_A,
+                      int32_t lanes_bias_At);
 
 /* Bytes of device workspace pdhg_solve_many needs for `count` handles. */
 size_t pdhg_solve_many_workspace_bytes(int32_t count);

@@ -72,7 +72,9 @@ class Tune(C.Structure):
                 ("candidates_A", C.c_int32), ("candidates_At", C.c_int32),
                 ("tried_A", C.c_int32 * 4), ("tried_At", C.c_int32 * 4),
                 ("ms_A", C.c_double * 4), ("ms_At", C.c_double * 4),
-                ("from_cache", C.c_int32), ("reserved", C.c_int32)]
+                ("from_cache", C.c_int32), ("reserved", C.c_int32),
+                ("lanes_bias_A", C.c_int32), ("lanes_bias_At", C.c_int32),
+                ("ms_lanes_A", C.c_double * 3), ("ms_lanes_At", C.c_double * 3)]
 
 
 class BatchTune(C.Structure):
@@ -138,6 +140,8 @@ def load(build_if_missing: bool = True):
     L.pdhg_get_iterate.restype = C.c_int
     L.pdhg_set_iterate.argtypes = [P, P, P]
     L.pdhg_set_iterate.restype = C.c_int
+    L.pdhg_set_schedule.argtypes = [P, i32, i32, i32, i32]
+    L.pdhg_set_schedule.restype = C.c_int
     L.pdhg_state_bytes.argtypes = [P]
     L.pdhg_state_bytes.restype = C.c_size_t
     L.pdhg_get_state.argtypes = [P, P, C.c_size_t]
@@ -316,14 +320,25 @@ class Solver:
 
     def autotune(self, iters=20, use_cache=True):
         """pdhg_autotune: time the column-slab counts of A x and A'y on this
-        matrix and keep the fastest; returns the slab counts in use and the
-        timings (ms per product) of the counts tried."""
+        matrix, then the lanes per row (one power of two below, at and above
+        the rule), keeping the fastest of each; returns the choices in use
+        and the timings (ms per product) of the candidates tried."""
         t = Tune()
         _check(self._L.pdhg_autotune(self.h, int(iters), 1 if use_cache else 0, C.byref(t)),
                "pdhg_autotune")
-        return dict(slabs_A=t.slabs_A, slabs_At=t.slabs_At, from_cache=bool(t.from_cache),
+        cached = bool(t.from_cache)
+        return dict(slabs_A=t.slabs_A, slabs_At=t.slabs_At, from_cache=cached,
+                    lanes_bias_A=t.lanes_bias_A, lanes_bias_At=t.lanes_bias_At,
                     A={int(t.tried_A[i]): float(t.ms_A[i]) for i in range(t.candidates_A)},
-                    At={int(t.tried_At[i]): float(t.ms_At[i]) for i in range(t.candidates_At)})
+                    At={int(t.tried_At[i]): float(t.ms_At[i]) for i in range(t.candidates_At)},
+                    lanes_A={} if cached else {b - 1: float(t.ms_lanes_A[b]) for b in range(3)},
+                    lanes_At={} if cached else {b - 1: float(t.ms_lanes_At[b])
+                                                for b in range(3)})
+
+    def set_schedule(self, slabs_A=1, slabs_At=1, lanes_bias_A=0, lanes_bias_At=0):
+        """pdhg_set_schedule: pin the slab counts and lanes-per-row biases."""
+        _check(self._L.pdhg_set_schedule(self.h, int(slabs_A), int(slabs_At), int(lanes_bias_A),
+                                         int(lanes_bias_At)), "pdhg_set_schedule")
 
     # -- evaluation --------------------------------------------------------
     def kkt(self, which=POINT_CURRENT):

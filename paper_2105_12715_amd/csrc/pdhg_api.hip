@@ -1016,8 +1016,17 @@ static int matrix_signature(pdhg_t *h, uint64_t *sig) {
     return PDHG_OK;
 }
 
+struct TuneChoice {
+    int slabs[2], lbias[2];  // [0] A x, [1] A'y
+};
 static std::mutex g_tune_mu;
-static std::map<uint64_t, std::pair<int, int>> g_tune_cache;
+static std::map<uint64_t, TuneChoice> g_tune_cache;
+
+static void set_lbias(pdhg_t *h, int t, int b) {
+    int &cur = t == 0 ? h->d.lbA : h->d.lbT;
+    if (cur != b) h->g_valid = false;  // the recorded block holds the old value
+    cur = b;
+}
 
 int pdhg_autotune(pdhg_t *h, int32_t iters, int32_t use_cache, pdhg_tune *out) {
     if (!h || iters < 1 || iters > 10000) return PDHG_E_INVALID;
@@ -1027,7 +1036,7 @@ int pdhg_autotune(pdhg_t *h, int32_t iters, int32_t use_cache, pdhg_tune *out) {
     uint64_t sig = 0;
     if ((rc = matrix_signature(h, &sig))) return rc;
     bool cached = false;
-    std::pair<int, int> choice(h->d.slA.S, h->d.slT.S);
+    TuneChoice choice{{h->d.slA.S, h->d.slT.S}, {h->d.lbA, h->d.lbT}};
     if (use_cache) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(sig);
@@ -1037,38 +1046,81 @@ int pdhg_autotune(pdhg_t *h, int32_t iters, int32_t use_cache, pdhg_tune *out) {
         }
     }
     if (cached) {
-        if ((rc = set_slabs(h, 0, choice.first)) || (rc = set_slabs(h, 1, choice.second)))
-            return rc;
+        for (int t = 0; t < 2; ++t) {
+            if ((rc = set_slabs(h, t, choice.slabs[t]))) return rc;
+            set_lbias(h, t, choice.lbias[t]);
+        }
         r.from_cache = 1;
     } else {
         int *tried[2] = {r.tried_A, r.tried_At};
         double *ms[2] = {r.ms_A, r.ms_At};
         int *ncand[2] = {&r.candidates_A, &r.candidates_At};
-        int best[2] = {h->d.slA.S, h->d.slT.S};
+        double *msl[2] = {r.ms_lanes_A, r.ms_lanes_At};
         for (int t = 0; t < 2; ++t) {
-            if (h->slab_cap[t] <= 1) continue;
-            double bt = 0.0;
-            for (int S = 1; S <= h->slab_cap[t] && *ncand[t] < 4; S <<= 1) {
+            // 1. column slabs (when the gathered vector exceeds one L2),
+            //    with the lanes rule as it is
+            set_lbias(h, t, 0);
+            int best = t == 0 ? h->d.slA.S : h->d.slT.S;
+            if (h->slab_cap[t] > 1) {
+                double bt = 0.0;
+                for (int S = 1; S <= h->slab_cap[t] && *ncand[t] < 4; S <<= 1) {
+                    double m = 0.0;
+                    if ((rc = set_slabs(h, t, S)) || (rc = time_product(h, t, iters, &m)))
+                        return rc;
+                    tried[t][*ncand[t]] = S;
+                    ms[t][*ncand[t]] = m;
+                    ++*ncand[t];
+                    if (*ncand[t] == 1 || m < bt) {
+                        bt = m;
+                        best = S;
+                    }
+                }
+                if ((rc = set_slabs(h, t, best))) return rc;
+            }
+            choice.slabs[t] = best;
+            // 2. lanes per row one power of two below, at and above the rule
+            int bb = 0;
+            double bl = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const int b = k - 1;
+                set_lbias(h, t, b);
                 double m = 0.0;
-                if ((rc = set_slabs(h, t, S)) || (rc = time_product(h, t, iters, &m))) return rc;
-                tried[t][*ncand[t]] = S;
-                ms[t][*ncand[t]] = m;
-                ++*ncand[t];
-                if (*ncand[t] == 1 || m < bt) {
-                    bt = m;
-                    best[t] = S;
+                if ((rc = time_product(h, t, iters, &m))) return rc;
+                msl[t][k] = m;
+                if (k == 0 || m < bl) {
+                    bl = m;
+                    bb = b;
                 }
             }
-            if ((rc = set_slabs(h, t, best[t]))) return rc;
+            set_lbias(h, t, bb);
+            choice.lbias[t] = bb;
         }
-        choice = std::make_pair(best[0], best[1]);
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[sig] = choice;
     }
     CK(hipStreamSynchronize(h->stream));
     r.slabs_A = h->d.slA.S;
     r.slabs_At = h->d.slT.S;
+    r.lanes_bias_A = h->d.lbA;
+    r.lanes_bias_At = h->d.lbT;
     if (out) *out = r;
+    return last_error();
+}
+
+int pdhg_set_schedule(pdhg_t *h, int32_t slabs_A, int32_t slabs_At, int32_t lanes_bias_A,
+                      int32_t lanes_bias_At) {
+    if (!h) return PDHG_E_INVALID;
+    const int sl[2] = {slabs_A, slabs_At}, lb[2] = {lanes_bias_A, lanes_bias_At};
+    for (int t = 0; t < 2; ++t) {
+        const int S = sl[t];
+        if (S < 1 || (S & (S - 1)) || S > h->slab_cap[t] || lb[t] < -1 || lb[t] > 1)
+            return PDHG_E_INVALID;
+    }
+    for (int t = 0; t < 2; ++t) {
+        const int rc = set_slabs(h, t, sl[t]);
+        if (rc) return rc;
+        set_lbias(h, t, lb[t]);
+    }
     return last_error();
 }
 

@@ -2473,7 +2473,7 @@ int pdhg_batch_unrolled_backward(pdhg_batch_t *h, int64_t K, void *tape, size_t 
                                    t.yh, t.syh, t.vh, gb);
             EpiAdjPrimal ep{xt, xp, d.l, d.u, t.xh, t.sxh, gcw, t.uw, d.lp_col, d.lp};
             hipLaunchKernelGGL(k_spmv<EpiAdjPrimal>, dim3(d.nblkT), dim3(kWG), 0, s, d.trp, d.tci,
-                               d.tv, t.vh, d.brT, d.nblkT, ep, (const int *)nullptr);
+                               d.tv, t.vh, d.brT, d.nblkT, ep, (const int *)nullptr, 0);
             if (M)
                 hipLaunchKernelGGL(k_adj_rows, dim3(d.nblkA), dim3(kWG), 0, s, d,
                                    (const double2 *)t.uw, yp, t.vh, t.yh, gA);

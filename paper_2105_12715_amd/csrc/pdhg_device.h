@@ -103,11 +103,14 @@ __device__ __forceinline__ T ld_matrix(const T *p) {
 // Idx: int column indices, or unsigned short ones relative to the start of
 // xin (a caller that knows a block's columns lie in one 65,536-wide window
 // passes xin shifted to that window)
+// lbias moves the lanes per row one power of two down (-1) or up (+1) from
+// the rule below (a per-matrix choice of the tuner; 0 keeps the rule)
 template <class Epi, class Idx = int>
 __device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const Idx *__restrict__ ci,
                                           const double *__restrict__ v,
                                           const double *__restrict__ xin, int r0, int r1,
-                                          int p0, int p1, const Epi &epi, SpmvShared &sm) {
+                                          int p0, int p1, const Epi &epi, SpmvShared &sm,
+                                          int lbias = 0) {
     // rows [r0, r1) hold entries [p0, p1) (from the block table, see
     // k_rowsplit)
     const int tid = threadIdx.x;
@@ -142,6 +145,10 @@ __device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const Idx 
         const int avg = nb / R;
         int L = 1;
         while (L < 64 && 2 * L <= avg) L <<= 1;
+        // the bias keeps R L <= kLdsProducts, so the rounds below still
+        // cover every row
+        if (lbias < 0 && L > 1) L >>= 1;
+        else if (lbias > 0 && L < 64 && R * 2 * L <= kLdsProducts) L <<= 1;
         const int G = kWG / L;
         const int lane = tid & (L - 1), grp = tid / L;
         // A group reduces at most kLdsProducts / kWG rows: L = 1 when the
@@ -189,14 +196,14 @@ __global__ __launch_bounds__(kWG) void k_spmv(const int *__restrict__ rp,
                                               const double *__restrict__ v,
                                               const double *__restrict__ xin,
                                               const int *__restrict__ br, int nblk, Epi epi,
-                                              const int *skip) {
+                                              const int *skip, int lbias = 0) {
     __shared__ SpmvShared lds;
     // the gate and the block table are loaded together (one round trip)
     const int b = blockIdx.x;
     const int r0 = br[b], r1 = br[b + 1], p0 = br[nblk + 1 + b], p1 = br[nblk + 2 + b];
     const int off = skip ? *skip : 0;
     if (off || r0 >= r1) return;
-    spmv_rows(rp, ci, v, xin, r0, r1, p0, p1, epi, lds);
+    spmv_rows(rp, ci, v, xin, r0, r1, p0, p1, epi, lds, lbias);
 }
 
 struct EpiStore {

@@ -127,6 +127,7 @@ struct Dev {
     double omega;              // primal weight (norm of the gap and radii)
     Slabs slA;                 // A by column slabs (gathers x), for A x
     Slabs slT;                 // A' by column slabs (gathers y), for A' y
+    int lbA, lbT;              // lanes-per-row bias of the A x and A'y blocks (-1, 0, +1)
     // Column order.  Columns are kept sorted by entry count (largest first,
     // ties by the row of their first entry), so the most gathered entries
     // of x share cache lines, neighbouring rows of A gather neighbouring
@@ -305,13 +306,8 @@ void launch_tr_raw(int64_t N, const double *a, const double *dd, double r,
 // row fits the registers of its lanes, the matrix) fit one CU's LDS: whole
 // blocks of iterations plus their checks in one launch.
 // ---------------------------------------------------------------------
-// threads of the one workgroup (a build parameter for tuning sweeps); each
-// thread holds at most two trust-region coordinates
-#ifndef PDHG_TINY_WG
-#define PDHG_TINY_WG 512
-#endif
-constexpr int kTinyWG = PDHG_TINY_WG;
-constexpr int kTinyMaxCoords = 2 * kTinyWG;  // n + m
+constexpr int kTinyWG = 512;                 // threads of the one workgroup
+constexpr int kTinyMaxCoords = 2 * kTinyWG;  // n + m (two trust-region coordinates per thread)
 constexpr int kTinyK = 8;                    // matrix entries per lane held in registers
 constexpr size_t kTinyLdsMax = 148u << 10;   // dynamic LDS bytes (static LDS + this <= 160 KB)
 struct TinyPlan {

@@ -140,7 +140,9 @@ void launch_rowsplit(const int *rp, int rows, int nnz, int nblk, int *br, hipStr
 
 // One slab at a time: the sums of slab sl go to acc (slab 0) or are added
 // to it in slab order, and the last slab applies the epilogue to the full
-// sum.
+// sum.  (Letting rows whose entries all lie in one slab take the epilogue
+// in that slab's launch, and skip the accumulator, measured slower: each
+// block then mixes two access streams of partial waves.)
 struct EpiSlabAcc {
     double *acc;
     int first;
@@ -158,7 +160,7 @@ struct EpiSlabLast {
 
 template <class Epi>
 __global__ __launch_bounds__(kWG) void k_slab_one(Slabs sb, int sl, const double *__restrict__ xin,
-                                                  Epi epi, const int *skip) {
+                                                  Epi epi, const int *skip, int lbias) {
     __shared__ SpmvShared lds;
     // the gate and the slab's metadata are loaded together
     const long long *me = sb.smeta + 4 * sl;
@@ -169,19 +171,19 @@ __global__ __launch_bounds__(kWG) void k_slab_one(Slabs sb, int sl, const double
     const int r0 = br[b], r1 = br[b + 1];
     if (r0 >= r1) return;
     spmv_rows(sb.srp + me[0], sb.sci + me[1], sb.sv + me[1], xin + (size_t)sl * sb.W, r0, r1,
-              br[nb + 1 + b], br[nb + 2 + b], epi, lds);
+              br[nb + 1 + b], br[nb + 2 + b], epi, lds, lbias);
 }
 
 // the slabs one after the other, the last with the epilogue fused
 template <class Epi>
 static void slabs_in_turn(const Slabs &sb, const double *in, const Epi &e, const int *skip,
-                          hipStream_t s) {
+                          int lbias, hipStream_t s) {
     double *acc = sb.spart;
     for (int sl = 0; sl + 1 < sb.S; ++sl)
         hipLaunchKernelGGL(k_slab_one<EpiSlabAcc>, dim3(sb.nbmax), dim3(kWG), 0, s, sb, sl, in,
-                           EpiSlabAcc{acc, sl == 0 ? 1 : 0}, skip);
+                           EpiSlabAcc{acc, sl == 0 ? 1 : 0}, skip, lbias);
     hipLaunchKernelGGL(k_slab_one<EpiSlabLast<Epi>>, dim3(sb.nbmax), dim3(kWG), 0, s, sb, sb.S - 1,
-                       in, EpiSlabLast<Epi>{e, acc}, skip);
+                       in, EpiSlabLast<Epi>{e, acc}, skip, lbias);
 }
 
 template <class Epi>
@@ -189,11 +191,11 @@ static void product_A(const Dev &d, const double *in, const Epi &e, const int *s
                       hipStream_t s) {
     if (d.m == 0) return;
     if (d.slA.S > 1) {
-        slabs_in_turn(d.slA, in, e, skip, s);
+        slabs_in_turn(d.slA, in, e, skip, d.lbA, s);
         return;
     }
     hipLaunchKernelGGL(k_spmv<Epi>, dim3(d.nblkA), dim3(kWG), 0, s, d.rp, d.ci, d.v, in, d.brA,
-                       d.nblkA, e, skip);
+                       d.nblkA, e, skip, d.lbA);
 }
 
 // the same over the rows of A' (explicit transpose)
@@ -201,11 +203,11 @@ template <class Epi>
 static void product_T(const Dev &d, const double *in, const Epi &e, const int *skip,
                       hipStream_t s) {
     if (d.slT.S > 1) {
-        slabs_in_turn(d.slT, in, e, skip, s);
+        slabs_in_turn(d.slT, in, e, skip, d.lbT, s);
         return;
     }
     hipLaunchKernelGGL(k_spmv<Epi>, dim3(d.nblkT), dim3(kWG), 0, s, d.trp, d.tci, d.tv, in,
-                       d.brT, d.nblkT, e, skip);
+                       d.brT, d.nblkT, e, skip, d.lbT);
 }
 
 void launch_primal(const Dev &d, double tau, int smode, hipStream_t s) {
