@@ -110,6 +110,9 @@ def traffic(a):
         parts[kf] = {"fetch_bytes": round(fb), "write_bytes": round(wb)}
         total += fb + wb
     return {"kernels": parts, "hbm_bytes_per_launch": round(total),
+            "counts": "bytes between L2 and the memory fabric (FETCH_SIZE, WRITE_SIZE), "
+                      "scaled by the copy yardstick; reads served by the MALL (Infinity "
+                      "Cache) count too, so this is an upper bound on DRAM bytes",
             "copy_kernel": ck, "copy_bytes_each_way": a.copy_bytes,
             "fetch_scale": f_scale, "write_scale": w_scale,
             "kernel_source_hash": a.source_hash, "command": a.cmd}
