@@ -490,6 +490,23 @@ def test_lp_without_rows_and_empty_columns(lib):
     o.solve(900, 0.0)
     s.solve(900, 0.0)
     _compare_points(o, s)
+    # rows with no entries (an = row with b = 0 and a >= row with b <= 0)
+    # and a column with no entries, on both the one-workgroup and the
+    # multi-kernel path
+    A = np.array([[1.0, 0, 2.0, 0], [0, 0, 0, 0], [3.0, 0, -1.0, 0], [0, 0, 0, 0]])
+    lp = lp_from_dense(A, [1.0, 0.0, 2.0, -1.0], [1.0, 1.0, -1.0, 0.5], [0, 0, 0, -1],
+                       [5, 5, 5, 3], kind=[0, 0, 1, 1])
+    for tiny in ("1", "0"):
+        import os
+        os.environ["PDHG_TINY"] = tiny
+        try:
+            o, s = _pair(lp, oracle.MODE_ADAPTIVE)
+        finally:
+            os.environ.pop("PDHG_TINY", None)
+        assert (s.info()["one_workgroup"] != 0) == (tiny == "1")
+        ro, rg = o.solve(20_000, 1e-9), s.solve(20_000, 1e-9)
+        assert (rg["status"], rg["k"], rg["restarts"]) == (ro["status"], ro["k"], ro["restarts"])
+        _compare_points(o, s, where=f"empty rows, one workgroup {tiny}")
 
 
 def test_invalid_lp_is_rejected(lib):
