@@ -56,6 +56,14 @@ static int64_t slab_slice_bytes() {
     return 4ll << 20;
 }
 
+// A's merge-path blocks sorted by column (k_sort_blocks) unless
+// PDHG_SORTED_BLOCKS=0 (read at create; the plain layout gives bitwise the
+// same sums, so tests compare the two)
+static bool sorted_blocks_wanted() {
+    const char *e = getenv("PDHG_SORTED_BLOCKS");
+    return !(e && e[0] == '0');
+}
+
 size_t tr_work_bytes(int64_t N) {
     size_t b = 0;
     b += al(sizeof(unsigned int) * 2 * kBuckets);
@@ -155,6 +163,11 @@ bool make_layout(int64_t m, int64_t n, int64_t nnz, Layout *L) {
     o += al(sizeof(double) * n1);
     L->o_bcls = o;
     o += al(n1);
+    const bool pk = sorted_blocks_fit(n);
+    L->o_apk = o;
+    o += al(pk ? sizeof(unsigned) * z1 : 0);
+    L->o_asv = o;
+    o += al(pk ? sizeof(double) * z1 : 0);
     L->o_part = o;
     o += al(sizeof(double) * kRedBlocks * kKktSums);
     L->o_log = o;
@@ -523,6 +536,13 @@ int pdhg_create(const pdhg_lp *lp, const pdhg_params *prm_in, void *workspace,
         if ((rc = order_columns(d, L, ws, s)) != PDHG_OK) break;
         if ((rc = bound_classes(d, L, ws, s)) != PDHG_OK) break;
         launch_rowsplit(d.rp, d.m, d.nnz, d.nblkA, d.brA, s);
+        if (sorted_blocks_fit(d.n) && d.nnz > 0 && d.m > 0 && sorted_blocks_wanted()) {
+            unsigned *apk = (unsigned *)(ws + L.o_apk);
+            double *asv = (double *)(ws + L.o_asv);
+            launch_sort_blocks(d.rp, d.ci, d.v, d.brA, d.nblkA, apk, asv, s);
+            d.apk = apk;
+            d.asv = asv;
+        }
         launch_transpose(d, s);
         launch_rowsplit(d.trp, d.n, d.nnz, d.nblkT, d.brT, s);
         if (d.slA.S > 1 && (rc = build_slabs(d.slA, d.rp, d.ci, d.v, d.nnz, d.nblkA,

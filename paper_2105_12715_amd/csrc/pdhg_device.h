@@ -103,9 +103,14 @@ __device__ __forceinline__ T ld_matrix(const T *p) {
 // Idx: int column indices, or unsigned short ones relative to the start of
 // xin (a caller that knows a block's columns lie in one 65,536-wide window
 // passes xin shifted to that window)
+// PK: the block's entries are stored sorted by column, each as one 32-bit
+// word col << kPkSlotBits | slot, where slot is the entry's place in the
+// block's row order (see k_sort_blocks); values follow the same order.
+// The product of an entry goes to LDS at its slot, so the row sums add
+// exactly the same terms in exactly the same order as the plain layout.
 // lbias moves the lanes per row one power of two down (-1) or up (+1) from
 // the rule below (a per-matrix choice of the tuner; 0 keeps the rule)
-template <class Epi, class Idx = int>
+template <class Epi, class Idx = int, bool PK = false>
 __device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const Idx *__restrict__ ci,
                                           const double *__restrict__ v,
                                           const double *__restrict__ xin, int r0, int r1,
@@ -135,11 +140,11 @@ __device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const Idx 
         }
 #pragma unroll
         for (int k = 0; k < kPerThread; ++k)
-            if (tid + k * kWG < nb) g[k] = xin[col[k]];
+            if (tid + k * kWG < nb) g[k] = xin[PK ? (int)((unsigned)col[k] >> kPkSlotBits) : col[k]];
 #pragma unroll
         for (int k = 0; k < kPerThread; ++k) {
             const int e = tid + k * kWG;
-            if (e < nb) sm.prod[e] = val[k] * g[k];
+            if (e < nb) sm.prod[PK ? (int)((unsigned)col[k] & kPkSlotMask) : e] = val[k] * g[k];
         }
         __syncthreads();
         const int avg = nb / R;
@@ -182,17 +187,19 @@ __device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const Idx 
         const int wave = tid >> 6, lane = tid & 63;
         for (int row = r0 + wave; row < r1; row += kWG / 64) {
             double s = 0.0;
-            for (int p = rp[row] + lane; p < rp[row + 1]; p += 64)
-                s += ld_matrix(v + p) * xin[ld_matrix(ci + p)];
+            for (int p = rp[row] + lane; p < rp[row + 1]; p += 64) {
+                const Idx c = ld_matrix(ci + p);
+                s += ld_matrix(v + p) * xin[PK ? (int)((unsigned)c >> kPkSlotBits) : (int)c];
+            }
             s = wave_sum(s);
             if (lane == 0) epi(row, s);
         }
     }
 }
 
-template <class Epi>
+template <class Epi, class Idx = int, bool PK = false>
 __global__ __launch_bounds__(kWG) void k_spmv(const int *__restrict__ rp,
-                                              const int *__restrict__ ci,
+                                              const Idx *__restrict__ ci,
                                               const double *__restrict__ v,
                                               const double *__restrict__ xin,
                                               const int *__restrict__ br, int nblk, Epi epi,
@@ -203,7 +210,7 @@ __global__ __launch_bounds__(kWG) void k_spmv(const int *__restrict__ rp,
     const int r0 = br[b], r1 = br[b + 1], p0 = br[nblk + 1 + b], p1 = br[nblk + 2 + b];
     const int off = skip ? *skip : 0;
     if (off || r0 >= r1) return;
-    spmv_rows(rp, ci, v, xin, r0, r1, p0, p1, epi, lds, lbias);
+    spmv_rows<Epi, Idx, PK>(rp, ci, v, xin, r0, r1, p0, p1, epi, lds, lbias);
 }
 
 struct EpiStore {

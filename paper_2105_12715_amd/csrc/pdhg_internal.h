@@ -16,6 +16,15 @@ constexpr int kWG = 256;             // threads per workgroup (4 wave64)
 constexpr int kUnits = PDHG_SPMV_UNITS;
 constexpr int kLdsProducts = 2 * kUnits;  // products staged in LDS per SpMV block
 static_assert(kLdsProducts <= 65535, "row starts are staged as 16-bit offsets");
+// Blocks stored sorted by column (Dev::apk): one 32-bit word per entry,
+// column << kPkSlotBits | slot, with the slot the entry's place in its block
+// (so a block holds at most 2^kPkSlotBits staged entries)
+constexpr int kPkSlotBits = 11;
+constexpr unsigned kPkSlotMask = (1u << kPkSlotBits) - 1u;
+constexpr int64_t kPkMaxCols = 1ll << (32 - kPkSlotBits);
+inline bool sorted_blocks_fit(int64_t cols) {
+    return kLdsProducts <= (1 << kPkSlotBits) && cols <= kPkMaxCols;
+}
 constexpr int kRedBlocks = 1024;     // max blocks of a partial-sum reduction
 constexpr int kKktSums = 14;         // partial sums of the KKT / radius pass
 constexpr int kBuckets = 2048;       // radix buckets of the multiplier search
@@ -144,6 +153,12 @@ struct Dev {
     const unsigned char *bcls;
     double blo[kBoundClasses], bhi[kBoundClasses];
     int nbcls;                 // distinct pairs in use (0 with bcls null)
+    // A with each merge-path block's entries sorted by column (k_sort_blocks):
+    // the lanes of a wave that gather the same cache line of x are then
+    // neighbours and share one request.  Null when A runs over column slabs
+    // or has too many columns for the packed word.
+    const unsigned *apk;       // [nnz] column << kPkSlotBits | slot
+    const double *asv;         // [nnz] values in the same order
 };
 
 // Column slabs: each slab's slice of the gathered vector is meant to fit
@@ -200,6 +215,7 @@ struct Layout {
     size_t o_slab[2][6];       // srp, sci, sv, sbr, smeta, spart of slA, slT
     size_t o_xt, o_yt;
     size_t o_ci2, o_cperm, o_cinv, o_c2, o_l2, o_u2, o_bcls;
+    size_t o_apk, o_asv;       // A's blocks sorted by column (empty when they cannot be packed)
     size_t o_tr[kTrSlots];
 };
 bool make_layout(int64_t m, int64_t n, int64_t nnz, Layout *L);
@@ -215,6 +231,12 @@ int nblocks_for(int rows, int nnz);
 void launch_validate(const Dev &d, hipStream_t s);
 void launch_transpose(const Dev &d, hipStream_t s);
 void launch_rowsplit(const int *rp, int rows, int nnz, int nblk, int *br, hipStream_t s);
+// the merge-path blocks of the CSR (rp, ci, v) with table br (k_rowsplit),
+// each block's entries sorted by column into pk (column << kPkSlotBits |
+// place in the block) and sv; blocks too long for the LDS stage keep their
+// order
+void launch_sort_blocks(const int *rp, const int *ci, const double *v, const int *br, int nblk,
+                        unsigned *pk, double *sv, hipStream_t s);
 void launch_init_point(const Dev &d, hipStream_t s);
 // column slabs (when sb.S > 1) of the CSR (rp, ci, v): row starts of every
 // slab (scan scratch: div_up(rows + 1, 2048) ints), then the entries

@@ -138,6 +138,67 @@ void launch_rowsplit(const int *rp, int rows, int nnz, int nblk, int *br, hipStr
     hipLaunchKernelGGL(k_rowsplit, dim3(div_up(nblk + 1, kWG)), dim3(kWG), 0, s, rp, rows, nblk, br);
 }
 
+// Each merge-path block's entries sorted by column: the key of an entry is
+// column << kPkSlotBits | its place in the block, unique within the block,
+// so an ascending bitonic sort of the keys in LDS gives one definite order
+// (columns ascending, then places).  Padding keys (all ones) sort last; a
+// real key can only equal them as the block's largest, whose slot then
+// holds that same value.  Blocks longer than the LDS stage (the one-wave-
+// per-row path of spmv_rows) keep their order.
+__global__ __launch_bounds__(kWG) void k_sort_blocks(const int *__restrict__ rp,
+                                                     const int *__restrict__ ci,
+                                                     const double *__restrict__ v,
+                                                     const int *__restrict__ br, int nblk,
+                                                     unsigned *__restrict__ pk,
+                                                     double *__restrict__ sv) {
+    __shared__ unsigned key[kLdsProducts];
+    (void)rp;
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int p0 = br[nblk + 1 + b], p1 = br[nblk + 2 + b];
+    const int nb = p1 - p0;
+    if (nb <= 0) return;
+    if (nb > kLdsProducts) {
+        for (int e = tid; e < nb; e += kWG) {
+            pk[p0 + e] = ((unsigned)ci[p0 + e] << kPkSlotBits) | ((unsigned)e & kPkSlotMask);
+            sv[p0 + e] = v[p0 + e];
+        }
+        return;
+    }
+    int P2 = 1;
+    while (P2 < nb) P2 <<= 1;
+    for (int e = tid; e < P2; e += kWG)
+        key[e] = e < nb ? (((unsigned)ci[p0 + e] << kPkSlotBits) | (unsigned)e) : 0xFFFFFFFFu;
+    __syncthreads();
+    for (int k = 2; k <= P2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < P2; i += kWG) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const unsigned a = key[i], c = key[l];
+                    const bool up = (i & k) == 0;
+                    if ((a > c) == up) {
+                        key[i] = c;
+                        key[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = tid; e < nb; e += kWG) {
+        const unsigned w = key[e];
+        pk[p0 + e] = w;
+        sv[p0 + e] = v[p0 + (int)(w & kPkSlotMask)];
+    }
+}
+
+void launch_sort_blocks(const int *rp, const int *ci, const double *v, const int *br, int nblk,
+                        unsigned *pk, double *sv, hipStream_t s) {
+    if (nblk > 0)
+        hipLaunchKernelGGL(k_sort_blocks, dim3(nblk), dim3(kWG), 0, s, rp, ci, v, br, nblk, pk,
+                           sv);
+}
+
 // One slab at a time: the sums of slab sl go to acc (slab 0) or are added
 // to it in slab order, and the last slab applies the epilogue to the full
 // sum.  (Letting rows whose entries all lie in one slab take the epilogue
@@ -192,6 +253,11 @@ static void product_A(const Dev &d, const double *in, const Epi &e, const int *s
     if (d.m == 0) return;
     if (d.slA.S > 1) {
         slabs_in_turn(d.slA, in, e, skip, d.lbA, s);
+        return;
+    }
+    if (d.apk) {
+        hipLaunchKernelGGL((k_spmv<Epi, unsigned, true>), dim3(d.nblkA), dim3(kWG), 0, s, d.rp,
+                           d.apk, d.asv, in, d.brA, d.nblkA, e, skip, d.lbA);
         return;
     }
     hipLaunchKernelGGL(k_spmv<Epi>, dim3(d.nblkA), dim3(kWG), 0, s, d.rp, d.ci, d.v, in, d.brA,

@@ -1,0 +1,79 @@
+"""A's merge-path blocks stored sorted by column (the layout the A x products
+use by default when the columns fit the packed word) against the plain row
+order.  Each product lands in LDS at its place in the row order, so the row
+sums add the same terms in the same order: iterates, check records and
+products must be bitwise equal, including blocks longer than the LDS stage
+(one dense row of 6000 entries) and LPs whose A has no column slabs.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2105_12715_amd import lpgen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2105_12715_amd import _lib
+    _lib.load(build_if_missing=False)
+    return _lib
+
+
+def dense_row_lp(seed=31, m=400, n=6000, per_col=3):
+    """Row 0 holds an entry in every column (a block longer than the LDS
+    stage); every column has per_col more entries at distinct rows 1..m-1."""
+    rng = np.random.default_rng(seed)
+    cols = np.repeat(np.arange(n), per_col)
+    rows = np.concatenate([rng.choice(np.arange(1, m), per_col, replace=False)
+                           for _ in range(n)])
+    rows = np.concatenate([np.zeros(n, np.int64), rows])
+    cols = np.concatenate([np.arange(n), cols])
+    vals = rng.standard_normal(rows.size)
+    return lpgen.planted_lp(rng, m, n, rows, cols, vals, np.zeros(n), np.ones(n),
+                            name="dense_row")
+
+
+CASES = {
+    "powerlaw": lambda: lpgen.column_count_lp(3, 3000, 7000, counts="powerlaw2",
+                                              values="loguniform", bounds="mix"),
+    "dense_row": dense_row_lp,
+    "medium20kx50k": lambda: lpgen.medium(2),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_sorted_blocks_bitwise_equal(lib, name, monkeypatch):
+    lp = CASES[name]()
+    _say(f"[sorted-blocks] {name}: m={lp.m} n={lp.n} nnz={lp.nnz}")
+    out = {}
+    for mode in ("sorted", "plain"):
+        if mode == "plain":
+            monkeypatch.setenv("PDHG_SORTED_BLOCKS", "0")
+        else:
+            monkeypatch.delenv("PDHG_SORTED_BLOCKS", raising=False)
+        monkeypatch.setenv("PDHG_TINY", "0")
+        s = lib.Solver(lp, eta=0.0)
+        r = s.solve(600, 0.0)
+        x, y = (t.cpu().numpy() for t in s.get_iterate(lib.POINT_CURRENT))
+        xa, ya = (t.cpu().numpy() for t in s.get_iterate(lib.POINT_AVERAGE))
+        v = np.random.default_rng(5).standard_normal(lp.n)
+        ax = s.matvec(torch.from_numpy(v).to("cuda")).cpu().numpy()
+        out[mode] = (r, s.info()["eta"], x, y, xa, ya, ax, s.check_log())
+        s.close()
+    a, b = out["sorted"], out["plain"]
+    assert a[0]["k"] == b[0]["k"] and a[0]["restarts"] == b[0]["restarts"]
+    assert a[1] == b[1], "power iteration (A'A products) differs"
+    for k, what in ((2, "x"), (3, "y"), (4, "x-bar"), (5, "y-bar"), (6, "A v")):
+        assert np.array_equal(a[k], b[k]), f"{name}: {what} differs between layouts"
+    assert np.array_equal(np.asarray(a[7]), np.asarray(b[7])), "check records differ"
