@@ -64,6 +64,15 @@ static bool sorted_blocks_wanted() {
     return !(e && e[0] == '0');
 }
 
+// threads per workgroup of the single-LP products; PDHG_SPMV_WG=128 or 256
+// overrides the default (read at create)
+static int spmv_wg_default() {
+    const char *e = getenv("PDHG_SPMV_WG");
+    if (e && atoi(e) == 128) return 128;
+    if (e && atoi(e) == 256) return kWG;
+    return kWG;
+}
+
 size_t tr_work_bytes(int64_t N) {
     size_t b = 0;
     b += al(sizeof(unsigned int) * 2 * kBuckets);
@@ -497,6 +506,7 @@ int pdhg_create(const pdhg_lp *lp, const pdhg_params *prm_in, void *workspace,
     for (int sidx = 0; sidx < kTrSlots; ++sidx)
         carve_tr(ws + L.o_tr[sidx], (int64_t)d.n + d.m, &d.tr[sidx]);
     d.omega = prm.omega;
+    d.swg = spmv_wg_default();
     Slabs *sl[2] = {&d.slA, &d.slT};
     const int rows_of[2] = {d.m, d.n}, gath_of[2] = {d.n, d.m};
     for (int t = 0; t < 2; ++t) {

@@ -100,6 +100,40 @@ __device__ __forceinline__ T ld_matrix(const T *p) {
 #endif
 }
 
+// One chunk of a block's staging: row starts [rbase, rbase + KR WG) and
+// entries [ebase, ebase + K WG) (clipped to the block), every slot loading
+// from a clamped address so that the loads of a thread form one straight
+// run: the compiler's wait counts then keep them all in flight (a branch per
+// slot made it wait for each load before issuing the next).  Loads are
+// issued row starts first, then column indices, then values, then gathers.
+template <int WG, int K, int KR, class Idx, bool PK>
+__device__ __forceinline__ void spmv_stage(const int *__restrict__ rp, const Idx *__restrict__ ci,
+                                           const double *__restrict__ v,
+                                           const double *__restrict__ xin, int r0, int R, int p0,
+                                           int nb, int rbase, int ebase, SpmvShared &sm) {
+    const int tid = threadIdx.x;
+    int rw[KR], col[K];
+    double val[K], g[K];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) rw[k] = rp[r0 + min(rbase + tid + k * WG, R)];
+#pragma unroll
+    for (int k = 0; k < K; ++k) col[k] = (int)ld_matrix(ci + p0 + min(ebase + tid + k * WG, nb - 1));
+#pragma unroll
+    for (int k = 0; k < K; ++k) val[k] = ld_matrix(v + p0 + min(ebase + tid + k * WG, nb - 1));
+#pragma unroll
+    for (int k = 0; k < K; ++k) g[k] = xin[PK ? (int)((unsigned)col[k] >> kPkSlotBits) : col[k]];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+        const int i = rbase + tid + k * WG;
+        if (i <= R) sm.rows[i] = (unsigned short)(rw[k] - p0);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int e = ebase + tid + k * WG;
+        if (e < nb) sm.prod[PK ? (int)((unsigned)col[k] & kPkSlotMask) : e] = val[k] * g[k];
+    }
+}
+
 // Idx: int column indices, or unsigned short ones relative to the start of
 // xin (a caller that knows a block's columns lie in one 65,536-wide window
 // passes xin shifted to that window)
@@ -108,9 +142,10 @@ __device__ __forceinline__ T ld_matrix(const T *p) {
 // block's row order (see k_sort_blocks); values follow the same order.
 // The product of an entry goes to LDS at its slot, so the row sums add
 // exactly the same terms in exactly the same order as the plain layout.
+// WG: threads of the workgroup running the block.
 // lbias moves the lanes per row one power of two down (-1) or up (+1) from
 // the rule below (a per-matrix choice of the tuner; 0 keeps the rule)
-template <class Epi, class Idx = int, bool PK = false>
+template <class Epi, class Idx = int, bool PK = false, int WG = kWG>
 __device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const Idx *__restrict__ ci,
                                           const double *__restrict__ v,
                                           const double *__restrict__ xin, int r0, int r1,
@@ -122,29 +157,23 @@ __device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const Idx 
     const int nb = p1 - p0;
     const int R = r1 - r0;  // <= kUnits: every row start takes one unit of the block
     if (nb <= kLdsProducts) {
-        // Every global load of a thread is issued before the first is used:
-        // row starts and matrix entries together, then all gathers, so one
-        // block waits on three memory round trips instead of one per entry.
+        // The block's row starts, entries and gathers in chunks (one chunk
+        // for a typical block: about kUnits entries and a few hundred rows).
         // The matrix is read once per launch: non-temporal loads keep it
         // from evicting the gathered vector from L2 and the MALL.
-        for (int i = tid; i <= R; i += kWG) sm.rows[i] = (unsigned short)(rp[r0 + i] - p0);
-        int col[kPerThread];
-        double val[kPerThread], g[kPerThread];
-#pragma unroll
-        for (int k = 0; k < kPerThread; ++k) {
-            const int e = tid + k * kWG;
-            if (e < nb) {
-                col[k] = ld_matrix(ci + p0 + e);
-                val[k] = ld_matrix(v + p0 + e);
+        constexpr int K = 1024 / WG, KR = 512 / WG;
+        if (nb == 0) {
+            for (int i = tid; i <= R; i += WG) sm.rows[i] = 0;
+        } else {
+            for (int base = 0, rbase = 0; base < nb || rbase <= R;
+                 base += K * WG, rbase += KR * WG) {
+                if (base < nb)
+                    spmv_stage<WG, K, KR, Idx, PK>(rp, ci, v, xin, r0, R, p0, nb,
+                                                   rbase <= R ? rbase : R, base, sm);
+                else
+                    for (int i = rbase + tid; i <= R && i < rbase + KR * WG; i += WG)
+                        sm.rows[i] = (unsigned short)(rp[r0 + i] - p0);
             }
-        }
-#pragma unroll
-        for (int k = 0; k < kPerThread; ++k)
-            if (tid + k * kWG < nb) g[k] = xin[PK ? (int)((unsigned)col[k] >> kPkSlotBits) : col[k]];
-#pragma unroll
-        for (int k = 0; k < kPerThread; ++k) {
-            const int e = tid + k * kWG;
-            if (e < nb) sm.prod[PK ? (int)((unsigned)col[k] & kPkSlotMask) : e] = val[k] * g[k];
         }
         __syncthreads();
         const int avg = nb / R;
@@ -154,12 +183,12 @@ __device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const Idx 
         // cover every row
         if (lbias < 0 && L > 1) L >>= 1;
         else if (lbias > 0 && L < 64 && R * 2 * L <= kLdsProducts) L <<= 1;
-        const int G = kWG / L;
+        const int G = WG / L;
         const int lane = tid & (L - 1), grp = tid / L;
-        // A group reduces at most kLdsProducts / kWG rows: L = 1 when the
+        // A group reduces at most kLdsProducts / WG rows: L = 1 when the
         // mean row length avg = nb / R is below 2 (and R <= kUnits), else
-        // L <= avg, so R L <= nb <= kLdsProducts and R / G = R L / kWG.
-        constexpr int kRounds = kLdsProducts / kWG;
+        // L <= avg, so R L <= nb <= kLdsProducts and R / G = R L / WG.
+        constexpr int kRounds = kLdsProducts / WG;
         double mine[kRounds];
 #pragma unroll
         for (int t = 0; t < kRounds; ++t) {
@@ -182,10 +211,10 @@ __device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const Idx 
                 if (grp + t * G < R) sm.prod[grp + t * G] = mine[t];
         }
         __syncthreads();
-        for (int rr = tid; rr < R; rr += kWG) epi(r0 + rr, sm.prod[rr]);
+        for (int rr = tid; rr < R; rr += WG) epi(r0 + rr, sm.prod[rr]);
     } else {
         const int wave = tid >> 6, lane = tid & 63;
-        for (int row = r0 + wave; row < r1; row += kWG / 64) {
+        for (int row = r0 + wave; row < r1; row += WG / 64) {
             double s = 0.0;
             for (int p = rp[row] + lane; p < rp[row + 1]; p += 64) {
                 const Idx c = ld_matrix(ci + p);
@@ -197,20 +226,20 @@ __device__ __forceinline__ void spmv_rows(const int *__restrict__ rp, const Idx 
     }
 }
 
-template <class Epi, class Idx = int, bool PK = false>
-__global__ __launch_bounds__(kWG) void k_spmv(const int *__restrict__ rp,
-                                              const Idx *__restrict__ ci,
-                                              const double *__restrict__ v,
-                                              const double *__restrict__ xin,
-                                              const int *__restrict__ br, int nblk, Epi epi,
-                                              const int *skip, int lbias = 0) {
+template <class Epi, class Idx = int, bool PK = false, int WG = kWG>
+__global__ __launch_bounds__(WG) void k_spmv(const int *__restrict__ rp,
+                                             const Idx *__restrict__ ci,
+                                             const double *__restrict__ v,
+                                             const double *__restrict__ xin,
+                                             const int *__restrict__ br, int nblk, Epi epi,
+                                             const int *skip, int lbias = 0) {
     __shared__ SpmvShared lds;
     // the gate and the block table are loaded together (one round trip)
     const int b = blockIdx.x;
     const int r0 = br[b], r1 = br[b + 1], p0 = br[nblk + 1 + b], p1 = br[nblk + 2 + b];
     const int off = skip ? *skip : 0;
     if (off || r0 >= r1) return;
-    spmv_rows<Epi, Idx, PK>(rp, ci, v, xin, r0, r1, p0, p1, epi, lds, lbias);
+    spmv_rows<Epi, Idx, PK, WG>(rp, ci, v, xin, r0, r1, p0, p1, epi, lds, lbias);
 }
 
 struct EpiStore {

@@ -159,6 +159,7 @@ struct Dev {
     // or has too many columns for the packed word.
     const unsigned *apk;       // [nnz] column << kPkSlotBits | slot
     const double *asv;         // [nnz] values in the same order
+    int swg;                   // threads per workgroup of the products: 128 or kWG
 };
 
 // Column slabs: each slab's slice of the gathered vector is meant to fit

@@ -219,9 +219,9 @@ struct EpiSlabLast {
     __device__ __forceinline__ void operator()(int r, double s) const { inner(r, acc[r] + s); }
 };
 
-template <class Epi>
-__global__ __launch_bounds__(kWG) void k_slab_one(Slabs sb, int sl, const double *__restrict__ xin,
-                                                  Epi epi, const int *skip, int lbias) {
+template <class Epi, int WG = kWG>
+__global__ __launch_bounds__(WG) void k_slab_one(Slabs sb, int sl, const double *__restrict__ xin,
+                                                 Epi epi, const int *skip, int lbias) {
     __shared__ SpmvShared lds;
     // the gate and the slab's metadata are loaded together
     const long long *me = sb.smeta + 4 * sl;
@@ -231,49 +231,65 @@ __global__ __launch_bounds__(kWG) void k_slab_one(Slabs sb, int sl, const double
     const int *br = sb.sbr + me[2];
     const int r0 = br[b], r1 = br[b + 1];
     if (r0 >= r1) return;
-    spmv_rows(sb.srp + me[0], sb.sci + me[1], sb.sv + me[1], xin + (size_t)sl * sb.W, r0, r1,
-              br[nb + 1 + b], br[nb + 2 + b], epi, lds, lbias);
+    spmv_rows<Epi, int, false, WG>(sb.srp + me[0], sb.sci + me[1], sb.sv + me[1],
+                                   xin + (size_t)sl * sb.W, r0, r1, br[nb + 1 + b], br[nb + 2 + b],
+                                   epi, lds, lbias);
 }
 
 // the slabs one after the other, the last with the epilogue fused
-template <class Epi>
+template <class Epi, int WG>
 static void slabs_in_turn(const Slabs &sb, const double *in, const Epi &e, const int *skip,
                           int lbias, hipStream_t s) {
     double *acc = sb.spart;
     for (int sl = 0; sl + 1 < sb.S; ++sl)
-        hipLaunchKernelGGL(k_slab_one<EpiSlabAcc>, dim3(sb.nbmax), dim3(kWG), 0, s, sb, sl, in,
-                           EpiSlabAcc{acc, sl == 0 ? 1 : 0}, skip, lbias);
-    hipLaunchKernelGGL(k_slab_one<EpiSlabLast<Epi>>, dim3(sb.nbmax), dim3(kWG), 0, s, sb, sb.S - 1,
-                       in, EpiSlabLast<Epi>{e, acc}, skip, lbias);
+        hipLaunchKernelGGL((k_slab_one<EpiSlabAcc, WG>), dim3(sb.nbmax), dim3(WG), 0, s, sb, sl,
+                           in, EpiSlabAcc{acc, sl == 0 ? 1 : 0}, skip, lbias);
+    hipLaunchKernelGGL((k_slab_one<EpiSlabLast<Epi>, WG>), dim3(sb.nbmax), dim3(WG), 0, s, sb,
+                       sb.S - 1, in, EpiSlabLast<Epi>{e, acc}, skip, lbias);
 }
 
+template <class Epi, int WG>
+static void product_A_wg(const Dev &d, const double *in, const Epi &e, const int *skip,
+                         hipStream_t s) {
+    if (d.slA.S > 1) {
+        slabs_in_turn<Epi, WG>(d.slA, in, e, skip, d.lbA, s);
+        return;
+    }
+    if (d.apk) {
+        hipLaunchKernelGGL((k_spmv<Epi, unsigned, true, WG>), dim3(d.nblkA), dim3(WG), 0, s, d.rp,
+                           d.apk, d.asv, in, d.brA, d.nblkA, e, skip, d.lbA);
+        return;
+    }
+    hipLaunchKernelGGL((k_spmv<Epi, int, false, WG>), dim3(d.nblkA), dim3(WG), 0, s, d.rp, d.ci,
+                       d.v, in, d.brA, d.nblkA, e, skip, d.lbA);
+}
+
+// workgroup size of the single-LP products (Dev::swg)
 template <class Epi>
 static void product_A(const Dev &d, const double *in, const Epi &e, const int *skip,
                       hipStream_t s) {
     if (d.m == 0) return;
-    if (d.slA.S > 1) {
-        slabs_in_turn(d.slA, in, e, skip, d.lbA, s);
-        return;
-    }
-    if (d.apk) {
-        hipLaunchKernelGGL((k_spmv<Epi, unsigned, true>), dim3(d.nblkA), dim3(kWG), 0, s, d.rp,
-                           d.apk, d.asv, in, d.brA, d.nblkA, e, skip, d.lbA);
-        return;
-    }
-    hipLaunchKernelGGL(k_spmv<Epi>, dim3(d.nblkA), dim3(kWG), 0, s, d.rp, d.ci, d.v, in, d.brA,
-                       d.nblkA, e, skip, d.lbA);
+    if (d.swg == 128) product_A_wg<Epi, 128>(d, in, e, skip, s);
+    else product_A_wg<Epi, kWG>(d, in, e, skip, s);
 }
 
 // the same over the rows of A' (explicit transpose)
+template <class Epi, int WG>
+static void product_T_wg(const Dev &d, const double *in, const Epi &e, const int *skip,
+                         hipStream_t s) {
+    if (d.slT.S > 1) {
+        slabs_in_turn<Epi, WG>(d.slT, in, e, skip, d.lbT, s);
+        return;
+    }
+    hipLaunchKernelGGL((k_spmv<Epi, int, false, WG>), dim3(d.nblkT), dim3(WG), 0, s, d.trp,
+                       d.tci, d.tv, in, d.brT, d.nblkT, e, skip, d.lbT);
+}
+
 template <class Epi>
 static void product_T(const Dev &d, const double *in, const Epi &e, const int *skip,
                       hipStream_t s) {
-    if (d.slT.S > 1) {
-        slabs_in_turn(d.slT, in, e, skip, d.lbT, s);
-        return;
-    }
-    hipLaunchKernelGGL(k_spmv<Epi>, dim3(d.nblkT), dim3(kWG), 0, s, d.trp, d.tci, d.tv, in,
-                       d.brT, d.nblkT, e, skip, d.lbT);
+    if (d.swg == 128) product_T_wg<Epi, 128>(d, in, e, skip, s);
+    else product_T_wg<Epi, kWG>(d, in, e, skip, s);
 }
 
 void launch_primal(const Dev &d, double tau, int smode, hipStream_t s) {
