@@ -235,6 +235,9 @@ typedef struct pdhg_tune {
                                              of two from the block's rule        */
     double ms_lanes_A[3], ms_lanes_At[3]; /* one product with bias -1, 0, +1, ms
                                              (not filled when cached)            */
+    int32_t threads_A, threads_At;        /* threads per workgroup in use, 256 or 128 */
+    double ms_threads_A[2], ms_threads_At[2]; /* one product with 256 and with 128
+                                                 threads, ms (not filled when cached) */
 } pdhg_tune;
 
 /* Per-matrix choice of the SpMV schedule of A x and A'y (Section 7's
@@ -244,7 +247,11 @@ typedef struct pdhg_tune {
  * than one 4 MiB L2 slice) and keeps the fastest -- then the row split:
  * with that slab count, the lanes that reduce one row (a power of two near
  * each block's mean row length) one power of two lower, as the rule, and
- * one higher, keeping the fastest.  The choice is remembered for the
+ * one higher, keeping the fastest -- then the threads per workgroup (256,
+ * or 128 with twice the entries in flight per thread), keeping the fastest.
+ * Before any tuning a product runs 128 threads per workgroup when its launch
+ * has at least 2048 blocks of at most 128 rows on average, else 256.  The
+ * choice is remembered for the
  * process under a signature of the matrix (sizes and sampled row starts);
  * with use_cache != 0 a remembered choice is applied without timing.  The iterates, averages and counters are left as they are; the
  * products are written to scratch vectors.  Later solves follow the same

@@ -74,7 +74,9 @@ class Tune(C.Structure):
                 ("ms_A", C.c_double * 4), ("ms_At", C.c_double * 4),
                 ("from_cache", C.c_int32), ("reserved", C.c_int32),
                 ("lanes_bias_A", C.c_int32), ("lanes_bias_At", C.c_int32),
-                ("ms_lanes_A", C.c_double * 3), ("ms_lanes_At", C.c_double * 3)]
+                ("ms_lanes_A", C.c_double * 3), ("ms_lanes_At", C.c_double * 3),
+                ("threads_A", C.c_int32), ("threads_At", C.c_int32),
+                ("ms_threads_A", C.c_double * 2), ("ms_threads_At", C.c_double * 2)]
 
 
 class BatchTune(C.Structure):
@@ -321,8 +323,9 @@ class Solver:
     def autotune(self, iters=20, use_cache=True):
         """pdhg_autotune: time the column-slab counts of A x and A'y on this
         matrix, then the lanes per row (one power of two below, at and above
-        the rule), keeping the fastest of each; returns the choices in use
-        and the timings (ms per product) of the candidates tried."""
+        the rule), then the threads per workgroup (256 or 128), keeping the
+        fastest of each; returns the choices in use and the timings (ms per
+        product) of the candidates tried."""
         t = Tune()
         _check(self._L.pdhg_autotune(self.h, int(iters), 1 if use_cache else 0, C.byref(t)),
                "pdhg_autotune")
@@ -333,7 +336,12 @@ class Solver:
                     At={int(t.tried_At[i]): float(t.ms_At[i]) for i in range(t.candidates_At)},
                     lanes_A={} if cached else {b - 1: float(t.ms_lanes_A[b]) for b in range(3)},
                     lanes_At={} if cached else {b - 1: float(t.ms_lanes_At[b])
-                                                for b in range(3)})
+                                                for b in range(3)},
+                    threads_A=t.threads_A, threads_At=t.threads_At,
+                    ms_threads_A={} if cached else {256: float(t.ms_threads_A[0]),
+                                                    128: float(t.ms_threads_A[1])},
+                    ms_threads_At={} if cached else {256: float(t.ms_threads_At[0]),
+                                                     128: float(t.ms_threads_At[1])})
 
     def set_schedule(self, slabs_A=1, slabs_At=1, lanes_bias_A=0, lanes_bias_At=0):
         """pdhg_set_schedule: pin the slab counts and lanes-per-row biases."""

@@ -64,13 +64,13 @@ static bool sorted_blocks_wanted() {
     return !(e && e[0] == '0');
 }
 
-// threads per workgroup of the single-LP products; PDHG_SPMV_WG=128 or 256
-// overrides the default (read at create)
-static int spmv_wg_default() {
+// threads per workgroup of a single-LP product (spmv_threads_for);
+// PDHG_SPMV_WG=128 or 256 sets both products instead (read at create)
+static int spmv_wg_for(int64_t rows, int64_t nblk) {
     const char *e = getenv("PDHG_SPMV_WG");
     if (e && atoi(e) == 128) return 128;
     if (e && atoi(e) == 256) return kWG;
-    return kWG;
+    return spmv_threads_for(rows, nblk);
 }
 
 size_t tr_work_bytes(int64_t N) {
@@ -506,7 +506,6 @@ int pdhg_create(const pdhg_lp *lp, const pdhg_params *prm_in, void *workspace,
     for (int sidx = 0; sidx < kTrSlots; ++sidx)
         carve_tr(ws + L.o_tr[sidx], (int64_t)d.n + d.m, &d.tr[sidx]);
     d.omega = prm.omega;
-    d.swg = spmv_wg_default();
     Slabs *sl[2] = {&d.slA, &d.slT};
     const int rows_of[2] = {d.m, d.n}, gath_of[2] = {d.n, d.m};
     for (int t = 0; t < 2; ++t) {
@@ -561,6 +560,8 @@ int pdhg_create(const pdhg_lp *lp, const pdhg_params *prm_in, void *workspace,
         if (d.slT.S > 1 && (rc = build_slabs(d.slT, d.trp, d.tci, d.tv, d.nnz, d.nblkT,
                                              d.long_rows, s)) != PDHG_OK)
             break;
+        d.swgA = spmv_wg_for(d.m, d.slA.S > 1 ? d.slA.nbmax : d.nblkA);
+        d.swgT = spmv_wg_for(d.n, d.slT.S > 1 ? d.slT.nbmax : d.nblkT);
         launch_norms(d, s);
         launch_init_point(d, s);
         if ((rc = last_error()) != PDHG_OK) break;
@@ -1047,7 +1048,7 @@ static int matrix_signature(pdhg_t *h, uint64_t *sig) {
 }
 
 struct TuneChoice {
-    int slabs[2], lbias[2];  // [0] A x, [1] A'y
+    int slabs[2], lbias[2], threads[2];  // [0] A x, [1] A'y
 };
 static std::mutex g_tune_mu;
 static std::map<uint64_t, TuneChoice> g_tune_cache;
@@ -1058,6 +1059,12 @@ static void set_lbias(pdhg_t *h, int t, int b) {
     cur = b;
 }
 
+static void set_threads(pdhg_t *h, int t, int wg) {
+    int &cur = t == 0 ? h->d.swgA : h->d.swgT;
+    if (cur != wg) h->g_valid = false;  // the recorded block holds the old launches
+    cur = wg;
+}
+
 int pdhg_autotune(pdhg_t *h, int32_t iters, int32_t use_cache, pdhg_tune *out) {
     if (!h || iters < 1 || iters > 10000) return PDHG_E_INVALID;
     pdhg_tune r;
@@ -1066,7 +1073,7 @@ int pdhg_autotune(pdhg_t *h, int32_t iters, int32_t use_cache, pdhg_tune *out) {
     uint64_t sig = 0;
     if ((rc = matrix_signature(h, &sig))) return rc;
     bool cached = false;
-    TuneChoice choice{{h->d.slA.S, h->d.slT.S}, {h->d.lbA, h->d.lbT}};
+    TuneChoice choice{{h->d.slA.S, h->d.slT.S}, {h->d.lbA, h->d.lbT}, {h->d.swgA, h->d.swgT}};
     if (use_cache) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(sig);
@@ -1079,6 +1086,7 @@ int pdhg_autotune(pdhg_t *h, int32_t iters, int32_t use_cache, pdhg_tune *out) {
         for (int t = 0; t < 2; ++t) {
             if ((rc = set_slabs(h, t, choice.slabs[t]))) return rc;
             set_lbias(h, t, choice.lbias[t]);
+            set_threads(h, t, choice.threads[t]);
         }
         r.from_cache = 1;
     } else {
@@ -1124,6 +1132,24 @@ int pdhg_autotune(pdhg_t *h, int32_t iters, int32_t use_cache, pdhg_tune *out) {
             }
             set_lbias(h, t, bb);
             choice.lbias[t] = bb;
+            // 3. threads per workgroup: kWG or 128 (twice the entries per
+            //    thread), with that slab count and lanes rule
+            double *mst = t == 0 ? r.ms_threads_A : r.ms_threads_At;
+            const int wgs[2] = {kWG, 128};
+            int bw = kWG;
+            double bwt = 0.0;
+            for (int k = 0; k < 2; ++k) {
+                set_threads(h, t, wgs[k]);
+                double m = 0.0;
+                if ((rc = time_product(h, t, iters, &m))) return rc;
+                mst[k] = m;
+                if (k == 0 || m < bwt) {
+                    bwt = m;
+                    bw = wgs[k];
+                }
+            }
+            set_threads(h, t, bw);
+            choice.threads[t] = bw;
         }
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[sig] = choice;
@@ -1133,6 +1159,8 @@ int pdhg_autotune(pdhg_t *h, int32_t iters, int32_t use_cache, pdhg_tune *out) {
     r.slabs_At = h->d.slT.S;
     r.lanes_bias_A = h->d.lbA;
     r.lanes_bias_At = h->d.lbT;
+    r.threads_A = h->d.swgA;
+    r.threads_At = h->d.swgT;
     if (out) *out = r;
     return last_error();
 }

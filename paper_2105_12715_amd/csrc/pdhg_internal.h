@@ -159,7 +159,7 @@ struct Dev {
     // or has too many columns for the packed word.
     const unsigned *apk;       // [nnz] column << kPkSlotBits | slot
     const double *asv;         // [nnz] values in the same order
-    int swg;                   // threads per workgroup of the products: 128 or kWG
+    int swgA, swgT;            // threads per workgroup of A x and A'y: 128 or kWG
 };
 
 // Column slabs: each slab's slice of the gathered vector is meant to fit
@@ -173,6 +173,15 @@ inline int slab_count_for(int64_t rows, int64_t gathered, int64_t scratch_ints,
     int S = 1;
     while (S < 8 && (int64_t)S * slice_bytes < bytes) S <<= 1;
     return S;
+}
+
+// Threads per workgroup of a product's launches: 128 when the launch has
+// many blocks (more than fill the chip at kWG threads) of few rows each
+// (one pass of the epilogue over the block's rows), so each thread keeps
+// twice the entries in flight; kWG otherwise (a short grid keeps all its
+// threads, and blocks of many rows keep the epilogue to a pass or two).
+inline int spmv_threads_for(int64_t rows, int64_t nblk) {
+    return (nblk >= 2048 && rows <= 128 * nblk) ? 128 : kWG;
 }
 
 // Slab counts the workspace reserves room for when a product uses slabs at

@@ -269,7 +269,7 @@ template <class Epi>
 static void product_A(const Dev &d, const double *in, const Epi &e, const int *skip,
                       hipStream_t s) {
     if (d.m == 0) return;
-    if (d.swg == 128) product_A_wg<Epi, 128>(d, in, e, skip, s);
+    if (d.swgA == 128) product_A_wg<Epi, 128>(d, in, e, skip, s);
     else product_A_wg<Epi, kWG>(d, in, e, skip, s);
 }
 
@@ -288,7 +288,7 @@ static void product_T_wg(const Dev &d, const double *in, const Epi &e, const int
 template <class Epi>
 static void product_T(const Dev &d, const double *in, const Epi &e, const int *skip,
                       hipStream_t s) {
-    if (d.swg == 128) product_T_wg<Epi, 128>(d, in, e, skip, s);
+    if (d.swgT == 128) product_T_wg<Epi, 128>(d, in, e, skip, s);
     else product_T_wg<Epi, kWG>(d, in, e, skip, s);
 }
 

@@ -1,9 +1,14 @@
-"""A's merge-path blocks stored sorted by column (the layout the A x products
+"""Layouts and launch shapes of the products that must not change a bit of
+the results.
+
+A's merge-path blocks stored sorted by column (the layout the A x products
 use by default when the columns fit the packed word) against the plain row
-order.  Each product lands in LDS at its place in the row order, so the row
-sums add the same terms in the same order: iterates, check records and
+order: each product lands in LDS at its place in the row order, so the row
+sums add the same terms in the same order.  The same holds for 128 against
+256 threads per workgroup: a row is reduced by the same number of lanes in
+the same order whatever the workgroup size.  Iterates, check records and
 products must be bitwise equal, including blocks longer than the LDS stage
-(one dense row of 6000 entries) and LPs whose A has no column slabs.
+(one dense row of 6000 entries).
 """
 import sys
 
@@ -77,3 +82,25 @@ def test_sorted_blocks_bitwise_equal(lib, name, monkeypatch):
     for k, what in ((2, "x"), (3, "y"), (4, "x-bar"), (5, "y-bar"), (6, "A v")):
         assert np.array_equal(a[k], b[k]), f"{name}: {what} differs between layouts"
     assert np.array_equal(np.asarray(a[7]), np.asarray(b[7])), "check records differ"
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_threads_per_workgroup_bitwise_equal(lib, name, monkeypatch):
+    lp = CASES[name]()
+    _say(f"[threads] {name}: m={lp.m} n={lp.n} nnz={lp.nnz}")
+    out = {}
+    monkeypatch.setenv("PDHG_TINY", "0")
+    for wg in ("256", "128"):
+        monkeypatch.setenv("PDHG_SPMV_WG", wg)
+        s = lib.Solver(lp, eta=0.0)
+        r = s.solve(600, 0.0)
+        x, y = (t.cpu().numpy() for t in s.get_iterate(lib.POINT_CURRENT))
+        v = np.random.default_rng(6).standard_normal(lp.m)
+        aty = s.matvec(torch.from_numpy(v).to("cuda"), transpose=True).cpu().numpy()
+        out[wg] = (r, x, y, aty, s.check_log())
+        s.close()
+    a, b = out["256"], out["128"]
+    assert a[0]["k"] == b[0]["k"] and a[0]["restarts"] == b[0]["restarts"]
+    for k, what in ((1, "x"), (2, "y"), (3, "A'v")):
+        assert np.array_equal(a[k], b[k]), f"{name}: {what} differs between 256 and 128 threads"
+    assert np.array_equal(np.asarray(a[4]), np.asarray(b[4])), "check records differ"

@@ -1,4 +1,5 @@
-"""pdhg_autotune: per-matrix choice of the column slabs of A x and A'y.
+"""pdhg_autotune: per-matrix choice of the column slabs, lanes per row and
+threads per workgroup of A x and A'y.
 The tuner times the products only, so the solver state stays bitwise the
 same; solves after a re-slabbing still match the oracle; a second handle on
 the same matrix takes the remembered choice.
@@ -61,6 +62,9 @@ def test_autotune_keeps_state_and_parity(lib):
     assert sorted(r["lanes_A"]) == [-1, 0, 1] and sorted(r["lanes_At"]) == [-1, 0, 1]
     assert r["lanes_bias_A"] == min(r["lanes_A"], key=r["lanes_A"].get)
     assert r["lanes_bias_At"] == min(r["lanes_At"], key=r["lanes_At"].get)
+    assert sorted(r["ms_threads_A"]) == [128, 256] and sorted(r["ms_threads_At"]) == [128, 256]
+    assert r["threads_A"] == min(r["ms_threads_A"], key=r["ms_threads_A"].get)
+    assert r["threads_At"] == min(r["ms_threads_At"], key=r["ms_threads_At"].get)
     after = [t for w in (0, 1, 2) for t in s.get_iterate(w)]
     torch.cuda.synchronize()
     assert all(torch.equal(a, b) for a, b in zip(before, after))
@@ -88,6 +92,7 @@ def test_autotune_keeps_state_and_parity(lib):
     assert r2["from_cache"] and r2["A"] == {} and r2["At"] == {}
     assert (r2["slabs_A"], r2["slabs_At"]) == (r["slabs_A"], r["slabs_At"])
     assert (r2["lanes_bias_A"], r2["lanes_bias_At"]) == (r["lanes_bias_A"], r["lanes_bias_At"])
+    assert (r2["threads_A"], r2["threads_At"]) == (r["threads_A"], r["threads_At"])
 
 
 @pytest.mark.parametrize("name", ["powerlaw", "medium"])
