@@ -293,19 +293,85 @@ const char *pdhg_strerror(int code) {
 // Split the CSR (rp, ci, v) with nblk merge-path blocks into sb.S column
 // slabs (see slab_count_for); one host round trip for the entry count of
 // every slab.
+// Each slab's launch covers the rows from the first to the last one with an
+// entry in the slab (PDHG_SLAB_RANGES=0: every row, for comparisons); the
+// first range starts at row 0, the last ends at the last row, and the last
+// range is stretched down over any row no range holds (rows without
+// entries), so every row has a launch that applies its update.
+static bool slab_ranges_wanted() {
+    const char *e = getenv("PDHG_SLAB_RANGES");
+    return !(e && e[0] == '0');
+}
+
+static void fit_slab_bounds(Slabs &sb) {
+    const int S = sb.S;
+    int end = 0;
+    for (int q = 0; q < S; ++q) {
+        sb.before[q] = end;
+        if (sb.hi[q] > end) end = sb.hi[q];
+    }
+    int beg = sb.rows;
+    for (int q = S - 1; q >= 0; --q) {
+        sb.after[q] = beg;
+        if (sb.lo[q] < beg) beg = sb.lo[q];
+    }
+    for (int q = S; q < kSlabMax; ++q) {
+        sb.before[q] = sb.rows;
+        sb.after[q] = sb.rows;
+    }
+}
+
+static void fit_slab_ranges(Slabs &sb, const int *range) {
+    const int S = sb.S, rows = sb.rows;
+    const bool want = slab_ranges_wanted();
+    for (int q = 0; q < kSlabMax; ++q) {
+        sb.lo[q] = 0;
+        sb.hi[q] = q < S ? rows : 0;
+    }
+    if (!want) {
+        fit_slab_bounds(sb);
+        return;
+    }
+    for (int q = 0; q < S; ++q) {
+        int lo = range[2 * q], hi = range[2 * q + 1];
+        if (hi < 0) lo = hi = 0;  // no entries in this slab
+        if (q == 0) lo = 0;
+        if (q == S - 1) hi = rows;
+        sb.lo[q] = lo;
+        sb.hi[q] = hi > lo ? hi : lo;
+    }
+    // widen: the ranges of slabs 0..q cover [0, end) with no gap, and those
+    // of slabs q..S-1 cover [start, rows) with no gap
+    int end = sb.hi[0];
+    for (int q = 1; q < S; ++q) {
+        if (sb.lo[q] > end) sb.lo[q] = end;
+        if (sb.hi[q] > end) end = sb.hi[q];
+    }
+    int beg = sb.lo[S - 1];
+    for (int q = S - 2; q >= 0; --q) {
+        if (sb.hi[q] < beg) sb.hi[q] = beg;
+        if (sb.lo[q] < beg) beg = sb.lo[q];
+    }
+}
+
 static int build_slabs(Slabs &sb, const int *rp, const int *ci, const double *v, int nnz,
                        int nblk, int *scratch, hipStream_t s) {
     launch_slab_count(sb, rp, ci, scratch, s);
+    launch_slab_ranges(sb, scratch, s);
     int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int range[2 * kSlabMax];
     for (int q = 0; q < sb.S; ++q)
         CK(hipMemcpyAsync(&cnt[q], sb.srp + (size_t)q * (sb.rows + 1) + sb.rows, sizeof(int),
                           hipMemcpyDeviceToHost, s));
+    CK(hipMemcpyAsync(range, scratch, sizeof(int) * 2 * sb.S, hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
+    fit_slab_ranges(sb, range);
+    fit_slab_bounds(sb);
     long long meta[32];
     long long eoff = 0, boff = 0;
     int nbmax = 0;
     for (int q = 0; q < sb.S; ++q) {
-        const int nb = nblocks_for(sb.rows, cnt[q]);
+        const int nb = nblocks_for(sb.hi[q] - sb.lo[q], cnt[q]);
         meta[4 * q + 0] = (long long)q * (sb.rows + 1);
         meta[4 * q + 1] = eoff;
         meta[4 * q + 2] = boff;
@@ -321,8 +387,8 @@ static int build_slabs(Slabs &sb, const int *rp, const int *ci, const double *v,
     sb.nbmax = nbmax;
     launch_slab_fill(sb, rp, ci, v, s);
     for (int q = 0; q < sb.S; ++q)
-        launch_rowsplit(sb.srp + meta[4 * q], sb.rows, cnt[q], (int)meta[4 * q + 3],
-                        sb.sbr + meta[4 * q + 2], s);
+        launch_rowsplit_range(sb.srp + meta[4 * q] + sb.lo[q], sb.hi[q] - sb.lo[q],
+                              (int)meta[4 * q + 3], sb.sbr + meta[4 * q + 2], s);
     return last_error();
 }
 
@@ -360,20 +426,52 @@ static int order_columns(Dev &d, const Layout &L, char *ws, hipStream_t s) {
     std::vector<int> start((size_t)cmax + 2, 0);
     for (int j = 0; j < n; ++j) start[(size_t)(cmax - cnt[j + 1]) + 1] += 1;
     for (int k = 0; k <= cmax; ++k) start[k + 1] += start[k];
+    std::vector<int> by_count((size_t)n);
+    for (int t = 0; t < n; ++t) {
+        const int j = by_first[(size_t)t];
+        by_count[(size_t)start[(size_t)(cmax - cnt[j + 1])]++] = j;
+    }
+    // When A'y runs over two column slabs of y, the columns go in three
+    // regions (each in the order above): those whose rows all lie in the
+    // first slab of y, those with rows in both, those with rows all in the
+    // second (then empty columns).  A'y's first launch then covers the rows
+    // of A' up to the end of the middle region and its second launch the
+    // rows from the start of the middle region, and only the middle region
+    // goes through the accumulator of the slabs (Slabs).
+    std::vector<int> cls((size_t)n, 0);
+    const char *reg_env = getenv("PDHG_COLUMN_REGIONS");
+    const bool regions = d.slT.S == 2 && d.m > 0 && !(reg_env && reg_env[0] == '0');
+    if (regions) {
+        int *last_dev = d.long_rows;  // n ints of transpose scratch, free until then
+        launch_last_rows(d.rp, d.ci, m, n, d.nnz, last_dev, s);
+        std::vector<int> last((size_t)n);
+        CK(hipMemcpyAsync(last.data(), last_dev, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost,
+                          s));
+        CK(hipStreamSynchronize(s));
+        const int W = d.slT.W;
+        for (int j = 0; j < n; ++j)
+            cls[(size_t)j] = cnt[j + 1] == 0 ? 3 : last[j] < W ? 0 : first[j] >= W ? 2 : 1;
+    }
+    std::vector<int> cstart(5, 0);
+    for (int j = 0; j < n; ++j) cstart[(size_t)cls[(size_t)j] + 1] += 1;
+    for (int k = 0; k < 4; ++k) cstart[k + 1] += cstart[k];
+    const int ncls0 = regions ? cstart[1] : 0;  // where the middle region starts
     std::vector<int> order((size_t)n), inv((size_t)n);
     bool ident = true;
     for (int t = 0; t < n; ++t) {
-        const int j = by_first[(size_t)t];
-        const int q = start[(size_t)(cmax - cnt[j + 1])]++;
+        const int j = by_count[(size_t)t];
+        const int q = cstart[(size_t)cls[(size_t)j]]++;
         order[q] = j;
         inv[j] = q;
         ident &= (q == j);
     }
-    // share of the entries in the first L2-sized run of columns: when the
-    // hot columns hold most of them, A x gathers from one L2 without slabs
+    // share of the entries in the L2-sized run of columns where the most
+    // gathered ones start (the first column, or the middle region): when
+    // the hot columns hold most of them, A x gathers from one L2 without
+    // slabs
     const long long w0 = slab_slice_bytes() / 8;
     long long hot = 0;
-    for (long long q = 0; q < n && q < w0; ++q) hot += cnt[(size_t)order[q] + 1];
+    for (long long q = ncls0; q < n && q < ncls0 + w0; ++q) hot += cnt[(size_t)order[q] + 1];
     if (d.slA.S > 1 && 10 * hot >= 6 * (long long)d.nnz) d.slA.S = 1;
     if (ident) return PDHG_OK;
     int *ci2 = (int *)(ws + L.o_ci2);

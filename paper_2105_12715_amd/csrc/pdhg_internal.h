@@ -98,14 +98,28 @@ constexpr unsigned int kFinishMax = 65536;
 // A sparse matrix (CSR, rows x cols) split into S column slabs of width W:
 // slab s holds the entries with column in [s W, (s+1) W), in CSR of its own
 // with local column indices, and its own merge-path block table.
+//
+// Each slab's launch runs over a range of rows [lo[s], hi[s]) holding every
+// row with an entry in that slab.  The ranges are widened so that those of
+// slabs 0..s always cover [0, before[s + 1]) and those of slabs s..S-1
+// cover [after[s - 1], rows) with no gap: a row of launch s is then the
+// row's first launch iff it is at or past before[s] (the end of the
+// earlier ranges), and its last iff it lies below after[s] (the start of
+// the later ones).  The first launch writes the row's partial sum to the
+// accumulator (or, when it is also the last, applies the update to it
+// directly), later launches add to it, and the last applies the update.
+constexpr int kSlabMax = 8;
 struct Slabs {
     int S, W, nbmax, rows;
     int *srp;                  // [S][rows + 1] row starts within each slab
     int *sci;                  // [nnz] local column index
     double *sv;                // [nnz]
-    int *sbr;                  // block tables of every slab (k_rowsplit)
+    int *sbr;                  // block tables of every slab over its row range (k_rowsplit)
     long long *smeta;          // [S][4]: row-start offset, entry offset, block offset, blocks
     double *spart;             // [rows] running sum of the slabs done so far
+    int lo[kSlabMax], hi[kSlabMax];  // row range of each slab's launch
+    int before[kSlabMax];      // end of the ranges of slabs < s (0 for s = 0)
+    int after[kSlabMax];       // start of the ranges of slabs > s (rows for s = S - 1)
 };
 
 // Device-side view of one LP and its solver state.
@@ -186,7 +200,6 @@ inline int spmv_threads_for(int64_t rows, int64_t nblk) {
 
 // Slab counts the workspace reserves room for when a product uses slabs at
 // all (the tuner may try any power of two up to it)
-constexpr int kSlabMax = 8;
 inline int slab_reserve_for(int64_t rows, int64_t gathered, int64_t scratch_ints,
                             int64_t slice_bytes) {
     return slab_count_for(rows, gathered, scratch_ints, slice_bytes) > 1 ? kSlabMax : 1;
@@ -260,6 +273,15 @@ void launch_col_counts(const int *ci, int nnz, int n, int *cnt, hipStream_t s);
 // first[j] = smallest row with an entry in column j (m if none), j < n
 void launch_first_rows(const int *rp, const int *ci, int m, int n, int nnz, int *first,
                        hipStream_t s);
+// last[j] = largest row with an entry in column j (-1 if none), j < n
+void launch_last_rows(const int *rp, const int *ci, int m, int n, int nnz, int *last,
+                      hipStream_t s);
+// range[2q], range[2q + 1] = smallest row and largest row + 1 with an entry
+// in slab q (rows, -1 for an empty slab), from the slab row starts
+void launch_slab_ranges(const Slabs &sb, int *range, hipStream_t s);
+// merge-path block table of the rows [0, rows) of a CSR whose row starts rp
+// need not begin at 0 (a row range of a larger matrix)
+void launch_rowsplit_range(const int *rp, int rows, int nblk, int *br, hipStream_t s);
 // ci2 = cinv[ci]; c2, l2, u2 = c, l, u in the internal column order
 void launch_permute_cols(const int *ci, int nnz, const int *cinv, int *ci2, const double *c,
                          const double *l, const double *u, const int *cperm, int n, double *c2,

@@ -138,6 +138,61 @@ void launch_rowsplit(const int *rp, int rows, int nnz, int nblk, int *br, hipStr
     hipLaunchKernelGGL(k_rowsplit, dim3(div_up(nblk + 1, kWG)), dim3(kWG), 0, s, rp, rows, nblk, br);
 }
 
+// k_rowsplit for row starts that begin at rp[0] (a row range): the merge
+// path counts rp[i] - rp[0] entries before row i; the entry starts stored
+// are rp's own values
+__global__ void k_rowsplit_range(const int *__restrict__ rp, int rows, int nblk, int *br) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > nblk) return;
+    const int base = rp[0];
+    int lo = rows;
+    if (c < nblk) {
+        long long target = (long long)c * kUnits;
+        int hi = rows;
+        lo = 0;
+        while (lo < hi) {
+            int mid = lo + ((hi - lo) >> 1);
+            if ((long long)mid + (rp[mid] - base) >= target) hi = mid;
+            else lo = mid + 1;
+        }
+    }
+    br[c] = lo;
+    br[nblk + 1 + c] = rp[lo];
+}
+
+void launch_rowsplit_range(const int *rp, int rows, int nblk, int *br, hipStream_t s) {
+    hipLaunchKernelGGL(k_rowsplit_range, dim3(div_up(nblk + 1, kWG)), dim3(kWG), 0, s, rp, rows,
+                       nblk, br);
+}
+
+// per slab, the smallest and the largest row (+ 1) holding one of its
+// entries; range is preset to (rows, -1) per slab
+__global__ void k_slab_ranges(Slabs sb, int *range) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sb.rows) return;
+    for (int q = 0; q < sb.S; ++q) {
+        const int *a = sb.srp + (size_t)q * (sb.rows + 1);
+        if (a[i + 1] > a[i]) {
+            atomicMin(&range[2 * q], i);
+            atomicMax(&range[2 * q + 1], i + 1);
+        }
+    }
+}
+
+__global__ void k_slab_ranges_init(int *range, int S, int rows) {
+    const int q = threadIdx.x;
+    if (q < S) {
+        range[2 * q] = rows;
+        range[2 * q + 1] = -1;
+    }
+}
+
+void launch_slab_ranges(const Slabs &sb, int *range, hipStream_t s) {
+    hipLaunchKernelGGL(k_slab_ranges_init, dim3(1), dim3(kSlabMax), 0, s, range, sb.S, sb.rows);
+    if (sb.rows > 0)
+        hipLaunchKernelGGL(k_slab_ranges, dim3(div_up(sb.rows, kWG)), dim3(kWG), 0, s, sb, range);
+}
+
 // Each merge-path block's entries sorted by column: the key of an entry is
 // column << kPkSlotBits | its place in the block, unique within the block,
 // so an ascending bitonic sort of the keys in LDS gives one definite order
@@ -199,24 +254,27 @@ void launch_sort_blocks(const int *rp, const int *ci, const double *v, const int
                            sv);
 }
 
-// One slab at a time: the sums of slab sl go to acc (slab 0) or are added
-// to it in slab order, and the last slab applies the epilogue to the full
-// sum.  (Letting rows whose entries all lie in one slab take the epilogue
-// in that slab's launch, and skip the accumulator, measured slower: each
-// block then mixes two access streams of partial waves.)
-struct EpiSlabAcc {
-    double *acc;
-    int first;
-    __device__ __forceinline__ void operator()(int r, double s) const {
-        acc[r] = first ? s : acc[r] + s;
-    }
-};
-
+// One slab at a time, each launch over its row range (Slabs): row r of
+// the range is row lo[sl] + r of the matrix.  Its sum goes to acc when an
+// earlier range holds nothing of the row (or is added to acc otherwise);
+// the launch of the last range holding the row applies the epilogue to the
+// full sum instead.  The sums of a row are added in slab order, so every
+// row gets the same value as with all rows in every launch (a row with no
+// entries in a slab adds +0.0 there, which changes no sum but the sign of
+// a zero one, and the update rounds it the same).
 template <class Epi>
-struct EpiSlabLast {
+struct EpiSlab {
     Epi inner;
-    const double *acc;
-    __device__ __forceinline__ void operator()(int r, double s) const { inner(r, acc[r] + s); }
+    double *acc;
+    int lo;      // first row of this launch's range
+    int before;  // rows at or past it are in no earlier range
+    int after;   // rows below it are in no later range
+    __device__ __forceinline__ void operator()(int r, double s) const {
+        const int j = lo + r;
+        const double t = j >= before ? s : acc[j] + s;
+        if (j < after) inner(j, t);
+        else acc[j] = t;
+    }
 };
 
 template <class Epi, int WG = kWG>
@@ -231,21 +289,20 @@ __global__ __launch_bounds__(WG) void k_slab_one(Slabs sb, int sl, const double 
     const int *br = sb.sbr + me[2];
     const int r0 = br[b], r1 = br[b + 1];
     if (r0 >= r1) return;
-    spmv_rows<Epi, int, false, WG>(sb.srp + me[0], sb.sci + me[1], sb.sv + me[1],
+    spmv_rows<Epi, int, false, WG>(sb.srp + me[0] + sb.lo[sl], sb.sci + me[1], sb.sv + me[1],
                                    xin + (size_t)sl * sb.W, r0, r1, br[nb + 1 + b], br[nb + 2 + b],
                                    epi, lds, lbias);
 }
 
-// the slabs one after the other, the last with the epilogue fused
+// the slabs one after the other, each row's update fused into the last
+// launch whose range holds it
 template <class Epi, int WG>
 static void slabs_in_turn(const Slabs &sb, const double *in, const Epi &e, const int *skip,
                           int lbias, hipStream_t s) {
-    double *acc = sb.spart;
-    for (int sl = 0; sl + 1 < sb.S; ++sl)
-        hipLaunchKernelGGL((k_slab_one<EpiSlabAcc, WG>), dim3(sb.nbmax), dim3(WG), 0, s, sb, sl,
-                           in, EpiSlabAcc{acc, sl == 0 ? 1 : 0}, skip, lbias);
-    hipLaunchKernelGGL((k_slab_one<EpiSlabLast<Epi>, WG>), dim3(sb.nbmax), dim3(WG), 0, s, sb,
-                       sb.S - 1, in, EpiSlabLast<Epi>{e, acc}, skip, lbias);
+    for (int sl = 0; sl < sb.S; ++sl)
+        hipLaunchKernelGGL((k_slab_one<EpiSlab<Epi>, WG>), dim3(sb.nbmax), dim3(WG), 0, s, sb, sl,
+                           in, EpiSlab<Epi>{e, sb.spart, sb.lo[sl], sb.before[sl], sb.after[sl]},
+                           skip, lbias);
 }
 
 template <class Epi, int WG>
@@ -766,6 +823,29 @@ __global__ void k_first_rows(const int *__restrict__ rp, const int *__restrict__
         else hi = mid - 1;
     }
     atomicMin(&first[ci[e]], lo);
+}
+
+// last[j] = the largest row holding an entry of column j (-1 for an empty
+// column), as k_first_rows
+__global__ void k_last_rows(const int *__restrict__ rp, const int *__restrict__ ci, int m,
+                            int nnz, int *last) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    int lo = 0, hi = m - 1;  // last row r with rp[r] <= e
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rp[mid] <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    atomicMax(&last[ci[e]], lo);
+}
+
+void launch_last_rows(const int *rp, const int *ci, int m, int n, int nnz, int *last,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_int, dim3(div_up(n, kWG)), dim3(kWG), 0, s, last, (long long)n, -1);
+    if (nnz > 0 && m > 0)
+        hipLaunchKernelGGL(k_last_rows, dim3(div_up(nnz, kWG)), dim3(kWG), 0, s, rp, ci, m, nnz,
+                           last);
 }
 
 void launch_first_rows(const int *rp, const int *ci, int m, int n, int nnz, int *first,

@@ -104,3 +104,46 @@ def test_threads_per_workgroup_bitwise_equal(lib, name, monkeypatch):
     for k, what in ((1, "x"), (2, "y"), (3, "A'v")):
         assert np.array_equal(a[k], b[k]), f"{name}: {what} differs between 256 and 128 threads"
     assert np.array_equal(np.asarray(a[4]), np.asarray(b[4])), "check records differ"
+
+
+@pytest.mark.parametrize("slab_bytes", ["65536", "131072"])
+def test_slab_row_ranges_follow_the_oracle(lib, slab_bytes, monkeypatch):
+    """Column slabs whose launches cover only the rows with entries in them
+    (the update fused into each row's last launch) and launches over every
+    row.  The merge-path blocks differ between the two, and with them the
+    lanes that reduce a row, so the sums may round differently: both must
+    give products within the summation-order bound and iterates that follow
+    the oracle over 600 iterations with restarts.  Small slab slices force
+    slabs on the medium LP: 131072 bytes gives A'y two slabs of y (the
+    columns then go in three regions by the slabs their rows fall in) and A x
+    four; 65536 bytes gives four and eight."""
+    import oracle
+    from tests.parity import assert_points_match, assert_within_sum_bound
+    lp = lpgen.medium(2)
+    A = abs(lp.scipy_csr())
+    eta = 0.9 / np.sqrt(float(A.sum(axis=0).max()) * float(A.sum(axis=1).max()))
+    o = oracle.Oracle(lp, eta=eta)
+    o.solve(600, 0.0)
+    v = np.random.default_rng(7).standard_normal(lp.m)
+    u = np.random.default_rng(8).standard_normal(lp.n)
+    monkeypatch.setenv("PDHG_TINY", "0")
+    monkeypatch.setenv("PDHG_SLAB_BYTES", slab_bytes)
+    for mode in ("ranges", "all"):
+        if mode == "all":
+            monkeypatch.setenv("PDHG_SLAB_RANGES", "0")
+        else:
+            monkeypatch.delenv("PDHG_SLAB_RANGES", raising=False)
+        s = lib.Solver(lp, eta=eta)
+        assert_within_sum_bound(s.matvec(torch.from_numpy(u).to("cuda")).cpu().numpy(),
+                                o.matvec(u), A, u, f"{mode} A u")
+        assert_within_sum_bound(s.matvec(torch.from_numpy(v).to("cuda"), transpose=True)
+                                .cpu().numpy(), o.matvec_t(v), A.T.tocsr(), v, f"{mode} A'v")
+        r = s.solve(600, 0.0)
+        _say(f"[slab ranges] {slab_bytes} {mode}: k {r['k']} restarts {r['restarts']}")
+        assert r["restarts"] == o.info()["restarts"]
+        for which in (0, 1, 2):
+            xo, yo = o.get(which)
+            xg, yg = (t.cpu().numpy() for t in s.get_iterate(which))
+            assert_points_match(np.concatenate([xg, yg]), np.concatenate([xo, yo]), 1e-10,
+                                f"{slab_bytes} {mode} point {which}")
+        s.close()
