@@ -5,11 +5,13 @@
     python -m paper_2105_12715_amd.profsum pmc DIR [DIR ...]
         mean of every collected counter per dispatch, per kernel
     python -m paper_2105_12715_amd.profsum traffic --fetch D1 --write D2
-            --copy-fetch D3 --copy-write D4 --copy-bytes B --kernels K1,K2
+            --copy-fetch D3 --copy-write D4 --copy-bytes B --kernels K1,K2*2
             --source-hash H --cmd C
         HBM bytes per launch of the kernels K1 + K2 (one half-step) from
         FETCH_SIZE and WRITE_SIZE runs, each scaled by what the same counter
-        reads for a copy kernel that moves B bytes each way (JSON)
+        reads for a copy kernel that moves B bytes each way (JSON); K*n
+        counts n dispatches of kernel K per half-step (the column slabs of
+        one product run the same kernel once per slab)
 
 Runs on the host on files that rocprofv3 wrote (``--output-format csv``);
 nothing here touches a GPU.
@@ -103,11 +105,13 @@ def traffic(a):
     w_scale = a.copy_bytes / (cwrite[_match(cwrite, a.copy_kernel)]["WRITE_SIZE"] * kib)
     parts = {}
     total = 0.0
-    for pat in a.kernels.split(","):
+    for item in a.kernels.split(","):
+        pat, _, times = item.partition("*")
+        n = int(times) if times else 1
         kf, kw = _match(fetch, pat), _match(write, pat)
-        fb = fetch[kf]["FETCH_SIZE"] * kib * f_scale
-        wb = write[kw]["WRITE_SIZE"] * kib * w_scale
-        parts[kf] = {"fetch_bytes": round(fb), "write_bytes": round(wb)}
+        fb = fetch[kf]["FETCH_SIZE"] * kib * f_scale * n
+        wb = write[kw]["WRITE_SIZE"] * kib * w_scale * n
+        parts[kf] = {"fetch_bytes": round(fb), "write_bytes": round(wb), "dispatches": n}
         total += fb + wb
     return {"kernels": parts, "hbm_bytes_per_launch": round(total),
             "counts": "bytes between L2 and the memory fabric (FETCH_SIZE, WRITE_SIZE), "

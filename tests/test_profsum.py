@@ -39,10 +39,16 @@ def test_traffic_scales_by_the_copy_kernel(tmp_path):
     ka = r["kernels"]["pdhg::k_a<X>"]
     kb = r["kernels"]["pdhg::k_b<Y>"]
     # k_a: 150 KiB per dispatch fetched (x 2), 10 KiB written (x 1)
-    assert ka == {"fetch_bytes": 150 * 1024 * 2, "write_bytes": 10 * 1024}
-    assert kb == {"fetch_bytes": 40 * 1024 * 2, "write_bytes": 6 * 1024}
+    assert ka == {"fetch_bytes": 150 * 1024 * 2, "write_bytes": 10 * 1024, "dispatches": 1}
+    assert kb == {"fetch_bytes": 40 * 1024 * 2, "write_bytes": 6 * 1024, "dispatches": 1}
     assert r["hbm_bytes_per_launch"] == (300 + 10 + 80 + 6) * 1024
     assert r["kernel_source_hash"] == "abc"
+    # k_a dispatched twice per half-step (two column slabs of one product)
+    a.kernels = "k_a<X>*2,k_b<Y>"
+    r2 = profsum.traffic(a)
+    assert r2["kernels"]["pdhg::k_a<X>"] == {"fetch_bytes": 150 * 1024 * 2 * 2,
+                                             "write_bytes": 10 * 1024 * 2, "dispatches": 2}
+    assert r2["hbm_bytes_per_launch"] == (600 + 20 + 80 + 6) * 1024
 
 
 def test_stats_table(tmp_path):
