@@ -407,7 +407,9 @@ def run_ceiling(args):
     LP's two products (A x+: A's column indices in the solver's column
     order into a 16 MB x; A'y: A''s row indices into an 8 MB y) and with
     uniform random indices into vectors of 4, 8 and 16 MB, each over the
-    large LP's entry count.  Prints one JSON line."""
+    large LP's entry count; then the gathers alone (pdhg_time_gather_only)
+    with the two index streams and with hashed indices over 1 to 16 MB.
+    Prints one JSON line."""
     import numpy as np
     import torch
     from paper_2105_12715_amd import _lib, lpgen
@@ -448,8 +450,30 @@ def run_ceiling(args):
                         "ms": round(ms, 5), "g_gathers_per_s": round(rate, 1),
                         "stream_gbs": round(20 * nnz / ms / 1e6, 1), "result_checked": ok})
         log(f"gather {name}: {ms * 1e3:.1f} us, {rate:.1f} G gathers/s")
+    del out
+    # the gathers alone (no values, rows or update; 4 per thread, one sum
+    # stored per thread): the large LP's two index streams, then hashed
+    # indices over windows of 1 to 16 MB (no index stream at all)
+    only = []
+    for name, idx_np, ln in pats[:2]:
+        idx = torch.as_tensor(np.ascontiguousarray(idx_np, dtype=np.int32), device=dev)
+        x = torch.as_tensor(rng.standard_normal(ln), device=dev)
+        ms, _ = _lib.time_gather_only(x, nnz, idx=idx, reps=20)
+        rate = nnz / (ms * 1e-3) / 1e9
+        only.append({"pattern": name, "entries": nnz, "vector_bytes": 8 * ln,
+                     "ms": round(ms, 5), "g_gathers_per_s": round(rate, 1)})
+        log(f"gathers alone, {name}: {ms * 1e3:.1f} us, {rate:.1f} G gathers/s")
+    for mb in (1, 2, 4, 8, 16):
+        ln = mb * (1 << 20) // 8
+        x = torch.as_tensor(rng.standard_normal(ln), device=dev)
+        cnt = 1 << 24
+        ms, _ = _lib.time_gather_only(x, cnt, reps=20)
+        rate = cnt / (ms * 1e-3) / 1e9
+        only.append({"pattern": f"hashed indices over {mb} MB", "entries": cnt,
+                     "vector_bytes": 8 * ln, "ms": round(ms, 5), "g_gathers_per_s": round(rate, 1)})
+        log(f"gathers alone, hashed over {mb} MB: {ms * 1e3:.1f} us, {rate:.1f} G gathers/s")
     print(json.dumps({"metric": "yardstick ceilings", "dtype": "f64", "n_gpus": 1,
-                      "copy": copy, "gather": gathers}), flush=True)
+                      "copy": copy, "gather": gathers, "gathers_alone": only}), flush=True)
 
 
 def run_to_tol(args, lp, wdesc):

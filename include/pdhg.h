@@ -365,6 +365,20 @@ int pdhg_time_copy(const double *src, double *dst, int64_t n, int32_t reps, void
 int pdhg_time_gather(const int32_t *idx, const double *val, const double *x, double *out,
                      int64_t n, int32_t reps, void *stream, double *ms);
 
+/* Gathers alone, the request rate a product's gathers can reach with
+ * nothing else in flight: each thread sums x at 4 indices and stores the
+ * sum (pdhg_gather_only_outputs(n) doubles of `out`, device).  With `idx`
+ * (device, n indices into x of xlen doubles) the indices are that stream;
+ * with idx NULL they are Fibonacci hashes of the entry number into
+ * [0, xlen), xlen a power of two, so no index stream is read and the
+ * footprint is 8 xlen bytes.  Mean ms of `reps` (1..1000) launches after one
+ * warm-up (host *ms), enqueued on `stream`, synchronizes.  Errors:
+ * PDHG_E_INVALID (also for a hashed window that is not a power of two),
+ * PDHG_E_HIP. */
+int64_t pdhg_gather_only_outputs(int64_t n);
+int pdhg_time_gather_only(const int32_t *idx, int64_t n, const double *x, int64_t xlen,
+                          double *out, int32_t reps, void *stream, double *ms);
+
 /* Primal-weight search of Section 7 (experimental setup).  For each of the
  * `count` weights omega[w] (host array; every omega > 0; 1 <= count <= 16)
  * run `iters` (>= 0) iterations of the handle's method (PDHG or

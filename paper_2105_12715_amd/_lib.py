@@ -176,6 +176,10 @@ def load(build_if_missing: bool = True):
     L.pdhg_time_copy.restype = C.c_int
     L.pdhg_time_gather.argtypes = [P, P, P, P, i64, i32, P, C.POINTER(d)]
     L.pdhg_time_gather.restype = C.c_int
+    L.pdhg_gather_only_outputs.argtypes = [i64]
+    L.pdhg_gather_only_outputs.restype = i64
+    L.pdhg_time_gather_only.argtypes = [P, i64, P, i64, P, i32, P, C.POINTER(d)]
+    L.pdhg_time_gather_only.restype = C.c_int
     L.pdhg_linear_trust_region_static.argtypes = [i64, P, P, d, P, C.POINTER(d), C.POINTER(d)]
     L.pdhg_linear_trust_region_static.restype = C.c_int
     L.pdhg_batch_workspace_bytes.argtypes = [i32, P, P, P]
@@ -722,6 +726,23 @@ def time_gather(idx, val, x, out, reps=20, stream=None):
                               int(reps), _stream_handle(stream), C.byref(ms)),
            "pdhg_time_gather")
     return ms.value
+
+
+def time_gather_only(x, n, idx=None, reps=20, stream=None):
+    """Mean ms of the library's gathers alone: n gathers of x at idx (a
+    device int32 tensor of n indices) or, with idx None, at hashed indices
+    over all of x (its length a power of two).  Returns (ms, out)."""
+    import torch
+    L = load()
+    nout = int(L.pdhg_gather_only_outputs(int(n)))
+    if nout < 1:
+        raise PdhgError(E_INVALID, "pdhg_gather_only_outputs")
+    out = torch.empty(nout, dtype=torch.float64, device=x.device)
+    ms = C.c_double()
+    _check(L.pdhg_time_gather_only(None if idx is None else _ptr(idx), int(n), _ptr(x),
+                                   int(x.numel()), _ptr(out), int(reps), _stream_handle(stream),
+                                   C.byref(ms)), "pdhg_time_gather_only")
+    return ms.value, out
 
 
 TR_STATIC_MAX_N = 262144

@@ -1682,6 +1682,25 @@ int pdhg_time_gather(const int32_t *idx, const double *val, const double *x, dou
     return time_launches(s, reps, [&] { launch_gather_yard(idx, val, x, out, n, s); }, ms);
 }
 
+int64_t pdhg_gather_only_outputs(int64_t n) {
+    if (n < 1 || n > 0x7fffffffLL) return 0;
+    return gather_only_outputs(n);
+}
+
+int pdhg_time_gather_only(const int32_t *idx, int64_t n, const double *x, int64_t xlen,
+                          double *out, int32_t reps, void *stream, double *ms) {
+    if (!x || !out || n < 1 || n > 0x7fffffffLL || reps < 1 || reps > 1000 || xlen < 1 ||
+        xlen > 0x7fffffffLL)
+        return PDHG_E_INVALID;
+    int lg = 0;
+    if (!idx) {
+        if (xlen < 2 || (xlen & (xlen - 1))) return PDHG_E_INVALID;
+        while ((1ll << lg) < xlen) ++lg;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    return time_launches(s, reps, [&] { launch_gather_only(idx, x, n, lg, out, s); }, ms);
+}
+
 size_t pdhg_trust_region_workspace_bytes(int64_t N) {
     if (N < 0 || N > 0x7fffffffLL) return 0;
     return al(sizeof(TRState)) + tr_work_bytes(N);

@@ -350,6 +350,11 @@ int red_grid(long long N);
 void launch_copy_yard(const double *src, double *dst, long long n, hipStream_t s);
 void launch_gather_yard(const int *idx, const double *val, const double *x, double *out,
                         long long n, hipStream_t s);
+// gathers only (4 per thread, one sum stored per thread): x[idx[i]], i < n,
+// or with idx null x at hashed indices in [0, 2^lg); outputs: doubles of out
+long long gather_only_outputs(long long n);
+void launch_gather_only(const int *idx, const double *x, long long n, int lg, double *out,
+                        hipStream_t s);
 
 // stand-alone trust region on raw (a, d)
 void launch_tr_raw(int64_t N, const double *a, const double *dd, double r,

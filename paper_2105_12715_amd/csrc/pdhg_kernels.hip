@@ -1247,6 +1247,44 @@ __global__ __launch_bounds__(kWG) void k_gather_yard(const int *__restrict__ idx
     }
 }
 
+// gathers alone: thread t adds x at the indices of entries t, t + kWG, ...
+// (4 per thread, from an index stream, or, with idx null, from Fibonacci
+// hashing of the entry number into a window of 2^lg doubles) and stores one
+// sum; no values, no rows, no update
+constexpr int kGatherOnly = 4;
+__global__ __launch_bounds__(kWG) void k_gather_only(const int *__restrict__ idx,
+                                                     const double *__restrict__ x, long long n,
+                                                     int lg, double *__restrict__ out) {
+    const long long base = (long long)blockIdx.x * kWG * kGatherOnly + threadIdx.x;
+    int c[kGatherOnly];
+#pragma unroll
+    for (int k = 0; k < kGatherOnly; ++k) {
+        const long long e = min(base + (long long)k * kWG, n - 1);
+        c[k] = idx ? ld_matrix(idx + e)
+                   : (int)(((unsigned long long)e * 0x9E3779B97F4A7C15ull) >> (64 - lg));
+    }
+    double g[kGatherOnly];
+#pragma unroll
+    for (int k = 0; k < kGatherOnly; ++k) g[k] = x[c[k]];
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < kGatherOnly; ++k)
+        if (base + (long long)k * kWG < n) sum += g[k];
+    out[(long long)blockIdx.x * kWG + threadIdx.x] = sum;
+}
+
+long long gather_only_outputs(long long n) {
+    const long long per = (long long)kWG * kGatherOnly;
+    return (n + per - 1) / per * kWG;
+}
+
+void launch_gather_only(const int *idx, const double *x, long long n, int lg, double *out,
+                        hipStream_t s) {
+    const long long per = (long long)kWG * kGatherOnly;
+    const long long g = (n + per - 1) / per;
+    if (g > 0) hipLaunchKernelGGL(k_gather_only, dim3((unsigned)g), dim3(kWG), 0, s, idx, x, n, lg, out);
+}
+
 void launch_gather_yard(const int *idx, const double *val, const double *x, double *out,
                         long long n, hipStream_t s) {
     const long long per = (long long)kWG * kYardPer;
