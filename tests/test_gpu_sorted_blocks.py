@@ -106,6 +106,18 @@ def test_threads_per_workgroup_bitwise_equal(lib, name, monkeypatch):
     assert np.array_equal(np.asarray(a[4]), np.asarray(b[4])), "check records differ"
 
 
+def empty_columns_lp(seed=41, m=20000, n=40000):
+    """Column counts 0 (5%), 1 (40%), 2 (25%) and 3..20, >= rows and every
+    bound class: with two slabs of y every column region is populated, and
+    the empty columns (rows of A' with no entry in any slab) come last."""
+    rng = np.random.default_rng(seed)
+    u = rng.random(n)
+    counts = np.where(u < 0.05, 0, np.where(u < 0.45, 1, np.where(u < 0.70, 2,
+                      rng.integers(3, 21, n))))
+    return lpgen.column_count_lp(seed, m, n, counts=counts, bounds="mixed_inf",
+                                 ge_frac=0.3, name="empty_cols")
+
+
 @pytest.mark.parametrize("slab_bytes", ["65536", "131072"])
 def test_slab_row_ranges_follow_the_oracle(lib, slab_bytes, monkeypatch):
     """Column slabs whose launches cover only the rows with entries in them
@@ -114,12 +126,14 @@ def test_slab_row_ranges_follow_the_oracle(lib, slab_bytes, monkeypatch):
     lanes that reduce a row, so the sums may round differently: both must
     give products within the summation-order bound and iterates that follow
     the oracle over 600 iterations with restarts.  Small slab slices force
-    slabs on the medium LP: 131072 bytes gives A'y two slabs of y (the
-    columns then go in three regions by the slabs their rows fall in) and A x
-    four; 65536 bytes gives four and eight."""
+    slabs: 65536 bytes gives the medium LP four slabs of y for A'y and eight
+    of x for A x; 131072 bytes gives a 20,000 x 40,000 LP with empty
+    columns, >= rows and every bound class two slabs of y (the columns then
+    go in three regions by the slabs their rows fall in, then the empty
+    ones) and four of x."""
     import oracle
     from tests.parity import assert_points_match, assert_within_sum_bound
-    lp = lpgen.medium(2)
+    lp = lpgen.medium(2) if slab_bytes == "65536" else empty_columns_lp()
     A = abs(lp.scipy_csr())
     eta = 0.9 / np.sqrt(float(A.sum(axis=0).max()) * float(A.sum(axis=1).max()))
     o = oracle.Oracle(lp, eta=eta)
