@@ -142,10 +142,16 @@ typedef struct pdhg_info {
                                  restarts other than fixed length, n + m <= 1024
                                  and the iteration vectors within 148 KiB of
                                  LDS); 1: every lane holds its matrix entries
-                                 in registers, 2: the matrix is in LDS too.
+                                 in registers, 2: the matrix is in LDS too,
+                                 3: as 1, and each check runs on half the
+                                 workgroup beside the next period's
+                                 iterations on the other half (the same
+                                 iterates and checks; every row within half
+                                 the workgroup).
                                  0: one launch per product and check step.
                                  Environment: PDHG_TINY=0 at pdhg_create turns
-                                 the path off, PDHG_TINY=lds asks for 2 */
+                                 the path off, PDHG_TINY=lds asks for 2,
+                                 PDHG_TINY_OVERLAP=0 keeps 1 instead of 3 */
     int32_t bound_classes;    /* distinct (l, u) pairs the primal update reads
                                  as a one-byte class per column (1..4), or 0:
                                  it reads l and u */

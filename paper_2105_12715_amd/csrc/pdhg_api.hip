@@ -1010,7 +1010,8 @@ int pdhg_solve_many(pdhg_t *const *hs, int32_t count, int64_t max_iters, double 
         size_t lds = 0;
         for (int32_t i = lead; i < count; ++i) {
             const TinyPlan &q = hs[i]->tiny;
-            if (joint[i] && q.reg == pl.reg && (!pl.reg || (q.Lp == pl.Lp && q.Ld == pl.Ld))) {
+            if (joint[i] && q.reg == pl.reg && q.ov == pl.ov &&
+                (!pl.reg || (q.Lp == pl.Lp && q.Ld == pl.Ld))) {
                 g.push_back(i);
                 lds = q.lds > lds ? q.lds : lds;
                 joint[i] = 0;
@@ -1533,7 +1534,7 @@ int pdhg_get_info(pdhg_t *h, pdhg_info *out) {
     out->one_workgroup = 0;
     if (h->tiny.ok && h->prm.method == PDHG_METHOD_PDHG &&
         h->prm.restart_mode != PDHG_RESTART_FIXED)
-        out->one_workgroup = h->tiny.reg ? 1 : 2;
+        out->one_workgroup = h->tiny.reg ? (h->tiny.ov ? 3 : 1) : 2;
     out->bound_classes = h->d.nbcls;
     return PDHG_OK;
 }

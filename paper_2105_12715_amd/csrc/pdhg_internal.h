@@ -372,6 +372,7 @@ constexpr size_t kTinyLdsMax = 148u << 10;   // dynamic LDS bytes (static LDS + 
 struct TinyPlan {
     int ok;                // the LP fits
     int reg;               // 1: matrix rows in registers, 0: matrix in LDS
+    int ov;                // 1: each check overlaps the next block's iterations
     int Lp, Ld;            // lanes per row of A' (primal) and of A (dual)
     size_t lds;            // dynamic LDS bytes
 };
@@ -387,12 +388,15 @@ struct TinyArgs {
 // trust-region keys, d^2, a^2 and a d (n + m each) and candidate indices
 // (n + m ints); m bytes of row kinds; and,
 // with the matrix in LDS, the values of A and A' (nnz doubles each), their
-// row starts (ints) and 16-bit column indices
+// row starts (ints) and 16-bit column indices; with the overlapped check,
+// the copy of x (n + 1), sx (n), y (m + 1), sy and q (m each) it reads
 __host__ __device__ inline size_t tiny_lds_bytes(long long n, long long m, long long nnz,
-                                                 int reg) {
+                                                 int reg, int ov = 0) {
     long long b = 8 * (8 * n + 6 * m + 4) + 36 * (n + m) + m;
     b = (b + 7) & ~7ll;
     if (!reg) b += 16 * nnz + 4 * (n + m + 2) + 4 * nnz;
+    b = (b + 7) & ~7ll;
+    if (ov) b += 8 * (2 * n + 3 * m + 2);
     return (size_t)((b + 15) & ~15ll);
 }
 // plan for an LP already on the device (reads its row starts)

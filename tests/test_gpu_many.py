@@ -65,7 +65,7 @@ def _same_state(a, b):
 def test_solve_many_matches_single_solves(lib, budget, tol):
     lps = _lps()
     paths = [s.info()["one_workgroup"] for s in _solvers(lib, lps)]
-    assert paths.count(0) == 1 and 2 in paths and 1 in paths
+    assert paths.count(0) == 1 and 2 in paths and (1 in paths or 3 in paths)
     _say("many", budget, tol)
     single = _solvers(lib, lps)
     ref = [s.solve(budget, tol) for s in single]

@@ -66,6 +66,11 @@ CASES = {
 }
 # cases whose rows cannot all sit in registers
 LDS_ONLY = {"max_coords"}
+# rows in registers: 1, or 3 when the check also overlaps the next block's
+# iterations (every row within half the workgroup)
+REG_PATHS = (1, 3)
+# cases on the overlapped path
+OVERLAP = ["small50x100", "ge_rows"]
 
 
 def _solver(lib, lp, env=None, **kw):
@@ -83,8 +88,8 @@ def _pair(lib, lp, mode, eta=None, tiny="reg", name=None, **kw):
         eta = oracle.Oracle(lp).info()["eta"]
     o = oracle.Oracle(lp, eta=eta, mode=mode, **kw)
     s = _solver(lib, lp, "lds" if tiny == "lds" else None, eta=eta, restart_mode=mode, **kw)
-    want = 2 if (tiny == "lds" or name in LDS_ONLY) else 1
-    assert s.info()["one_workgroup"] == want
+    want = (2,) if (tiny == "lds" or name in LDS_ONLY) else REG_PATHS
+    assert s.info()["one_workgroup"] in want
     return o, s
 
 
@@ -114,12 +119,17 @@ def test_plan_eligibility(lib):
     LPs that fit; not to fixed-length restarts, extragradient, LPs without
     rows or LPs too large for the LDS budget."""
     for name, mk in CASES.items():
-        want = 2 if name in LDS_ONLY else 1
+        want = 2 if name in LDS_ONLY else (3 if name in OVERLAP else 1)
         assert lib.Solver(mk(), eta=0.1).info()["one_workgroup"] == want, name
         assert _solver(lib, mk(), "lds", eta=0.1).info()["one_workgroup"] == 2, name
     lp = CASES["small50x100"]()
-    assert lib.Solver(lp, eta=0.1, restart_mode=lib.RESTART_FLEXIBLE).info()["one_workgroup"] == 1
-    assert lib.Solver(lp, eta=0.1, restart_mode=lib.RESTART_NONE).info()["one_workgroup"] == 1
+    assert lib.Solver(lp, eta=0.1, restart_mode=lib.RESTART_FLEXIBLE).info()["one_workgroup"] == 3
+    assert lib.Solver(lp, eta=0.1, restart_mode=lib.RESTART_NONE).info()["one_workgroup"] == 3
+    os.environ["PDHG_TINY_OVERLAP"] = "0"
+    try:
+        assert lib.Solver(lp, eta=0.1).info()["one_workgroup"] == 1
+    finally:
+        os.environ.pop("PDHG_TINY_OVERLAP", None)
     assert lib.Solver(lp, eta=0.1, restart_mode=lib.RESTART_FIXED,
                       fixed_len=64).info()["one_workgroup"] == 0
     assert lib.Solver(lp, eta=0.1, method=lib.METHOD_EGM).info()["one_workgroup"] == 0
@@ -197,3 +207,42 @@ def test_repeated_solves_and_determinism(lib):
             s.solve(600, 0.0)
         outs.append([t.clone() for t in s.get_iterate(0)])
     assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("mode", [oracle.MODE_ADAPTIVE, oracle.MODE_FLEXIBLE])
+@pytest.mark.parametrize("name", OVERLAP)
+def test_overlapped_check_follows_the_plain_order(lib, name, mode):
+    """With the check of each block beside the next block's iterations (the
+    block dropped and run again after a restart or a stop), the iterates,
+    check records and solves are those of the plain order: iterates within
+    1e-12 per coordinate after pieces that start off and on the check
+    period, integer fields of every check record equal, and the same
+    iterations, restarts and returned point to 1e-8."""
+    lp = CASES[name]()
+    _say("overlap", name, mode)
+    eta = oracle.Oracle(lp).info()["eta"]
+    a = lib.Solver(lp, eta=eta, restart_mode=mode)
+    os.environ["PDHG_TINY_OVERLAP"] = "0"
+    try:
+        b = lib.Solver(lp, eta=eta, restart_mode=mode)
+    finally:
+        os.environ.pop("PDHG_TINY_OVERLAP", None)
+    assert a.info()["one_workgroup"] == 3 and b.info()["one_workgroup"] == 1
+    done = 0
+    for k in [30, 61, 300, 1000, 4000]:
+        a.solve(k - done, 0.0)
+        b.solve(k - done, 0.0)
+        done = k
+        _compare_points(lambda w: tuple(t.cpu().numpy() for t in b.get_iterate(w)), a, 1e-12)
+    la, lb = a.check_log(), b.check_log()
+    assert la.shape == lb.shape and la.shape[0] >= 100
+    np.testing.assert_array_equal(la[:, [0, 1, 2, 9, 10, 11]], lb[:, [0, 1, 2, 9, 10, 11]])
+    assert la[:, 9].sum() >= 1  # restarts happened inside the launches
+    ia, ib = a.info(), b.info()
+    for key in ("k", "t", "restarts", "checks"):
+        assert ia[key] == ib[key], key
+    ra = a.solve(400_000, 1e-8)
+    rb = b.solve(400_000, 1e-8)
+    assert ra["status"] == 0 and rb["status"] == 0
+    assert ra["k"] == rb["k"] and ra["restarts"] == rb["restarts"] and ra["which"] == rb["which"]
+    _compare_points(lambda w: tuple(t.cpu().numpy() for t in b.get_iterate(w)), a, 1e-12)
