@@ -28,8 +28,11 @@ struct pdhg_handle {
     double eta, tau, sigma, sigma_max;
     int64_t pw_used;
     hipGraphExec_t gexec;   // one block of iterations plus its check
+    hipGraphExec_t gexec_r; // the same, its first primal update from the last check's A'y
     double g_tol;
     bool g_valid;
+    bool reuse;             // blocks right after a check take A'y from it (PDHG)
+    bool fresh;             // the last step on the state was a check of this path
     TinyPlan tiny;          // one-workgroup solver, when the LP fits one CU's LDS
     int slab_cap[2];        // slab counts the workspace has room for (A, A')
 };
@@ -232,13 +235,17 @@ static void enqueue_check(pdhg_t *h, double tol, hipStream_t s) {
     launch_apply(d, s);
 }
 
-static void enqueue_iters(pdhg_t *h, int64_t iters, hipStream_t s) {
+// from_check: the iterations start right after a check, whose A'y (or
+// A'y-bar after a restart at the average) the first primal update takes
+// instead of the product
+static void enqueue_iters(pdhg_t *h, int64_t iters, hipStream_t s, bool from_check = false) {
     for (int64_t i = 0; i < iters; ++i) {
         if (h->prm.method == PDHG_METHOD_EGM) {
             launch_egm(h->d, h->tau, h->sigma, -1, s);
         } else {
             const int sm = sum_mode(i, iters);
-            launch_primal(h->d, h->tau, sm, s);
+            if (i == 0 && from_check) launch_primal_from_check(h->d, h->tau, sm, s);
+            else launch_primal(h->d, h->tau, sm, s);
             launch_dual(h->d, h->sigma, sm, s);
         }
     }
@@ -561,6 +568,13 @@ int pdhg_create(const pdhg_lp *lp, const pdhg_params *prm_in, void *workspace,
     h->prm = prm;
     h->g_valid = false;
     h->gexec = nullptr;
+    h->gexec_r = nullptr;
+    h->fresh = false;
+    {
+        // PDHG_CHECK_REUSE=0: every primal half-step runs its product
+        const char *e = getenv("PDHG_CHECK_REUSE");
+        h->reuse = !(e && e[0] == '0');
+    }
     h->cap = nullptr;
     char *ws = (char *)workspace;
     Dev &d = h->d;
@@ -707,12 +721,14 @@ void pdhg_destroy(pdhg_t *h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->gexec_r) (void)hipGraphExecDestroy(h->gexec_r);
     if (h->cap) (void)hipStreamDestroy(h->cap);
     delete h;
 }
 
 // plain iterations; fixed-length restarts happen when t reaches fixed_len
 static int run_iters(pdhg_t *h, int64_t iters, int64_t *t_host) {
+    if (iters > 0) h->fresh = false;
     if (h->prm.restart_mode != PDHG_RESTART_FIXED) {
         enqueue_iters(h, iters, h->stream);
         return last_error();
@@ -764,6 +780,7 @@ int pdhg_restart_check(pdhg_t *h, double tol, int32_t *converged, int32_t *resta
     enqueue_check(h, tol, h->stream);
     int rc = last_error();
     if (rc) return rc;
+    h->fresh = true;
     DevState hs;
     if ((rc = read_state(h, &hs))) return rc;
     double r[kRec];
@@ -812,22 +829,27 @@ int pdhg_gap(pdhg_t *h, int32_t which, double r, double *rho, double *r_used, do
 // record one block: check_period iterations followed by the check
 static int build_graph(pdhg_t *h, double tol) {
     if (h->g_valid && h->g_tol == tol) return PDHG_OK;
-    if (h->gexec) {
-        (void)hipGraphExecDestroy(h->gexec);
-        h->gexec = nullptr;
-    }
+    hipGraphExec_t *ex[2] = {&h->gexec, &h->gexec_r};
+    for (int v = 0; v < 2; ++v)
+        if (*ex[v]) {
+            (void)hipGraphExecDestroy(*ex[v]);
+            *ex[v] = nullptr;
+        }
     h->g_valid = false;
-    hipGraph_t g = nullptr;
-    CK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    enqueue_iters(h, h->prm.check_period, h->cap);
-    enqueue_check(h, tol, h->cap);
-    hipError_t e = hipStreamEndCapture(h->cap, &g);
-    if (e != hipSuccess) return PDHG_E_HIP;
-    e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) {
-        h->gexec = nullptr;
-        return PDHG_E_HIP;
+    for (int v = 0; v < 2; ++v) {
+        if (v == 1 && !(h->reuse && h->prm.method == PDHG_METHOD_PDHG)) break;
+        hipGraph_t g = nullptr;
+        CK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+        enqueue_iters(h, h->prm.check_period, h->cap, v == 1);
+        enqueue_check(h, tol, h->cap);
+        hipError_t e = hipStreamEndCapture(h->cap, &g);
+        if (e != hipSuccess) return PDHG_E_HIP;
+        e = hipGraphInstantiate(ex[v], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            *ex[v] = nullptr;
+            return PDHG_E_HIP;
+        }
     }
     h->g_tol = tol;
     h->g_valid = true;
@@ -871,6 +893,7 @@ static int solve_eager_step(pdhg_t *h, int64_t *k, int64_t k_end, double tol, in
     if (*k % P == 0) {
         enqueue_check(h, tol, h->stream);
         if ((rc = last_error())) return rc;
+        h->fresh = true;
         DevState hs;
         if ((rc = read_state(h, &hs))) return rc;
         if (hs.numerr) return PDHG_E_NUMERICAL;
@@ -928,8 +951,13 @@ int pdhg_solve(pdhg_t *h, int64_t max_iters, double tol, pdhg_result *out) {
                 if (tiny) {
                     ta.blocks = (int)nb;
                     CK(launch_tiny_blocks(h->d, ta, h->tiny, h->stream));
+                    h->fresh = false;
                 } else {
-                    for (int64_t q = 0; q < nb; ++q) CK(hipGraphLaunch(h->gexec, h->stream));
+                    for (int64_t q = 0; q < nb; ++q) {
+                        CK(hipGraphLaunch(h->fresh && h->gexec_r ? h->gexec_r : h->gexec,
+                                          h->stream));
+                        h->fresh = true;
+                    }
                 }
                 if ((rc = read_state(h, &hs))) return rc;
                 if (hs.numerr) return PDHG_E_NUMERICAL;
@@ -1037,6 +1065,7 @@ int pdhg_solve_many(pdhg_t *const *hs, int32_t count, int64_t max_iters, double 
             }
             CK(hipMemcpyAsync(dargs, harg.data(), sizeof(TinyArgs) * ng, hipMemcpyHostToDevice, s));
             CK(launch_tiny_many(ddev, dargs, ng, pl, lds, s));
+            for (int j = 0; j < ng; ++j) hs[g[j]]->fresh = false;
             CK(hipMemcpyAsync(hsum.data(), dsum, sizeof(long long) * 2 * ng,
                               hipMemcpyDeviceToHost, s));
             CK(hipStreamSynchronize(s));
@@ -1084,6 +1113,7 @@ static int set_slabs(pdhg_t *h, int t, int S) {
     if (S < 1 || S > h->slab_cap[t]) return PDHG_E_INVALID;
     const int gath = t == 0 ? d.n : d.m;
     h->g_valid = false;
+    h->fresh = false;  // A'y of the last check was summed in the old layout
     sb.S = S;
     sb.W = (int)(((long long)gath + S - 1) / S);
     if (S == 1) return PDHG_OK;
@@ -1154,13 +1184,13 @@ static std::map<uint64_t, TuneChoice> g_tune_cache;
 
 static void set_lbias(pdhg_t *h, int t, int b) {
     int &cur = t == 0 ? h->d.lbA : h->d.lbT;
-    if (cur != b) h->g_valid = false;  // the recorded block holds the old value
+    if (cur != b) h->g_valid = h->fresh = false;  // the recorded block holds the old value
     cur = b;
 }
 
 static void set_threads(pdhg_t *h, int t, int wg) {
     int &cur = t == 0 ? h->d.swgA : h->d.swgT;
-    if (cur != wg) h->g_valid = false;  // the recorded block holds the old launches
+    if (cur != wg) h->g_valid = h->fresh = false;  // the recorded block holds the old launches
     cur = wg;
 }
 
@@ -1295,6 +1325,7 @@ int pdhg_get_iterate(pdhg_t *h, int32_t which, double *x, double *y) {
 
 int pdhg_set_iterate(pdhg_t *h, const double *x, const double *y) {
     if (!h || !x || (h->d.m > 0 && !y)) return PDHG_E_INVALID;
+    h->fresh = false;
     const Dev &d = h->d;
     if (d.permuted) {
         launch_gather(x, d.cperm, d.n, d.gx, h->stream);
@@ -1380,6 +1411,7 @@ int pdhg_get_state(pdhg_t *h, void *state, size_t bytes) {
 
 int pdhg_set_state(pdhg_t *h, const void *state, size_t bytes) {
     if (!h || !state) return PDHG_E_INVALID;
+    h->fresh = false;
     Dev &d = h->d;
     const StateLayout L = state_layout(d);
     if (bytes < L.total || ((uintptr_t)state & 255)) return PDHG_E_WORKSPACE;
@@ -1429,6 +1461,7 @@ int pdhg_weight_search(pdhg_t *h, const double *omega, int32_t count, int64_t it
     if (!h || !omega || !kkt || count < 1 || count > kWMax || iters < 0) return PDHG_E_INVALID;
     for (int w = 0; w < count; ++w)
         if (!(omega[w] > 0.0) || !isfinite(omega[w])) return PDHG_E_INVALID;
+    h->fresh = false;
     const Dev &d = h->d;
     if (!workspace || ((uintptr_t)workspace & 255u) ||
         workspace_bytes < wsearch_bytes(d.m, d.n, count))
@@ -1512,6 +1545,7 @@ int pdhg_set_primal_weight(pdhg_t *h, double omega) {
     h->tau = h->eta / omega;
     h->sigma = h->eta * omega;
     h->g_valid = false;  // the recorded block holds the old step sizes
+    h->fresh = false;
     launch_init_point(h->d, h->stream);
     return last_error();
 }

@@ -297,6 +297,8 @@ void launch_transpose_out(const Dev &d, int *orp, int *oci, double *ov, int *ope
 // smode (sum_mode below): 0 adds the new iterate to S, 1 leaves S for the
 // next iteration, 2 adds the previous iterate and then the new one.
 void launch_primal(const Dev &d, double tau, int smode, hipStream_t s);
+// the primal update from the A'y (or A'y-bar) of the check just done
+void launch_primal_from_check(const Dev &d, double tau, int smode, hipStream_t s);
 void launch_dual(const Dev &d, double sigma, int smode, hipStream_t s);
 // How iteration i of a run of `iters` iterations updates the running sums:
 // in pairs, so S is read and written every other iteration; a run of odd

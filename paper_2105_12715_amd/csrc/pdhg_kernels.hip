@@ -358,6 +358,28 @@ void launch_primal(const Dev &d, double tau, int smode, hipStream_t s) {
     product_T(d, d.y, e, &d.st->done, s);
 }
 
+// The primal update of eq. (PDHG-update) from an A'y the check has just
+// computed: A'y of the current y, or A'y-bar when the check restarted at
+// the average (y became y-bar).  The row sums are those the product would
+// give (the same launches computed them), so the update is bitwise the
+// fused one.
+__global__ __launch_bounds__(kWG) void k_primal_from_check(Dev d, EpiPrimal e) {
+    if (d.st->done) return;
+    const int j = blockIdx.x * kWG + threadIdx.x;
+    if (j >= d.n) return;
+    const bool bar = d.st->restarted && d.st->cand == 0;
+    e(j, bar ? d.atyb[j] : d.aty[j]);
+}
+
+void launch_primal_from_check(const Dev &d, double tau, int smode, hipStream_t s) {
+    EpiPrimal e{d.c, d.l, d.u, d.x, d.sx, tau, d.st, d.bcls, {}, {}, smode};
+    for (int k = 0; k < kBoundClasses; ++k) {
+        e.blo[k] = d.blo[k];
+        e.bhi[k] = d.bhi[k];
+    }
+    hipLaunchKernelGGL(k_primal_from_check, dim3(div_up(d.n, kWG)), dim3(kWG), 0, s, d, e);
+}
+
 void launch_dual(const Dev &d, double sigma, int smode, hipStream_t s) {
     product_A(d, d.x, EpiDual{d.b, d.kind, d.y, d.sy, d.q, sigma, smode}, &d.st->done, s);
 }
