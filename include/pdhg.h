@@ -225,7 +225,10 @@ int pdhg_gap(pdhg_t *h, int32_t which, double r, double *rho, double *r_used,
  * Returns PDHG_OK when converged, PDHG_NOT_CONVERGED when the budget ran
  * out, or an error.  *out (host, may be NULL) is filled either way.  The
  * check blocks run as a replayed HIP graph; the host reads one status word
- * per batch of blocks. */
+ * per batch of blocks.  A block that directly follows a check takes its
+ * first primal update from the A'y (or, after a restart at the average,
+ * A'y-bar) the check computed, instead of a product: bitwise the same
+ * update (PDHG_CHECK_REUSE=0 at pdhg_create runs the product). */
 int pdhg_solve(pdhg_t *h, int64_t max_iters, double tol, pdhg_result *out);
 
 /* Outcome of pdhg_autotune.  A product with slabs gathers one column slab

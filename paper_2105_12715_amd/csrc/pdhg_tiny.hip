@@ -249,8 +249,8 @@ struct Grp {
 // longer than any correct run needs stops waiting and flags the run (ends
 // it as a numerical breakdown) rather than hang.
 struct Barriers {
-    int n = 0;             // barriers passed
-    int *ctr = nullptr;    // the group's counter (null: workgroup barrier)
+    unsigned n = 0;        // barriers passed
+    unsigned *ctr = nullptr;  // the group's counter (null: workgroup barrier)
     int *fault = nullptr;  // set when a wait ran out
     int waves = 0;         // waves of the group
     bool sleep = true;     // sleep between polls (yield the SIMD to the other group)
@@ -260,17 +260,20 @@ struct Barriers {
             __syncthreads();
             return;
         }
-        const int target = __builtin_amdgcn_readfirstlane(n * waves);  // the same in every lane
+        // the same in every lane; counts wrap modulo 2^32, and a wave is
+        // never more than a barrier ahead, so the signed difference decides
+        const unsigned target = __builtin_amdgcn_readfirstlane(n * (unsigned)waves);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         if ((threadIdx.x & 63) == 0)
-            __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         // the count is read as one value per wave, so the wait is a scalar loop
-        auto seen = [&]() {
-            return __builtin_amdgcn_readfirstlane(
+        auto behind = [&]() {
+            const unsigned seen = __builtin_amdgcn_readfirstlane(
                 __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+            return (int)(target - seen) > 0;
         };
         int polls = 0;
-        while (seen() < target) {
+        while (behind()) {
             if (sleep) __builtin_amdgcn_s_sleep(1);
             if (++polls > (1 << 24)) {
                 *fault = 1;
@@ -635,7 +638,7 @@ __device__ __forceinline__ void tiny_body(const Dev &d, const TinyArgs &a) {
     __shared__ TrShared trs;
     __shared__ double red[kWaves * kKktSums];
     __shared__ int armed;
-    __shared__ int gctr[2];  // OV: group barrier counters
+    __shared__ unsigned gctr[2];  // OV: group barrier counters
     __shared__ int gfault;   // OV: a group barrier wait ran out
     using GC = Grp<OV ? kTinyTI : 0, OV ? WG - kTinyTI : WG>;  // the check group
     const int tid = threadIdx.x;
@@ -677,8 +680,8 @@ __device__ __forceinline__ void tiny_body(const Dev &d, const TinyArgs &a) {
             t.sn_x[n] = 0.0;
             t.sn_y[m] = 0.0;
         }
-        gctr[0] = 0;
-        gctr[1] = 0;
+        gctr[0] = 0u;
+        gctr[1] = 0u;
         gfault = 0;
     }
     if (!REG) {
