@@ -6,7 +6,8 @@ must be bitwise the one with the product: iterates, running sums, counters
 and check records equal bit for bit against PDHG_CHECK_REUSE=0, over solves
 that start on and off the check period, with restarts at the average and
 (flexible restarts) at the current point, with column slabs of y, and
-across the calls that change the state between solves.
+across the calls that change the state or the product layout between
+solves.
 """
 import os
 import sys
@@ -107,3 +108,21 @@ def test_check_reuse_is_bitwise(lib, name, mode):
     rb = b.solve(200_000, 1e-8)
     assert ra == rb
     _same(a, b, f"{name} {mode} solved")
+
+
+def test_check_reuse_after_layout_changes(lib):
+    """A new SpMV layout (column slabs, lanes per row) sums A'y in another
+    order, so the block after the change must run its product again rather
+    than take the check's A'y from the old layout: bitwise equal to a solver
+    that never reuses it, through two layout changes."""
+    lp = lpgen.medium(2)
+    a = _make(lib, lp, "65536", True)
+    b = _make(lib, lp, "65536", False, eta=a.info()["eta"])
+    for s in (a, b):
+        s.solve(600, 0.0)
+    _same(a, b, "before the changes")
+    for sched in ((1, 1, 0, 0), (2, 2, 0, 1)):
+        for s in (a, b):
+            s.set_schedule(*sched)
+            s.solve(630, 0.0)
+        _same(a, b, f"schedule {sched}")
