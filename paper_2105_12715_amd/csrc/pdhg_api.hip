@@ -882,6 +882,13 @@ static int finish_result(pdhg_t *h, const DevState &hs, pdhg_result *out) {
 
 // Plain iterations up to the next check point (or k_end if sooner), then the
 // check when it falls there: the eager part of pdhg_solve.
+// Blocks of iterations plus check per round before the host reads the
+// state: rounds of 1, 2, 4, ... up to these.  A one-workgroup launch runs
+// its blocks in one kernel (and stops at convergence by itself), so long
+// rounds cost nothing; the graph path queues one replay per block.
+constexpr int64_t kTinyBatchMax = 1024;
+constexpr int64_t kGraphBatchMax = 64;
+
 static int solve_eager_step(pdhg_t *h, int64_t *k, int64_t k_end, double tol, int64_t *t_host,
                             bool *conv) {
     const int64_t P = h->prm.check_period;
@@ -964,7 +971,7 @@ int pdhg_solve(pdhg_t *h, int64_t max_iters, double tol, pdhg_result *out) {
                 blocks -= nb;
                 k += nb * P;
                 conv = hs.conv_which >= 0 && hs.done;
-                if (batch < 64) batch *= 2;
+                if (batch < (tiny ? kTinyBatchMax : kGraphBatchMax)) batch *= 2;
             }
             continue;
         }
@@ -1030,7 +1037,7 @@ int pdhg_solve_many(pdhg_t *const *hs, int32_t count, int64_t max_iters, double 
         CK(hipStreamSynchronize(h->stream));
     }
     // whole blocks of every remaining handle, one workgroup each, a group of
-    // handles sharing one kernel per launch; rounds of 1, 2, 4, ... 64 blocks
+    // handles sharing one kernel per launch; rounds of 1, 2, 4, ... kTinyBatchMax blocks
     for (int32_t lead = 0; lead < count; ++lead) {
         if (!joint[lead]) continue;
         const TinyPlan &pl = hs[lead]->tiny;
@@ -1083,7 +1090,7 @@ int pdhg_solve_many(pdhg_t *const *hs, int32_t count, int64_t max_iters, double 
                     --nlive;
                 }
             }
-            if (batch < 64) batch *= 2;
+            if (batch < kTinyBatchMax) batch *= 2;
         }
     }
     // the iterations after the last whole block, and the results
