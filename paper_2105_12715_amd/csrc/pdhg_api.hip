@@ -953,6 +953,7 @@ int pdhg_solve(pdhg_t *h, int64_t max_iters, double tol, pdhg_result *out) {
             if (!tiny && (rc = build_graph(h, tol))) return rc;
             int64_t blocks = (k_end - k) / P;
             int64_t batch = 1;
+            double kkt_prev = 0.0;  // the smaller KKT of the last round's last check
             while (blocks > 0 && !conv) {
                 int64_t nb = batch < blocks ? batch : blocks;
                 if (tiny) {
@@ -972,6 +973,19 @@ int pdhg_solve(pdhg_t *h, int64_t max_iters, double tol, pdhg_result *out) {
                 k += nb * P;
                 conv = hs.conv_which >= 0 && hs.done;
                 if (batch < (tiny ? kTinyBatchMax : kGraphBatchMax)) batch *= 2;
+                // Replays queued past convergence still launch every kernel
+                // (each returns at once): near the tolerance, size the next
+                // round by the KKT's decay over this one, at half the blocks
+                // that rate would need
+                if (!tiny && tol > 0.0 && !conv) {
+                    const double kk = fmin(hs.kkt_cur[0], hs.kkt_avg[0]);
+                    if (kkt_prev > 0.0 && kk > tol && kk < kkt_prev) {
+                        const double need = log(tol / kk) / (log(kk / kkt_prev) / (double)nb);
+                        const int64_t cap = need < 2.0 ? 1 : (int64_t)(0.5 * need);
+                        if (batch > cap) batch = cap;
+                    }
+                    kkt_prev = kk;
+                }
             }
             continue;
         }
