@@ -233,16 +233,52 @@ static void bspmv_T(const BDev &d, const double *in, double *out, int gate_kind,
                        d.brT, d.nblkT, e, d.lp_col, d.lp, gate_kind, d.xpT, d.tci16, d.lp_r0);
 }
 
-// one iteration; xcopy / ycopy (optional) receive copies of x+ and y+
+// The primal update from the A'y (or, for an LP restarted at its average,
+// A'y-bar) the check has just computed, over the same blocks and with the
+// same gate and steps as the product's launch: a block of one converged LP
+// does nothing, a block of several LPs updates every row (a converged LP's
+// with step 0).  The check's products ran those blocks, so every row this
+// touches has the sum the product would give: bitwise the fused update.
+__global__ __launch_bounds__(kWG) void k_bprimal_from_check(const int *__restrict__ br,
+                                                            EpiPrimalB epi,
+                                                            const int *__restrict__ lp_of,
+                                                            const BLP *lps,
+                                                            const int *__restrict__ xp,
+                                                            const double *__restrict__ aty,
+                                                            const double *__restrict__ atyb) {
+    const int c = xp ? xp[blockIdx.x] : (int)blockIdx.x;
+    if (c < 0) return;
+    const int r0 = br[c], r1 = br[c + 1];
+    if (r0 >= r1) return;
+    const int a = lp_of[r0], z = lp_of[r1 - 1];
+    const BLP *one = nullptr;
+    if (a == z) {
+        if (lps[a].done) return;
+        one = &lps[a];
+    }
+    decltype(auto) eb = for_block(epi, one);
+    for (int j = r0 + (int)threadIdx.x; j < r1; j += kWG) {
+        const BLP &L = lps[lp_of[j]];
+        eb(j, (L.restarted && L.cand == 0) ? atyb[j] : aty[j]);
+    }
+}
+
+// one iteration; xcopy / ycopy (optional) receive copies of x+ and y+;
+// from_check: right after a check, whose A'y the primal update takes
 static void b_iteration(const BDev &d, int smode, hipStream_t s, double *xcopy = nullptr,
-                        double *ycopy = nullptr) {
+                        double *ycopy = nullptr, bool from_check = false) {
     EpiPrimalB ep{d.c, d.l, d.u, d.x, d.sx, d.tau_col, d.bcls, {}, {}, smode, xcopy};
     for (int k = 0; k < kBoundClasses; ++k) {
         ep.blo[k] = d.blo[k];
         ep.bhi[k] = d.bhi[k];
     }
-    hipLaunchKernelGGL(k_bspmv<EpiPrimalB>, dim3(d.nslotT), dim3(kWG), 0, s, d.trp, d.tci, d.tv,
-                       d.y, d.brT, d.nblkT, ep, d.lp_col, d.lp, 0, d.xpT, d.tci16, d.lp_r0);
+    if (from_check)
+        hipLaunchKernelGGL(k_bprimal_from_check, dim3(d.nslotT), dim3(kWG), 0, s, d.brT, ep,
+                           d.lp_col, d.lp, d.xpT, d.aty, d.atyb);
+    else
+        hipLaunchKernelGGL(k_bspmv<EpiPrimalB>, dim3(d.nslotT), dim3(kWG), 0, s, d.trp, d.tci,
+                           d.tv, d.y, d.brT, d.nblkT, ep, d.lp_col, d.lp, 0, d.xpT, d.tci16,
+                           d.lp_r0);
     EpiDualB ed{d.b, d.kind, d.y, d.sy, d.q, d.sigma_row, smode, ycopy};
     hipLaunchKernelGGL(k_bspmv<EpiDualB>, dim3(d.nslotA), dim3(kWG), 0, s, d.rp, d.ci, d.v, d.x,
                        d.brA, d.nblkA, ed, d.lp_row, d.lp, 0, d.xpA, d.ci16, d.lp_c0);
@@ -259,9 +295,10 @@ __global__ void k_badvance(BDev d, int iters) {
     L.t += iters;
 }
 
-static void b_iterations(const BDev &d, long long iters, hipStream_t s) {
+static void b_iterations(const BDev &d, long long iters, hipStream_t s, bool from_check = false) {
     if (iters <= 0) return;
-    for (long long i = 0; i < iters; ++i) b_iteration(d, sum_mode(i, iters), s);
+    for (long long i = 0; i < iters; ++i)
+        b_iteration(d, sum_mode(i, iters), s, nullptr, nullptr, from_check && i == 0);
     hipLaunchKernelGGL(k_badvance, dim3(div_up(d.count, kWG)), dim3(kWG), 0, s, d, (int)iters);
 }
 
@@ -1666,8 +1703,11 @@ struct pdhg_batch_handle {
     int count;
     int mode, period, kkt_kind;
     hipGraphExec_t gexec;
+    hipGraphExec_t gexec_r;  // the same block, its first primal update from the check's A'y
     double g_tol;
     bool g_valid;
+    bool reuse;              // PDHG_CHECK_REUSE=0 at creation: never take the check's A'y
+    bool fresh;              // the last step on the batch was a check
     std::vector<int> pw_used;
     // the tape of the last unrolled forward call, while nothing has changed
     // the batch since (the backward recomputes its windows from it)
@@ -1749,7 +1789,13 @@ int pdhg_batch_create(int32_t count, const pdhg_lp *lps, const pdhg_params *prm,
     h->stream = (hipStream_t)stream;
     h->cap = nullptr;
     h->gexec = nullptr;
+    h->gexec_r = nullptr;
     h->g_valid = false;
+    h->fresh = false;
+    {
+        const char *e = getenv("PDHG_CHECK_REUSE");
+        h->reuse = !(e && e[0] == '0');
+    }
     h->count = count;
     h->mode = P[0].restart_mode;
     h->period = P[0].check_period;
@@ -2033,6 +2079,7 @@ void pdhg_batch_destroy(pdhg_batch_t *h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->gexec_r) (void)hipGraphExecDestroy(h->gexec_r);
     if (h->cap) (void)hipStreamDestroy(h->cap);
     delete h;
 }
@@ -2040,27 +2087,32 @@ void pdhg_batch_destroy(pdhg_batch_t *h) {
 int pdhg_batch_step(pdhg_batch_t *h, int64_t iters) {
     if (!h || iters < 0) return PDHG_E_INVALID;
     h->tape_ok = false;
+    if (iters > 0) h->fresh = false;
     b_iterations(h->d, iters, h->stream);
     return b_last_error();
 }
 
 static int b_build_graph(pdhg_batch_t *h, double tol) {
     if (h->g_valid && h->g_tol == tol) return PDHG_OK;
-    if (h->gexec) {
-        (void)hipGraphExecDestroy(h->gexec);
-        h->gexec = nullptr;
-    }
+    hipGraphExec_t *ex[2] = {&h->gexec, &h->gexec_r};
+    for (int v = 0; v < 2; ++v)
+        if (*ex[v]) {
+            (void)hipGraphExecDestroy(*ex[v]);
+            *ex[v] = nullptr;
+        }
     h->g_valid = false;
-    hipGraph_t g = nullptr;
-    BCK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    b_iterations(h->d, h->period, h->cap);
-    b_check(h->d, tol, h->kkt_kind, b_slots(h->mode), h->cap);
-    if (hipStreamEndCapture(h->cap, &g) != hipSuccess) return PDHG_E_HIP;
-    hipError_t e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) {
-        h->gexec = nullptr;
-        return PDHG_E_HIP;
+    for (int v = 0; v < (h->reuse ? 2 : 1); ++v) {
+        hipGraph_t g = nullptr;
+        BCK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+        b_iterations(h->d, h->period, h->cap, v == 1);
+        b_check(h->d, tol, h->kkt_kind, b_slots(h->mode), h->cap);
+        if (hipStreamEndCapture(h->cap, &g) != hipSuccess) return PDHG_E_HIP;
+        hipError_t e = hipGraphInstantiate(ex[v], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            *ex[v] = nullptr;
+            return PDHG_E_HIP;
+        }
     }
     h->g_tol = tol;
     h->g_valid = true;
@@ -2092,7 +2144,11 @@ int pdhg_batch_solve(pdhg_batch_t *h, int64_t max_iters, double tol, pdhg_result
             int64_t blocks = (k_end - k) / P, batch = 1;
             while (blocks > 0 && !all_done) {
                 const int64_t nb = batch < blocks ? batch : blocks;
-                for (int64_t q = 0; q < nb; ++q) BCK(hipGraphLaunch(h->gexec, h->stream));
+                for (int64_t q = 0; q < nb; ++q) {
+                    BCK(hipGraphLaunch(h->fresh && h->gexec_r ? h->gexec_r : h->gexec,
+                                       h->stream));
+                    h->fresh = true;
+                }
                 if ((rc = b_read_lps(h, cur))) return rc;
                 blocks -= nb;
                 k += nb * P;
@@ -2108,10 +2164,12 @@ int pdhg_batch_solve(pdhg_batch_t *h, int64_t max_iters, double tol, pdhg_result
         const int64_t to_check = P - (k % P);
         const int64_t sstep = to_check < k_end - k ? to_check : k_end - k;
         b_iterations(h->d, sstep, h->stream);
+        if (sstep > 0) h->fresh = false;
         k += sstep;
         if (k % P == 0) {
             b_check(h->d, tol, h->kkt_kind, b_slots(h->mode), h->stream);
             if ((rc = b_last_error())) return rc;
+            h->fresh = true;
         }
         if ((rc = b_read_lps(h, cur))) return rc;
         all_done = true;
@@ -2172,11 +2230,13 @@ int pdhg_batch_set_schedule(pdhg_batch_t *h, int32_t placement, int32_t index16)
     h->placement = placement;
     h->index16 = index16;
     h->g_valid = false;  // the recorded graph holds the old launch arguments
+    h->fresh = false;
     return PDHG_OK;
 }
 
 int pdhg_batch_autotune(pdhg_batch_t *h, int32_t iters, pdhg_batch_tune *out) {
     if (!h || iters < 1 || iters > 10000) return PDHG_E_INVALID;
+    h->fresh = false;
     pdhg_batch_tune r;
     memset(&r, 0, sizeof(r));
     hipStream_t s = h->stream;
@@ -2357,6 +2417,7 @@ size_t pdhg_batch_tape_bytes(pdhg_batch_t *h, int64_t K) {
 
 int pdhg_batch_set_data(pdhg_batch_t *h, const double *c, const double *b, const double *vals) {
     if (!h || !c || (h->d.M > 0 && !b) || (h->d.NNZ > 0 && !vals)) return PDHG_E_INVALID;
+    h->fresh = false;
     h->tape_ok = false;
     const BDev &d = h->d;
     hipStream_t s = h->stream;
@@ -2375,6 +2436,7 @@ int pdhg_batch_set_data(pdhg_batch_t *h, const double *c, const double *b, const
 int pdhg_batch_unrolled_forward(pdhg_batch_t *h, int64_t K, void *tape, size_t tape_bytes,
                                 double *xK) {
     if (!h) return PDHG_E_INVALID;
+    h->fresh = false;
     Tape t;
     size_t need = 0;
     if (!tape_carve(h, K, (char *)tape, &t, &need)) return PDHG_E_INVALID;
@@ -2422,6 +2484,7 @@ int pdhg_batch_unrolled_forward(pdhg_batch_t *h, int64_t K, void *tape, size_t t
 int pdhg_batch_unrolled_backward(pdhg_batch_t *h, int64_t K, void *tape, size_t tape_bytes,
                                  const double *dLdx, double *gc, double *gb, double *gA) {
     if (!h || !dLdx || !gc || (h->d.M > 0 && !gb) || (h->d.NNZ > 0 && !gA)) return PDHG_E_INVALID;
+    h->fresh = false;
     Tape t;
     size_t need = 0;
     if (!tape_carve(h, K, (char *)tape, &t, &need)) return PDHG_E_INVALID;

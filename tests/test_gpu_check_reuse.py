@@ -126,3 +126,51 @@ def test_check_reuse_after_layout_changes(lib):
             s.set_schedule(*sched)
             s.solve(630, 0.0)
         _same(a, b, f"schedule {sched}")
+
+
+def test_batch_check_reuse_is_bitwise(lib):
+    """The batched solver takes the check's A'y the same way: per LP, A'y, or
+    A'y-bar when that LP restarted at its average; blocks of one converged LP
+    do nothing and blocks of several LPs update every row (a converged LP's
+    with step 0), as the product's launch does.  Small LPs converge early and
+    share blocks of A' with each other and with the larger members, so the
+    later solves run over converged LPs too; every iterate stays bitwise equal
+    to the batch that never reuses the check's products."""
+    lps = [lpgen.small_dense(5), lpgen.batch_member(2), lpgen.small_dense(6),
+           lpgen.small_dense(7), lpgen.batch_member(3), lpgen.small_dense(8)]
+    import oracle
+    params = [{"eta": oracle.Oracle(lp).info()["eta"]} for lp in lps]
+    saved = os.environ.get("PDHG_CHECK_REUSE")
+    a = lib.BatchSolver(lps, params=params)
+    os.environ["PDHG_CHECK_REUSE"] = "0"
+    try:
+        b = lib.BatchSolver(lps, params=params)
+    finally:
+        if saved is None:
+            os.environ.pop("PDHG_CHECK_REUSE", None)
+        else:
+            os.environ["PDHG_CHECK_REUSE"] = saved
+
+    def same(where):
+        for i in range(len(lps)):
+            for w in (0, 1, 2):
+                xa, ya = a.get_iterate(i, w)
+                xb, yb = b.get_iterate(i, w)
+                assert torch.equal(xa, xb) and torch.equal(ya, yb), (where, i, w)
+            ia, ib = a.info(i), b.info(i)
+            for key in ("k", "t", "restarts", "checks"):
+                assert ia[key] == ib[key], (where, i, key)
+
+    for s in (a, b):
+        s.solve(331, 0.0)
+    same("331 iterations")
+    ra = a.solve(30_000, 1e-8)
+    rb = b.solve(30_000, 1e-8)
+    assert ra == rb
+    done = [r["status"] == 0 for r in ra]
+    assert any(done) and not all(done)
+    same("some converged")
+    for s in (a, b):
+        s.step(11)
+        s.solve(3_019, 1e-8)
+    same("after eager steps, over converged LPs")
